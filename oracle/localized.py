@@ -1,0 +1,137 @@
+"""Algorithm 1 (localized Newton) and Algorithm 2 (adaptive nonlinear
+domain decomposition), oracle versions (test infrastructure only).
+
+Each local solve is the restricted Newton step of Section 4.3,
+J_A du_A = -F_A with J_A = R_A J R_A^T: the full residual and Jacobian are
+formed (the plain definition) and restricted to the active rows and
+columns, so inactive neighbours enter as frozen Dirichlet values.
+
+Readings where the paper is silent (shared with the HIP library):
+
+* the loop of Algorithm 1 starts in 'expand' mode; convergence is
+  ||dp||_inf over the active cells below eps_conv, and the loop continues
+  while expanding even when converged;
+* the initial active set is the fracture/perforated cells and their m-layer
+  neighbourhood on the first step, then the previous step's support
+  {|p^n - p^{n-1}| >= eps_loc} plus the always-active cells;
+* Algorithm 2: each visit of a subdomain is one Newton iteration on it;
+  last_dp[i] holds |dp_i| from the latest solve that touched cell i; a
+  subdomain is skipped when last_dp < eps on V_A^k and on its outer layer;
+  the sweeps stop when no subdomain would be solved.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .jacobian import adjacency
+from .newton import Options, Solver, State, converged
+from .physics import accumulation
+from . import sets
+
+
+class LocalSolver(Solver):
+    def __init__(self, model, opts: Options | None = None):
+        super().__init__(model, opts)
+        self.rp, self.nb = adjacency(model)
+        self.aa = np.nonzero(model.always_active)[0]
+
+    # ------------------------------------------------------ Algorithm 1
+    def alg1_timestep(self, st: State, dt, prev_support, log=None):
+        o = self.opts
+        m_old = accumulation(self.model, st.u, st.status)
+        work = st.copy()
+        act = sets.initial_active(self.rp, self.nb, self.aa, o.m_layers,
+                                  prev_support)
+        bnd = sets.boundary(self.rp, self.nb, act)
+        is_expand, conv = True, False
+        it = 0
+        while is_expand or not conv:
+            it += 1
+            if it > o.max_newton:
+                return None, it, None
+            n_a = len(act)
+            dp, ds, nsw = self.newton_iteration(work, m_old, dt, active=act)
+            if not np.all(np.isfinite(work.u)):
+                return None, it, None
+            conv = converged(o, float(dp.max()), ds, nsw)
+            if log is not None:
+                log.append(dict(n_a=n_a, n_b=len(bnd), dp=float(dp.max())))
+            act, bnd, is_expand = sets.alg1_update(
+                self.rp, self.nb, act, bnd, dp, o.eps_loc, o.m_layers, self.aa)
+        support = set(np.nonzero(np.abs(work.u[0] - st.u[0]) >= o.eps_loc)[0].tolist())
+        return work, it, support
+
+    # ------------------------------------------------------ Algorithm 2
+    def alg2_timestep(self, st: State, dt, prev_support, log=None):
+        o = self.opts
+        m = o.m_layers_dd
+        m_old = accumulation(self.model, st.u, st.status)
+        work = st.copy()
+        va = sets.initial_active(self.rp, self.nb, self.aa, m, prev_support)
+        vt = set(va)
+        vb = sets.boundary(self.rp, self.nb, va)
+        db = sets.outer_layer(self.rp, self.nb, va)
+        last_dp = np.zeros(self.model.n)
+        subs = []
+        inner = 0
+        is_expand = True
+        while is_expand:                       # phase 1: build subdomains
+            inner += 1
+            if inner > o.max_newton:
+                return None, inner, None
+            dp, _, _ = self.newton_iteration(work, m_old, dt, active=va)
+            idx = np.fromiter(va, np.int64)
+            last_dp[idx] = dp[idx]
+            subs.append((idx, np.fromiter(db, np.int64)))
+            if log is not None:
+                log.append(dict(n_a=len(va), phase=1, dp=float(dp.max())))
+            va, vt, vb, db, is_expand = sets.alg2_expand(
+                self.rp, self.nb, vt, vb, dp, o.eps_loc, m)
+
+        def pending(k):
+            a, d = subs[k]
+            mx = last_dp[a].max() if a.size else 0.0
+            if d.size:
+                mx = max(mx, last_dp[d].max())
+            return mx >= o.eps_loc
+
+        sweeps = 0
+        while any(pending(k) for k in range(len(subs))):   # phase 2
+            sweeps += 1
+            if sweeps > o.max_sweeps:
+                return None, inner, None
+            for k in range(len(subs)):
+                if not pending(k):
+                    continue
+                a = subs[k][0]
+                inner += 1
+                dp, _, _ = self.newton_iteration(work, m_old, dt,
+                                                 active=set(a.tolist()))
+                if not np.all(np.isfinite(work.u)):
+                    return None, inner, None
+                last_dp[a] = dp[a]
+                if log is not None:
+                    log.append(dict(n_a=int(a.size), phase=2, sweep=sweeps,
+                                    sub=k, dp=float(dp.max())))
+        support = set(np.nonzero(np.abs(work.u[0] - st.u[0]) >= o.eps_loc)[0].tolist())
+        return work, inner, support
+
+    # ------------------------------------------------------ schedules
+    def run_local(self, st: State, schedule, alg=1, log=None):
+        """Run a schedule with Algorithm 1 or 2, halving dt on failure."""
+        step = self.alg1_timestep if alg == 1 else self.alg2_timestep
+        prev = None
+        recs = []
+        for dt in schedule:
+            pending = [dt]
+            while pending:
+                h = pending.pop(0)
+                new, its, sup = step(st, h, prev, log)
+                if new is None:
+                    if h < dt / 2 ** self.opts.max_cuts:
+                        raise RuntimeError("timestep cut limit reached")
+                    pending = [h / 2, h / 2] + pending
+                    continue
+                recs.append(dict(dt=h, iters=its))
+                st, prev = new, sup
+        return st, recs

@@ -1,0 +1,107 @@
+"""Active-set logic of Algorithms 1 and 2 with Python sets (oracle; test
+infrastructure only).
+
+Definitions (Section 4.3):
+
+* V_A: active cells; V_B: the outermost layer of V_A, read here as the
+  active cells with at least one neighbour outside V_A;
+* V_nbr^{i,m}: the cells within m layers of i.  Fig. 2, which draws it, is
+  not available; it is read as all cells at graph distance <= m from i over
+  the connection graph (matrix, fracture and non-neighbour connections),
+  i included;
+* a cell's update is non-negligible when |dp_i| >= eps (the cutoff is a
+  pressure quantity in Section 5);
+* the outer layer dB of a set (Section 4.4, Step 1): the cells outside the
+  set adjacent to it.
+
+Everything here is the plain definition over Python sets; nothing is
+vectorized.
+"""
+from __future__ import annotations
+
+
+def neighbours(rp, nb, i):
+    return nb[rp[i]:rp[i + 1]]
+
+
+def ball(rp, nb, i, m):
+    """V_nbr^{i,m}: breadth-first search to depth m."""
+    seen = {int(i)}
+    frontier = [int(i)]
+    for _ in range(m):
+        nxt = []
+        for c in frontier:
+            for j in neighbours(rp, nb, c):
+                j = int(j)
+                if j not in seen:
+                    seen.add(j)
+                    nxt.append(j)
+        frontier = nxt
+    return seen
+
+
+def boundary(rp, nb, act):
+    """V_B: active cells with a neighbour outside the active set."""
+    return {i for i in act
+            if any(int(j) not in act for j in neighbours(rp, nb, i))}
+
+
+def outer_layer(rp, nb, act):
+    """dB: cells outside ``act`` adjacent to it."""
+    out = set()
+    for i in act:
+        for j in neighbours(rp, nb, i):
+            if int(j) not in act:
+                out.add(int(j))
+    return out
+
+
+def initial_active(rp, nb, always_active, m, prev_support=None):
+    """Initial V_A.  First step: the wells / fractures and their m-layer
+    neighbourhood (Section 4.3 remark on the initial set); later steps:
+    the support of the previous timestep plus the always-active cells
+    (Section 5.2.1 takes the last timestep's support)."""
+    aa = {int(i) for i in always_active}
+    if prev_support is None:
+        out = set()
+        for i in aa:
+            out |= ball(rp, nb, i, m)
+        return out
+    return {int(i) for i in prev_support} | aa
+
+
+def alg1_update(rp, nb, act, bnd, dp_abs, eps, m, always_active):
+    """One pass of the set logic of Algorithm 1 after a local solve.
+
+    For each boundary cell with a non-negligible update, V_A grows by its
+    m-layer neighbourhood ('expand').  If no boundary update is
+    non-negligible, V_A becomes the support of the update plus the
+    always-active cells ('shrink').  Returns (act, bnd, is_expand)."""
+    new = set(act)
+    is_expand = False
+    for i in bnd:
+        if dp_abs[i] >= eps:
+            is_expand = True
+            new |= ball(rp, nb, i, m)
+    if not is_expand:
+        new = {i for i in act if dp_abs[i] >= eps} | {int(i) for i in always_active}
+    return new, boundary(rp, nb, new), is_expand
+
+
+def alg2_expand(rp, nb, vt, bnd_k, dp_abs, eps, m):
+    """Phase-1 set logic of Algorithm 2 after the local solve on V_A^k.
+
+    Returns (V_A^{k+1}, V_T, V_B^{k+1}, dB^{k+1}, is_expand)."""
+    nxt = set()
+    vt = set(vt)
+    is_expand = False
+    for i in bnd_k:
+        if dp_abs[i] >= eps:
+            is_expand = True
+            bl = ball(rp, nb, i, m)
+            vt |= bl
+            nxt |= bl
+    if not is_expand:
+        return set(), vt, set(), set(), False
+    vb_t = boundary(rp, nb, vt)
+    return nxt, vt, vb_t & nxt, outer_layer(rp, nb, nxt), True
