@@ -1,0 +1,226 @@
+/*
+ * fim.h -- C ABI of the localized fully implicit Newton library for
+ * fractured reservoirs on MI355X (gfx950).
+ *
+ * The library advances a discrete reservoir model by fully implicit
+ * timesteps.  Jiang (2020), Section 4.1, states the problem: given the
+ * state u^n and a timestep dt, find u^{n+1} with F(u^{n+1}) = 0 by Newton
+ * iterates J(u^nu) du^nu = -F(u^nu); Section 4.3 (Algorithm 1, localized
+ * Newton) and Section 4.4 (Algorithm 2, adaptive nonlinear domain
+ * decomposition) restrict each iteration to an a-priori active set.  F is
+ * the finite-volume two-point-flux residual with phase-potential upwinding
+ * of Appendix A.
+ *
+ * Conventions
+ *  - SI units everywhere (Pa, m, m^2, m^3, s, kg, Pa s).
+ *  - Cells are numbered 0..n-1.  A state is b planes of n doubles:
+ *    plane 0 pressure, plane 1 water saturation (b >= 2), plane 2 the
+ *    black-oil variable X (b = 3): gas saturation where status = 1
+ *    (saturated), dissolved-gas ratio R_s where status = 0.
+ *  - Every call is stream-ordered on the stream given at creation
+ *    (NULL: the library creates its own).  Calls that return host data
+ *    synchronise that stream.
+ *  - Return codes: FIM_OK = 0; negative = hard error (the message is in
+ *    fim_last_error; the model keeps its last valid state only where the
+ *    call says so); positive = soft failure, state rolled back.
+ *  - One host thread per handle.  Different handles may be driven from
+ *    different threads on different streams.
+ */
+#ifndef FIM_H
+#define FIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fim_status {
+    FIM_OK = 0,
+    FIM_NOT_CONVERGED = 1,   /* Newton failed; state rolled back to u^n   */
+    FIM_E_ARG = -1,          /* invalid argument or model description     */
+    FIM_E_NOMEM = -2,        /* device allocation failed                  */
+    FIM_E_HIP = -3,          /* HIP runtime error                         */
+    FIM_E_STATE = -4,        /* call not valid in the current step state  */
+    FIM_E_NONFINITE = -5     /* non-finite input                          */
+} fim_status;
+
+enum { FIM_FULL = 0, FIM_LOCAL = 1, FIM_DD = 2 };          /* solver mode */
+enum { FIM_FP64 = 0, FIM_MIXED = 1 };                     /* Krylov precision */
+enum { FIM_HOST = 0, FIM_DEVICE = 1 };                    /* pointer kind */
+enum { FIM_FLUID_SINGLE = 1, FIM_FLUID_DEADOIL = 2, FIM_FLUID_BLACKOIL = 3 };
+
+/* Fluid description (Section 2 and Appendix A leave the fluid open; these
+ * are the three closed families the library implements).  Unused fields
+ * are ignored.
+ *  single  : rho = rho_ref exp(c (p - p_ref)), viscosity mu, b = 1.
+ *  deadoil : rho_w = rho_w exp(c_w (p - p_ref)), rho_o likewise with c_o;
+ *            Corey exponent 2, S_wn = clamp((S_w - swc)/(1 - swc - sor)),
+ *            k_rw = S_wn^2, k_ro = (1 - S_wn)^2; b = 2 (water, oil).
+ *  blackoil: R_s,sat = rs_b p / p_b, B_o = (1 + bo_slope R_s)
+ *            exp(-c_o (p - p_b R_s / rs_b)), B_g = bg_c / p,
+ *            B_w = exp(-c_w (p - p_ref)); surface densities rho_*sc;
+ *            k_rw = ((S_w - swc)/span)^2, k_rg = (S_g/span)^2,
+ *            k_ro = (S_o/span)^2 (clamped); b = 3 (water, oil, gas). */
+typedef struct fim_fluid {
+    int32_t kind;
+    double p_ref;
+    double rho_ref, c, mu;                                       /* single */
+    double rho_w, c_w, mu_w, rho_o, c_o, mu_o, swc, sor;         /* dead oil */
+    double rs_b, p_b, bo_slope, bg_c, rho_osc, rho_gsc, rho_wsc, /* black oil */
+           mu_g, span;
+} fim_fluid;
+
+/* The discrete problem (host pointers; the library copies everything and
+ * the caller keeps ownership).  Connections need conn_i < conn_j, no
+ * duplicates, T >= 0; pore volumes > 0; at most one perforation per cell.
+ * Pore volume is pv_ref (1 + c_r (p - p_ref_rock)).  always_active may be
+ * NULL (no cell always active); the paper keeps fracture cells active. */
+typedef struct fim_model_desc {
+    int32_t n_cells, n_conn, n_perf;
+    const double*  pv_ref;        /* [n] m^3                               */
+    const double*  depth;         /* [n] m, positive downward              */
+    const uint8_t* always_active; /* [n] or NULL                           */
+    const int32_t* conn_i;        /* [n_conn]                              */
+    const int32_t* conn_j;        /* [n_conn]                              */
+    const double*  conn_T;        /* [n_conn] m^3                          */
+    const int32_t* perf_cell;     /* [n_perf]                              */
+    const double*  perf_wi;       /* [n_perf] m^3                          */
+    const double*  perf_bhp;      /* [n_perf] Pa                           */
+    double c_r, p_ref_rock, gravity;
+    fim_fluid fluid;
+} fim_model_desc;
+
+/* Solver options.  fim_default_options fills the paper's settings
+ * (Section 5: eps_p = 0.3 psi cutoff and convergence, m = 2 for
+ * Algorithm 1, m = 4 for Algorithm 2). */
+typedef struct fim_options {
+    double  eps_conv;        /* Newton convergence: ||dp||_inf < eps_conv (Pa) */
+    double  eps_loc;         /* active/boundary cutoff |dp_i| >= eps_loc (Pa)  */
+    double  eps_s;           /* tight mode: ||dS||_inf < eps_s                 */
+    int32_t tight;           /* 1: also require ||dS|| < eps_s and no switch   */
+    int32_t m_layers;        /* neighbour layers, Algorithm 1                  */
+    int32_t m_layers_dd;     /* neighbour layers, Algorithm 2                  */
+    int32_t max_newton;      /* Newton iteration cap per timestep              */
+    int32_t max_sweeps;      /* Algorithm 2 outer sweep cap                    */
+    int32_t auto_cut;        /* solve_timestep halves dt on failure            */
+    int32_t max_cuts;
+    double  ds_max;          /* saturation chop per iteration                  */
+    int32_t precision;       /* FIM_FP64 or FIM_MIXED (FP32 Krylov + FP64 IR)  */
+    double  lin_rtol;        /* ||J x + F|| <= lin_rtol ||F||                  */
+    double  inner_rtol;      /* FP32 inner reduction per refinement pass       */
+    int32_t krylov_maxit;    /* BiCGStab iterations per refinement pass        */
+    int32_t max_refine;      /* refinement passes                              */
+    int32_t check_every;     /* BiCGStab iterations between host checks        */
+} fim_options;
+
+typedef struct fim_iter_stats {
+    int32_t n_active;        /* n_A of this iteration                     */
+    int32_t n_boundary;      /* |V_B| of this iteration                   */
+    int32_t is_expand;       /* mode after this iteration                 */
+    int32_t converged;       /* timestep converged and committed          */
+    int32_t krylov_iters;
+    int32_t refine_passes;
+    int32_t n_switch;
+    int32_t nonfinite;
+    int32_t phase;           /* Algorithm 2: 1 build, 2 sweep; else 0     */
+    int32_t subdomain;       /* Algorithm 2 subdomain index               */
+    double  dp_max;          /* ||dp||_inf over the active cells (Pa)     */
+    double  ds_max;
+    double  lin_relres;      /* ||J x + F|| / ||F||                       */
+} fim_iter_stats;
+
+typedef struct fim_step_stats {
+    int32_t iterations;      /* Newton (or Algorithm 2 inner) iterations  */
+    int32_t converged;
+    int32_t cuts;            /* dt halvings used                          */
+    int32_t krylov_iters;
+    double  sum_active;      /* sum of n_A over the iterations            */
+    int32_t max_active;
+    int32_t subdomains;      /* Algorithm 2: N                            */
+} fim_step_stats;
+
+typedef struct fim_model fim_model;
+
+void fim_default_options(fim_options* o);
+
+/* Uploads the model (Section 4.3, the index set V and the connection
+ * graph).  hip_stream: a hipStream_t or NULL.  Errors: FIM_E_ARG on an
+ * invalid description, FIM_E_NOMEM / FIM_E_HIP on device failures; *out
+ * is NULL then. */
+fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
+                            void* hip_stream, fim_model** out);
+
+/* Replaces the state (b planes of n doubles, status may be NULL for
+ * b < 3) and ends any timestep in progress; the next Newton call starts a
+ * new timestep from this state with a fresh history (first-step initial
+ * active set).  mem: FIM_HOST or FIM_DEVICE.  Non-finite input returns
+ * FIM_E_NONFINITE and leaves the previous state. */
+fim_status fim_set_state(fim_model* m, const double* u, const int8_t* status, int mem);
+
+/* Copies the current state (mid-step: the current Newton iterate). */
+fim_status fim_get_state(fim_model* m, double* u_out, int8_t* status_out, int mem);
+
+/* One Newton iteration (Algorithm 1 in FIM_LOCAL, the standard iteration
+ * in FIM_FULL, one subdomain solve of Algorithm 2 in FIM_DD).  The first
+ * call of a timestep stores u^n and the initial active set.  When the
+ * stopping test of the algorithm holds the step is committed and
+ * st->converged = 1.  Calling with a different dt or mode inside a step
+ * returns FIM_E_STATE.  Hitting max_newton rolls back and returns
+ * FIM_NOT_CONVERGED.  st may be NULL. */
+fim_status fim_newton_step(fim_model* m, double dt, int mode, fim_iter_stats* st);
+
+/* Loops fim_newton_step to convergence (Section 4.1).  On failure rolls
+ * back to u^n and returns FIM_NOT_CONVERGED, or with auto_cut substeps
+ * with halved dt (at most max_cuts halvings). */
+fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats* st);
+
+/* Frees all device memory after synchronising the stream. */
+fim_status fim_destroy_model(fim_model* m);
+
+/* Last error message of the handle (never NULL); with m = NULL, the
+ * reason the calling thread's last fim_create_model failed. */
+const char* fim_last_error(const fim_model* m);
+
+int32_t fim_num_cells(const fim_model* m);
+int32_t fim_block_size(const fim_model* m);
+
+/* ---------------- inspection entry points (used by parity tests) -------- */
+
+/* Assembles F_A and J_A = R_A J R_A^T (Section 4.3) at iterate u_iter with
+ * old-time state u_old, on the active set act (host u8[n], NULL = all
+ * cells), without solving.  Outputs (host, caller-allocated): n_active,
+ * l2g[n] (first n_active used), F[n_active b], and the matrix in block
+ * CSR form: row_ptr[n_active+1], col[cap_blocks], val[cap_blocks b b]
+ * (row-major blocks, diagonal block first in each row, then active
+ * neighbours ascending).  FIM_E_ARG if cap_blocks is too small.  Ends any
+ * timestep in progress and leaves u_iter as the current state. */
+fim_status fim_inspect_assemble(fim_model* m, const double* u_old,
+                                const double* u_iter, const int8_t* status,
+                                double dt, const uint8_t* act,
+                                int32_t* n_active, int32_t* l2g, double* F,
+                                int32_t* row_ptr, int32_t* col, double* val,
+                                int64_t cap_blocks);
+
+/* Runs one active-set update of Algorithm 1 (expand or shrink) on given
+ * inputs: act_in and dp_abs (host, [n]); writes act_out, bnd_out (host
+ * u8[n], boundary of the new set), l2g_out (host i32[n]; first *n_active
+ * entries), *is_expand.  bnd of the input set is computed by the library. */
+fim_status fim_inspect_sets(fim_model* m, const uint8_t* act_in,
+                            const double* dp_abs, double eps, int32_t layers,
+                            uint8_t* act_out, uint8_t* bnd_out,
+                            int32_t* l2g_out, int32_t* n_active,
+                            int32_t* is_expand);
+
+/* Solves J_A x = -F_A for the system of the last fim_inspect_assemble with
+ * the library's Krylov solver (precision as in the options); x (host,
+ * [n_active b]).  *iters receives BiCGStab iterations, *relres the final
+ * ||J x + F|| / ||F||. */
+fim_status fim_inspect_solve(fim_model* m, double* x, int32_t* iters,
+                             double* relres);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIM_H */

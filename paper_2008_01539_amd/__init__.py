@@ -1,0 +1,13 @@
+"""Localized fully implicit Newton solver for fractured reservoirs on
+MI355X (gfx950): HIP kernels behind the C ABI of include/fim.h, with a thin
+ctypes binding.
+
+    from paper_2008_01539_amd import FimModel, Options, LOCAL
+"""
+from .fim import (DD, DEVICE, FP64, FULL, HOST, LIB_PATH, LOCAL, MIXED, FimError,
+                  FimModel, IterStats, NotConverged, Options, StepStats,
+                  exported_symbols)
+
+__all__ = ["FimModel", "Options", "FimError", "NotConverged", "IterStats",
+           "StepStats", "FULL", "LOCAL", "DD", "FP64", "MIXED", "HOST", "DEVICE",
+           "LIB_PATH", "exported_symbols"]

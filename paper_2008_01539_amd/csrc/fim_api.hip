@@ -1,0 +1,962 @@
+// Host driver and C ABI of libfim: model residency in HBM, the Newton
+// iteration (Section 4.1), the localized Newton state machine
+// (Algorithm 1), the adaptive nonlinear domain decomposition
+// (Algorithm 2), the iterative-refinement Krylov driver and the inspection
+// entry points.  All arithmetic of the path runs in the kernels; the host
+// only sequences launches and reads one small status record per Newton
+// iteration (plus one per block of Krylov iterations).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fim_internal.hpp"
+
+using namespace fimk;
+
+
+struct fim_model {
+    int n = 0, nconn = 0, B = 1, fk = 1;
+    fim_options o{};
+    DevFluid f{};
+    hipStream_t s = nullptr;
+    bool own_stream = false;
+    Graph g{};
+    // static data
+    int *adj_ptr = nullptr, *adj_nbr = nullptr;
+    double *adj_T = nullptr, *pv = nullptr, *depth = nullptr, *wi = nullptr, *bhp = nullptr;
+    uint8_t* flags = nullptr;
+    int max_deg = 0;
+    // state
+    double *u = nullptr, *un = nullptr, *Mn = nullptr, *dp_abs = nullptr, *last_dp = nullptr;
+    int8_t *st = nullptr, *stn = nullptr;
+    uint8_t *act = nullptr, *act2 = nullptr, *supp = nullptr, *bnd = nullptr, *vt = nullptr,
+            *outer = nullptr;
+    // local system
+    int *l2g = nullptr, *g2l = nullptr, *swidth = nullptr, *sptr = nullptr, *blk = nullptr;
+    int *col = nullptr;
+    double *J = nullptr, *F = nullptr, *dinv = nullptr;
+    void* At = nullptr;
+    long slot_cap = 0;
+    // Krylov
+    double *x64 = nullptr, *rir = nullptr, *part = nullptr;
+    void* kvec = nullptr;   // 9 vectors of nA b elements in the Krylov precision
+    KScal* sc = nullptr;
+    NStat* ns = nullptr;
+    int* dint = nullptr;    // [0] expand flag, [1] n_next, [2] boundary count
+    double* dsub = nullptr; // Algorithm 2 per-subdomain maxima
+    // pinned host mirrors
+    KScal* hsc = nullptr;
+    NStat* hns = nullptr;
+    int* hint = nullptr;
+    double* hsub = nullptr;
+    // Algorithm 2 storage
+    int *sd_cells = nullptr, *sd_outer = nullptr;
+    long sd_cap = 0, sd_used = 0, ob_cap = 0, ob_used = 0;
+    std::vector<DDSub> subs;
+    int dd_phase = 0, dd_next = 0, dd_sweeps = 0, dd_k = 0;
+    // step state machine
+    bool in_step = false, have_history = false, full_ready = false;
+    double step_dt = 0.0;
+    int step_mode = 0, nu = 0, nA = 0, nB = 0;
+    bool is_expand = true;
+    double sum_active = 0.0;
+    int max_active = 0, step_kry = 0;
+    int last_kry = 0, last_refine = 0;
+    double last_relres = 0.0;
+    bool inspect_ready = false;
+    std::string err;
+};
+
+#define HIPX(call)                                                           \
+    do {                                                                     \
+        hipError_t e_ = (call);                                              \
+        if (e_ != hipSuccess) {                                              \
+            m->err = std::string(#call) + ": " + hipGetErrorString(e_);      \
+            return FIM_E_HIP;                                                \
+        }                                                                    \
+    } while (0)
+
+#define TRY(x)                                                               \
+    do {                                                                     \
+        fim_status r_ = (x);                                                 \
+        if (r_ != FIM_OK) return r_;                                         \
+    } while (0)
+
+static fim_status dalloc(fim_model* m, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        m->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
+        *p = nullptr;
+        return FIM_E_NOMEM;
+    }
+    return FIM_OK;
+}
+
+template <typename P>
+static fim_status dal(fim_model* m, P** p, size_t count) {
+    return dalloc(m, (void**)p, count * sizeof(P));
+}
+
+static size_t kbytes(const fim_model* m) { return m->o.precision == FIM_MIXED ? 4 : 8; }
+
+static fim_status sync_read(fim_model* m, void* host, const void* dev, size_t bytes) {
+    HIPX(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    return FIM_OK;
+}
+
+static KrylovBufs kbufs(fim_model* m) {
+    KrylovBufs kb;
+    const size_t vb = (size_t)m->n * m->B * kbytes(m);
+    char* base = (char*)m->kvec;
+    kb.x = base + 0 * vb;
+    kb.r = base + 1 * vb;
+    kb.rh = base + 2 * vb;
+    kb.p[0] = base + 3 * vb;
+    kb.p[1] = base + 4 * vb;
+    kb.v[0] = base + 5 * vb;
+    kb.v[1] = base + 6 * vb;
+    kb.sv = base + 7 * vb;
+    kb.t = base + 8 * vb;
+    kb.x64 = m->x64;
+    kb.rir = m->rir;
+    kb.part = m->part;
+    kb.sc = m->sc;
+    kb.dinv = m->dinv;
+    kb.At = m->At;
+    return kb;
+}
+
+static LocalSys lsys(fim_model* m) {
+    LocalSys ls;
+    ls.l2g = m->l2g;
+    ls.g2l = m->g2l;
+    ls.sptr = m->sptr;
+    ls.col = m->col;
+    ls.J = m->J;
+    ls.F = m->F;
+    return ls;
+}
+
+// ---------------------------------------------------------------- pieces
+// compaction of m->act into l2g/g2l; n_A lands in dint[1]
+static void compact(fim_model* m) {
+    launch_compact(m->act, m->n, m->blk, m->l2g, m->g2l, &m->dint[1], m->s);
+}
+
+static fim_status read_int(fim_model* m) {
+    return sync_read(m, m->hint, m->dint, 4 * sizeof(int));
+}
+
+static fim_status structure(fim_model* m) {
+    launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, m->sptr, m->blk, m->s);
+    return FIM_OK;
+}
+
+// Local linear solve: J_A x = -F_A by iterative refinement around
+// BiCGStab on the block-Jacobi scaled system.
+static fim_status linear_solve(fim_model* m) {
+    const bool fp32 = m->o.precision == FIM_MIXED;
+    const LocalSys ls = lsys(m);
+    const KrylovBufs kb = kbufs(m);
+    launch_precond(m->B, fp32, m->nA, ls, m->dinv, m->At, m->s);
+    launch_fill_f64(m->x64, (long)m->nA * m->B, 0.0, m->s);
+    const double inner = fp32 ? std::max(m->o.inner_rtol, 1e-6) : 1e-15;
+    launch_ir_residual(m->B, fp32, m->nA, ls, kb, true, m->o.lin_rtol, inner, m->s);
+    int total = 0, passes = 0;
+    for (int pass = 0; pass <= m->o.max_refine; pass++) {
+        TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
+        if (m->hsc->outer_done || pass == m->o.max_refine) break;
+        passes++;
+        int parity = 0;
+        const int max_chunks = m->o.krylov_maxit / m->o.check_every + 2;
+        for (int chunk = 0; chunk < max_chunks; chunk++) {
+            for (int c = 0; c < m->o.check_every; c++) {
+                launch_bicg_iter(m->B, fp32, m->nA, ls, kb, parity, m->o.krylov_maxit, m->s);
+                parity ^= 1;
+            }
+            TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
+            if (m->hsc->done) break;
+        }
+        total += m->hsc->iters;
+        launch_ir_accumulate(m->B, fp32, m->nA, kb, m->s);
+        launch_ir_residual(m->B, fp32, m->nA, ls, kb, false, m->o.lin_rtol, inner, m->s);
+    }
+    m->last_kry = total;
+    m->last_refine = passes;
+    m->last_relres = m->hsc->fnorm2 > 0 ? std::sqrt(m->hsc->rir2 / m->hsc->fnorm2) : 0.0;
+    return FIM_OK;
+}
+
+static bool converged(const fim_model* m, const NStat& ns) {
+    bool ok = ns.dp_max < m->o.eps_conv;
+    if (m->o.tight) ok = ok && ns.ds_max < m->o.eps_s && ns.nswitch == 0;
+    return ok;
+}
+
+// Assembly + solve + update on the current active rows.
+static fim_status local_newton(fim_model* m, fim_iter_stats* it) {
+    const LocalSys ls = lsys(m);
+    launch_assemble(m->fk, m->nA, ls, m->g, m->f, m->u, m->st, m->Mn, 1.0 / m->step_dt, m->s);
+    TRY(linear_solve(m));
+    launch_update(m->fk, m->nA, m->l2g, m->x64, m->u, m->st, m->n, m->f, m->o.ds_max,
+                  m->dp_abs, m->part, m->ns, m->s);
+    if (it) {
+        it->n_active = m->nA;
+        it->krylov_iters = m->last_kry;
+        it->refine_passes = m->last_refine;
+        it->lin_relres = m->last_relres;
+    }
+    m->sum_active += m->nA;
+    m->max_active = std::max(m->max_active, m->nA);
+    m->step_kry += m->last_kry;
+    return FIM_OK;
+}
+
+static fim_status prepare_active(fim_model* m, bool need_bnd) {
+    compact(m);
+    TRY(read_int(m));
+    m->nA = m->hint[1];
+    TRY(structure(m));
+    if (need_bnd) {
+        launch_fill_i32(&m->dint[2], 1, 0, m->s);
+        launch_boundary(m->nA, m->l2g, m->g2l, m->g, m->bnd, &m->dint[2], m->s);
+    }
+    return FIM_OK;
+}
+
+static fim_status begin_step(fim_model* m, double dt, int mode) {
+    launch_copy_state(m->B, m->n, m->u, m->st, m->un, m->stn, m->s);
+    launch_accumulation(m->fk, m->n, m->un, m->stn, m->g, m->f, m->Mn, m->s);
+    m->in_step = true;
+    m->step_dt = dt;
+    m->step_mode = mode;
+    m->nu = 0;
+    m->is_expand = true;
+    m->sum_active = 0.0;
+    m->max_active = 0;
+    m->step_kry = 0;
+    m->inspect_ready = false;
+    if (mode == FIM_FULL) {
+        if (!m->full_ready) {
+            launch_fill_u8(m->act, m->n, 1, m->s);
+            TRY(prepare_active(m, false));
+            m->full_ready = true;
+        }
+        m->nA = m->n;
+        return FIM_OK;
+    }
+    m->full_ready = false;
+    const int layers = mode == FIM_DD ? m->o.m_layers_dd : m->o.m_layers;
+    if (m->have_history) {
+        HIPX(hipMemcpyAsync(m->act, m->supp, m->n, hipMemcpyDeviceToDevice, m->s));
+    } else {
+        launch_fill_u8(m->act, m->n, 0, m->s);
+        launch_mark_seeds(m->n, m->g, layers, m->act, m->s);
+    }
+    if (mode == FIM_DD) {
+        launch_fill_f64(m->last_dp, m->n, 0.0, m->s);
+        HIPX(hipMemcpyAsync(m->vt, m->act, m->n, hipMemcpyDeviceToDevice, m->s));
+        m->subs.clear();
+        m->sd_used = m->ob_used = 0;
+        m->dd_phase = 1;
+        m->dd_sweeps = 0;
+        m->dd_next = 0;
+        m->dd_k = 0;
+    }
+    TRY(prepare_active(m, true));
+    if (mode == FIM_DD) {
+        launch_fill_u8(m->outer, m->n, 0, m->s);
+        launch_outer_layer(m->nA, m->l2g, m->act, m->g, m->outer, m->s);
+    }
+    return FIM_OK;
+}
+
+static void commit(fim_model* m) {
+    launch_support(m->n, m->u, m->un, m->o.eps_loc, m->g, m->supp, m->s);
+    m->have_history = true;
+    m->in_step = false;
+}
+
+static fim_status rollback(fim_model* m) {
+    launch_copy_state(m->B, m->n, m->un, m->stn, m->u, m->st, m->s);
+    m->in_step = false;
+    HIPX(hipStreamSynchronize(m->s));
+    return FIM_OK;
+}
+
+// ------------------------------------------------------- Algorithm 2 util
+static fim_status dd_grow(fim_model* m, int** buf, long* cap, long need) {
+    if (need <= *cap) return FIM_OK;
+    long nc = std::max(need, 2 * *cap);
+    int* nb = nullptr;
+    TRY(dal(m, &nb, nc));
+    if (*buf) {
+        HIPX(hipMemcpyAsync(nb, *buf, *cap * sizeof(int), hipMemcpyDeviceToDevice, m->s));
+        HIPX(hipStreamSynchronize(m->s));
+        HIPX(hipFree(*buf));
+    }
+    *buf = nb;
+    *cap = nc;
+    return FIM_OK;
+}
+
+// store V_A^k (= current l2g) and its outer layer (flags in m->outer)
+static fim_status dd_store(fim_model* m) {
+    if ((int)m->subs.size() >= MAX_SUBS) {
+        m->err = "Algorithm 2 built more than 64 subdomains";
+        return FIM_NOT_CONVERGED;
+    }
+    DDSub sd;
+    TRY(dd_grow(m, &m->sd_cells, &m->sd_cap, m->sd_used + m->nA));
+    HIPX(hipMemcpyAsync(m->sd_cells + m->sd_used, m->l2g, (size_t)m->nA * sizeof(int),
+                        hipMemcpyDeviceToDevice, m->s));
+    sd.cells_off = m->sd_used;
+    sd.cells_n = m->nA;
+    m->sd_used += m->nA;
+    // compact the outer-layer flags into a list, using the upper halves of
+    // the l2g / g2l buffers as scratch
+    launch_compact(m->outer, m->n, m->blk, m->l2g + m->n, m->g2l + m->n, &m->dint[3], m->s);
+    TRY(read_int(m));
+    const int nob = m->hint[3];
+    TRY(dd_grow(m, &m->sd_outer, &m->ob_cap, m->ob_used + nob + 1));
+    HIPX(hipMemcpyAsync(m->sd_outer + m->ob_used, m->l2g + m->n, (size_t)nob * sizeof(int),
+                        hipMemcpyDeviceToDevice, m->s));
+    sd.outer_off = m->ob_used;
+    sd.outer_n = nob;
+    m->ob_used += nob;
+    m->subs.push_back(sd);
+    return FIM_OK;
+}
+
+// activate a stored subdomain: l2g = its list, g2l = inverse
+static fim_status dd_activate(fim_model* m, int k) {
+    const DDSub& sd = m->subs[k];
+    launch_fill_u8(m->act, m->n, 0, m->s);
+    launch_scatter_flags(sd.cells_n, m->sd_cells + sd.cells_off, m->act, m->s);
+    compact(m);
+    m->nA = sd.cells_n;
+    TRY(structure(m));
+    return FIM_OK;
+}
+
+// ----------------------------------------------------------- C ABI
+extern "C" {
+
+void fim_default_options(fim_options* o) {
+    const double psi = 6894.757293168;
+    std::memset(o, 0, sizeof(*o));
+    o->eps_conv = 0.3 * psi;
+    o->eps_loc = 0.3 * psi;
+    o->eps_s = 1e-10;
+    o->tight = 0;
+    o->m_layers = 2;
+    o->m_layers_dd = 4;
+    o->max_newton = 25;
+    o->max_sweeps = 40;
+    o->auto_cut = 0;
+    o->max_cuts = 8;
+    o->ds_max = 0.2;
+    o->precision = FIM_FP64;
+    o->lin_rtol = 1e-6;
+    o->inner_rtol = 1e-5;
+    o->krylov_maxit = 2000;
+    o->max_refine = 20;
+    o->check_every = 8;
+}
+
+static thread_local std::string g_create_err;
+
+const char* fim_last_error(const fim_model* m) { return m ? m->err.c_str() : g_create_err.c_str(); }
+int32_t fim_num_cells(const fim_model* m) { return m ? m->n : 0; }
+int32_t fim_block_size(const fim_model* m) { return m ? m->B : 0; }
+
+static void free_all(fim_model* m) {
+    void* ptrs[] = {m->adj_ptr, m->adj_nbr, m->adj_T, m->pv, m->depth, m->wi, m->bhp, m->flags,
+                    m->u, m->un, m->Mn, m->dp_abs, m->last_dp, m->st, m->stn, m->act, m->act2,
+                    m->supp, m->bnd, m->vt, m->outer, m->l2g, m->g2l, m->swidth, m->sptr,
+                    m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->rir, m->part,
+                    m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (m->hsc) (void)hipHostFree(m->hsc);
+    if (m->hns) (void)hipHostFree(m->hns);
+    if (m->hint) (void)hipHostFree(m->hint);
+    if (m->hsub) (void)hipHostFree(m->hsub);
+    if (m->own_stream && m->s) (void)hipStreamDestroy(m->s);
+}
+
+static fim_status validate(const fim_model_desc* d, std::string& e) {
+    if (!d) { e = "null description"; return FIM_E_ARG; }
+    const int n = d->n_cells;
+    if (n <= 0) { e = "n_cells must be positive"; return FIM_E_ARG; }
+    if (d->n_conn < 0 || d->n_perf < 0) { e = "negative count"; return FIM_E_ARG; }
+    if (!d->pv_ref || !d->depth || (d->n_conn && (!d->conn_i || !d->conn_j || !d->conn_T)) ||
+        (d->n_perf && (!d->perf_cell || !d->perf_wi || !d->perf_bhp))) {
+        e = "null array";
+        return FIM_E_ARG;
+    }
+    const int k = d->fluid.kind;
+    if (k < 1 || k > 3) { e = "fluid kind must be 1, 2 or 3"; return FIM_E_ARG; }
+    for (int i = 0; i < n; i++) {
+        if (!(d->pv_ref[i] > 0.0) || !std::isfinite(d->pv_ref[i])) {
+            e = "pore volume must be positive at cell " + std::to_string(i);
+            return FIM_E_ARG;
+        }
+        if (!std::isfinite(d->depth[i])) { e = "non-finite depth"; return FIM_E_ARG; }
+    }
+    for (int c = 0; c < d->n_conn; c++) {
+        const int a = d->conn_i[c], b = d->conn_j[c];
+        if (a < 0 || b >= n || a >= b) {
+            e = "connection " + std::to_string(c) + " needs 0 <= conn_i < conn_j < n";
+            return FIM_E_ARG;
+        }
+        if (!(d->conn_T[c] >= 0.0) || !std::isfinite(d->conn_T[c])) {
+            e = "transmissibility must be finite and >= 0";
+            return FIM_E_ARG;
+        }
+    }
+    std::vector<uint8_t> seen(n, 0);
+    for (int p = 0; p < d->n_perf; p++) {
+        const int c = d->perf_cell[p];
+        if (c < 0 || c >= n) { e = "perforation cell out of range"; return FIM_E_ARG; }
+        if (seen[c]) { e = "at most one perforation per cell"; return FIM_E_ARG; }
+        seen[c] = 1;
+        if (!(d->perf_wi[p] >= 0.0) || !std::isfinite(d->perf_bhp[p])) {
+            e = "invalid well index or BHP";
+            return FIM_E_ARG;
+        }
+    }
+    return FIM_OK;
+}
+
+fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
+                            void* hip_stream, fim_model** out) {
+    if (!out) return FIM_E_ARG;
+    *out = nullptr;
+    std::string e;
+    fim_status vs = validate(d, e);
+    if (vs != FIM_OK) {
+        g_create_err = e;
+        return vs;
+    }
+    fim_model* m = new fim_model();
+    if (o) m->o = *o;
+    else fim_default_options(&m->o);
+    if (m->o.check_every <= 0) m->o.check_every = 8;
+    if (m->o.m_layers < 0 || m->o.m_layers > MAX_LAYERS || m->o.m_layers_dd < 0 ||
+        m->o.m_layers_dd > MAX_LAYERS) {
+        g_create_err = "neighbour layers must be in [0, 8]";
+        delete m;
+        return FIM_E_ARG;
+    }
+    const int n = d->n_cells;
+    m->n = n;
+    m->nconn = d->n_conn;
+    m->fk = d->fluid.kind;
+    m->B = m->fk;
+    const fim_fluid& ff = d->fluid;
+    m->f = DevFluid{ff.kind, ff.p_ref, ff.rho_ref, ff.c, ff.mu, ff.rho_w, ff.c_w, ff.mu_w,
+                    ff.rho_o, ff.c_o, ff.mu_o, ff.swc, ff.sor, ff.rs_b, ff.p_b, ff.bo_slope,
+                    ff.bg_c, ff.rho_osc, ff.rho_gsc, ff.rho_wsc, ff.mu_g, ff.span,
+                    d->c_r, d->p_ref_rock, d->gravity};
+    fim_status rc = FIM_OK;
+#define CK(x)                                                                \
+    do {                                                                     \
+        rc = (x);                                                            \
+        if (rc != FIM_OK) {                                                  \
+            g_create_err = m->err;                                           \
+            free_all(m);                                                     \
+            delete m;                                                        \
+            return rc;                                                       \
+        }                                                                    \
+    } while (0)
+    if (hip_stream) {
+        m->s = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreate(&m->s) != hipSuccess) {
+            g_create_err = "hipStreamCreate failed";
+            delete m;
+            return FIM_E_HIP;
+        }
+        m->own_stream = true;
+    }
+    // host-side adjacency (both directions, neighbours ascending)
+    std::vector<int> deg(n + 1, 0);
+    for (int c = 0; c < d->n_conn; c++) {
+        deg[d->conn_i[c] + 1]++;
+        deg[d->conn_j[c] + 1]++;
+    }
+    for (int i = 0; i < n; i++) deg[i + 1] += deg[i];
+    std::vector<int> nbr(2 * (size_t)d->n_conn);
+    std::vector<double> tt(2 * (size_t)d->n_conn);
+    {
+        std::vector<int> fillp(deg.begin(), deg.end() - 1);
+        for (int c = 0; c < d->n_conn; c++) {
+            const int a = d->conn_i[c], b = d->conn_j[c];
+            nbr[fillp[a]] = b; tt[fillp[a]++] = d->conn_T[c];
+            nbr[fillp[b]] = a; tt[fillp[b]++] = d->conn_T[c];
+        }
+        std::vector<std::pair<int, double>> row;
+        for (int i = 0; i < n; i++) {
+            row.clear();
+            for (int q = deg[i]; q < deg[i + 1]; q++) row.emplace_back(nbr[q], tt[q]);
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<int, double>& x, const std::pair<int, double>& y) {
+                          return x.first < y.first;
+                      });
+            for (size_t q = 0; q < row.size(); q++) {
+                if (q && row[q].first == row[q - 1].first) {
+                    g_create_err = "duplicate connection";
+                    if (m->own_stream) (void)hipStreamDestroy(m->s);
+                    delete m;
+                    return FIM_E_ARG;
+                }
+                nbr[deg[i] + q] = row[q].first;
+                tt[deg[i] + q] = row[q].second;
+            }
+            m->max_deg = std::max(m->max_deg, deg[i + 1] - deg[i]);
+        }
+    }
+    std::vector<uint8_t> fl(n, 0);
+    std::vector<double> wi(n, 0.0), bh(n, 0.0);
+    for (int i = 0; i < n; i++)
+        if (d->always_active && d->always_active[i]) fl[i] |= CF_AA;
+    for (int p = 0; p < d->n_perf; p++) {
+        fl[d->perf_cell[p]] |= CF_PERF;
+        wi[d->perf_cell[p]] = d->perf_wi[p];
+        bh[d->perf_cell[p]] = d->perf_bhp[p];
+    }
+    const size_t nn = (size_t)n;
+    const size_t nsl = (nn + SLICE - 1) / SLICE;
+    m->slot_cap = (long)(m->max_deg + 1) * SLICE * (long)nsl;
+    const int B = m->B;
+    const size_t ntile = std::max((nn + TILE - 1) / TILE, (nsl + TILE - 1) / TILE) + 1;
+    CK(dal(m, &m->adj_ptr, nn + 1));
+    CK(dal(m, &m->adj_nbr, nbr.size()));
+    CK(dal(m, &m->adj_T, tt.size()));
+    CK(dal(m, &m->pv, nn));
+    CK(dal(m, &m->depth, nn));
+    CK(dal(m, &m->wi, nn));
+    CK(dal(m, &m->bhp, nn));
+    CK(dal(m, &m->flags, nn));
+    CK(dal(m, &m->u, nn * B));
+    CK(dal(m, &m->un, nn * B));
+    CK(dal(m, &m->Mn, nn * B));
+    CK(dal(m, &m->dp_abs, nn));
+    CK(dal(m, &m->last_dp, nn));
+    CK(dal(m, &m->st, nn));
+    CK(dal(m, &m->stn, nn));
+    CK(dal(m, &m->act, nn));
+    CK(dal(m, &m->act2, nn));
+    CK(dal(m, &m->supp, nn));
+    CK(dal(m, &m->bnd, nn));
+    CK(dal(m, &m->vt, nn));
+    CK(dal(m, &m->outer, nn));
+    CK(dal(m, &m->l2g, 2 * nn));
+    CK(dal(m, &m->g2l, 2 * nn));
+    CK(dal(m, &m->swidth, nsl + 1));
+    CK(dal(m, &m->sptr, nsl + 1));
+    CK(dal(m, &m->blk, ntile));
+    CK(dal(m, &m->col, (size_t)m->slot_cap));
+    CK(dal(m, &m->J, (size_t)m->slot_cap * B * B));
+    CK(dal(m, &m->F, nn * B));
+    CK(dal(m, &m->dinv, nn * B * B));
+    CK(dalloc(m, &m->At, (size_t)m->slot_cap * B * B * kbytes(m)));
+    CK(dal(m, &m->x64, nn * B));
+    CK(dal(m, &m->rir, nn * B));
+    CK(dal(m, &m->part, 4 * ((nn * B + NT - 1) / NT + 1)));
+    CK(dalloc(m, &m->kvec, 9 * nn * B * kbytes(m)));
+    CK(dal(m, &m->sc, 1));
+    CK(dal(m, &m->ns, 1));
+    CK(dal(m, &m->dint, 8));
+    CK(dal(m, &m->dsub, 1024));
+    if (hipHostMalloc((void**)&m->hsc, sizeof(KScal)) != hipSuccess ||
+        hipHostMalloc((void**)&m->hns, sizeof(NStat)) != hipSuccess ||
+        hipHostMalloc((void**)&m->hint, 8 * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&m->hsub, 1024 * sizeof(double)) != hipSuccess) {
+        m->err = "hipHostMalloc failed";
+        CK(FIM_E_NOMEM);
+    }
+    auto up = [&](void* dst, const void* src, size_t bytes) -> fim_status {
+        if (!bytes) return FIM_OK;
+        HIPX(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, m->s));
+        return FIM_OK;
+    };
+    CK(up(m->adj_ptr, deg.data(), (nn + 1) * sizeof(int)));
+    CK(up(m->adj_nbr, nbr.data(), nbr.size() * sizeof(int)));
+    CK(up(m->adj_T, tt.data(), tt.size() * sizeof(double)));
+    CK(up(m->pv, d->pv_ref, nn * sizeof(double)));
+    CK(up(m->depth, d->depth, nn * sizeof(double)));
+    CK(up(m->wi, wi.data(), nn * sizeof(double)));
+    CK(up(m->bhp, bh.data(), nn * sizeof(double)));
+    CK(up(m->flags, fl.data(), nn));
+    // zero the counters and state
+    std::vector<char> z(std::max(sizeof(KScal), sizeof(NStat)), 0);
+    CK(up(m->sc, z.data(), sizeof(KScal)));
+    CK(up(m->ns, z.data(), sizeof(NStat)));
+    launch_fill_f64(m->u, (long)nn * B, 0.0, m->s);
+    launch_fill_u8((uint8_t*)m->st, n, 0, m->s);
+    launch_fill_i32(m->dint, 8, 0, m->s);
+    if (hipStreamSynchronize(m->s) != hipSuccess) {
+        m->err = "initial upload failed";
+        CK(FIM_E_HIP);
+    }
+    m->g = Graph{n, m->adj_ptr, m->adj_nbr, m->adj_T, m->pv, m->depth, m->flags, m->wi, m->bhp};
+#undef CK
+    *out = m;
+    return FIM_OK;
+}
+
+fim_status fim_destroy_model(fim_model* m) {
+    if (!m) return FIM_E_ARG;
+    if (m->s) (void)hipStreamSynchronize(m->s);
+    free_all(m);
+    delete m;
+    return FIM_OK;
+}
+
+fim_status fim_set_state(fim_model* m, const double* u, const int8_t* status, int mem) {
+    if (!m || !u) return FIM_E_ARG;
+    const size_t nb = (size_t)m->n * m->B;
+    std::vector<double> hu;
+    const double* src = u;
+    if (mem == FIM_DEVICE) {
+        hu.resize(nb);
+        HIPX(hipMemcpyAsync(hu.data(), u, nb * sizeof(double), hipMemcpyDeviceToHost, m->s));
+        HIPX(hipStreamSynchronize(m->s));
+        src = hu.data();
+    }
+    for (size_t q = 0; q < nb; q++)
+        if (!std::isfinite(src[q])) {
+            m->err = "non-finite state value";
+            return FIM_E_NONFINITE;
+        }
+    const hipMemcpyKind kind = mem == FIM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPX(hipMemcpyAsync(m->u, u, nb * sizeof(double), kind, m->s));
+    if (status) HIPX(hipMemcpyAsync(m->st, status, m->n, kind, m->s));
+    else launch_fill_u8((uint8_t*)m->st, m->n, 0, m->s);
+    HIPX(hipStreamSynchronize(m->s));
+    m->in_step = false;
+    m->have_history = false;
+    m->inspect_ready = false;
+    return FIM_OK;
+}
+
+fim_status fim_get_state(fim_model* m, double* u_out, int8_t* status_out, int mem) {
+    if (!m || !u_out) return FIM_E_ARG;
+    const hipMemcpyKind kind = mem == FIM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPX(hipMemcpyAsync(u_out, m->u, (size_t)m->n * m->B * sizeof(double), kind, m->s));
+    if (status_out) HIPX(hipMemcpyAsync(status_out, m->st, m->n, kind, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    return FIM_OK;
+}
+
+static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
+    const bool local = m->step_mode == FIM_LOCAL;
+    if (it) it->n_boundary = local ? m->hint[2] : 0;
+    TRY(local_newton(m, it));
+    if (local) {
+        launch_fill_i32(m->dint, 1, 0, m->s);
+        launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, m->o.eps_loc, m->o.m_layers, m->g,
+                           m->act, nullptr, m->dint, m->s);
+        launch_shrink(m->nA, m->l2g, m->dp_abs, m->o.eps_loc, m->g, m->act, m->dint, m->s);
+        compact(m);
+    }
+    HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
+    TRY(read_int(m));
+    const NStat ns = *m->hns;
+    m->nu++;
+    const bool conv = converged(m, ns);
+    if (it) {
+        it->dp_max = ns.dp_max;
+        it->ds_max = ns.ds_max;
+        it->n_switch = ns.nswitch;
+        it->nonfinite = ns.nonfinite;
+    }
+    if (ns.nonfinite) {
+        TRY(rollback(m));
+        m->err = "non-finite update";
+        return FIM_NOT_CONVERGED;
+    }
+    bool done;
+    if (local) {
+        m->is_expand = m->hint[0] != 0;
+        done = conv && !m->is_expand;
+        if (it) it->is_expand = m->is_expand;
+    } else {
+        done = conv;
+    }
+    if (done) {
+        commit(m);
+        if (it) it->converged = 1;
+        return FIM_OK;
+    }
+    if (m->nu >= m->o.max_newton) {
+        TRY(rollback(m));
+        m->err = "Newton iteration cap reached";
+        return FIM_NOT_CONVERGED;
+    }
+    if (local) {
+        m->nA = m->hint[1];
+        TRY(structure(m));
+        launch_fill_i32(&m->dint[2], 1, 0, m->s);
+        launch_boundary(m->nA, m->l2g, m->g2l, m->g, m->bnd, &m->dint[2], m->s);
+    }
+    return FIM_OK;
+}
+
+// one inner iteration of Algorithm 2
+static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
+    if (it) it->phase = m->dd_phase;
+    if (m->dd_phase == 1) {
+        if (it) it->subdomain = (int)m->subs.size();
+        TRY(local_newton(m, it));
+        launch_copy_masked(m->nA, m->l2g, m->dp_abs, m->last_dp, m->s);
+        TRY(dd_store(m));
+        launch_fill_u8(m->act2, m->n, 0, m->s);
+        launch_fill_i32(m->dint, 1, 0, m->s);
+        launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, m->o.eps_loc, m->o.m_layers_dd,
+                           m->g, m->vt, m->act2, m->dint, m->s);
+        HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
+        TRY(read_int(m));
+        m->nu++;
+        const NStat ns = *m->hns;
+        if (it) { it->dp_max = ns.dp_max; it->ds_max = ns.ds_max; it->nonfinite = ns.nonfinite; }
+        if (ns.nonfinite) {
+            TRY(rollback(m));
+            m->err = "non-finite update";
+            return FIM_NOT_CONVERGED;
+        }
+        if (m->hint[0]) {
+            // V_A^{k+1} = new balls; V_B^{k+1} = boundary(V_T) ^ V_A^{k+1}
+            HIPX(hipMemcpyAsync(m->act, m->act2, m->n, hipMemcpyDeviceToDevice, m->s));
+            TRY(prepare_active(m, false));
+            launch_dd_boundary(m->nA, m->l2g, m->vt, m->g, m->bnd, m->s);
+            launch_fill_u8(m->outer, m->n, 0, m->s);
+            launch_outer_layer(m->nA, m->l2g, m->act, m->g, m->outer, m->s);
+            if (it) it->is_expand = 1;
+        } else {
+            m->dd_phase = 2;
+            m->dd_next = 0;
+            m->dd_sweeps = 1;
+        }
+    } else {
+        const int N = (int)m->subs.size();
+        // find the next subdomain (in sweep order) whose update or whose
+        // outer-layer boundary values are not negligible
+        launch_sub_max(N, m->subs.data(), m->sd_cells, m->sd_outer, m->last_dp, m->dsub, m->s);
+        TRY(sync_read(m, m->hsub, m->dsub, N * sizeof(double)));
+        int pick = -1;
+        for (int q = 0; q < N; q++) {
+            const int k = (m->dd_next + q) % N;
+            if (m->hsub[k] >= m->o.eps_loc) { pick = k; break; }
+        }
+        if (pick < 0) {
+            commit(m);
+            if (it) it->converged = 1;
+            return FIM_OK;
+        }
+        if (pick < m->dd_next) m->dd_sweeps++;
+        if (m->dd_sweeps > m->o.max_sweeps || m->nu >= m->o.max_newton * 8) {
+            TRY(rollback(m));
+            m->err = "Algorithm 2 sweep cap reached";
+            return FIM_NOT_CONVERGED;
+        }
+        if (it) it->subdomain = pick;
+        TRY(dd_activate(m, pick));
+        TRY(local_newton(m, it));
+        launch_copy_masked(m->nA, m->l2g, m->dp_abs, m->last_dp, m->s);
+        HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
+        HIPX(hipStreamSynchronize(m->s));
+        m->nu++;
+        const NStat ns = *m->hns;
+        if (it) { it->dp_max = ns.dp_max; it->ds_max = ns.ds_max; it->nonfinite = ns.nonfinite; }
+        if (ns.nonfinite) {
+            TRY(rollback(m));
+            m->err = "non-finite update";
+            return FIM_NOT_CONVERGED;
+        }
+        m->dd_next = pick + 1;
+        if (m->dd_next >= N) { m->dd_next = 0; }
+        m->dd_k = pick;
+    }
+    return FIM_OK;
+}
+
+fim_status fim_newton_step(fim_model* m, double dt, int mode, fim_iter_stats* it) {
+    if (!m) return FIM_E_ARG;
+    if (!(dt > 0.0) || !std::isfinite(dt) || mode < FIM_FULL || mode > FIM_DD) {
+        m->err = "dt must be positive and mode FULL, LOCAL or DD";
+        return FIM_E_ARG;
+    }
+    if (it) std::memset(it, 0, sizeof(*it));
+    if (m->in_step && (dt != m->step_dt || mode != m->step_mode)) {
+        m->err = "dt or mode changed inside a timestep";
+        return FIM_E_STATE;
+    }
+    if (!m->in_step) TRY(begin_step(m, dt, mode));
+    return mode == FIM_DD ? newton_dd(m, it) : newton_full_or_local(m, it);
+}
+
+static fim_status solve_once(fim_model* m, double dt, int mode, fim_step_stats* st) {
+    fim_iter_stats it;
+    for (;;) {
+        fim_status r = fim_newton_step(m, dt, mode, &it);
+        if (st) {
+            st->iterations += 1;
+            st->krylov_iters += it.krylov_iters;
+            st->sum_active += it.n_active;
+            st->max_active = std::max(st->max_active, it.n_active);
+        }
+        if (r != FIM_OK) return r;
+        if (it.converged) {
+            if (st) {
+                st->converged = 1;
+                st->subdomains = (int)m->subs.size();
+            }
+            return FIM_OK;
+        }
+    }
+}
+
+fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats* st) {
+    if (!m) return FIM_E_ARG;
+    if (st) std::memset(st, 0, sizeof(*st));
+    if (m->in_step) {
+        m->err = "a timestep is already in progress";
+        return FIM_E_STATE;
+    }
+    fim_status r = solve_once(m, dt, mode, st);
+    if (r != FIM_NOT_CONVERGED || !m->o.auto_cut) return r;
+    // halve dt and substep; each substep may be cut further
+    std::vector<std::pair<double, int>> todo{{dt * 0.5, 1}, {dt * 0.5, 1}};
+    while (!todo.empty()) {
+        auto [h, depth] = todo.front();
+        todo.erase(todo.begin());
+        if (st) st->cuts = std::max(st->cuts, depth);
+        r = solve_once(m, h, mode, st);
+        if (r == FIM_OK) continue;
+        if (r != FIM_NOT_CONVERGED || depth >= m->o.max_cuts) return r;
+        todo.insert(todo.begin(), {{h * 0.5, depth + 1}, {h * 0.5, depth + 1}});
+    }
+    if (st) st->converged = 1;
+    return FIM_OK;
+}
+
+// --------------------------------------------------------- inspection
+fim_status fim_inspect_assemble(fim_model* m, const double* u_old, const double* u_iter,
+                                const int8_t* status, double dt, const uint8_t* act,
+                                int32_t* n_active, int32_t* l2g, double* F,
+                                int32_t* row_ptr, int32_t* col, double* val,
+                                int64_t cap_blocks) {
+    if (!m || !u_old || !u_iter || !n_active || !F || !row_ptr || !col || !val || !(dt > 0))
+        return FIM_E_ARG;
+    const size_t nb = (size_t)m->n * m->B;
+    m->in_step = false;
+    m->full_ready = false;
+    HIPX(hipMemcpyAsync(m->un, u_old, nb * sizeof(double), hipMemcpyHostToDevice, m->s));
+    HIPX(hipMemcpyAsync(m->u, u_iter, nb * sizeof(double), hipMemcpyHostToDevice, m->s));
+    if (status) {
+        HIPX(hipMemcpyAsync(m->st, status, m->n, hipMemcpyHostToDevice, m->s));
+        HIPX(hipMemcpyAsync(m->stn, status, m->n, hipMemcpyHostToDevice, m->s));
+    } else {
+        launch_fill_u8((uint8_t*)m->st, m->n, 0, m->s);
+        launch_fill_u8((uint8_t*)m->stn, m->n, 0, m->s);
+    }
+    launch_accumulation(m->fk, m->n, m->un, m->stn, m->g, m->f, m->Mn, m->s);
+    if (act) HIPX(hipMemcpyAsync(m->act, act, m->n, hipMemcpyHostToDevice, m->s));
+    else launch_fill_u8(m->act, m->n, 1, m->s);
+    TRY(prepare_active(m, false));
+    m->step_dt = dt;
+    const LocalSys ls = lsys(m);
+    launch_assemble(m->fk, m->nA, ls, m->g, m->f, m->u, m->st, m->Mn, 1.0 / dt, m->s);
+    const int nA = m->nA, B = m->B, BB = B * B;
+    const int nsl = (nA + SLICE - 1) / SLICE;
+    std::vector<int> sptr(nsl + 1), hl2g(nA);
+    HIPX(hipMemcpyAsync(sptr.data(), m->sptr, (nsl + 1) * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    const long slots = nA ? sptr[nsl] : 0;
+    std::vector<int> hcol(slots);
+    std::vector<double> hJ(slots * BB);
+    HIPX(hipMemcpyAsync(hl2g.data(), m->l2g, nA * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(hcol.data(), m->col, slots * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(hJ.data(), m->J, slots * BB * sizeof(double), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(F, m->F, (size_t)nA * B * sizeof(double), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    *n_active = nA;
+    if (l2g) std::memcpy(l2g, hl2g.data(), nA * sizeof(int));
+    long nz = 0;
+    row_ptr[0] = 0;
+    for (int r = 0; r < nA; r++) {
+        const int s = r / SLICE, lane = r % SLICE;
+        const int w = (sptr[s + 1] - sptr[s]) / SLICE;
+        for (int k = 0; k < w; k++) {
+            const long pos = sptr[s] + (long)k * SLICE + lane;
+            if (k > 0 && hcol[pos] == r) break;   // padding
+            if (nz >= cap_blocks) {
+                m->err = "cap_blocks too small";
+                return FIM_E_ARG;
+            }
+            col[nz] = hcol[pos];
+            std::memcpy(val + nz * BB, hJ.data() + pos * BB, BB * sizeof(double));
+            nz++;
+        }
+        row_ptr[r + 1] = (int32_t)nz;
+    }
+    m->inspect_ready = true;
+    return FIM_OK;
+}
+
+fim_status fim_inspect_solve(fim_model* m, double* x, int32_t* iters, double* relres) {
+    if (!m || !x) return FIM_E_ARG;
+    if (!m->inspect_ready) {
+        m->err = "call fim_inspect_assemble first";
+        return FIM_E_STATE;
+    }
+    TRY(linear_solve(m));
+    HIPX(hipMemcpyAsync(x, m->x64, (size_t)m->nA * m->B * sizeof(double), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    if (iters) *iters = m->last_kry;
+    if (relres) *relres = m->last_relres;
+    return FIM_OK;
+}
+
+fim_status fim_inspect_sets(fim_model* m, const uint8_t* act_in, const double* dp_abs,
+                            double eps, int32_t layers, uint8_t* act_out, uint8_t* bnd_out,
+                            int32_t* l2g_out, int32_t* n_active, int32_t* is_expand) {
+    if (!m || !act_in || !dp_abs || !act_out || !bnd_out || !l2g_out || !n_active || !is_expand)
+        return FIM_E_ARG;
+    if (layers < 0 || layers > MAX_LAYERS) {
+        m->err = "layers must be in [0, 8]";
+        return FIM_E_ARG;
+    }
+    m->in_step = false;
+    m->full_ready = false;
+    m->inspect_ready = false;
+    HIPX(hipMemcpyAsync(m->act, act_in, m->n, hipMemcpyHostToDevice, m->s));
+    HIPX(hipMemcpyAsync(m->dp_abs, dp_abs, m->n * sizeof(double), hipMemcpyHostToDevice, m->s));
+    TRY(prepare_active(m, true));
+    launch_fill_i32(m->dint, 1, 0, m->s);
+    launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, eps, layers, m->g, m->act, nullptr,
+                       m->dint, m->s);
+    launch_shrink(m->nA, m->l2g, m->dp_abs, eps, m->g, m->act, m->dint, m->s);
+    TRY(read_int(m));
+    *is_expand = m->hint[0] != 0;
+    TRY(prepare_active(m, true));
+    HIPX(hipMemcpyAsync(act_out, m->act, m->n, hipMemcpyDeviceToHost, m->s));
+    // boundary flags are meaningful on active cells only: export 0 elsewhere
+    std::vector<uint8_t> hb(m->n);
+    HIPX(hipMemcpyAsync(hb.data(), m->bnd, m->n, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(l2g_out, m->l2g, m->nA * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    for (int i = 0; i < m->n; i++) bnd_out[i] = act_out[i] ? hb[i] : 0;
+    *n_active = m->nA;
+    return FIM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,302 @@
+// Residual and Jacobian assembly on the active rows (Appendix A residual;
+// J_A = R_A J R_A^T built directly, Section 4.3) and the block-Jacobi
+// scaling of the local system.
+//
+// One thread per active row.  The row gathers every connection of its
+// cell (an inactive neighbour contributes its frozen state: the Dirichlet
+// condition of the local subproblem) and writes the off-diagonal block only
+// for active neighbours.  Each connection is evaluated from both sides with
+// the same canonical orientation (lower index first), so the two rows see
+// bitwise-identical potential differences and upwind choices and the
+// fluxes cancel exactly in the mass balance.  No atomics.
+#include "fim_device.hpp"
+#include "fim_physics.hpp"
+
+namespace fimk {
+
+template <int FK>
+__global__ __launch_bounds__(NT) void k_accumulation(int n, const double* __restrict__ u,
+                                                     const int8_t* __restrict__ st,
+                                                     Graph g, DevFluid f,
+                                                     double* __restrict__ M) {
+    constexpr int B = FluidTraits<FK>::B;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double uu[B];
+#pragma unroll
+    for (int v = 0; v < B; v++) uu[v] = u[(long)v * n + i];
+    Props<FK> P;
+    cell_props<FK>(uu, st[i], g.pv[i], f, P);
+#pragma unroll
+    for (int c = 0; c < B; c++) M[(long)c * n + i] = P.M[c].v;
+}
+
+template <int FK>
+__global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, DevFluid f,
+                                                 const double* __restrict__ u,
+                                                 const int8_t* __restrict__ st,
+                                                 const double* __restrict__ Mn,
+                                                 double inv_dt) {
+    constexpr int B = FluidTraits<FK>::B;
+    constexpr int NPH = FluidTraits<FK>::NPH;
+    constexpr int BB = B * B;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nA) return;
+    const int n = g.n;
+    const int i = ls.l2g[r];
+    const int s = r / SLICE, lane = r % SLICE;
+    const int base = ls.sptr[s];
+    const int width = (ls.sptr[s + 1] - base) / SLICE;
+
+    double ui[B];
+#pragma unroll
+    for (int v = 0; v < B; v++) ui[v] = u[(long)v * n + i];
+    Props<FK> Pi;
+    cell_props<FK>(ui, st[i], g.pv[i], f, Pi);
+
+    double R[B], Jd[B][B];
+#pragma unroll
+    for (int c = 0; c < B; c++) {
+        R[c] = (Pi.M[c].v - Mn[(long)c * n + i]) * inv_dt;
+#pragma unroll
+        for (int v = 0; v < B; v++) Jd[c][v] = Pi.M[c].d[v] * inv_dt;
+    }
+    const double zi = g.depth[i];
+    const double gg = f.gravity;
+    int k = 1;
+    const int e0 = g.adj_ptr[i], e1 = g.adj_ptr[i + 1];
+    for (int e = e0; e < e1; e++) {
+        const int j = g.adj_nbr[e];
+        const double T = g.adj_T[e];
+        const int lj = ls.g2l[j];
+        double uj[B];
+#pragma unroll
+        for (int v = 0; v < B; v++) uj[v] = u[(long)v * n + j];
+        Props<FK> Pj;
+        cell_props<FK>(uj, st[j], g.pv[j], f, Pj);
+        const double zj = g.depth[j];
+        // canonical orientation: lo = lower index; flux f flows hi -> lo
+        const bool i_lo = i < j;
+        const double sgn = i_lo ? -1.0 : 1.0;   // R_i += sgn * f
+        const double p_lo = i_lo ? ui[0] : uj[0];
+        const double p_hi = i_lo ? uj[0] : ui[0];
+        const double dz = i_lo ? (zj - zi) : (zi - zj);   // z_hi - z_lo
+        double Jo[B][B];
+#pragma unroll
+        for (int c = 0; c < B; c++)
+#pragma unroll
+            for (int v = 0; v < B; v++) Jo[c][v] = 0.0;
+#pragma unroll
+        for (int l = 0; l < NPH; l++) {
+            const Dual<B>& rlo = i_lo ? Pi.rho[l] : Pj.rho[l];
+            const Dual<B>& rhi = i_lo ? Pj.rho[l] : Pi.rho[l];
+            const double dphi = (p_hi - p_lo) - 0.5 * (rlo.v + rhi.v) * gg * dz;
+            // d(dphi)/du_i and d(dphi)/du_j
+            double ddi[B], ddj[B];
+            const double gw = 0.5 * gg * dz;
+#pragma unroll
+            for (int v = 0; v < B; v++) {
+                ddi[v] = -gw * Pi.rho[l].d[v];
+                ddj[v] = -gw * Pj.rho[l].d[v];
+            }
+            ddi[0] += i_lo ? -1.0 : 1.0;
+            ddj[0] += i_lo ? 1.0 : -1.0;
+            const bool up_hi = dphi > 0.0;
+            const bool up_i = (up_hi != i_lo);   // upstream cell is i
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                if (!carries<FK>(c, l)) continue;
+                const Dual<B>& mu_ = up_i ? Pi.mob[c][l] : Pj.mob[c][l];
+                const double fl = T * mu_.v * dphi;
+                R[c] += sgn * fl;
+#pragma unroll
+                for (int v = 0; v < B; v++) {
+                    double di = T * mu_.v * ddi[v];
+                    double dj = T * mu_.v * ddj[v];
+                    if (up_i) di += T * mu_.d[v] * dphi;
+                    else dj += T * mu_.d[v] * dphi;
+                    Jd[c][v] += sgn * di;
+                    Jo[c][v] += sgn * dj;
+                }
+            }
+        }
+        if (lj >= 0) {
+            const long pos = (long)base + (long)k * SLICE + lane;
+            ls.col[pos] = lj;
+            double* out = ls.J + pos * BB;
+#pragma unroll
+            for (int c = 0; c < B; c++)
+#pragma unroll
+                for (int v = 0; v < B; v++) out[c * B + v] = Jo[c][v];
+            k++;
+        }
+    }
+    if (g.flags[i] & CF_PERF) {
+        const double wi = g.wi[i];
+        const double dpw = g.bhp[i] - ui[0];
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            Dual<B> ms = dconst<B>(0.0);
+#pragma unroll
+            for (int l = 0; l < NPH; l++)
+                if (carries<FK>(c, l)) ms = ms + Pi.mob[c][l];
+            R[c] -= wi * ms.v * dpw;
+#pragma unroll
+            for (int v = 0; v < B; v++) Jd[c][v] -= wi * ms.d[v] * dpw;
+            Jd[c][0] += wi * ms.v;
+        }
+    }
+    // diagonal block and residual
+    {
+        const long pos = (long)base + lane;
+        ls.col[pos] = r;
+        double* out = ls.J + pos * BB;
+#pragma unroll
+        for (int c = 0; c < B; c++)
+#pragma unroll
+            for (int v = 0; v < B; v++) out[c * B + v] = Jd[c][v];
+    }
+    for (; k < width; k++) {
+        const long pos = (long)base + (long)k * SLICE + lane;
+        ls.col[pos] = r;
+        double* out = ls.J + pos * BB;
+#pragma unroll
+        for (int q = 0; q < BB; q++) out[q] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < B; c++) ls.F[(long)r * B + c] = R[c];
+}
+
+// ---------------------------------------------------------------------
+// Block-Jacobi scaling: dinv = (J_ii)^{-1} (FP64) and the scaled blocks
+// A~_ik = dinv J_ik stored in the Krylov precision (the scaled diagonal is
+// the identity and is not stored).
+template <int B>
+__device__ inline bool invert_block(const double* a, double* inv) {
+    if constexpr (B == 1) {
+        inv[0] = 1.0 / a[0];
+        return a[0] != 0.0;
+    } else if constexpr (B == 2) {
+        const double det = a[0] * a[3] - a[1] * a[2];
+        const double id = 1.0 / det;
+        inv[0] = a[3] * id;
+        inv[1] = -a[1] * id;
+        inv[2] = -a[2] * id;
+        inv[3] = a[0] * id;
+        return det != 0.0;
+    } else {
+        // Gauss-Jordan with partial pivoting
+        double m[B][2 * B];
+#pragma unroll
+        for (int r = 0; r < B; r++)
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                m[r][c] = a[r * B + c];
+                m[r][B + c] = (r == c) ? 1.0 : 0.0;
+            }
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            int piv = c;
+            double best = fabs(m[c][c]);
+#pragma unroll
+            for (int r = c + 1; r < B; r++)
+                if (fabs(m[r][c]) > best) { best = fabs(m[r][c]); piv = r; }
+            if (best == 0.0) ok = false;
+#pragma unroll
+            for (int q = 0; q < 2 * B; q++) {
+                double t0 = m[c][q], t1 = m[piv][q];
+                m[c][q] = (piv == c) ? t0 : t1;
+                m[piv][q] = (piv == c) ? t1 : t0;
+            }
+            const double ip = 1.0 / m[c][c];
+#pragma unroll
+            for (int q = 0; q < 2 * B; q++) m[c][q] *= ip;
+#pragma unroll
+            for (int r = 0; r < B; r++) {
+                if (r == c) continue;
+                const double fct = m[r][c];
+#pragma unroll
+                for (int q = 0; q < 2 * B; q++) m[r][q] -= fct * m[c][q];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < B; r++)
+#pragma unroll
+            for (int c = 0; c < B; c++) inv[r * B + c] = m[r][B + c];
+        return ok;
+    }
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(NT) void k_precond(int nA, LocalSys ls, double* __restrict__ dinv,
+                                                T* __restrict__ At) {
+    constexpr int BB = B * B;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nA) return;
+    const int s = r / SLICE, lane = r % SLICE;
+    const int base = ls.sptr[s];
+    const int width = (ls.sptr[s + 1] - base) / SLICE;
+    double d[BB], di[BB];
+    const double* J = ls.J;
+#pragma unroll
+    for (int q = 0; q < BB; q++) d[q] = J[((long)base + lane) * BB + q];
+    invert_block<B>(d, di);
+#pragma unroll
+    for (int q = 0; q < BB; q++) dinv[(long)r * BB + q] = di[q];
+    for (int k = 1; k < width; k++) {
+        const long pos = (long)base + (long)k * SLICE + lane;
+        double a[BB];
+#pragma unroll
+        for (int q = 0; q < BB; q++) a[q] = J[pos * BB + q];
+#pragma unroll
+        for (int rr = 0; rr < B; rr++)
+#pragma unroll
+            for (int cc = 0; cc < B; cc++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int t = 0; t < B; t++) acc += di[rr * B + t] * a[t * B + cc];
+                At[pos * BB + rr * B + cc] = (T)acc;
+            }
+    }
+}
+
+// ------------------------------------------------------------- launches
+void launch_accumulation(int fk, int n, const double* u, const int8_t* st,
+                         const Graph& g, const DevFluid& f, double* M,
+                         hipStream_t s) {
+    if (n <= 0) return;
+    const int nb = nblocks(n);
+    switch (fk) {
+    case 1: k_accumulation<1><<<nb, NT, 0, s>>>(n, u, st, g, f, M); break;
+    case 2: k_accumulation<2><<<nb, NT, 0, s>>>(n, u, st, g, f, M); break;
+    default: k_accumulation<3><<<nb, NT, 0, s>>>(n, u, st, g, f, M); break;
+    }
+}
+
+void launch_assemble(int fk, int nA, const LocalSys& ls, const Graph& g,
+                     const DevFluid& f, const double* u, const int8_t* st,
+                     const double* Mn, double inv_dt, hipStream_t s) {
+    if (nA <= 0) return;
+    const int nb = nblocks(nA);
+    switch (fk) {
+    case 1: k_assemble<1><<<nb, NT, 0, s>>>(nA, ls, g, f, u, st, Mn, inv_dt); break;
+    case 2: k_assemble<2><<<nb, NT, 0, s>>>(nA, ls, g, f, u, st, Mn, inv_dt); break;
+    default: k_assemble<3><<<nb, NT, 0, s>>>(nA, ls, g, f, u, st, Mn, inv_dt); break;
+    }
+}
+
+void launch_precond(int b, bool fp32, int nA, const LocalSys& ls,
+                    double* dinv, void* At, hipStream_t s) {
+    if (nA <= 0) return;
+    const int nb = nblocks(nA);
+#define PC(BV, TT) k_precond<BV, TT><<<nb, NT, 0, s>>>(nA, ls, dinv, (TT*)At)
+    if (fp32) {
+        if (b == 1) PC(1, float); else if (b == 2) PC(2, float); else PC(3, float);
+    } else {
+        if (b == 1) PC(1, double); else if (b == 2) PC(2, double); else PC(3, double);
+    }
+#undef PC
+}
+
+} // namespace fimk

@@ -1,0 +1,101 @@
+// Device helpers: deterministic block reductions and the last-block
+// pattern used to finish grid-wide reductions without an extra launch.
+#pragma once
+
+#include "fim_internal.hpp"
+
+namespace fimk {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+__device__ inline int wave_max_i(int v) {
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// Sum of K values over the block (blockDim.x a multiple of 64, <= 1024);
+// fixed butterfly + fixed wave order: deterministic for a given shape.
+template <int K>
+__device__ inline void block_sum(double (&v)[K]) {
+    __shared__ double sh[K][1024 / WAVE];
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    const int nw = blockDim.x / WAVE;
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = wave_sum(v[k]);
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) sh[k][w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        double r = 0.0;
+        for (int q = 0; q < nw; q++) r += sh[k][q];
+        v[k] = r;
+    }
+}
+
+template <int K>
+__device__ inline void block_max(double (&v)[K]) {
+    __shared__ double sh[K][1024 / WAVE];
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    const int nw = blockDim.x / WAVE;
+#pragma unroll
+    for (int k = 0; k < K; k++) v[k] = wave_max(v[k]);
+    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k++) sh[k][w] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        double r = sh[k][0];
+        for (int q = 1; q < nw; q++) r = fmax(r, sh[k][q]);
+        v[k] = r;
+    }
+}
+
+__device__ inline int block_sum_i(int v) {
+    __shared__ int sh[1024 / WAVE];
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    const int w = threadIdx.x / WAVE, l = threadIdx.x % WAVE;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    int r = 0;
+    for (int q = 0; q < (int)(blockDim.x / WAVE); q++) r += sh[q];
+    return r;
+}
+
+// Thread 0 has written this block's partials; returns true in every thread
+// of the block that finishes last (all partials of the grid are visible).
+__device__ inline bool last_block(unsigned* counter) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned t = atomicAdd(counter, 1u);
+        last = (t == gridDim.x - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
+inline int nblocks(long n, int nt = NT) { return (int)((n + nt - 1) / nt); }
+
+} // namespace fimk

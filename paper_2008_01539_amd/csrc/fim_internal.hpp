@@ -1,0 +1,150 @@
+// Internal declarations shared by the HIP translation units of libfim.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "fim.h"
+
+namespace fimk {
+
+constexpr int WAVE = 64;        // CDNA wavefront
+constexpr int SLICE = 64;       // rows per sliced-ELL slice (= one wave)
+constexpr int NT = 256;         // threads per block of row kernels
+constexpr int TILE = 4096;      // cells per block in compaction (256 x 16)
+constexpr int MAX_LAYERS = 8;   // deepest neighbourhood the marker walks
+constexpr int MAX_SUBS = 64;    // Algorithm 2 subdomains per timestep
+
+// per-cell flag bits
+enum : uint8_t { CF_FRAC = 1, CF_PERF = 2, CF_AA = 4 };
+
+struct DevFluid {
+    int kind;
+    double p_ref, rho_ref, c, mu;
+    double rho_w, c_w, mu_w, rho_o, c_o, mu_o, swc, sor;
+    double rs_b, p_b, bo_slope, bg_c, rho_osc, rho_gsc, rho_wsc, mu_g, span;
+    double c_r, p_ref_rock, gravity;
+};
+
+// Static model data resident in HBM (structure of arrays).
+struct Graph {
+    int n;
+    const int* adj_ptr;     // [n+1]
+    const int* adj_nbr;     // [2 nc] neighbours, ascending per row
+    const double* adj_T;    // [2 nc] transmissibility of that connection
+    const double* pv;       // [n]
+    const double* depth;    // [n]
+    const uint8_t* flags;   // [n]
+    const double* wi;       // [n] well index (0 if not perforated)
+    const double* bhp;      // [n]
+};
+
+// Local (compacted) block system in sliced-ELL form: slice s holds rows
+// 64s..64s+63; slot (row r, k) sits at sptr[s] + 64 k + (r - 64 s); slot
+// k = 0 is the diagonal block; padding slots have col = r and zero value.
+struct LocalSys {
+    const int* l2g;         // [nA]
+    const int* g2l;         // [n], -1 = inactive
+    const int* sptr;        // [nslices+1]
+    int* col;               // [slots]
+    double* J;              // [slots b b] FP64 Jacobian blocks
+    double* F;              // [nA b]
+};
+
+// Scalars of the Krylov solve, written by the last block of each kernel.
+struct KScal {
+    double rho, rho_prev, alpha, omega;
+    double sigma, ts, tt, rr;
+    double bnorm2, tol2, fnorm2, rir2;
+    double target2;         // outer target ||r||^2 = (lin_rtol ||F||)^2
+    int done, iters, breakdown, outer_done;
+    int outer;
+    int pad[3];
+    unsigned counter[8];
+};
+
+// Newton-iteration status words (one readback per iteration).
+struct NStat {
+    double dp_max, ds_max;
+    int nswitch, nonfinite;
+    int n_active, n_bnd, is_expand, n_next;
+    unsigned counter[4];
+};
+
+// ------------------------------------------------------------ launches
+// sets / compaction (fim_sets.hip)
+void launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s);
+void launch_fill_i32(int* a, int n, int v, hipStream_t s);
+void launch_fill_f64(double* a, long n, double v, hipStream_t s);
+void launch_compact(const uint8_t* act, int n, int* blk_cnt, int* l2g,
+                    int* g2l, int* n_out, hipStream_t s);
+void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
+                      int* swidth, int* sptr, int* blk, hipStream_t s);
+void launch_boundary(int nA, const int* l2g, const int* g2l, const Graph& g,
+                     uint8_t* bnd, int* count, hipStream_t s);
+void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
+                        const double* dp_abs, double eps, int m,
+                        const Graph& g, uint8_t* act, uint8_t* act2,
+                        int* flag, hipStream_t s);
+void launch_shrink(int nA, const int* l2g, const double* dp_abs, double eps,
+                   const Graph& g, uint8_t* act, const int* flag,
+                   hipStream_t s);
+void launch_mark_seeds(int n, const Graph& g, int m, uint8_t* act,
+                       hipStream_t s);
+void launch_support(int n, const double* p, const double* pn, double eps,
+                    const Graph& g, uint8_t* act, hipStream_t s);
+void launch_dd_boundary(int nA, const int* l2g, const uint8_t* vt,
+                        const Graph& g, uint8_t* bnd, hipStream_t s);
+void launch_outer_layer(int nA, const int* l2g, const uint8_t* in_set,
+                        const Graph& g, uint8_t* outer, hipStream_t s);
+void launch_gather_max(int cnt, const int* idx, const double* v, double* out,
+                       hipStream_t s);
+void launch_scatter_flags(int cnt, const int* idx, uint8_t* flags, hipStream_t s);
+void launch_copy_masked(int nA, const int* l2g, const double* src, double* dst,
+                        hipStream_t s);
+
+// Algorithm 2 subdomain k: cells sd_cells[cells_off .. +cells_n) (= V_A^k,
+// ascending) and its outer layer sd_outer[outer_off .. +outer_n)
+struct DDSub {
+    long cells_off;
+    int cells_n;
+    long outer_off;
+    int outer_n;
+};
+// out[k] = max of last_dp over V_A^k and its outer layer, k < N <= MAX_SUBS
+void launch_sub_max(int N, const DDSub* subs, const int* cells, const int* outer,
+                    const double* last_dp, double* out, hipStream_t s);
+
+// physics (fim_assemble.hip)
+void launch_accumulation(int fk, int n, const double* u, const int8_t* st,
+                         const Graph& g, const DevFluid& f, double* M,
+                         hipStream_t s);
+void launch_assemble(int fk, int nA, const LocalSys& ls, const Graph& g,
+                     const DevFluid& f, const double* u, const int8_t* st,
+                     const double* Mn, double inv_dt, hipStream_t s);
+void launch_precond(int b, bool fp32, int nA, const LocalSys& ls,
+                    double* dinv, void* At, hipStream_t s);
+
+// Krylov (fim_krylov.hip)
+struct KrylovBufs {
+    void* x; void* r; void* rh; void* p[2]; void* v[2]; void* sv; void* t;
+    double* x64; double* rir; double* part; KScal* sc;
+    const double* dinv; const void* At;
+};
+void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
+                        const KrylovBufs& kb, bool x_zero, double lin_rtol,
+                        double inner_rtol, hipStream_t s);
+void launch_bicg_iter(int b, bool fp32, int nA, const LocalSys& ls,
+                      const KrylovBufs& kb, int parity, int maxit, hipStream_t s);
+void launch_ir_accumulate(int b, bool fp32, int nA, const KrylovBufs& kb,
+                          hipStream_t s);
+
+// update (fim_update.hip)
+void launch_update(int fk, int nA, const int* l2g, const double* x64,
+                   double* u, int8_t* st, int n, const DevFluid& f,
+                   double ds_max, double* dp_abs, double* part, NStat* ns,
+                   hipStream_t s);
+void launch_copy_state(int b, int n, const double* src, const int8_t* ssrc,
+                       double* dst, int8_t* sdst, hipStream_t s);
+
+} // namespace fimk

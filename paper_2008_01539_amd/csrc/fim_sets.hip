@@ -1,0 +1,419 @@
+// Active-set estimation (Algorithms 1 and 2), compaction of the active
+// rows (the restriction R_A of Section 4.3) and the sliced-ELL structure of
+// the local system.
+//
+// * compaction: one 4096-cell tile per block; each thread owns 16 flags,
+//   a wave ballot counts the active ones and a block scan orders them, so
+//   l2g comes out ascending and g2l is the inverse map (-1 = inactive);
+//   tile offsets are prefix sums of the per-tile counts (two launches, no
+//   spin waits, deterministic);
+// * neighbourhood marking: each boundary cell with a non-negligible update
+//   walks every path of length <= m from itself and sets the byte flag of
+//   each cell reached; the writes are idempotent, so the set is the same in
+//   any schedule;
+// * the slice width of the sliced-ELL matrix is the wave maximum of the
+//   active-neighbour counts of its 64 rows.
+#include "fim_device.hpp"
+
+namespace fimk {
+
+__global__ void k_fill_u8(uint8_t* a, int n, uint8_t v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+__global__ void k_fill_i32(int* a, int n, int v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+__global__ void k_fill_f64(double* a, long n, double v) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+void launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s) {
+    if (n > 0) k_fill_u8<<<nblocks(n), NT, 0, s>>>(a, n, v);
+}
+void launch_fill_i32(int* a, int n, int v, hipStream_t s) {
+    if (n > 0) k_fill_i32<<<nblocks(n), NT, 0, s>>>(a, n, v);
+}
+void launch_fill_f64(double* a, long n, double v, hipStream_t s) {
+    if (n > 0) k_fill_f64<<<nblocks(n), NT, 0, s>>>(a, n, v);
+}
+
+// ------------------------------------------------------------ compaction
+constexpr int PER = TILE / NT;   // 16 cells per thread
+
+__global__ __launch_bounds__(NT) void k_compact_count(const uint8_t* __restrict__ act, int n,
+                                                      int* __restrict__ blk_cnt) {
+    const int base = blockIdx.x * TILE + threadIdx.x * PER;
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = base + q;
+        if (i < n && act[i]) c++;
+    }
+    c = block_sum_i(c);
+    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(NT) void k_compact_scatter(const uint8_t* __restrict__ act, int n,
+                                                        const int* __restrict__ blk_cnt,
+                                                        int* __restrict__ l2g,
+                                                        int* __restrict__ g2l,
+                                                        int* __restrict__ n_out) {
+    __shared__ int wsum[NT / WAVE];
+    // offset of this tile: sum of the preceding tile counts
+    int off = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += NT) off += blk_cnt[t];
+    off = block_sum_i(off);
+    const int base = blockIdx.x * TILE + threadIdx.x * PER;
+    uint8_t f[PER];
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = base + q;
+        f[q] = (i < n && act[i]) ? 1 : 0;
+        c += f[q];
+    }
+    // exclusive scan of c across the block: wave inclusive scan + wave sums
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    int inc = c;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int y = __shfl_up(inc, o, WAVE);
+        if (lane >= o) inc += y;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    int wo = 0;
+    for (int q = 0; q < w; q++) wo += wsum[q];
+    int pos = off + wo + inc - c;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = base + q;
+        if (i < n) {
+            if (f[q]) {
+                l2g[pos] = i;
+                g2l[i] = pos;
+                pos++;
+            } else {
+                g2l[i] = -1;
+            }
+        }
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == NT - 1) *n_out = pos;
+}
+
+void launch_compact(const uint8_t* act, int n, int* blk_cnt, int* l2g,
+                    int* g2l, int* n_out, hipStream_t s) {
+    const int nt = (n + TILE - 1) / TILE;
+    k_compact_count<<<nt, NT, 0, s>>>(act, n, blk_cnt);
+    k_compact_scatter<<<nt, NT, 0, s>>>(act, n, blk_cnt, l2g, g2l, n_out);
+}
+
+// ------------------------------------------------------------- structure
+__global__ __launch_bounds__(NT) void k_slice_width(int nA, const int* __restrict__ l2g,
+                                                    const int* __restrict__ g2l, Graph g,
+                                                    int* __restrict__ swidth) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int cnt = 0;
+    if (r < nA) {
+        const int i = l2g[r];
+        cnt = 1;
+        for (int e = g.adj_ptr[i]; e < g.adj_ptr[i + 1]; e++)
+            cnt += (g2l[g.adj_nbr[e]] >= 0) ? 1 : 0;
+    }
+    cnt = wave_max_i(cnt);
+    if ((threadIdx.x % WAVE) == 0 && r < nA) swidth[r / SLICE] = cnt;
+}
+
+// exclusive scan of swidth (x SLICE) into sptr[0..ns]; tiles of NT*16
+__global__ __launch_bounds__(NT) void k_scan_count(const int* __restrict__ a, int ns,
+                                                   int* __restrict__ blk) {
+    const int base = blockIdx.x * TILE + threadIdx.x * PER;
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++)
+        if (base + q < ns) c += a[base + q];
+    c = block_sum_i(c);
+    if (threadIdx.x == 0) blk[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(NT) void k_scan_apply(const int* __restrict__ a, int ns,
+                                                   const int* __restrict__ blk,
+                                                   int* __restrict__ sptr) {
+    __shared__ int wsum[NT / WAVE];
+    int off = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += NT) off += blk[t];
+    off = block_sum_i(off);
+    const int base = blockIdx.x * TILE + threadIdx.x * PER;
+    int v[PER];
+    int c = 0;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        v[q] = (base + q < ns) ? a[base + q] : 0;
+        c += v[q];
+    }
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    int inc = c;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int y = __shfl_up(inc, o, WAVE);
+        if (lane >= o) inc += y;
+    }
+    __syncthreads();
+    if (lane == WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    int wo = 0;
+    for (int q = 0; q < w; q++) wo += wsum[q];
+    int pos = off + wo + inc - c;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        if (base + q < ns) sptr[base + q] = pos * SLICE;
+        pos += v[q];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == NT - 1) sptr[ns] = pos * SLICE;
+}
+
+void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
+                      int* swidth, int* sptr, int* blk, hipStream_t s) {
+    if (nA <= 0) return;
+    const int ns = (nA + SLICE - 1) / SLICE;
+    k_slice_width<<<nblocks(nA), NT, 0, s>>>(nA, l2g, g2l, g, swidth);
+    const int nt = (ns + TILE - 1) / TILE;
+    k_scan_count<<<nt, NT, 0, s>>>(swidth, ns, blk);
+    k_scan_apply<<<nt, NT, 0, s>>>(swidth, ns, blk, sptr);
+}
+
+// -------------------------------------------------------------- boundary
+// V_B: active cells with at least one inactive neighbour.
+__global__ __launch_bounds__(NT) void k_boundary(int nA, const int* __restrict__ l2g,
+                                                 const int* __restrict__ g2l, Graph g,
+                                                 uint8_t* __restrict__ bnd,
+                                                 int* __restrict__ count) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = 0;
+    if (r < nA) {
+        const int i = l2g[r];
+        for (int e = g.adj_ptr[i]; e < g.adj_ptr[i + 1]; e++)
+            if (g2l[g.adj_nbr[e]] < 0) { b = 1; break; }
+        bnd[i] = (uint8_t)b;
+    }
+    b = block_sum_i(b);
+    if (threadIdx.x == 0 && b) atomicAdd(count, b);
+}
+
+void launch_boundary(int nA, const int* l2g, const int* g2l, const Graph& g,
+                     uint8_t* bnd, int* count, hipStream_t s) {
+    if (nA > 0) k_boundary<<<nblocks(nA), NT, 0, s>>>(nA, l2g, g2l, g, bnd, count);
+}
+
+// ------------------------------------------------- neighbourhood marking
+// Marks V_nbr^{i,m}: every cell reachable by a path of length <= m.
+__device__ inline void mark_ball(int i, int m, const Graph& g, uint8_t* act,
+                                 uint8_t* act2) {
+    int node[MAX_LAYERS + 1];
+    int pos[MAX_LAYERS + 1];
+    act[i] = 1;
+    if (act2) act2[i] = 1;
+    if (m <= 0) return;
+    int d = 0;
+    node[0] = i;
+    pos[0] = g.adj_ptr[i];
+    while (d >= 0) {
+        const int c = node[d];
+        if (pos[d] >= g.adj_ptr[c + 1]) { d--; continue; }
+        const int j = g.adj_nbr[pos[d]++];
+        act[j] = 1;
+        if (act2) act2[j] = 1;
+        if (d + 1 < m) {
+            d++;
+            node[d] = j;
+            pos[d] = g.adj_ptr[j];
+        }
+    }
+}
+
+// Algorithm 1/2 expansion: for i in V_B with |dp_i| >= eps, V_A (and the
+// optional second set) grows by V_nbr^{i,m}; *flag = 1 if any did.
+__global__ __launch_bounds__(NT) void k_mark_expand(int nA, const int* __restrict__ l2g,
+                                                    const uint8_t* __restrict__ bnd,
+                                                    const double* __restrict__ dp_abs,
+                                                    double eps, int m, Graph g,
+                                                    uint8_t* act, uint8_t* act2,
+                                                    int* flag) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int hit = 0;
+    if (r < nA) {
+        const int i = l2g[r];
+        if (bnd[i] && dp_abs[i] >= eps) {
+            hit = 1;
+            mark_ball(i, m, g, act, act2);
+        }
+    }
+    hit = block_sum_i(hit);
+    if (threadIdx.x == 0 && hit) atomicOr(flag, 1);
+}
+
+void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
+                        const double* dp_abs, double eps, int m,
+                        const Graph& g, uint8_t* act, uint8_t* act2,
+                        int* flag, hipStream_t s) {
+    if (nA > 0)
+        k_mark_expand<<<nblocks(nA), NT, 0, s>>>(nA, l2g, bnd, dp_abs, eps,
+                                                 m < MAX_LAYERS ? m : MAX_LAYERS,
+                                                 g, act, act2, flag);
+}
+
+// Algorithm 1 shrink (only when no boundary update was non-negligible):
+// V_A = supp du_A plus the always-active cells.
+__global__ __launch_bounds__(NT) void k_shrink(int nA, const int* __restrict__ l2g,
+                                               const double* __restrict__ dp_abs, double eps,
+                                               Graph g, uint8_t* act, const int* flag) {
+    if (*flag) return;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nA) return;
+    const int i = l2g[r];
+    act[i] = (dp_abs[i] >= eps || (g.flags[i] & CF_AA)) ? 1 : 0;
+}
+
+void launch_shrink(int nA, const int* l2g, const double* dp_abs, double eps,
+                   const Graph& g, uint8_t* act, const int* flag,
+                   hipStream_t s) {
+    if (nA > 0) k_shrink<<<nblocks(nA), NT, 0, s>>>(nA, l2g, dp_abs, eps, g, act, flag);
+}
+
+// First-step initial set: the always-active cells and their m-layer
+// neighbourhood (act must be cleared before).
+__global__ __launch_bounds__(NT) void k_mark_seeds(int n, Graph g, int m, uint8_t* act) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && (g.flags[i] & CF_AA)) mark_ball(i, m, g, act, nullptr);
+}
+
+void launch_mark_seeds(int n, const Graph& g, int m, uint8_t* act, hipStream_t s) {
+    if (n > 0) k_mark_seeds<<<nblocks(n), NT, 0, s>>>(n, g, m < MAX_LAYERS ? m : MAX_LAYERS, act);
+}
+
+// Later steps: the support of the previous timestep plus the always-active
+// cells.
+__global__ __launch_bounds__(NT) void k_support(int n, const double* __restrict__ p,
+                                                const double* __restrict__ pn, double eps,
+                                                Graph g, uint8_t* __restrict__ act) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    act[i] = (fabs(p[i] - pn[i]) >= eps || (g.flags[i] & CF_AA)) ? 1 : 0;
+}
+
+void launch_support(int n, const double* p, const double* pn, double eps,
+                    const Graph& g, uint8_t* act, hipStream_t s) {
+    if (n > 0) k_support<<<nblocks(n), NT, 0, s>>>(n, p, pn, eps, g, act);
+}
+
+// Algorithm 2: V_B^{k+1} = boundary(V_T) intersected with V_A^{k+1}.
+__global__ __launch_bounds__(NT) void k_dd_boundary(int nA, const int* __restrict__ l2g,
+                                                    const uint8_t* __restrict__ vt, Graph g,
+                                                    uint8_t* __restrict__ bnd) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nA) return;
+    const int i = l2g[r];
+    uint8_t b = 0;
+    for (int e = g.adj_ptr[i]; e < g.adj_ptr[i + 1]; e++)
+        if (!vt[g.adj_nbr[e]]) { b = 1; break; }
+    bnd[i] = b;
+}
+
+void launch_dd_boundary(int nA, const int* l2g, const uint8_t* vt,
+                        const Graph& g, uint8_t* bnd, hipStream_t s) {
+    if (nA > 0) k_dd_boundary<<<nblocks(nA), NT, 0, s>>>(nA, l2g, vt, g, bnd);
+}
+
+// Outer layer dB of a set: cells outside it adjacent to it.
+__global__ __launch_bounds__(NT) void k_outer_layer(int nA, const int* __restrict__ l2g,
+                                                    const uint8_t* __restrict__ in_set,
+                                                    Graph g, uint8_t* outer) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nA) return;
+    const int i = l2g[r];
+    for (int e = g.adj_ptr[i]; e < g.adj_ptr[i + 1]; e++) {
+        const int j = g.adj_nbr[e];
+        if (!in_set[j]) outer[j] = 1;
+    }
+}
+
+void launch_outer_layer(int nA, const int* l2g, const uint8_t* in_set,
+                        const Graph& g, uint8_t* outer, hipStream_t s) {
+    if (nA > 0) k_outer_layer<<<nblocks(nA), NT, 0, s>>>(nA, l2g, in_set, g, outer);
+}
+
+// max of v[idx[k]] over k < cnt into *out (single block, deterministic)
+__global__ __launch_bounds__(NT) void k_gather_max(int cnt, const int* __restrict__ idx,
+                                                   const double* __restrict__ v,
+                                                   double* __restrict__ out) {
+    double m[1] = {0.0};
+    for (int k = threadIdx.x; k < cnt; k += NT) m[0] = fmax(m[0], v[idx[k]]);
+    block_max<1>(m);
+    if (threadIdx.x == 0) *out = m[0];
+}
+
+void launch_gather_max(int cnt, const int* idx, const double* v, double* out,
+                       hipStream_t s) {
+    k_gather_max<<<1, NT, 0, s>>>(cnt, idx, v, out);
+}
+
+__global__ void k_scatter_flags(int cnt, const int* __restrict__ idx, uint8_t* flags) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < cnt) flags[idx[k]] = 1;
+}
+
+void launch_scatter_flags(int cnt, const int* idx, uint8_t* flags, hipStream_t s) {
+    if (cnt > 0) k_scatter_flags<<<nblocks(cnt), NT, 0, s>>>(cnt, idx, flags);
+}
+
+__global__ void k_copy_masked(int nA, const int* __restrict__ l2g,
+                              const double* __restrict__ src, double* __restrict__ dst) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nA) {
+        const int i = l2g[r];
+        dst[i] = src[i];
+    }
+}
+
+void launch_copy_masked(int nA, const int* l2g, const double* src, double* dst,
+                        hipStream_t s) {
+    if (nA > 0) k_copy_masked<<<nblocks(nA), NT, 0, s>>>(nA, l2g, src, dst);
+}
+
+struct SubTab {
+    long co[MAX_SUBS];
+    long oo[MAX_SUBS];
+    int cn[MAX_SUBS];
+    int on[MAX_SUBS];
+};
+
+__global__ __launch_bounds__(NT) void k_sub_max(SubTab t, const int* __restrict__ cells,
+                                                const int* __restrict__ outer,
+                                                const double* __restrict__ last_dp,
+                                                double* __restrict__ out) {
+    const int k = blockIdx.x;
+    double m[1] = {0.0};
+    for (int q = threadIdx.x; q < t.cn[k]; q += NT) m[0] = fmax(m[0], last_dp[cells[t.co[k] + q]]);
+    for (int q = threadIdx.x; q < t.on[k]; q += NT) m[0] = fmax(m[0], last_dp[outer[t.oo[k] + q]]);
+    block_max<1>(m);
+    if (threadIdx.x == 0) out[k] = m[0];
+}
+
+void launch_sub_max(int N, const DDSub* subs, const int* cells, const int* outer,
+                    const double* last_dp, double* out, hipStream_t s) {
+    if (N <= 0) return;
+    SubTab t;
+    for (int k = 0; k < N && k < MAX_SUBS; k++) {
+        t.co[k] = subs[k].cells_off;
+        t.cn[k] = subs[k].cells_n;
+        t.oo[k] = subs[k].outer_off;
+        t.on[k] = subs[k].outer_n;
+    }
+    k_sub_max<<<N < MAX_SUBS ? N : MAX_SUBS, NT, 0, s>>>(t, cells, outer, last_dp, out);
+}
+
+} // namespace fimk
