@@ -128,6 +128,8 @@ typedef struct fim_iter_stats {
     double  dp_max;          /* ||dp||_inf over the active cells (Pa)     */
     double  ds_max;
     double  lin_relres;      /* ||J x + F|| / ||F||                       */
+    int32_t fp64_fallback;   /* mixed precision: FP32 passes stalled and the
+                                solve finished with the FP64 Krylov        */
 } fim_iter_stats;
 
 typedef struct fim_step_stats {
@@ -184,6 +186,31 @@ const char* fim_last_error(const fim_model* m);
 
 int32_t fim_num_cells(const fim_model* m);
 int32_t fim_block_size(const fim_model* m);
+
+/* ---------------- profiling ------------------------------------------- */
+
+/* Per-kernel timing with hipEvents recorded on the model's stream around
+ * each launch (kernel classes: assemble, precond, ir_residual,
+ * bicg_spmv_p, bicg_spmv_s, bicg_update, update, sets_compact,
+ * step_setup).  BiCGStab launches queued after the solve converged return
+ * at once and are not counted.  rows = sum over launches of the active
+ * rows the launch processed, nnzb = sum of the blocks (diagonal included)
+ * of the local matrix for the kernels that read or write it.  Profiling
+ * adds event records and one extra synchronisation per linear solve and is
+ * off by default. */
+typedef struct fim_kernel_profile {
+    char    name[32];
+    int64_t launches;
+    double  total_ms;
+    double  rows;
+    double  nnzb;
+} fim_kernel_profile;
+
+/* on != 0 clears the counters and starts recording; 0 stops. */
+fim_status fim_profile_enable(fim_model* m, int32_t on);
+
+/* Fills up to cap records; returns the number written. */
+int32_t fim_profile_read(fim_model* m, fim_kernel_profile* out, int32_t cap);
 
 /* ---------------- inspection entry points (used by parity tests) -------- */
 

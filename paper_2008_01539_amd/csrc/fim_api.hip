@@ -6,6 +6,7 @@
 // only sequences launches and reads one small status record per Newton
 // iteration (plus one per block of Krylov iterations).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -15,6 +16,30 @@
 #include "fim_internal.hpp"
 
 using namespace fimk;
+
+// Optional event profiler: hipEvent pairs on the model's stream around each
+// kernel (or kernel group), read back at the next synchronisation.
+enum { PK_ASSEMBLE, PK_PRECOND, PK_IR, PK_BICG_A, PK_BICG_B, PK_BICG_C, PK_UPDATE,
+       PK_SETS, PK_SETUP, PK_N };
+static const char* const kPkName[PK_N] = {"assemble", "precond", "ir_residual",
+                                          "bicg_spmv_p", "bicg_spmv_s", "bicg_update",
+                                          "update", "sets_compact", "step_setup"};
+struct ProfRec {
+    int k;
+    hipEvent_t a, b;
+    double rows;
+    bool matrix;   // launch works on the current local matrix (nnzb known later)
+    int tag;       // BiCGStab iteration within a block of queued iterations, else -1
+};
+struct Prof {
+    bool on = false;
+    std::vector<ProfRec> pend;
+    std::vector<hipEvent_t> pool;
+    double ms[PK_N] = {};
+    double rows[PK_N] = {};
+    double nnzb[PK_N] = {};
+    long cnt[PK_N] = {};
+};
 
 
 struct fim_model {
@@ -41,7 +66,7 @@ struct fim_model {
     void* At = nullptr;
     long slot_cap = 0;
     // Krylov
-    double *x64 = nullptr, *rir = nullptr, *part = nullptr;
+    double *x64 = nullptr, *xprev = nullptr, *rir = nullptr, *part = nullptr;
     void* kvec = nullptr;   // 9 vectors of nA b elements in the Krylov precision
     KScal* sc = nullptr;
     NStat* ns = nullptr;
@@ -64,11 +89,61 @@ struct fim_model {
     bool is_expand = true;
     double sum_active = 0.0;
     int max_active = 0, step_kry = 0;
-    int last_kry = 0, last_refine = 0;
+    int last_kry = 0, last_refine = 0, last_fallback = 0;
     double last_relres = 0.0;
     bool inspect_ready = false;
+    int cur_nnzb = 0;   // blocks of the current local matrix (profiling)
+    Prof prof;
     std::string err;
 };
+
+static hipEvent_t ev_take(fim_model* m) {
+    if (!m->prof.pool.empty()) {
+        hipEvent_t e = m->prof.pool.back();
+        m->prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+static int pbeg(fim_model* m, int k, int tag = -1) {
+    if (!m->prof.on) return -1;
+    const bool mat = k == PK_ASSEMBLE || k == PK_PRECOND || k == PK_IR || k == PK_BICG_A ||
+                     k == PK_BICG_B;
+    ProfRec r{k, ev_take(m), ev_take(m), 0.0, mat, tag};
+    (void)hipEventRecord(r.a, m->s);
+    m->prof.pend.push_back(r);
+    return (int)m->prof.pend.size() - 1;
+}
+
+static void pend(fim_model* m, int idx, double rows) {
+    if (idx < 0) return;
+    ProfRec& r = m->prof.pend[idx];
+    r.rows = rows;
+    (void)hipEventRecord(r.b, m->s);
+}
+
+// after a stream synchronisation; BiCGStab records tagged >= keep_tag were
+// queued past convergence (the kernels returned at once) and are dropped
+static void pflush(fim_model* m, int keep_tag = INT_MAX) {
+    if (!m->prof.on) return;
+    for (const ProfRec& r : m->prof.pend) {
+        if (r.tag < keep_tag) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                m->prof.ms[r.k] += ms;
+                m->prof.cnt[r.k] += 1;
+                m->prof.rows[r.k] += r.rows;
+                if (r.matrix) m->prof.nnzb[r.k] += m->cur_nnzb;
+            }
+        }
+        m->prof.pool.push_back(r.a);
+        m->prof.pool.push_back(r.b);
+    }
+    m->prof.pend.clear();
+}
 
 #define HIPX(call)                                                           \
     do {                                                                     \
@@ -101,17 +176,18 @@ static fim_status dal(fim_model* m, P** p, size_t count) {
     return dalloc(m, (void**)p, count * sizeof(P));
 }
 
-static size_t kbytes(const fim_model* m) { return m->o.precision == FIM_MIXED ? 4 : 8; }
 
-static fim_status sync_read(fim_model* m, void* host, const void* dev, size_t bytes) {
+static fim_status sync_read(fim_model* m, void* host, const void* dev, size_t bytes,
+                            int keep_tag = INT_MAX) {
     HIPX(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, m->s));
     HIPX(hipStreamSynchronize(m->s));
+    pflush(m, keep_tag);
     return FIM_OK;
 }
 
-static KrylovBufs kbufs(fim_model* m) {
+static KrylovBufs kbufs(fim_model* m, bool fp32) {
     KrylovBufs kb;
-    const size_t vb = (size_t)m->n * m->B * kbytes(m);
+    const size_t vb = (size_t)m->n * m->B * (fp32 ? 4 : 8);
     char* base = (char*)m->kvec;
     kb.x = base + 0 * vb;
     kb.r = base + 1 * vb;
@@ -153,38 +229,89 @@ static fim_status read_int(fim_model* m) {
 }
 
 static fim_status structure(fim_model* m) {
-    launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, m->sptr, m->blk, m->s);
+    launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, m->sptr, m->blk, &m->dint[4],
+                     m->s);
     return FIM_OK;
 }
 
 // Local linear solve: J_A x = -F_A by iterative refinement around
-// BiCGStab on the block-Jacobi scaled system.
-static fim_status linear_solve(fim_model* m) {
-    const bool fp32 = m->o.precision == FIM_MIXED;
-    const LocalSys ls = lsys(m);
-    const KrylovBufs kb = kbufs(m);
-    launch_precond(m->B, fp32, m->nA, ls, m->dinv, m->At, m->s);
-    launch_fill_f64(m->x64, (long)m->nA * m->B, 0.0, m->s);
-    const double inner = fp32 ? std::max(m->o.inner_rtol, 1e-6) : 1e-15;
-    launch_ir_residual(m->B, fp32, m->nA, ls, kb, true, m->o.lin_rtol, inner, m->s);
-    int total = 0, passes = 0;
-    for (int pass = 0; pass <= m->o.max_refine; pass++) {
-        TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
-        if (m->hsc->outer_done || pass == m->o.max_refine) break;
-        passes++;
-        int parity = 0;
-        const int max_chunks = m->o.krylov_maxit / m->o.check_every + 2;
-        for (int chunk = 0; chunk < max_chunks; chunk++) {
-            for (int c = 0; c < m->o.check_every; c++) {
-                launch_bicg_iter(m->B, fp32, m->nA, ls, kb, parity, m->o.krylov_maxit, m->s);
-                parity ^= 1;
+// BiCGStab on the block-Jacobi scaled system.  In mixed precision the inner
+// solves run in FP32; a pass that fails to cut the FP64 residual norm by at
+// least 10 % (stagnation or breakdown of the FP32 iteration on a badly
+// conditioned fracture subsystem) is undone and the remaining passes run
+// the FP64 Krylov.
+static fim_status inner_solve(fim_model* m, bool fp32, const LocalSys& ls,
+                              const KrylovBufs& kb, int* iters) {
+    int parity = 0, before = 0;
+    const int max_chunks = m->o.krylov_maxit / m->o.check_every + 2;
+    for (int chunk = 0; chunk < max_chunks; chunk++) {
+        for (int c = 0; c < m->o.check_every; c++) {
+            for (int w = 0; w < 3; w++) {
+                const int q = pbeg(m, PK_BICG_A + w, c);
+                launch_bicg_part(w, m->B, fp32, m->nA, ls, kb, parity, m->o.krylov_maxit, m->s);
+                pend(m, q, m->nA);
             }
-            TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
-            if (m->hsc->done) break;
+            parity ^= 1;
         }
-        total += m->hsc->iters;
+        HIPX(hipMemcpyAsync(m->hsc, m->sc, sizeof(KScal), hipMemcpyDeviceToHost, m->s));
+        HIPX(hipStreamSynchronize(m->s));
+        pflush(m, m->hsc->iters - before);
+        before = m->hsc->iters;
+        if (m->hsc->done) break;
+    }
+    *iters = m->hsc->iters;
+    return FIM_OK;
+}
+
+static fim_status linear_solve(fim_model* m) {
+    bool fp32 = m->o.precision == FIM_MIXED;
+    const LocalSys ls = lsys(m);
+    KrylovBufs kb = kbufs(m, fp32);
+    auto inner_tol = [](bool f32, double opt) { return f32 ? std::max(opt, 1e-6) : 1e-15; };
+    int pi = pbeg(m, PK_PRECOND);
+    launch_precond(m->B, fp32, m->nA, ls, m->dinv, m->At, m->s);
+    pend(m, pi, m->nA);
+    launch_fill_f64(m->x64, (long)m->nA * m->B, 0.0, m->s);
+    pi = pbeg(m, PK_IR);
+    launch_ir_residual(m->B, fp32, m->nA, ls, kb, true, m->o.lin_rtol,
+                       inner_tol(fp32, m->o.inner_rtol), m->s);
+    pend(m, pi, m->nA);
+    if (m->prof.on)
+        HIPX(hipMemcpyAsync(&m->hint[4], &m->dint[4], sizeof(int), hipMemcpyDeviceToHost, m->s));
+    TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
+    if (m->prof.on) m->cur_nnzb = m->hint[4];
+    double prev = m->hsc->rir2;
+    int total = 0, passes = 0;
+    m->last_fallback = 0;
+    for (int pass = 0; pass < m->o.max_refine && !m->hsc->outer_done; pass++) {
+        passes++;
+        if (fp32) launch_copy_f64(m->xprev, m->x64, (long)m->nA * m->B, m->s);
+        int it = 0;
+        TRY(inner_solve(m, fp32, ls, kb, &it));
+        total += it;
         launch_ir_accumulate(m->B, fp32, m->nA, kb, m->s);
-        launch_ir_residual(m->B, fp32, m->nA, ls, kb, false, m->o.lin_rtol, inner, m->s);
+        pi = pbeg(m, PK_IR);
+        launch_ir_residual(m->B, fp32, m->nA, ls, kb, false, m->o.lin_rtol,
+                           inner_tol(fp32, m->o.inner_rtol), m->s);
+        pend(m, pi, m->nA);
+        TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
+        const double now = m->hsc->rir2;
+        if (fp32 && !(now < 0.81 * prev)) {
+            // undo the pass and continue in FP64
+            launch_copy_f64(m->x64, m->xprev, (long)m->nA * m->B, m->s);
+            fp32 = false;
+            kb = kbufs(m, false);
+            m->last_fallback = 1;
+            pi = pbeg(m, PK_PRECOND);
+            launch_precond(m->B, false, m->nA, ls, m->dinv, m->At, m->s);
+            pend(m, pi, m->nA);
+            pi = pbeg(m, PK_IR);
+            launch_ir_residual(m->B, false, m->nA, ls, kb, false, m->o.lin_rtol,
+                               inner_tol(false, m->o.inner_rtol), m->s);
+            pend(m, pi, m->nA);
+            TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
+        }
+        prev = m->hsc->rir2;
     }
     m->last_kry = total;
     m->last_refine = passes;
@@ -201,14 +328,19 @@ static bool converged(const fim_model* m, const NStat& ns) {
 // Assembly + solve + update on the current active rows.
 static fim_status local_newton(fim_model* m, fim_iter_stats* it) {
     const LocalSys ls = lsys(m);
+    int pi = pbeg(m, PK_ASSEMBLE);
     launch_assemble(m->fk, m->nA, ls, m->g, m->f, m->u, m->st, m->Mn, 1.0 / m->step_dt, m->s);
+    pend(m, pi, m->nA);
     TRY(linear_solve(m));
+    pi = pbeg(m, PK_UPDATE);
     launch_update(m->fk, m->nA, m->l2g, m->x64, m->u, m->st, m->n, m->f, m->o.ds_max,
                   m->dp_abs, m->part, m->ns, m->s);
+    pend(m, pi, m->nA);
     if (it) {
         it->n_active = m->nA;
         it->krylov_iters = m->last_kry;
         it->refine_passes = m->last_refine;
+        it->fp64_fallback = m->last_fallback;
         it->lin_relres = m->last_relres;
     }
     m->sum_active += m->nA;
@@ -230,8 +362,10 @@ static fim_status prepare_active(fim_model* m, bool need_bnd) {
 }
 
 static fim_status begin_step(fim_model* m, double dt, int mode) {
+    const int pi = pbeg(m, PK_SETUP);
     launch_copy_state(m->B, m->n, m->u, m->st, m->un, m->stn, m->s);
     launch_accumulation(m->fk, m->n, m->un, m->stn, m->g, m->f, m->Mn, m->s);
+    pend(m, pi, m->n);
     m->in_step = true;
     m->step_dt = dt;
     m->step_mode = mode;
@@ -376,10 +510,15 @@ int32_t fim_num_cells(const fim_model* m) { return m ? m->n : 0; }
 int32_t fim_block_size(const fim_model* m) { return m ? m->B : 0; }
 
 static void free_all(fim_model* m) {
+    for (const ProfRec& r : m->prof.pend) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
     void* ptrs[] = {m->adj_ptr, m->adj_nbr, m->adj_T, m->pv, m->depth, m->wi, m->bhp, m->flags,
                     m->u, m->un, m->Mn, m->dp_abs, m->last_dp, m->st, m->stn, m->act, m->act2,
                     m->supp, m->bnd, m->vt, m->outer, m->l2g, m->g2l, m->swidth, m->sptr,
-                    m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->rir, m->part,
+                    m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -566,11 +705,13 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(dal(m, &m->J, (size_t)m->slot_cap * B * B));
     CK(dal(m, &m->F, nn * B));
     CK(dal(m, &m->dinv, nn * B * B));
-    CK(dalloc(m, &m->At, (size_t)m->slot_cap * B * B * kbytes(m)));
+    // sized for FP64 so that a mixed-precision solve can fall back in place
+    CK(dalloc(m, &m->At, (size_t)m->slot_cap * B * B * sizeof(double)));
     CK(dal(m, &m->x64, nn * B));
     CK(dal(m, &m->rir, nn * B));
     CK(dal(m, &m->part, 4 * ((nn * B + NT - 1) / NT + 1)));
-    CK(dalloc(m, &m->kvec, 9 * nn * B * kbytes(m)));
+    CK(dalloc(m, &m->kvec, 9 * nn * B * sizeof(double)));
+    CK(dal(m, &m->xprev, nn * B));
     CK(dal(m, &m->sc, 1));
     CK(dal(m, &m->ns, 1));
     CK(dal(m, &m->dint, 8));
@@ -661,11 +802,13 @@ static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
     if (it) it->n_boundary = local ? m->hint[2] : 0;
     TRY(local_newton(m, it));
     if (local) {
+        const int pi = pbeg(m, PK_SETS);
         launch_fill_i32(m->dint, 1, 0, m->s);
         launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, m->o.eps_loc, m->o.m_layers, m->g,
                            m->act, nullptr, m->dint, m->s);
         launch_shrink(m->nA, m->l2g, m->dp_abs, m->o.eps_loc, m->g, m->act, m->dint, m->s);
         compact(m);
+        pend(m, pi, m->n);
     }
     HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
     TRY(read_int(m));
@@ -703,9 +846,11 @@ static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
     }
     if (local) {
         m->nA = m->hint[1];
+        const int pi = pbeg(m, PK_SETS);
         TRY(structure(m));
         launch_fill_i32(&m->dint[2], 1, 0, m->s);
         launch_boundary(m->nA, m->l2g, m->g2l, m->g, m->bnd, &m->dint[2], m->s);
+        pend(m, pi, m->nA);
     }
     return FIM_OK;
 }
@@ -846,6 +991,36 @@ fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats*
     }
     if (st) st->converged = 1;
     return FIM_OK;
+}
+
+// ----------------------------------------------------------- profiling
+fim_status fim_profile_enable(fim_model* m, int32_t on) {
+    if (!m) return FIM_E_ARG;
+    HIPX(hipStreamSynchronize(m->s));
+    pflush(m);
+    m->prof.on = on != 0;
+    for (int k = 0; k < PK_N; k++) {
+        m->prof.ms[k] = 0.0;
+        m->prof.rows[k] = 0.0;
+        m->prof.nnzb[k] = 0.0;
+        m->prof.cnt[k] = 0;
+    }
+    return FIM_OK;
+}
+
+int32_t fim_profile_read(fim_model* m, fim_kernel_profile* out, int32_t cap) {
+    if (!m) return 0;
+    if (hipStreamSynchronize(m->s) == hipSuccess) pflush(m);
+    int k = 0;
+    for (; k < PK_N && k < cap; k++) {
+        std::memset(out[k].name, 0, sizeof(out[k].name));
+        std::strncpy(out[k].name, kPkName[k], sizeof(out[k].name) - 1);
+        out[k].launches = m->prof.cnt[k];
+        out[k].total_ms = m->prof.ms[k];
+        out[k].rows = m->prof.rows[k];
+        out[k].nnzb = m->prof.nnzb[k];
+    }
+    return k;
 }
 
 // --------------------------------------------------------- inspection

@@ -57,6 +57,7 @@ struct KScal {
     double sigma, ts, tt, rr;
     double bnorm2, tol2, fnorm2, rir2;
     double target2;         // outer target ||r||^2 = (lin_rtol ||F||)^2
+    double brk;             // relative breakdown threshold for (r0, v)
     int done, iters, breakdown, outer_done;
     int outer;
     int pad[3];
@@ -78,8 +79,9 @@ void launch_fill_i32(int* a, int n, int v, hipStream_t s);
 void launch_fill_f64(double* a, long n, double v, hipStream_t s);
 void launch_compact(const uint8_t* act, int n, int* blk_cnt, int* l2g,
                     int* g2l, int* n_out, hipStream_t s);
+// also writes the number of blocks of the local matrix (diagonal included)
 void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
-                      int* swidth, int* sptr, int* blk, hipStream_t s);
+                      int* swidth, int* sptr, int* blk, int* nnzb, hipStream_t s);
 void launch_boundary(int nA, const int* l2g, const int* g2l, const Graph& g,
                      uint8_t* bnd, int* count, hipStream_t s);
 void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
@@ -134,10 +136,13 @@ struct KrylovBufs {
 void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
                         const KrylovBufs& kb, bool x_zero, double lin_rtol,
                         double inner_rtol, hipStream_t s);
-void launch_bicg_iter(int b, bool fp32, int nA, const LocalSys& ls,
+// x64 += sign * x (Krylov precision)
+// which: 0 = v = A p (with the p update), 1 = s, t = A s, 2 = x, r update
+void launch_bicg_part(int which, int b, bool fp32, int nA, const LocalSys& ls,
                       const KrylovBufs& kb, int parity, int maxit, hipStream_t s);
 void launch_ir_accumulate(int b, bool fp32, int nA, const KrylovBufs& kb,
                           hipStream_t s);
+void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);
 
 // update (fim_update.hip)
 void launch_update(int fk, int nA, const int* l2g, const double* x64,

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(NT) void k_ir_residual(int nA, LocalSys ls, KrylovB
             sc->outer_done = (!finite || t[0] <= sc->target2) ? 1 : 0;
             sc->breakdown = finite ? 0 : 1;
             sc->bnorm2 = t[1];
+            sc->brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
             sc->rho = t[1];
             sc->rho_prev = 1.0;
             sc->alpha = 1.0;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(NT) void k_bicg_a(int nA, LocalSys ls, const T* __r
     const double beta = first ? 0.0 : (sc->rho / sc->rho_prev) * (sc->alpha / sc->omega);
     const double om = sc->omega;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    double dot[1] = {0.0};
+    double dot[2] = {0.0, 0.0};
     if (r < nA) {
         double pi[B], vi[B];
 #pragma unroll
@@ -172,21 +173,32 @@ __global__ __launch_bounds__(NT) void k_bicg_a(int nA, LocalSys ls, const T* __r
             const T vT = (T)vi[c];
             V.v_new[q] = vT;
             dot[0] += (double)V.rh[q] * (double)vT;
+            dot[1] += (double)vT * (double)vT;
         }
     }
-    block_sum<1>(dot);
-    if (threadIdx.x == 0) part[blockIdx.x] = dot[0];
+    block_sum<2>(dot);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = dot[0];
+        part[2 * blockIdx.x + 1] = dot[1];
+    }
     if (last_block(&sc->counter[1])) {
-        double t[1] = {0.0};
-        for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) t[0] += part[q];
-        block_sum<1>(t);
+        double t[2] = {0.0, 0.0};
+        for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
+            t[0] += part[2 * q];
+            t[1] += part[2 * q + 1];
+        }
+        block_sum<2>(t);
         if (threadIdx.x == 0) {
             sc->sigma = t[0];
-            if (t[0] == 0.0 || !isfinite(t[0])) {
+            // (r0, v) lost against |r0| |v|: the direction carries no
+            // information in this precision; stop with the current x
+            const double lim = sc->brk * sqrt(sc->bnorm2 * t[1]);
+            const double al = sc->rho / t[0];
+            if (!(fabs(t[0]) > lim) || !isfinite(al)) {
                 sc->breakdown = 1;
                 sc->done = 1;
             } else {
-                sc->alpha = sc->rho / t[0];
+                sc->alpha = al;
             }
             sc->counter[1] = 0;
         }
@@ -321,6 +333,15 @@ __global__ __launch_bounds__(NT) void k_ir_accumulate(int nA, double* __restrict
     if (q < (long)nA * B) x64[q] += (double)xT[q];
 }
 
+__global__ void k_copy_f64(double* __restrict__ d, const double* __restrict__ s, long n) {
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) d[q] = s[q];
+}
+
+void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s) {
+    if (n > 0) k_copy_f64<<<nblocks(n), NT, 0, s>>>(dst, src, n);
+}
+
 // ------------------------------------------------------------- launches
 template <int B, typename T>
 static Vecs<B, T> make_vecs(const KrylovBufs& kb, int parity) {
@@ -338,13 +359,16 @@ static Vecs<B, T> make_vecs(const KrylovBufs& kb, int parity) {
 }
 
 template <int B, typename T>
-static void iter_impl(int nA, const LocalSys& ls, const KrylovBufs& kb,
+static void part_impl(int which, int nA, const LocalSys& ls, const KrylovBufs& kb,
                       int parity, int maxit, hipStream_t s) {
     const int nb = nblocks(nA);
     Vecs<B, T> V = make_vecs<B, T>(kb, parity);
-    k_bicg_a<B, T><<<nb, NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part);
-    k_bicg_b<B, T><<<nb, NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part);
-    k_bicg_c<B, T><<<nb, NT, 0, s>>>(nA, V, kb.sc, kb.part, maxit);
+    if (which == 0)
+        k_bicg_a<B, T><<<nb, NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part);
+    else if (which == 1)
+        k_bicg_b<B, T><<<nb, NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part);
+    else
+        k_bicg_c<B, T><<<nb, NT, 0, s>>>(nA, V, kb.sc, kb.part, maxit);
 }
 
 void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
@@ -360,17 +384,17 @@ void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
 #undef IR
 }
 
-void launch_bicg_iter(int b, bool fp32, int nA, const LocalSys& ls,
+void launch_bicg_part(int which, int b, bool fp32, int nA, const LocalSys& ls,
                       const KrylovBufs& kb, int parity, int maxit, hipStream_t s) {
     if (nA <= 0) return;
     if (fp32) {
-        if (b == 1) iter_impl<1, float>(nA, ls, kb, parity, maxit, s);
-        else if (b == 2) iter_impl<2, float>(nA, ls, kb, parity, maxit, s);
-        else iter_impl<3, float>(nA, ls, kb, parity, maxit, s);
+        if (b == 1) part_impl<1, float>(which, nA, ls, kb, parity, maxit, s);
+        else if (b == 2) part_impl<2, float>(which, nA, ls, kb, parity, maxit, s);
+        else part_impl<3, float>(which, nA, ls, kb, parity, maxit, s);
     } else {
-        if (b == 1) iter_impl<1, double>(nA, ls, kb, parity, maxit, s);
-        else if (b == 2) iter_impl<2, double>(nA, ls, kb, parity, maxit, s);
-        else iter_impl<3, double>(nA, ls, kb, parity, maxit, s);
+        if (b == 1) part_impl<1, double>(which, nA, ls, kb, parity, maxit, s);
+        else if (b == 2) part_impl<2, double>(which, nA, ls, kb, parity, maxit, s);
+        else part_impl<3, double>(which, nA, ls, kb, parity, maxit, s);
     }
 }
 

@@ -115,7 +115,8 @@ void launch_compact(const uint8_t* act, int n, int* blk_cnt, int* l2g,
 // ------------------------------------------------------------- structure
 __global__ __launch_bounds__(NT) void k_slice_width(int nA, const int* __restrict__ l2g,
                                                     const int* __restrict__ g2l, Graph g,
-                                                    int* __restrict__ swidth) {
+                                                    int* __restrict__ swidth,
+                                                    int* __restrict__ nnzb) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     int cnt = 0;
     if (r < nA) {
@@ -124,6 +125,8 @@ __global__ __launch_bounds__(NT) void k_slice_width(int nA, const int* __restric
         for (int e = g.adj_ptr[i]; e < g.adj_ptr[i + 1]; e++)
             cnt += (g2l[g.adj_nbr[e]] >= 0) ? 1 : 0;
     }
+    const int tot = block_sum_i(cnt);
+    if (threadIdx.x == 0 && tot) atomicAdd(nnzb, tot);
     cnt = wave_max_i(cnt);
     if ((threadIdx.x % WAVE) == 0 && r < nA) swidth[r / SLICE] = cnt;
 }
@@ -177,10 +180,11 @@ __global__ __launch_bounds__(NT) void k_scan_apply(const int* __restrict__ a, in
 }
 
 void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
-                      int* swidth, int* sptr, int* blk, hipStream_t s) {
+                      int* swidth, int* sptr, int* blk, int* nnzb, hipStream_t s) {
+    launch_fill_i32(nnzb, 1, 0, s);
     if (nA <= 0) return;
     const int ns = (nA + SLICE - 1) / SLICE;
-    k_slice_width<<<nblocks(nA), NT, 0, s>>>(nA, l2g, g2l, g, swidth);
+    k_slice_width<<<nblocks(nA), NT, 0, s>>>(nA, l2g, g2l, g, swidth, nnzb);
     const int nt = (ns + TILE - 1) / TILE;
     k_scan_count<<<nt, NT, 0, s>>>(swidth, ns, blk);
     k_scan_apply<<<nt, NT, 0, s>>>(swidth, ns, blk, sptr);

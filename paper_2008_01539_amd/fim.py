@@ -72,10 +72,15 @@ class IterStats(C.Structure):
                 ("n_switch", C.c_int32), ("nonfinite", C.c_int32),
                 ("phase", C.c_int32), ("subdomain", C.c_int32),
                 ("dp_max", C.c_double), ("ds_max", C.c_double),
-                ("lin_relres", C.c_double)]
+                ("lin_relres", C.c_double), ("fp64_fallback", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KernelProfile(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64),
+                ("total_ms", C.c_double), ("rows", C.c_double), ("nnzb", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -113,6 +118,8 @@ def _load():
                                        C.c_int64]),
         "fim_inspect_sets": (i32, [vp, vp, vp, f64, i32, vp, vp, vp, vp, vp]),
         "fim_inspect_solve": (i32, [vp, vp, vp, vp]),
+        "fim_profile_enable": (i32, [vp, i32]),
+        "fim_profile_read": (i32, [vp, vp, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -275,6 +282,17 @@ class FimModel:
     def run(self, schedule, mode=LOCAL):
         """Advance through a schedule; returns the per-step statistics."""
         return [self.solve_timestep(dt, mode).as_dict() for dt in schedule]
+
+    # ------------------------------------------------------------ profiling
+    def profile(self, on=True):
+        _check(_lib.fim_profile_enable(self._h, 1 if on else 0), self._h)
+
+    def profile_read(self):
+        arr = (KernelProfile * 16)()
+        k = _lib.fim_profile_read(self._h, arr, 16)
+        return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                           rows=arr[i].rows, nnzb=arr[i].nnzb)
+                for i in range(k)}
 
     # ------------------------------------------------------------ inspection
     def inspect_assemble(self, u_old, u_iter, status, dt, act=None, cap_blocks=None):
