@@ -67,6 +67,8 @@ struct fim_model {
     long slot_cap = 0;
     // Krylov
     double *x64 = nullptr, *xprev = nullptr, *rir = nullptr, *part = nullptr;
+    double* part_ir = nullptr;   // 4 x 2 x KB_MAXB Krylov partials
+    double* hpart = nullptr;     // pinned copy of the refinement partials
     void* kvec = nullptr;   // 9 vectors of nA b elements in the Krylov precision
     KScal* sc = nullptr;
     NStat* ns = nullptr;
@@ -200,8 +202,11 @@ static KrylovBufs kbufs(fim_model* m, bool fp32) {
     kb.t = base + 8 * vb;
     kb.x64 = m->x64;
     kb.rir = m->rir;
-    kb.part = m->part;
     kb.sc = m->sc;
+    kb.part_ir = m->part_ir;
+    kb.part_a = m->part_ir + 2 * KB_MAXB;
+    kb.part_b = m->part_ir + 4 * KB_MAXB;
+    kb.part_c = m->part_ir + 6 * KB_MAXB;
     kb.dinv = m->dinv;
     kb.At = m->At;
     return kb;
@@ -239,19 +244,33 @@ static fim_status structure(fim_model* m) {
 // solves run in FP32; a pass that fails to cut the FP64 residual norm by at
 // least 10 % (stagnation or breakdown of the FP32 iteration on a badly
 // conditioned fracture subsystem) is undone and the remaining passes run
-// the FP64 Krylov.
+// the FP64 Krylov.  The host sums the per-block partials of the refinement
+// residual itself (fixed order) to take its decisions.
+static fim_status read_ir(fim_model* m, double* rir2, double* bnorm2) {
+    const int nb = krylov_grid(m->nA);
+    TRY(sync_read(m, m->hpart, m->part_ir, 2 * nb * sizeof(double)));
+    double a = 0.0, b = 0.0;
+    for (int q = 0; q < nb; q++) {
+        a += m->hpart[2 * q];
+        b += m->hpart[2 * q + 1];
+    }
+    *rir2 = a;
+    *bnorm2 = b;
+    return FIM_OK;
+}
+
 static fim_status inner_solve(fim_model* m, bool fp32, const LocalSys& ls,
-                              const KrylovBufs& kb, int* iters) {
-    int parity = 0, before = 0;
+                              const KrylovBufs& kb, double tol2, double bnorm2, int* iters) {
+    int it = 0, before = 0;
     const int max_chunks = m->o.krylov_maxit / m->o.check_every + 2;
     for (int chunk = 0; chunk < max_chunks; chunk++) {
-        for (int c = 0; c < m->o.check_every; c++) {
+        for (int c = 0; c < m->o.check_every; c++, it++) {
             for (int w = 0; w < 3; w++) {
                 const int q = pbeg(m, PK_BICG_A + w, c);
-                launch_bicg_part(w, m->B, fp32, m->nA, ls, kb, parity, m->o.krylov_maxit, m->s);
+                launch_bicg_part(w, m->B, fp32, m->nA, ls, kb, it, tol2, bnorm2,
+                                 m->o.krylov_maxit, m->s);
                 pend(m, q, m->nA);
             }
-            parity ^= 1;
         }
         HIPX(hipMemcpyAsync(m->hsc, m->sc, sizeof(KScal), hipMemcpyDeviceToHost, m->s));
         HIPX(hipStreamSynchronize(m->s));
@@ -267,36 +286,41 @@ static fim_status linear_solve(fim_model* m) {
     bool fp32 = m->o.precision == FIM_MIXED;
     const LocalSys ls = lsys(m);
     KrylovBufs kb = kbufs(m, fp32);
-    auto inner_tol = [](bool f32, double opt) { return f32 ? std::max(opt, 1e-6) : 1e-15; };
     int pi = pbeg(m, PK_PRECOND);
     launch_precond(m->B, fp32, m->nA, ls, m->dinv, m->At, m->s);
     pend(m, pi, m->nA);
     launch_fill_f64(m->x64, (long)m->nA * m->B, 0.0, m->s);
     pi = pbeg(m, PK_IR);
-    launch_ir_residual(m->B, fp32, m->nA, ls, kb, true, m->o.lin_rtol,
-                       inner_tol(fp32, m->o.inner_rtol), m->s);
+    launch_ir_residual(m->B, fp32, m->nA, ls, kb, true, m->s);
     pend(m, pi, m->nA);
     if (m->prof.on)
         HIPX(hipMemcpyAsync(&m->hint[4], &m->dint[4], sizeof(int), hipMemcpyDeviceToHost, m->s));
-    TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
+    double rir2 = 0.0, bnorm2 = 0.0;
+    TRY(read_ir(m, &rir2, &bnorm2));
     if (m->prof.on) m->cur_nnzb = m->hint[4];
-    double prev = m->hsc->rir2;
+    const double fnorm2 = rir2;
+    const double target2 = m->o.lin_rtol * m->o.lin_rtol * fnorm2;
     int total = 0, passes = 0;
     m->last_fallback = 0;
-    for (int pass = 0; pass < m->o.max_refine && !m->hsc->outer_done; pass++) {
+    for (int pass = 0; pass < m->o.max_refine; pass++) {
+        if (!(rir2 > target2) || !std::isfinite(rir2)) break;
         passes++;
         if (fp32) launch_copy_f64(m->xprev, m->x64, (long)m->nA * m->B, m->s);
+        // inner target: the reduction this pass needs, not below what the
+        // Krylov precision can deliver
+        const double need = 0.5 * std::sqrt(target2 / rir2);
+        const double floor_ = fp32 ? std::max(m->o.inner_rtol, 1e-6) : 1e-15;
+        const double inner = std::max(need, floor_);
         int it = 0;
-        TRY(inner_solve(m, fp32, ls, kb, &it));
+        TRY(inner_solve(m, fp32, ls, kb, inner * inner * bnorm2, bnorm2, &it));
         total += it;
         launch_ir_accumulate(m->B, fp32, m->nA, kb, m->s);
         pi = pbeg(m, PK_IR);
-        launch_ir_residual(m->B, fp32, m->nA, ls, kb, false, m->o.lin_rtol,
-                           inner_tol(fp32, m->o.inner_rtol), m->s);
+        launch_ir_residual(m->B, fp32, m->nA, ls, kb, false, m->s);
         pend(m, pi, m->nA);
-        TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
-        const double now = m->hsc->rir2;
-        if (fp32 && !(now < 0.81 * prev)) {
+        double now = 0.0;
+        TRY(read_ir(m, &now, &bnorm2));
+        if (fp32 && !(now < 0.81 * rir2)) {
             // undo the pass and continue in FP64
             launch_copy_f64(m->x64, m->xprev, (long)m->nA * m->B, m->s);
             fp32 = false;
@@ -306,16 +330,15 @@ static fim_status linear_solve(fim_model* m) {
             launch_precond(m->B, false, m->nA, ls, m->dinv, m->At, m->s);
             pend(m, pi, m->nA);
             pi = pbeg(m, PK_IR);
-            launch_ir_residual(m->B, false, m->nA, ls, kb, false, m->o.lin_rtol,
-                               inner_tol(false, m->o.inner_rtol), m->s);
+            launch_ir_residual(m->B, false, m->nA, ls, kb, false, m->s);
             pend(m, pi, m->nA);
-            TRY(sync_read(m, m->hsc, m->sc, sizeof(KScal)));
+            TRY(read_ir(m, &now, &bnorm2));
         }
-        prev = m->hsc->rir2;
+        rir2 = now;
     }
     m->last_kry = total;
     m->last_refine = passes;
-    m->last_relres = m->hsc->fnorm2 > 0 ? std::sqrt(m->hsc->rir2 / m->hsc->fnorm2) : 0.0;
+    m->last_relres = fnorm2 > 0 ? std::sqrt(rir2 / fnorm2) : 0.0;
     return FIM_OK;
 }
 
@@ -519,13 +542,15 @@ static void free_all(fim_model* m) {
                     m->u, m->un, m->Mn, m->dp_abs, m->last_dp, m->st, m->stn, m->act, m->act2,
                     m->supp, m->bnd, m->vt, m->outer, m->l2g, m->g2l, m->swidth, m->sptr,
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
-                    m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer};
+                    m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
+                    m->part_ir};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (m->hsc) (void)hipHostFree(m->hsc);
     if (m->hns) (void)hipHostFree(m->hns);
     if (m->hint) (void)hipHostFree(m->hint);
     if (m->hsub) (void)hipHostFree(m->hsub);
+    if (m->hpart) (void)hipHostFree(m->hpart);
     if (m->own_stream && m->s) (void)hipStreamDestroy(m->s);
 }
 
@@ -713,13 +738,15 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(dalloc(m, &m->kvec, 9 * nn * B * sizeof(double)));
     CK(dal(m, &m->xprev, nn * B));
     CK(dal(m, &m->sc, 1));
+    CK(dal(m, &m->part_ir, 8 * KB_MAXB));
     CK(dal(m, &m->ns, 1));
     CK(dal(m, &m->dint, 8));
     CK(dal(m, &m->dsub, 1024));
     if (hipHostMalloc((void**)&m->hsc, sizeof(KScal)) != hipSuccess ||
         hipHostMalloc((void**)&m->hns, sizeof(NStat)) != hipSuccess ||
         hipHostMalloc((void**)&m->hint, 8 * sizeof(int)) != hipSuccess ||
-        hipHostMalloc((void**)&m->hsub, 1024 * sizeof(double)) != hipSuccess) {
+        hipHostMalloc((void**)&m->hsub, 1024 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc((void**)&m->hpart, 2 * KB_MAXB * sizeof(double)) != hipSuccess) {
         m->err = "hipHostMalloc failed";
         CK(FIM_E_NOMEM);
     }

@@ -14,6 +14,8 @@ constexpr int NT = 256;         // threads per block of row kernels
 constexpr int TILE = 4096;      // cells per block in compaction (256 x 16)
 constexpr int MAX_LAYERS = 8;   // deepest neighbourhood the marker walks
 constexpr int MAX_SUBS = 64;    // Algorithm 2 subdomains per timestep
+constexpr int KB_NT = 256;      // threads per block of the Krylov kernels
+constexpr int KB_MAXB = 1024;   // blocks per Krylov launch (grid-stride above)
 
 // per-cell flag bits
 enum : uint8_t { CF_FRAC = 1, CF_PERF = 2, CF_AA = 4 };
@@ -51,17 +53,12 @@ struct LocalSys {
     double* F;              // [nA b]
 };
 
-// Scalars of the Krylov solve, written by the last block of each kernel.
+// Scalars of the BiCGStab iteration, recorded by block 0 of each kernel
+// for the kernels that follow and for the host.
 struct KScal {
-    double rho, rho_prev, alpha, omega;
-    double sigma, ts, tt, rr;
-    double bnorm2, tol2, fnorm2, rir2;
-    double target2;         // outer target ||r||^2 = (lin_rtol ||F||)^2
-    double brk;             // relative breakdown threshold for (r0, v)
-    int done, iters, breakdown, outer_done;
-    int outer;
-    int pad[3];
-    unsigned counter[8];
+    double rho_hist[2];     // rho_i at slot i & 1
+    double alpha, omega, rr;
+    int done, iters, breakdown, pad;
 };
 
 // Newton-iteration status words (one readback per iteration).
@@ -69,7 +66,6 @@ struct NStat {
     double dp_max, ds_max;
     int nswitch, nonfinite;
     int n_active, n_bnd, is_expand, n_next;
-    unsigned counter[4];
 };
 
 // ------------------------------------------------------------ launches
@@ -130,16 +126,21 @@ void launch_precond(int b, bool fp32, int nA, const LocalSys& ls,
 // Krylov (fim_krylov.hip)
 struct KrylovBufs {
     void* x; void* r; void* rh; void* p[2]; void* v[2]; void* sv; void* t;
-    double* x64; double* rir; double* part; KScal* sc;
+    double* x64; double* rir; KScal* sc;
+    // per-block partial dot products (2 per block, KB_MAXB blocks)
+    double* part_ir; double* part_a; double* part_b; double* part_c;
     const double* dinv; const void* At;
 };
+int krylov_grid(int nA);
+// r64 = -F - J x64, b~ = D^{-1} r64, Krylov initialisation; part_ir holds
+// (|r64|^2, |b~|^2) per block
 void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
-                        const KrylovBufs& kb, bool x_zero, double lin_rtol,
-                        double inner_rtol, hipStream_t s);
-// x64 += sign * x (Krylov precision)
-// which: 0 = v = A p (with the p update), 1 = s, t = A s, 2 = x, r update
+                        const KrylovBufs& kb, bool x_zero, hipStream_t s);
+// which: 0 = v = A p (with the p update), 1 = s, t = A s, 2 = x, r update;
+// it = iteration index; tol2 = stop when |r|^2 <= tol2; bnorm2 = |b~|^2
 void launch_bicg_part(int which, int b, bool fp32, int nA, const LocalSys& ls,
-                      const KrylovBufs& kb, int parity, int maxit, hipStream_t s);
+                      const KrylovBufs& kb, int it, double tol2, double bnorm2, int maxit,
+                      hipStream_t s);
 void launch_ir_accumulate(int b, bool fp32, int nA, const KrylovBufs& kb,
                           hipStream_t s);
 void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);

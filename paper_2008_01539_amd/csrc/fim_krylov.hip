@@ -6,14 +6,18 @@
 //   solve A~ d = D^{-1} r64     (BiCGStab in precision T: float or double)
 //   x64 += d                    until ||r64|| <= lin_rtol ||F||.
 //
-// One BiCGStab iteration is three fused kernels; each finishes its dot
-// products with the last-block pattern and writes the scalars the next
-// kernel needs into device memory, so no host round trip is needed inside
-// an iteration.  Vector updates are fused into the matrix products: the
+// One BiCGStab iteration is three kernels.  Each writes per-block partial
+// dot products; the next kernel's blocks each reduce those partials in the
+// same fixed order (so every block derives the same scalar, and the result
+// is deterministic) before doing their rows.  No fences, atomics or extra
+// finishing launches are needed: kernel boundaries order everything.  Block
+// 0 also records the scalars (rho, alpha, omega, done, iters) for later
+// kernels and for the host, which looks at them once per block of queued
+// iterations.  Vector updates are fused into the matrix products: the
 // product kernel rebuilds p (or s) for each neighbour from r, p, v on the
-// fly, which saves a launch and a full vector pass.  Kernels return
-// immediately once the solve is done, so the host can queue several
-// iterations before it looks at the status.
+// fly, saving a launch and a vector pass.  Grids are capped at KB_MAXB
+// blocks of KB_NT threads (grid-stride over rows) so that a partial array
+// has at most KB_MAXB entries.
 #include "fim_device.hpp"
 
 namespace fimk {
@@ -35,18 +39,127 @@ __device__ inline double s_update(T r, T v, double al) {
     return (double)(T)((double)r - al * (double)v);
 }
 
-// --------------------------------------------- refinement residual + init
-template <int B, typename T>
-__global__ __launch_bounds__(NT) void k_ir_residual(int nA, LocalSys ls, KrylovBufs kb,
-                                                    int x_zero, double lin_rtol,
-                                                    double inner_rtol) {
+// Raw operands of one row of a product kernel: the slice geometry, the
+// column indices and blocks of the first UNR off-diagonal slots and the
+// values of NV source vectors at the row itself and at those neighbours.
+// They are fetched before the iteration's scalars are known, so the
+// fetches overlap the reduction of the previous kernel's partial sums; a
+// row then waits for about two memory round trips (columns, then gathers
+// and blocks) instead of two per slot.
+constexpr int UNR = 8;
+template <int B, typename T, int NV>
+struct RowRaw {
+    int base, width, lane;
+    int cl[UNR];
+    T a[UNR][B * B];
+    T xn[NV][UNR][B];
+    T xo[NV][B];
+};
+
+template <int B, typename T, int NV>
+__device__ inline void fetch_row(const LocalSys& ls, const T* __restrict__ At, int r,
+                                 const T* const (&src)[NV], RowRaw<B, T, NV>& R) {
     constexpr int BB = B * B;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = r / SLICE;
+    R.lane = r % SLICE;
+    R.base = ls.sptr[s];
+    R.width = (ls.sptr[s + 1] - R.base) / SLICE;
+#pragma unroll
+    for (int v = 0; v < NV; v++)
+#pragma unroll
+        for (int c = 0; c < B; c++) R.xo[v][c] = src[v][(long)r * B + c];
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+        const int k = 1 + u;   // k < width is uniform over the wave (one slice)
+        R.cl[u] = (k < R.width) ? ls.col[(long)R.base + (long)k * SLICE + R.lane] : r;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+        const int k = 1 + u;
+        if (k < R.width) {
+            const T* ap = At + ((long)R.base + (long)k * SLICE + R.lane) * BB;
+#pragma unroll
+            for (int q = 0; q < BB; q++) R.a[u][q] = ap[q];
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+#pragma unroll
+                for (int c = 0; c < B; c++) R.xn[v][u][c] = src[v][(long)R.cl[u] * B + c];
+        } else {
+#pragma unroll
+            for (int q = 0; q < BB; q++) R.a[u][q] = (T)0;
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+#pragma unroll
+                for (int c = 0; c < B; c++) R.xn[v][u][c] = (T)0;
+        }
+    }
+}
+
+// y += sum_k A~_rk x_k with x_k = f(raw source values at neighbour k);
+// slots past the first UNR (wide rows) are loaded here directly
+template <int B, typename T, int NV, class FX>
+__device__ inline void finish_row(const LocalSys& ls, const T* __restrict__ At,
+                                  const T* const (&src)[NV], const RowRaw<B, T, NV>& R,
+                                  double (&y)[B], FX fx) {
+    constexpr int BB = B * B;
+#pragma unroll
+    for (int u = 0; u < UNR; u++) {
+        if (1 + u >= R.width) break;
+        T raw[NV][B];
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+#pragma unroll
+            for (int c = 0; c < B; c++) raw[v][c] = R.xn[v][u][c];
+        double xj[B];
+        fx(raw, xj);
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int v = 0; v < B; v++) acc += (double)R.a[u][c * B + v] * xj[v];
+            y[c] += acc;
+        }
+    }
+    for (int k = 1 + UNR; k < R.width; k++) {
+        const long pos = (long)R.base + (long)k * SLICE + R.lane;
+        const int cl = ls.col[pos];
+        T raw[NV][B];
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+#pragma unroll
+            for (int c = 0; c < B; c++) raw[v][c] = src[v][(long)cl * B + c];
+        double xj[B];
+        fx(raw, xj);
+        const T* ap = At + pos * BB;
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int v = 0; v < B; v++) acc += (double)ap[c * B + v] * xj[v];
+            y[c] += acc;
+        }
+    }
+}
+
+static inline int kgrid(long rows) {
+    long g = (rows + KB_NT - 1) / KB_NT;
+    if (g < 1) g = 1;
+    return (int)(g < KB_MAXB ? g : KB_MAXB);
+}
+
+// --------------------------------------------- refinement residual + init
+// r64 = -F - J x64 (x64 skipped when zero), b~ = D^{-1} r64; x = 0,
+// r = rh = b~.  Partials: ir[q] = (|r64|^2, |b~|^2); pc[q] = ((rh,r), (r,r))
+// so that the first BiCGStab kernel finds rho_0 where it looks for rho.
+template <int B, typename T>
+__global__ __launch_bounds__(KB_NT) void k_ir_residual(int nA, LocalSys ls, KrylovBufs kb,
+                                                       int x_zero) {
+    constexpr int BB = B * B;
     T* xT = (T*)kb.x;
     T* rr = (T*)kb.r;
     T* rh = (T*)kb.rh;
     double part[2] = {0.0, 0.0};
-    if (r < nA) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nA; r += gridDim.x * blockDim.x) {
         double res[B];
 #pragma unroll
         for (int c = 0; c < B; c++) res[c] = -ls.F[(long)r * B + c];
@@ -84,88 +197,69 @@ __global__ __launch_bounds__(NT) void k_ir_residual(int nA, LocalSys ls, KrylovB
     }
     block_sum<2>(part);
     if (threadIdx.x == 0) {
-        kb.part[2 * blockIdx.x] = part[0];
-        kb.part[2 * blockIdx.x + 1] = part[1];
+        kb.part_ir[2 * blockIdx.x] = part[0];
+        kb.part_ir[2 * blockIdx.x + 1] = part[1];
+        kb.part_c[2 * blockIdx.x] = part[1];
+        kb.part_c[2 * blockIdx.x + 1] = part[1];
     }
-    if (last_block(&kb.sc->counter[0])) {
-        double t[2] = {0.0, 0.0};
-        for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
-            t[0] += kb.part[2 * q];
-            t[1] += kb.part[2 * q + 1];
-        }
-        block_sum<2>(t);
-        if (threadIdx.x == 0) {
-            KScal* sc = kb.sc;
-            sc->rir2 = t[0];
-            if (x_zero) {
-                sc->fnorm2 = t[0];
-                sc->target2 = lin_rtol * lin_rtol * t[0];
-                sc->outer = 0;
-            } else {
-                sc->outer += 1;
-            }
-            const bool finite = isfinite(t[0]) && isfinite(t[1]);
-            sc->outer_done = (!finite || t[0] <= sc->target2) ? 1 : 0;
-            sc->breakdown = finite ? 0 : 1;
-            sc->bnorm2 = t[1];
-            sc->brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
-            sc->rho = t[1];
-            sc->rho_prev = 1.0;
-            sc->alpha = 1.0;
-            sc->omega = 1.0;
-            sc->iters = 0;
-            double need = (t[0] > 0.0) ? 0.5 * sqrt(sc->target2 / t[0]) : 0.0;
-            double inner = need > inner_rtol ? need : inner_rtol;
-            sc->tol2 = inner * inner * t[1];
-            sc->done = sc->outer_done;
-            sc->counter[0] = 0;
-        }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        kb.sc->done = 0;
+        kb.sc->iters = 0;
+        kb.sc->breakdown = 0;
     }
 }
 
-// ----------------------------------------------- BiCGStab kernel A: v = A p
+// ----------------------------------------------- kernel A: v = A p
+// start: rho_i = (rh, r), |r|^2 from the previous kernel C (or the
+// initialisation); stop if converged or at the iteration cap.
 template <int B, typename T>
-__global__ __launch_bounds__(NT) void k_bicg_a(int nA, LocalSys ls, const T* __restrict__ At,
-                                               Vecs<B, T> V, KScal* __restrict__ sc,
-                                               double* __restrict__ part) {
-    if (sc->done) return;
-    constexpr int BB = B * B;
-    const bool first = sc->iters == 0;
-    const double beta = first ? 0.0 : (sc->rho / sc->rho_prev) * (sc->alpha / sc->omega);
-    const double om = sc->omega;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(KB_NT) void k_bicg_a(int nA, LocalSys ls, const T* __restrict__ At,
+                                                  Vecs<B, T> V, KScal* __restrict__ sc,
+                                                  const double* __restrict__ pc,
+                                                  double* __restrict__ pa, int it,
+                                                  double tol2, int maxit) {
+    const int done = sc->done;
+    const double rho_prev = it > 0 ? sc->rho_hist[(it - 1) & 1] : 1.0;
+    const double al_prev = sc->alpha, om_prev = sc->omega;
+    double red[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
+        red[0] += pc[2 * q];
+        red[1] += pc[2 * q + 1];
+    }
+    if (done) return;
+    const T* const src[3] = {V.r, V.p_old, V.v_old};
+    const int r0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    RowRaw<B, T, 3> R;
+    if (r0 < nA) fetch_row<B, T, 3>(ls, At, r0, src, R);
+    block_sum<2>(red);
+    const double rho = red[0], rr = red[1];
+    const bool stop = rr <= tol2 || it >= maxit || !isfinite(rr) || (it > 0 && rho == 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rho_hist[it & 1] = rho;
+        sc->rr = rr;
+        if (stop) {
+            sc->done = 1;
+            sc->iters = it;
+            sc->breakdown = (rr <= tol2) ? 0 : 1;
+        }
+    }
+    if (stop) return;
+    const bool first = it == 0;
+    const double beta = first ? 0.0 : (rho / rho_prev) * (al_prev / om_prev);
+    const double om = first ? 0.0 : om_prev;
+    auto fx = [&](const T (&raw)[3][B], double (&x)[B]) {
+#pragma unroll
+        for (int c = 0; c < B; c++) x[c] = p_update<T>(first, raw[0][c], raw[1][c], raw[2][c], beta, om);
+    };
     double dot[2] = {0.0, 0.0};
-    if (r < nA) {
+    for (int r = r0; r < nA; r += stride) {
+        if (r != r0) fetch_row<B, T, 3>(ls, At, r, src, R);
         double pi[B], vi[B];
+        fx(R.xo, pi);
 #pragma unroll
-        for (int c = 0; c < B; c++) {
-            const long q = (long)r * B + c;
-            pi[c] = p_update<T>(first, V.r[q], first ? V.r[q] : V.p_old[q],
-                                first ? V.r[q] : V.v_old[q], beta, om);
-            vi[c] = pi[c];
-        }
-        const int s = r / SLICE, lane = r % SLICE;
-        const int base = ls.sptr[s];
-        const int width = (ls.sptr[s + 1] - base) / SLICE;
-        for (int k = 1; k < width; k++) {
-            const long pos = (long)base + (long)k * SLICE + lane;
-            const int cl = ls.col[pos];
-            double pj[B];
-#pragma unroll
-            for (int c = 0; c < B; c++) {
-                const long q = (long)cl * B + c;
-                pj[c] = p_update<T>(first, V.r[q], first ? V.r[q] : V.p_old[q],
-                                    first ? V.r[q] : V.v_old[q], beta, om);
-            }
-            const T* a = At + pos * BB;
-#pragma unroll
-            for (int c = 0; c < B; c++) {
-                double acc = 0.0;
-#pragma unroll
-                for (int v = 0; v < B; v++) acc += (double)a[c * B + v] * pj[v];
-                vi[c] += acc;
-            }
-        }
+        for (int c = 0; c < B; c++) vi[c] = pi[c];
+        finish_row<B, T, 3>(ls, At, src, R, vi, fx);
 #pragma unroll
         for (int c = 0; c < B; c++) {
             const long q = (long)r * B + c;
@@ -178,72 +272,59 @@ __global__ __launch_bounds__(NT) void k_bicg_a(int nA, LocalSys ls, const T* __r
     }
     block_sum<2>(dot);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = dot[0];
-        part[2 * blockIdx.x + 1] = dot[1];
-    }
-    if (last_block(&sc->counter[1])) {
-        double t[2] = {0.0, 0.0};
-        for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
-            t[0] += part[2 * q];
-            t[1] += part[2 * q + 1];
-        }
-        block_sum<2>(t);
-        if (threadIdx.x == 0) {
-            sc->sigma = t[0];
-            // (r0, v) lost against |r0| |v|: the direction carries no
-            // information in this precision; stop with the current x
-            const double lim = sc->brk * sqrt(sc->bnorm2 * t[1]);
-            const double al = sc->rho / t[0];
-            if (!(fabs(t[0]) > lim) || !isfinite(al)) {
-                sc->breakdown = 1;
-                sc->done = 1;
-            } else {
-                sc->alpha = al;
-            }
-            sc->counter[1] = 0;
-        }
+        pa[2 * blockIdx.x] = dot[0];
+        pa[2 * blockIdx.x + 1] = dot[1];
     }
 }
 
 // ------------------------------------- kernel B: s = r - alpha v, t = A s
+// start: sigma = (rh, v); alpha = rho / sigma; a sigma lost against
+// |rh| |v| is a breakdown (stop with the current x).
 template <int B, typename T>
-__global__ __launch_bounds__(NT) void k_bicg_b(int nA, LocalSys ls, const T* __restrict__ At,
-                                               Vecs<B, T> V, KScal* __restrict__ sc,
-                                               double* __restrict__ part) {
-    if (sc->done) return;
-    constexpr int BB = B * B;
-    const double al = sc->alpha;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(KB_NT) void k_bicg_b(int nA, LocalSys ls, const T* __restrict__ At,
+                                                  Vecs<B, T> V, KScal* __restrict__ sc,
+                                                  const double* __restrict__ pa,
+                                                  double* __restrict__ pb, int it, double brk2,
+                                                  double bnorm2) {
+    const int done = sc->done;
+    const double rho = sc->rho_hist[it & 1];
+    double red[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
+        red[0] += pa[2 * q];
+        red[1] += pa[2 * q + 1];
+    }
+    if (done) return;
+    const T* const src[2] = {V.r, V.v_new};
+    const int r0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    RowRaw<B, T, 2> R;
+    if (r0 < nA) fetch_row<B, T, 2>(ls, At, r0, src, R);
+    block_sum<2>(red);
+    const double sigma = red[0], vv = red[1];
+    const double al = rho / sigma;
+    const bool bad = !(sigma * sigma > brk2 * bnorm2 * vv) || !isfinite(al);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bad) {
+            sc->done = 1;
+            sc->iters = it;
+            sc->breakdown = 1;
+        } else {
+            sc->alpha = al;
+        }
+    }
+    if (bad) return;
+    auto fx = [&](const T (&raw)[2][B], double (&x)[B]) {
+#pragma unroll
+        for (int c = 0; c < B; c++) x[c] = s_update<T>(raw[0][c], raw[1][c], al);
+    };
     double dot[2] = {0.0, 0.0};
-    if (r < nA) {
+    for (int r = r0; r < nA; r += stride) {
+        if (r != r0) fetch_row<B, T, 2>(ls, At, r, src, R);
         double si[B], ti[B];
+        fx(R.xo, si);
 #pragma unroll
-        for (int c = 0; c < B; c++) {
-            const long q = (long)r * B + c;
-            si[c] = s_update<T>(V.r[q], V.v_new[q], al);
-            ti[c] = si[c];
-        }
-        const int s = r / SLICE, lane = r % SLICE;
-        const int base = ls.sptr[s];
-        const int width = (ls.sptr[s + 1] - base) / SLICE;
-        for (int k = 1; k < width; k++) {
-            const long pos = (long)base + (long)k * SLICE + lane;
-            const int cl = ls.col[pos];
-            double sj[B];
-#pragma unroll
-            for (int c = 0; c < B; c++) {
-                const long q = (long)cl * B + c;
-                sj[c] = s_update<T>(V.r[q], V.v_new[q], al);
-            }
-            const T* a = At + pos * BB;
-#pragma unroll
-            for (int c = 0; c < B; c++) {
-                double acc = 0.0;
-#pragma unroll
-                for (int v = 0; v < B; v++) acc += (double)a[c * B + v] * sj[v];
-                ti[c] += acc;
-            }
-        }
+        for (int c = 0; c < B; c++) ti[c] = si[c];
+        finish_row<B, T, 2>(ls, At, src, R, ti, fx);
 #pragma unroll
         for (int c = 0; c < B; c++) {
             const long q = (long)r * B + c;
@@ -256,81 +337,82 @@ __global__ __launch_bounds__(NT) void k_bicg_b(int nA, LocalSys ls, const T* __r
     }
     block_sum<2>(dot);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = dot[0];
-        part[2 * blockIdx.x + 1] = dot[1];
-    }
-    if (last_block(&sc->counter[2])) {
-        double t[2] = {0.0, 0.0};
-        for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
-            t[0] += part[2 * q];
-            t[1] += part[2 * q + 1];
-        }
-        block_sum<2>(t);
-        if (threadIdx.x == 0) {
-            sc->ts = t[0];
-            sc->tt = t[1];
-            sc->omega = (t[1] > 0.0) ? t[0] / t[1] : 0.0;
-            if (!isfinite(t[0]) || !isfinite(t[1])) {
-                sc->breakdown = 1;
-                sc->done = 1;
-            }
-            sc->counter[2] = 0;
-        }
+        pb[2 * blockIdx.x] = dot[0];
+        pb[2 * blockIdx.x + 1] = dot[1];
     }
 }
 
 // ----------------------- kernel C: x += alpha p + omega s, r = s - omega t
 template <int B, typename T>
-__global__ __launch_bounds__(NT) void k_bicg_c(int nA, Vecs<B, T> V, KScal* __restrict__ sc,
-                                               double* __restrict__ part, int maxit) {
-    if (sc->done) return;
-    const double al = sc->alpha, om = sc->omega;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(KB_NT) void k_bicg_c(int nA, Vecs<B, T> V, KScal* __restrict__ sc,
+                                                  const double* __restrict__ pb,
+                                                  double* __restrict__ pc, int it) {
+    const int done = sc->done;
+    const double al = sc->alpha;
+    double red[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
+        red[0] += pb[2 * q];
+        red[1] += pb[2 * q + 1];
+    }
+    if (done) return;
+    const int r0 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int stride = gridDim.x * blockDim.x;
+    // prefetch the first row while the partial sums are combined
+    T s0[B], t0[B], p0[B], x0[B], h0[B];
+    if (r0 < nA) {
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            const long q = (long)r0 * B + c;
+            s0[c] = V.s[q]; t0[c] = V.t[q]; p0[c] = V.p_new[q]; x0[c] = V.x[q]; h0[c] = V.rh[q];
+        }
+    }
+    block_sum<2>(red);
+    // omega = 0 (t orthogonal to s): x += alpha p, r = s; the next kernel
+    // A stops on rho = 0 or converges
+    const double om = (red[1] > 0.0) ? red[0] / red[1] : 0.0;
+    const bool bad = !isfinite(om);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->omega = om;
+        sc->iters = it + 1;
+        if (bad) {
+            sc->done = 1;
+            sc->breakdown = 1;
+        }
+    }
+    if (bad) return;
     double dot[2] = {0.0, 0.0};
-    if (r < nA) {
+    for (int r = r0; r < nA; r += stride) {
+        if (r != r0) {
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                const long q = (long)r * B + c;
+                s0[c] = V.s[q]; t0[c] = V.t[q]; p0[c] = V.p_new[q]; x0[c] = V.x[q]; h0[c] = V.rh[q];
+            }
+        }
 #pragma unroll
         for (int c = 0; c < B; c++) {
             const long q = (long)r * B + c;
-            const double sv = (double)V.s[q];
-            V.x[q] = (T)((double)V.x[q] + al * (double)V.p_new[q] + om * sv);
-            const T rT = (T)(sv - om * (double)V.t[q]);
+            const double sv = (double)s0[c];
+            V.x[q] = (T)((double)x0[c] + al * (double)p0[c] + om * sv);
+            const T rT = (T)(sv - om * (double)t0[c]);
             V.r[q] = rT;
-            dot[0] += (double)V.rh[q] * (double)rT;
+            dot[0] += (double)h0[c] * (double)rT;
             dot[1] += (double)rT * (double)rT;
         }
     }
     block_sum<2>(dot);
     if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = dot[0];
-        part[2 * blockIdx.x + 1] = dot[1];
-    }
-    if (last_block(&sc->counter[3])) {
-        double t[2] = {0.0, 0.0};
-        for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
-            t[0] += part[2 * q];
-            t[1] += part[2 * q + 1];
-        }
-        block_sum<2>(t);
-        if (threadIdx.x == 0) {
-            sc->rho_prev = sc->rho;
-            sc->rho = t[0];
-            sc->rr = t[1];
-            sc->iters += 1;
-            if (t[1] <= sc->tol2 || sc->iters >= maxit) sc->done = 1;
-            if (!isfinite(t[1]) || t[0] == 0.0 || sc->omega == 0.0) {
-                sc->done = 1;
-                if (t[1] > sc->tol2) sc->breakdown = 1;
-            }
-            sc->counter[3] = 0;
-        }
+        pc[2 * blockIdx.x] = dot[0];
+        pc[2 * blockIdx.x + 1] = dot[1];
     }
 }
 
 template <int B, typename T>
-__global__ __launch_bounds__(NT) void k_ir_accumulate(int nA, double* __restrict__ x64,
-                                                      const T* __restrict__ xT) {
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q < (long)nA * B) x64[q] += (double)xT[q];
+__global__ __launch_bounds__(KB_NT) void k_ir_accumulate(int nA, double* __restrict__ x64,
+                                                         const T* __restrict__ xT) {
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < (long)nA * B;
+         q += (long)gridDim.x * blockDim.x)
+        x64[q] += (double)xT[q];
 }
 
 __global__ void k_copy_f64(double* __restrict__ d, const double* __restrict__ s, long n) {
@@ -359,23 +441,27 @@ static Vecs<B, T> make_vecs(const KrylovBufs& kb, int parity) {
 }
 
 template <int B, typename T>
-static void part_impl(int which, int nA, const LocalSys& ls, const KrylovBufs& kb,
-                      int parity, int maxit, hipStream_t s) {
-    const int nb = nblocks(nA);
-    Vecs<B, T> V = make_vecs<B, T>(kb, parity);
+static void part_impl(int which, int nA, const LocalSys& ls, const KrylovBufs& kb, int it,
+                      double tol2, double bnorm2, int maxit, hipStream_t s) {
+    const int nb = kgrid(nA);
+    Vecs<B, T> V = make_vecs<B, T>(kb, it & 1);
+    const double brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
     if (which == 0)
-        k_bicg_a<B, T><<<nb, NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part);
+        k_bicg_a<B, T><<<nb, KB_NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part_c,
+                                            kb.part_a, it, tol2, maxit);
     else if (which == 1)
-        k_bicg_b<B, T><<<nb, NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part);
+        k_bicg_b<B, T><<<nb, KB_NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part_a,
+                                            kb.part_b, it, brk * brk, bnorm2);
     else
-        k_bicg_c<B, T><<<nb, NT, 0, s>>>(nA, V, kb.sc, kb.part, maxit);
+        k_bicg_c<B, T><<<nb, KB_NT, 0, s>>>(nA, V, kb.sc, kb.part_b, kb.part_c, it);
 }
 
+int krylov_grid(int nA) { return kgrid(nA); }
+
 void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
-                        const KrylovBufs& kb, bool x_zero, double lin_rtol,
-                        double inner_rtol, hipStream_t s) {
-    const int nb = nblocks(nA > 0 ? nA : 1);
-#define IR(BV, TT) k_ir_residual<BV, TT><<<nb, NT, 0, s>>>(nA, ls, kb, x_zero ? 1 : 0, lin_rtol, inner_rtol)
+                        const KrylovBufs& kb, bool x_zero, hipStream_t s) {
+    const int nb = kgrid(nA);
+#define IR(BV, TT) k_ir_residual<BV, TT><<<nb, KB_NT, 0, s>>>(nA, ls, kb, x_zero ? 1 : 0)
     if (fp32) {
         if (b == 1) IR(1, float); else if (b == 2) IR(2, float); else IR(3, float);
     } else {
@@ -385,24 +471,25 @@ void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
 }
 
 void launch_bicg_part(int which, int b, bool fp32, int nA, const LocalSys& ls,
-                      const KrylovBufs& kb, int parity, int maxit, hipStream_t s) {
+                      const KrylovBufs& kb, int it, double tol2, double bnorm2, int maxit,
+                      hipStream_t s) {
     if (nA <= 0) return;
     if (fp32) {
-        if (b == 1) part_impl<1, float>(which, nA, ls, kb, parity, maxit, s);
-        else if (b == 2) part_impl<2, float>(which, nA, ls, kb, parity, maxit, s);
-        else part_impl<3, float>(which, nA, ls, kb, parity, maxit, s);
+        if (b == 1) part_impl<1, float>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
+        else if (b == 2) part_impl<2, float>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
+        else part_impl<3, float>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
     } else {
-        if (b == 1) part_impl<1, double>(which, nA, ls, kb, parity, maxit, s);
-        else if (b == 2) part_impl<2, double>(which, nA, ls, kb, parity, maxit, s);
-        else part_impl<3, double>(which, nA, ls, kb, parity, maxit, s);
+        if (b == 1) part_impl<1, double>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
+        else if (b == 2) part_impl<2, double>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
+        else part_impl<3, double>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
     }
 }
 
 void launch_ir_accumulate(int b, bool fp32, int nA, const KrylovBufs& kb,
                           hipStream_t s) {
     if (nA <= 0) return;
-    const int nb = nblocks((long)nA * b);
-#define AC(BV, TT) k_ir_accumulate<BV, TT><<<nb, NT, 0, s>>>(nA, kb.x64, (const TT*)kb.x)
+    const int nb = kgrid((long)nA * b);
+#define AC(BV, TT) k_ir_accumulate<BV, TT><<<nb, KB_NT, 0, s>>>(nA, kb.x64, (const TT*)kb.x)
     if (fp32) {
         if (b == 1) AC(1, float); else if (b == 2) AC(2, float); else AC(3, float);
     } else {

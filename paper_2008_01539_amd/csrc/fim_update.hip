@@ -82,23 +82,25 @@ __global__ __launch_bounds__(NT) void k_update(int nA, const int* __restrict__ l
 #pragma unroll
         for (int q = 0; q < 4; q++) part[4 * blockIdx.x + q] = red[q];
     }
-    if (last_block(&ns->counter[0])) {
-        double mx[2] = {0.0, 0.0}, sm[2] = {0.0, 0.0};
-        for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
-            mx[0] = fmax(mx[0], part[4 * q]);
-            mx[1] = fmax(mx[1], part[4 * q + 1]);
-            sm[0] += part[4 * q + 2];
-            sm[1] += part[4 * q + 3];
-        }
-        block_max<2>(mx);
-        block_sum<2>(sm);
-        if (threadIdx.x == 0) {
-            ns->dp_max = mx[0];
-            ns->ds_max = mx[1];
-            ns->nswitch = (int)sm[0];
-            ns->nonfinite = (int)sm[1];
-            ns->counter[0] = 0;
-        }
+}
+
+// one block: combine the per-block maxima and counts of k_update
+__global__ __launch_bounds__(1024) void k_update_finish(const double* __restrict__ part, int np,
+                                                        NStat* ns) {
+    double mx[2] = {0.0, 0.0}, sm[2] = {0.0, 0.0};
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        mx[0] = fmax(mx[0], part[4 * q]);
+        mx[1] = fmax(mx[1], part[4 * q + 1]);
+        sm[0] += part[4 * q + 2];
+        sm[1] += part[4 * q + 3];
+    }
+    block_max<2>(mx);
+    block_sum<2>(sm);
+    if (threadIdx.x == 0) {
+        ns->dp_max = mx[0];
+        ns->ds_max = mx[1];
+        ns->nswitch = (int)sm[0];
+        ns->nonfinite = (int)sm[1];
     }
 }
 
@@ -112,6 +114,7 @@ void launch_update(int fk, int nA, const int* l2g, const double* x64,
     case 2: k_update<2><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns); break;
     default: k_update<3><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns); break;
     }
+    k_update_finish<<<1, 1024, 0, s>>>(part, nb, ns);
 }
 
 __global__ void k_copy_state(int b, int n, const double* __restrict__ src,
