@@ -187,6 +187,17 @@ const char* fim_last_error(const fim_model* m);
 int32_t fim_num_cells(const fim_model* m);
 int32_t fim_block_size(const fim_model* m);
 
+/* ---------------- cell classes of an iteration ------------------------- */
+
+/* Section 5.2.1 plots four cell sets per Newton iteration: active cells,
+ * boundary cells, active cells with a non-negligible update and boundary
+ * cells with a non-negligible update.  When enabled, every iteration
+ * records per cell: bit 0 = active, bit 1 = boundary (V_B; never set in
+ * FIM_FULL), bit 2 = |dp| >= eps_loc; inactive cells read 0.  out: host
+ * u8[n], the classes of the last iteration run. */
+fim_status fim_flags_enable(fim_model* m, int32_t on);
+fim_status fim_get_flags(fim_model* m, uint8_t* out);
+
 /* ---------------- profiling ------------------------------------------- */
 
 /* Per-kernel timing with hipEvents recorded on the model's stream around

@@ -95,6 +95,8 @@ struct fim_model {
     double last_relres = 0.0;
     bool inspect_ready = false;
     int cur_nnzb = 0;   // blocks of the current local matrix (profiling)
+    bool flags_on = false;
+    uint8_t* classes = nullptr;   // per-cell classes of the last iteration
     Prof prof;
     std::string err;
 };
@@ -116,6 +118,15 @@ static int pbeg(fim_model* m, int k, int tag = -1) {
                      k == PK_BICG_B;
     ProfRec r{k, ev_take(m), ev_take(m), 0.0, mat, tag};
     (void)hipEventRecord(r.a, m->s);
+    m->prof.pend.push_back(r);
+    return (int)m->prof.pend.size() - 1;
+}
+
+// record for a launch whose events the dispatch stamps (hipExtLaunchKernel)
+static int pbeg_ext(fim_model* m, int k, int tag) {
+    if (!m->prof.on) return -1;
+    const bool mat = k == PK_BICG_A || k == PK_BICG_B;
+    ProfRec r{k, ev_take(m), ev_take(m), 0.0, mat, tag};
     m->prof.pend.push_back(r);
     return (int)m->prof.pend.size() - 1;
 }
@@ -266,10 +277,12 @@ static fim_status inner_solve(fim_model* m, bool fp32, const LocalSys& ls,
     for (int chunk = 0; chunk < max_chunks; chunk++) {
         for (int c = 0; c < m->o.check_every; c++, it++) {
             for (int w = 0; w < 3; w++) {
-                const int q = pbeg(m, PK_BICG_A + w, c);
+                // events stamped by the dispatch itself: kernel time only
+                const int q = pbeg_ext(m, PK_BICG_A + w, c);
                 launch_bicg_part(w, m->B, fp32, m->nA, ls, kb, it, tol2, bnorm2,
-                                 m->o.krylov_maxit, m->s);
-                pend(m, q, m->nA);
+                                 m->o.krylov_maxit, m->s, q >= 0 ? m->prof.pend[q].a : nullptr,
+                                 q >= 0 ? m->prof.pend[q].b : nullptr);
+                if (q >= 0) m->prof.pend[q].rows = m->nA;
             }
         }
         HIPX(hipMemcpyAsync(m->hsc, m->sc, sizeof(KScal), hipMemcpyDeviceToHost, m->s));
@@ -359,6 +372,11 @@ static fim_status local_newton(fim_model* m, fim_iter_stats* it) {
     launch_update(m->fk, m->nA, m->l2g, m->x64, m->u, m->st, m->n, m->f, m->o.ds_max,
                   m->dp_abs, m->part, m->ns, m->s);
     pend(m, pi, m->nA);
+    if (m->flags_on) {
+        launch_fill_u8(m->classes, m->n, 0, m->s);
+        launch_cell_classes(m->nA, m->l2g, m->bnd, m->step_mode != FIM_FULL, m->dp_abs,
+                            m->o.eps_loc, m->classes, m->s);
+    }
     if (it) {
         it->n_active = m->nA;
         it->krylov_iters = m->last_kry;
@@ -543,7 +561,7 @@ static void free_all(fim_model* m) {
                     m->supp, m->bnd, m->vt, m->outer, m->l2g, m->g2l, m->swidth, m->sptr,
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
-                    m->part_ir};
+                    m->part_ir, m->classes};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (m->hsc) (void)hipHostFree(m->hsc);
@@ -826,7 +844,6 @@ fim_status fim_get_state(fim_model* m, double* u_out, int8_t* status_out, int me
 
 static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
     const bool local = m->step_mode == FIM_LOCAL;
-    if (it) it->n_boundary = local ? m->hint[2] : 0;
     TRY(local_newton(m, it));
     if (local) {
         const int pi = pbeg(m, PK_SETS);
@@ -843,6 +860,9 @@ static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
     m->nu++;
     const bool conv = converged(m, ns);
     if (it) {
+        // dint[2] still holds |V_B| of this iteration (the next boundary
+        // pass runs after this readback)
+        it->n_boundary = local ? m->hint[2] : 0;
         it->dp_max = ns.dp_max;
         it->ds_max = ns.ds_max;
         it->n_switch = ns.nswitch;
@@ -1017,6 +1037,28 @@ fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats*
         todo.insert(todo.begin(), {{h * 0.5, depth + 1}, {h * 0.5, depth + 1}});
     }
     if (st) st->converged = 1;
+    return FIM_OK;
+}
+
+// ------------------------------------------------------- cell classes
+fim_status fim_flags_enable(fim_model* m, int32_t on) {
+    if (!m) return FIM_E_ARG;
+    if (on && !m->classes) {
+        TRY(dal(m, &m->classes, (size_t)m->n));
+        launch_fill_u8(m->classes, m->n, 0, m->s);
+    }
+    m->flags_on = on != 0;
+    return FIM_OK;
+}
+
+fim_status fim_get_flags(fim_model* m, uint8_t* out) {
+    if (!m || !out) return FIM_E_ARG;
+    if (!m->classes) {
+        m->err = "cell classes are not recorded (fim_flags_enable)";
+        return FIM_E_STATE;
+    }
+    HIPX(hipMemcpyAsync(out, m->classes, m->n, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
     return FIM_OK;
 }
 

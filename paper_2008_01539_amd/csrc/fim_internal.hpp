@@ -98,6 +98,8 @@ void launch_outer_layer(int nA, const int* l2g, const uint8_t* in_set,
 void launch_gather_max(int cnt, const int* idx, const double* v, double* out,
                        hipStream_t s);
 void launch_scatter_flags(int cnt, const int* idx, uint8_t* flags, hipStream_t s);
+void launch_cell_classes(int nA, const int* l2g, const uint8_t* bnd, bool use_bnd,
+                         const double* dp_abs, double eps, uint8_t* out, hipStream_t s);
 void launch_copy_masked(int nA, const int* l2g, const double* src, double* dst,
                         hipStream_t s);
 
@@ -138,9 +140,10 @@ void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
                         const KrylovBufs& kb, bool x_zero, hipStream_t s);
 // which: 0 = v = A p (with the p update), 1 = s, t = A s, 2 = x, r update;
 // it = iteration index; tol2 = stop when |r|^2 <= tol2; bnorm2 = |b~|^2
+// ev0/ev1: optional events stamped with the kernel's own start and end
 void launch_bicg_part(int which, int b, bool fp32, int nA, const LocalSys& ls,
                       const KrylovBufs& kb, int it, double tol2, double bnorm2, int maxit,
-                      hipStream_t s);
+                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_ir_accumulate(int b, bool fp32, int nA, const KrylovBufs& kb,
                           hipStream_t s);
 void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);

@@ -18,6 +18,8 @@
 // fly, saving a launch and a vector pass.  Grids are capped at KB_MAXB
 // blocks of KB_NT threads (grid-stride over rows) so that a partial array
 // has at most KB_MAXB entries.
+#include <hip/hip_ext.h>
+
 #include "fim_device.hpp"
 
 namespace fimk {
@@ -440,20 +442,25 @@ static Vecs<B, T> make_vecs(const KrylovBufs& kb, int parity) {
     return V;
 }
 
+// ev0/ev1 (optional): events stamped by the dispatch itself
+// (hipExtLaunchKernelGGL), i.e. the kernel's own start and end
 template <int B, typename T>
 static void part_impl(int which, int nA, const LocalSys& ls, const KrylovBufs& kb, int it,
-                      double tol2, double bnorm2, int maxit, hipStream_t s) {
-    const int nb = kgrid(nA);
+                      double tol2, double bnorm2, int maxit, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1) {
+    const dim3 nb(kgrid(nA)), nt(KB_NT);
     Vecs<B, T> V = make_vecs<B, T>(kb, it & 1);
     const double brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
+    const T* At = (const T*)kb.At;
     if (which == 0)
-        k_bicg_a<B, T><<<nb, KB_NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part_c,
-                                            kb.part_a, it, tol2, maxit);
+        hipExtLaunchKernelGGL(k_bicg_a<B, T>, nb, nt, 0, s, ev0, ev1, 0, nA, ls, At, V, kb.sc,
+                              (const double*)kb.part_c, kb.part_a, it, tol2, maxit);
     else if (which == 1)
-        k_bicg_b<B, T><<<nb, KB_NT, 0, s>>>(nA, ls, (const T*)kb.At, V, kb.sc, kb.part_a,
-                                            kb.part_b, it, brk * brk, bnorm2);
+        hipExtLaunchKernelGGL(k_bicg_b<B, T>, nb, nt, 0, s, ev0, ev1, 0, nA, ls, At, V, kb.sc,
+                              (const double*)kb.part_a, kb.part_b, it, brk * brk, bnorm2);
     else
-        k_bicg_c<B, T><<<nb, KB_NT, 0, s>>>(nA, V, kb.sc, kb.part_b, kb.part_c, it);
+        hipExtLaunchKernelGGL(k_bicg_c<B, T>, nb, nt, 0, s, ev0, ev1, 0, nA, V, kb.sc,
+                              (const double*)kb.part_b, kb.part_c, it);
 }
 
 int krylov_grid(int nA) { return kgrid(nA); }
@@ -472,17 +479,15 @@ void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
 
 void launch_bicg_part(int which, int b, bool fp32, int nA, const LocalSys& ls,
                       const KrylovBufs& kb, int it, double tol2, double bnorm2, int maxit,
-                      hipStream_t s) {
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (nA <= 0) return;
+#define PI(BV, TT) part_impl<BV, TT>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s, ev0, ev1)
     if (fp32) {
-        if (b == 1) part_impl<1, float>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
-        else if (b == 2) part_impl<2, float>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
-        else part_impl<3, float>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
+        if (b == 1) PI(1, float); else if (b == 2) PI(2, float); else PI(3, float);
     } else {
-        if (b == 1) part_impl<1, double>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
-        else if (b == 2) part_impl<2, double>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
-        else part_impl<3, double>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s);
+        if (b == 1) PI(1, double); else if (b == 2) PI(2, double); else PI(3, double);
     }
+#undef PI
 }
 
 void launch_ir_accumulate(int b, bool fp32, int nA, const KrylovBufs& kb,

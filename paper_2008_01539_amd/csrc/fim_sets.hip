@@ -365,6 +365,24 @@ void launch_gather_max(int cnt, const int* idx, const double* v, double* out,
     k_gather_max<<<1, NT, 0, s>>>(cnt, idx, v, out);
 }
 
+// four cell classes of one iteration: bit 0 active, bit 1 boundary,
+// bit 2 update >= eps (inactive cells keep 0)
+__global__ __launch_bounds__(NT) void k_cell_classes(int nA, const int* __restrict__ l2g,
+                                                     const uint8_t* __restrict__ bnd, int use_bnd,
+                                                     const double* __restrict__ dp_abs, double eps,
+                                                     uint8_t* __restrict__ out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nA) return;
+    const int i = l2g[r];
+    out[i] = (uint8_t)(1 | ((use_bnd && bnd[i]) ? 2 : 0) | (dp_abs[i] >= eps ? 4 : 0));
+}
+
+void launch_cell_classes(int nA, const int* l2g, const uint8_t* bnd, bool use_bnd,
+                         const double* dp_abs, double eps, uint8_t* out, hipStream_t s) {
+    if (nA > 0)
+        k_cell_classes<<<nblocks(nA), NT, 0, s>>>(nA, l2g, bnd, use_bnd ? 1 : 0, dp_abs, eps, out);
+}
+
 __global__ void k_scatter_flags(int cnt, const int* __restrict__ idx, uint8_t* flags) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < cnt) flags[idx[k]] = 1;

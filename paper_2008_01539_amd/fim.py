@@ -119,6 +119,8 @@ def _load():
         "fim_inspect_sets": (i32, [vp, vp, vp, f64, i32, vp, vp, vp, vp, vp]),
         "fim_inspect_solve": (i32, [vp, vp, vp, vp]),
         "fim_profile_enable": (i32, [vp, i32]),
+        "fim_flags_enable": (i32, [vp, i32]),
+        "fim_get_flags": (i32, [vp, vp]),
         "fim_profile_read": (i32, [vp, vp, i32]),
     }
     for name, (res, args) in sig.items():
@@ -282,6 +284,15 @@ class FimModel:
     def run(self, schedule, mode=LOCAL):
         """Advance through a schedule; returns the per-step statistics."""
         return [self.solve_timestep(dt, mode).as_dict() for dt in schedule]
+
+    # ---------------------------------------------------------- cell classes
+    def record_flags(self, on=True):
+        _check(_lib.fim_flags_enable(self._h, 1 if on else 0), self._h)
+
+    def flags(self):
+        out = np.empty(self.n, np.uint8)
+        _check(_lib.fim_get_flags(self._h, _ptr(out)), self._h)
+        return out
 
     # ------------------------------------------------------------ profiling
     def profile(self, on=True):

@@ -151,3 +151,31 @@ def test_run_twice_bitwise(c1):
     a, _, _ = _run_gpu(c1, P.Options(), P.LOCAL, c1.schedule[:6])
     b, _, _ = _run_gpu(c1, P.Options(), P.LOCAL, c1.schedule[:6])
     assert np.array_equal(a, b)
+
+
+def test_cell_classes_single_50_day_step(c1):
+    """One 50-day step with localized Newton (the paper's flag-profile
+    protocol): per iteration the recorded classes match the iteration's
+    statistics: boundary and support cells are active, the active count is
+    n_A, and the mode is 'expand' exactly when a boundary cell carries a
+    non-negligible update."""
+    import paper_2008_01539_amd as P
+    from fimgen import DAY
+    fm = P.FimModel(c1, P.Options())
+    fm.set_state(c1.u0, c1.status0)
+    fm.record_flags(True)
+    seen_expand = seen_shrink = False
+    for _ in range(25):
+        it = fm.newton_step(50 * DAY, P.LOCAL)
+        f = fm.flags()
+        act, bnd, sup = (f & 1) > 0, (f & 2) > 0, (f & 4) > 0
+        assert act.sum() == it.n_active
+        assert not np.any(bnd & ~act) and not np.any(sup & ~act)
+        assert bnd.sum() == it.n_boundary
+        assert bool(np.any(bnd & sup)) == bool(it.is_expand)
+        seen_expand |= bool(it.is_expand)
+        seen_shrink |= not it.is_expand
+        if it.converged:
+            break
+    assert it.converged and seen_expand and seen_shrink
+    fm.close()

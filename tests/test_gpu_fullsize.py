@@ -1,0 +1,130 @@
+"""Parity at the full config-2 size (258,096 cells), in the launch
+configuration the benchmark times: sampled residual and Jacobian rows
+against the oracle evaluated row by row on the sampled cells'
+neighbourhoods, the set logic bit for bit, and the converged timestep
+checked with the oracle's own residual and mass balance."""
+import numpy as np
+import pytest
+
+from fimgen import PSI, make_c2
+from fimgen.model import Model
+from oracle import sets as S
+from oracle.jacobian import JacobianBuilder, adjacency
+from oracle.physics import accumulation, residual, well_rates
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return make_c2()
+
+
+@pytest.fixture(scope="module")
+def c2_jb(c2):
+    return JacobianBuilder(c2)
+
+
+def _submodel(m, rows):
+    """Cells `rows`, their neighbours, and every connection touching a row:
+    the oracle's residual and Jacobian rows of `rows` on this model equal
+    the full model's."""
+    rp, nb = adjacency(m)
+    keep = set(rows.tolist())
+    for i in rows:
+        keep.update(nb[rp[i]:rp[i + 1]].tolist())
+    cells = np.array(sorted(keep))
+    idx = -np.ones(m.n, np.int64)
+    idx[cells] = np.arange(cells.size)
+    isrow = np.zeros(m.n, bool)
+    isrow[rows] = True
+    sel = isrow[m.conn_i] | isrow[m.conn_j]
+    pk = np.isin(m.perf_cell, cells)
+    sub = Model(name="sub", n_matrix=0, pv_ref=m.pv_ref[cells], depth=m.depth[cells],
+                kind=m.kind[cells], always_active=m.always_active[cells],
+                conn_i=idx[m.conn_i[sel]].astype(np.int32),
+                conn_j=idx[m.conn_j[sel]].astype(np.int32), conn_T=m.conn_T[sel],
+                perf_cell=idx[m.perf_cell[pk]].astype(np.int32), perf_wi=m.perf_wi[pk],
+                perf_bhp=m.perf_bhp[pk], fluid=m.fluid, rock=m.rock, gravity=m.gravity,
+                u0=m.u0[:, cells], status0=m.status0[cells], schedule=m.schedule)
+    return sub, cells, idx
+
+
+def test_sampled_rows_full_size(c2):
+    import paper_2008_01539_amd as P
+    rng = np.random.default_rng(21)
+    fm = P.FimModel(c2, P.Options(precision=P.MIXED))
+    uo = c2.u0.copy()
+    ui = c2.u0.copy()
+    ui[0] += rng.normal(0, 20 * PSI, c2.n)
+    ui[1] = np.clip(ui[1] + rng.uniform(0, 0.3, c2.n), 0, 1)
+    dt = c2.schedule[10]
+    g = fm.inspect_assemble(uo, ui, c2.status0, dt, cap_blocks=14 * c2.n)
+    fm.close()
+    assert g["n_active"] == c2.n
+    b = c2.b
+    # include all fracture/perforated kinds: sample matrix, fracture, perforated
+    rows = np.unique(np.concatenate([rng.choice(c2.n_matrix, 300, replace=False),
+                                     rng.choice(np.arange(c2.n_matrix, c2.n), 300, replace=False),
+                                     c2.perf_cell]))
+    sub, cells, idx = _submodel(c2, rows)
+    m_old = accumulation(sub, uo[:, cells], c2.status0[cells])
+    R, J = JacobianBuilder(sub).build(ui[:, cells], c2.status0[cells], m_old, dt)
+    J = J.tocsr()
+    for i in rows:
+        li = idx[i]
+        Fo = R[:, li]
+        assert np.allclose(g["F"][i], Fo, rtol=1e-11, atol=1e-12 * np.abs(J[li * b:(li + 1) * b]).sum())
+        ro = J[li * b:(li + 1) * b].toarray()
+        scale = np.abs(ro).max()
+        for q in range(g["row_ptr"][i], g["row_ptr"][i + 1]):
+            j = g["col"][q]
+            ref = ro[:, idx[j] * b:(idx[j] + 1) * b]
+            assert np.abs(g["val"][q] - ref).max() <= 1e-12 * scale
+
+
+def test_sets_full_size_bitwise(c2):
+    import paper_2008_01539_amd as P
+    rp, nb = adjacency(c2)
+    rng = np.random.default_rng(8)
+    aa = np.nonzero(c2.always_active)[0]
+    act0 = S.initial_active(rp, nb, aa, 2)
+    bnd0 = S.boundary(rp, nb, act0)
+    dp = np.zeros(c2.n)
+    idx = np.fromiter(act0, np.int64)
+    dp[idx] = rng.exponential(0.3 * PSI, idx.size)
+    ref_act, ref_bnd, ref_ex = S.alg1_update(rp, nb, act0, bnd0, dp, 0.3 * PSI, 2, aa)
+    a = np.zeros(c2.n, np.uint8)
+    a[idx] = 1
+    fm = P.FimModel(c2, P.Options())
+    out = fm.inspect_sets(a, dp, 0.3 * PSI, 2)
+    fm.close()
+    assert out["is_expand"] == ref_ex
+    assert np.array_equal(np.nonzero(out["act"])[0], np.array(sorted(ref_act)))
+    assert np.array_equal(np.nonzero(out["bnd"])[0], np.array(sorted(ref_bnd)))
+
+
+@pytest.mark.parametrize("mode_name", ["FULL", "LOCAL"])
+def test_converged_steps_satisfy_oracle_equations(c2, c2_jb, mode_name):
+    """Tight mode, mixed precision, the first three steps at full size: the
+    oracle's residual at the GPU state is at the level of a sub-1e-3 Pa
+    pressure error per row, and the step mass balance closes."""
+    import paper_2008_01539_amd as P
+    fm = P.FimModel(c2, P.Options.tight_mode(precision=P.MIXED))
+    fm.set_state(c2.u0, c2.status0)
+    prev, prev_st = c2.u0.copy(), c2.status0.copy()
+    for k, dt in enumerate(c2.schedule[:3]):
+        fm.solve_timestep(dt, getattr(P, mode_name))
+        u, st = fm.get_state()
+        m_old = accumulation(c2, prev, prev_st)
+        dm = (accumulation(c2, u, st) - m_old).sum(axis=1)
+        q = well_rates(c2, u, st).sum(axis=1)
+        assert np.all(np.abs(dm - dt * q) <= 1e-8 * np.abs(dm).max())
+        if k == 2:
+            R, J = c2_jb.build(u, st, m_old, dt)
+            # residual equivalent of a 1e-3 Pa pressure error, per row
+            pcols = J[:, 0::2]
+            scale = np.asarray(abs(pcols).sum(axis=1)).ravel().reshape(c2.n, 2).T
+            assert np.all(np.abs(R) <= 1e-3 * scale + 1e-30)
+        prev, prev_st = u, st
+    fm.close()
