@@ -187,6 +187,43 @@ const char* fim_last_error(const fim_model* m);
 int32_t fim_num_cells(const fim_model* m);
 int32_t fim_block_size(const fim_model* m);
 
+/* ---------------- device footprint -------------------------------------- */
+
+/* Device bytes a model holds, and the bytes fim_create_model would
+ * allocate for a description (computed without allocating; -1 on an
+ * invalid description).  Used for admission by HBM footprint. */
+int64_t fim_model_bytes(const fim_model* m);
+int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o);
+
+/* ---------------- batches of models ------------------------------------ */
+
+/* A batch advances several independent models together: each call runs
+ * one Newton iteration (Algorithm 1 or full Newton) of every member, with
+ * the members' local linear systems solved by one set of Krylov launches
+ * that covers all of them (per-member reductions and convergence).  A
+ * member's result is the same alone and in any batch.  Members keep their
+ * own state and may be in different phases of their own timesteps; a
+ * member whose step converged starts its next step at its next call.
+ * Members need the same block size and Krylov precision; the batch does
+ * not own them.  Membership can change between calls (fim_batch_set), which
+ * is how a serving loop admits and retires requests.  hip_stream: stream of
+ * the batch's launches (NULL: own stream); members' own streams are
+ * ordered before and after each call with events. */
+typedef struct fim_batch fim_batch;
+
+fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_stream,
+                            fim_batch** out);
+fim_status fim_batch_set(fim_batch* b, fim_model* const* models, int32_t k);
+
+/* dts[k], modes[k] (FIM_FULL or FIM_LOCAL) per member; stats (nullable)
+ * and codes receive each member's statistics and status (FIM_OK,
+ * FIM_NOT_CONVERGED after a rollback, or a negative error).  The call
+ * itself returns FIM_OK unless the batch as a whole failed. */
+fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t* modes,
+                                 fim_iter_stats* stats, int32_t* codes);
+fim_status fim_batch_destroy(fim_batch* b);
+const char* fim_batch_last_error(const fim_batch* b);
+
 /* ---------------- cell classes of an iteration ------------------------- */
 
 /* Section 5.2.1 plots four cell sets per Newton iteration: active cells,

@@ -4,10 +4,10 @@ ctypes binding.
 
     from paper_2008_01539_amd import FimModel, Options, LOCAL
 """
-from .fim import (DD, DEVICE, FP64, FULL, HOST, LIB_PATH, LOCAL, MIXED, FimError,
+from .fim import (DD, DEVICE, FP64, FULL, HOST, LIB_PATH, LOCAL, MIXED, FimBatch, FimError,
                   FimModel, IterStats, NotConverged, Options, StepStats,
-                  exported_symbols)
+                  estimate_bytes, exported_symbols)
 
-__all__ = ["FimModel", "Options", "FimError", "NotConverged", "IterStats",
+__all__ = ["FimModel", "FimBatch", "Options", "FimError", "NotConverged", "IterStats",
            "StepStats", "FULL", "LOCAL", "DD", "FP64", "MIXED", "HOST", "DEVICE",
-           "LIB_PATH", "exported_symbols"]
+           "LIB_PATH", "estimate_bytes", "exported_symbols"]

@@ -42,6 +42,16 @@ struct Prof {
 };
 
 
+// Tables of a (batched) Krylov launch: per-model descriptors and the
+// block -> model map, in device memory, plus pinned status records.
+struct SolveTable {
+    KSeg* dsegs = nullptr;
+    int* dblk = nullptr;
+    SegStatus* dstat = nullptr;
+    SegStatus* hstat = nullptr;
+    int cap = 0;
+};
+
 struct fim_model {
     int n = 0, nconn = 0, B = 1, fk = 1;
     fim_options o{};
@@ -96,6 +106,8 @@ struct fim_model {
     bool inspect_ready = false;
     int cur_nnzb = 0;   // blocks of the current local matrix (profiling)
     bool flags_on = false;
+    SolveTable solo;
+    size_t bytes = 0;   // device bytes held
     uint8_t* classes = nullptr;   // per-cell classes of the last iteration
     Prof prof;
     std::string err;
@@ -176,6 +188,7 @@ static void pflush(fim_model* m, int keep_tag = INT_MAX) {
 static fim_status dalloc(fim_model* m, void** p, size_t bytes) {
     if (bytes == 0) bytes = 8;
     hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) m->bytes += bytes;
     if (e != hipSuccess) {
         m->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
         *p = nullptr;
@@ -250,109 +263,269 @@ static fim_status structure(fim_model* m) {
     return FIM_OK;
 }
 
-// Local linear solve: J_A x = -F_A by iterative refinement around
-// BiCGStab on the block-Jacobi scaled system.  In mixed precision the inner
-// solves run in FP32; a pass that fails to cut the FP64 residual norm by at
-// least 10 % (stagnation or breakdown of the FP32 iteration on a badly
-// conditioned fracture subsystem) is undone and the remaining passes run
-// the FP64 Krylov.  The host sums the per-block partials of the refinement
-// residual itself (fixed order) to take its decisions.
-static fim_status read_ir(fim_model* m, double* rir2, double* bnorm2) {
-    const int nb = krylov_grid(m->nA);
-    TRY(sync_read(m, m->hpart, m->part_ir, 2 * nb * sizeof(double)));
-    double a = 0.0, b = 0.0;
-    for (int q = 0; q < nb; q++) {
-        a += m->hpart[2 * q];
-        b += m->hpart[2 * q + 1];
+static void table_free(SolveTable& t) {
+    if (t.dsegs) (void)hipFree(t.dsegs);
+    if (t.dblk) (void)hipFree(t.dblk);
+    if (t.dstat) (void)hipFree(t.dstat);
+    if (t.hstat) (void)hipHostFree(t.hstat);
+    t = SolveTable();
+}
+
+static fim_status table_alloc(fim_model* m, SolveTable& t, int cap) {
+    t.cap = cap;
+    TRY(dal(m, &t.dsegs, (size_t)2 * cap));
+    TRY(dal(m, &t.dblk, (size_t)2 * cap * KB_MAXB));
+    TRY(dal(m, &t.dstat, (size_t)2 * cap));
+    if (hipHostMalloc((void**)&t.hstat, 2 * cap * sizeof(SegStatus)) != hipSuccess) {
+        m->err = "hipHostMalloc failed";
+        return FIM_E_NOMEM;
     }
-    *rir2 = a;
-    *bnorm2 = b;
     return FIM_OK;
 }
 
-static fim_status inner_solve(fim_model* m, bool fp32, const LocalSys& ls,
-                              const KrylovBufs& kb, double tol2, double bnorm2, int* iters) {
-    int it = 0, before = 0;
-    const int max_chunks = m->o.krylov_maxit / m->o.check_every + 2;
-    for (int chunk = 0; chunk < max_chunks; chunk++) {
-        for (int c = 0; c < m->o.check_every; c++, it++) {
-            for (int w = 0; w < 3; w++) {
-                // events stamped by the dispatch itself: kernel time only
-                const int q = pbeg_ext(m, PK_BICG_A + w, c);
-                launch_bicg_part(w, m->B, fp32, m->nA, ls, kb, it, tol2, bnorm2,
-                                 m->o.krylov_maxit, m->s, q >= 0 ? m->prof.pend[q].a : nullptr,
-                                 q >= 0 ? m->prof.pend[q].b : nullptr);
-                if (q >= 0) m->prof.pend[q].rows = m->nA;
+// per-model state of one linear solve
+struct SolveItem {
+    fim_model* m;
+    bool fp32;
+    bool done_outer;
+    bool active;
+    double rir2, bnorm2, fnorm2, target2, tol2;
+    int passes, kry, fallback;
+};
+
+// A group = the models of one Krylov precision; region g of the tables
+// (g = 0: FP32, g = 1: FP64).
+struct Group {
+    std::vector<int> idx;   // items in this group
+    int nblk = 0;
+};
+
+static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
+                               std::vector<SolveItem>& items, hipStream_t s) {
+    std::vector<KSeg> segs;
+    std::vector<int> blk;
+    int off = 0;
+    for (int q : G.idx) {
+        SolveItem& it = items[q];
+        fim_model* m = it.m;
+        KSeg k;
+        k.ls = lsys(m);
+        k.kb = kbufs(m, g == 0);
+        k.nA = m->nA;
+        k.blk0 = off;
+        k.nblk = krylov_grid(m->nA);
+        k.active = it.active ? 1 : 0;
+        k.tol2 = it.tol2;
+        k.bnorm2 = it.bnorm2;
+        k.maxit = m->o.krylov_maxit;
+        k.pad = 0;
+        for (int b = 0; b < k.nblk; b++) blk.push_back((int)segs.size());
+        off += k.nblk;
+        segs.push_back(k);
+    }
+    G.nblk = off;
+    if (segs.empty()) return fim_status(FIM_OK);
+    fim_model* m = lead;
+    HIPX(hipMemcpyAsync(t.dsegs + (size_t)g * t.cap, segs.data(), segs.size() * sizeof(KSeg),
+                        hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(t.dblk + (size_t)g * t.cap * KB_MAXB, blk.data(), blk.size() * sizeof(int),
+                        hipMemcpyHostToDevice, s));
+    return FIM_OK;
+}
+
+static fim_status read_status(fim_model* lead, SolveTable& t, Group* G, std::vector<SolveItem>& items,
+                              hipStream_t s, bool flush = true) {
+    fim_model* m = lead;
+    for (int g = 0; g < 2; g++)
+        if (!G[g].idx.empty())
+            launch_seg_status(t.dsegs + (size_t)g * t.cap, (int)G[g].idx.size(),
+                              t.dstat + (size_t)g * t.cap, s);
+    for (int g = 0; g < 2; g++)
+        if (!G[g].idx.empty())
+            HIPX(hipMemcpyAsync(t.hstat + (size_t)g * t.cap, t.dstat + (size_t)g * t.cap,
+                                G[g].idx.size() * sizeof(SegStatus), hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    if (flush) pflush(lead);
+    (void)items;
+    return FIM_OK;
+}
+
+static const SegStatus& status_of(SolveTable& t, Group* G, int g, int pos) {
+    return t.hstat[(size_t)g * t.cap + pos];
+}
+
+// Local linear solves J_A x = -F_A of several models at once (one model:
+// a batch of one), by iterative refinement around BiCGStab on the
+// block-Jacobi scaled systems.  In mixed precision the inner solves run in
+// FP32; a model whose pass fails to cut its FP64 residual norm by at least
+// 10 % (stagnation or breakdown on a badly conditioned fracture subsystem)
+// has the pass undone and continues with the FP64 Krylov.
+static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStream_t s) {
+    fim_model* lead = ms[0];
+    fim_model* m = lead;
+    const int K = (int)ms.size();
+    std::vector<SolveItem> items(K);
+    Group G[2];
+    for (int q = 0; q < K; q++) {
+        fim_model* mq = ms[q];
+        SolveItem& it = items[q];
+        it = SolveItem{mq, mq->o.precision == FIM_MIXED, false, true, 0, 0, 0, 0, 0, 0, 0, 0};
+        const int pi = pbeg(lead, PK_PRECOND);
+        launch_precond(mq->B, it.fp32, mq->nA, lsys(mq), mq->dinv, mq->At, s);
+        pend(lead, pi, mq->nA);
+        launch_fill_f64(mq->x64, (long)mq->nA * mq->B, 0.0, s);
+        G[it.fp32 ? 0 : 1].idx.push_back(q);
+    }
+    const int b = lead->B;
+    for (int g = 0; g < 2; g++) TRY(upload_group(lead, t, g, G[g], items, s));
+    int pi = pbeg(lead, PK_IR);
+    for (int g = 0; g < 2; g++)
+        launch_ir_residual(b, g == 0, t.dsegs + (size_t)g * t.cap, t.dblk + (size_t)g * t.cap * KB_MAXB,
+                           G[g].nblk, true, s);
+    pend(lead, pi, lead->nA);
+    if (lead->prof.on)
+        HIPX(hipMemcpyAsync(&lead->hint[4], &lead->dint[4], sizeof(int), hipMemcpyDeviceToHost, s));
+    TRY(read_status(lead, t, G, items, s));
+    if (lead->prof.on) lead->cur_nnzb = lead->hint[4];
+    for (int g = 0; g < 2; g++)
+        for (size_t pos = 0; pos < G[g].idx.size(); pos++) {
+            SolveItem& it = items[G[g].idx[pos]];
+            const SegStatus& st = status_of(t, G, g, (int)pos);
+            it.rir2 = st.rir2;
+            it.bnorm2 = st.bnorm2;
+            it.fnorm2 = st.rir2;
+            it.target2 = it.m->o.lin_rtol * it.m->o.lin_rtol * it.fnorm2;
+        }
+    const int max_refine = lead->o.max_refine;
+    const int check = lead->o.check_every;
+    for (int pass = 0; pass < max_refine; pass++) {
+        int nact = 0;
+        for (SolveItem& it : items) {
+            it.done_outer = !(it.rir2 > it.target2) || !std::isfinite(it.rir2);
+            it.active = !it.done_outer;
+            if (!it.active) continue;
+            nact++;
+            it.passes++;
+            fim_model* mq = it.m;
+            if (it.fp32) launch_copy_f64(mq->xprev, mq->x64, (long)mq->nA * mq->B, s);
+            // inner target: the reduction this pass needs, not below what
+            // the Krylov precision can deliver
+            const double need = 0.5 * std::sqrt(it.target2 / it.rir2);
+            const double floor_ = it.fp32 ? std::max(mq->o.inner_rtol, 1e-6) : 1e-15;
+            const double inner = std::max(need, floor_);
+            it.tol2 = inner * inner * it.bnorm2;
+        }
+        if (!nact) break;
+        for (int g = 0; g < 2; g++) TRY(upload_group(lead, t, g, G[g], items, s));
+        // ---- BiCGStab in lockstep; finished models return at once
+        int iter = 0, before = 0;
+        const int max_chunks = lead->o.krylov_maxit / check + 2;
+        for (int chunk = 0; chunk < max_chunks; chunk++) {
+            for (int c = 0; c < check; c++, iter++)
+                for (int w = 0; w < 3; w++)
+                    for (int g = 0; g < 2; g++) {
+                        if (!G[g].nblk) continue;
+                        const int q = pbeg_ext(lead, PK_BICG_A + w, c);
+                        launch_bicg_part(w, b, g == 0, t.dsegs + (size_t)g * t.cap,
+                                         t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk, iter, s,
+                                         q >= 0 ? lead->prof.pend[q].a : nullptr,
+                                         q >= 0 ? lead->prof.pend[q].b : nullptr);
+                        if (q >= 0) lead->prof.pend[q].rows = lead->nA;
+                    }
+            TRY(read_status(lead, t, G, items, s, false));
+            // the lead model's iteration count tells which of its profiled
+            // launches did work (later ones returned at once)
+            for (int g = 0; g < 2; g++)
+                for (size_t pos = 0; pos < G[g].idx.size(); pos++)
+                    if (G[g].idx[pos] == 0) {
+                        const int its = status_of(t, G, g, (int)pos).iters;
+                        pflush(lead, its - before);
+                        before = its;
+                    }
+            bool all = true;
+            for (int g = 0; g < 2; g++)
+                for (size_t pos = 0; pos < G[g].idx.size(); pos++)
+                    if (items[G[g].idx[pos]].active && !status_of(t, G, g, (int)pos).done) all = false;
+            if (all) break;
+        }
+        for (int g = 0; g < 2; g++)
+            for (size_t pos = 0; pos < G[g].idx.size(); pos++) {
+                SolveItem& it = items[G[g].idx[pos]];
+                if (it.active) it.kry += status_of(t, G, g, (int)pos).iters;
+            }
+        pi = pbeg(lead, PK_IR);
+        for (int g = 0; g < 2; g++) {
+            launch_ir_accumulate(b, g == 0, t.dsegs + (size_t)g * t.cap,
+                                 t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk, s);
+            launch_ir_residual(b, g == 0, t.dsegs + (size_t)g * t.cap,
+                               t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk, false, s);
+        }
+        pend(lead, pi, lead->nA);
+        TRY(read_status(lead, t, G, items, s));
+        // new residuals; FP32 passes that stalled are undone -> FP64
+        bool moved = false;
+        std::vector<int> keep32;
+        for (size_t pos = 0; pos < G[0].idx.size(); pos++) {
+            const int q = G[0].idx[pos];
+            SolveItem& it = items[q];
+            const SegStatus& st = status_of(t, G, 0, (int)pos);
+            if (it.active && !(st.rir2 < 0.81 * it.rir2)) {
+                fim_model* mq = it.m;
+                launch_copy_f64(mq->x64, mq->xprev, (long)mq->nA * mq->B, s);
+                launch_precond(mq->B, false, mq->nA, lsys(mq), mq->dinv, mq->At, s);
+                it.fp32 = false;
+                it.fallback = 1;
+                G[1].idx.push_back(q);
+                moved = true;
+            } else {
+                keep32.push_back(q);
+                if (it.active) {
+                    it.rir2 = st.rir2;
+                    it.bnorm2 = st.bnorm2;
+                }
             }
         }
-        HIPX(hipMemcpyAsync(m->hsc, m->sc, sizeof(KScal), hipMemcpyDeviceToHost, m->s));
-        HIPX(hipStreamSynchronize(m->s));
-        pflush(m, m->hsc->iters - before);
-        before = m->hsc->iters;
-        if (m->hsc->done) break;
+        for (size_t pos = 0; pos < G[1].idx.size(); pos++) {
+            SolveItem& it = items[G[1].idx[pos]];
+            if (it.active && it.fallback != 1) {   // not moved in this pass
+                const SegStatus& st = status_of(t, G, 1, (int)pos);
+                it.rir2 = st.rir2;
+                it.bnorm2 = st.bnorm2;
+            }
+        }
+        if (moved) {
+            // recompute the FP64 refinement residual of the moved models
+            G[0].idx = keep32;
+            for (SolveItem& it : items) it.active = it.fallback == 1 && !it.fp32 && it.active;
+            for (int g = 0; g < 2; g++) TRY(upload_group(lead, t, g, G[g], items, s));
+            launch_ir_residual(b, false, t.dsegs + (size_t)t.cap, t.dblk + (size_t)t.cap * KB_MAXB,
+                               G[1].nblk, false, s);
+            TRY(read_status(lead, t, G, items, s));
+            for (size_t pos = 0; pos < G[1].idx.size(); pos++) {
+                SolveItem& it = items[G[1].idx[pos]];
+                if (it.active) {
+                    const SegStatus& st = status_of(t, G, 1, (int)pos);
+                    it.rir2 = st.rir2;
+                    it.bnorm2 = st.bnorm2;
+                }
+                it.fallback = it.fallback ? 2 : 0;
+            }
+        }
     }
-    *iters = m->hsc->iters;
+    for (SolveItem& it : items) {
+        fim_model* mq = it.m;
+        mq->last_kry = it.kry;
+        mq->last_refine = it.passes;
+        mq->last_fallback = it.fallback ? 1 : 0;
+        mq->last_relres = it.fnorm2 > 0 ? std::sqrt(it.rir2 / it.fnorm2) : 0.0;
+    }
     return FIM_OK;
 }
 
 static fim_status linear_solve(fim_model* m) {
-    bool fp32 = m->o.precision == FIM_MIXED;
-    const LocalSys ls = lsys(m);
-    KrylovBufs kb = kbufs(m, fp32);
-    int pi = pbeg(m, PK_PRECOND);
-    launch_precond(m->B, fp32, m->nA, ls, m->dinv, m->At, m->s);
-    pend(m, pi, m->nA);
-    launch_fill_f64(m->x64, (long)m->nA * m->B, 0.0, m->s);
-    pi = pbeg(m, PK_IR);
-    launch_ir_residual(m->B, fp32, m->nA, ls, kb, true, m->s);
-    pend(m, pi, m->nA);
-    if (m->prof.on)
-        HIPX(hipMemcpyAsync(&m->hint[4], &m->dint[4], sizeof(int), hipMemcpyDeviceToHost, m->s));
-    double rir2 = 0.0, bnorm2 = 0.0;
-    TRY(read_ir(m, &rir2, &bnorm2));
-    if (m->prof.on) m->cur_nnzb = m->hint[4];
-    const double fnorm2 = rir2;
-    const double target2 = m->o.lin_rtol * m->o.lin_rtol * fnorm2;
-    int total = 0, passes = 0;
-    m->last_fallback = 0;
-    for (int pass = 0; pass < m->o.max_refine; pass++) {
-        if (!(rir2 > target2) || !std::isfinite(rir2)) break;
-        passes++;
-        if (fp32) launch_copy_f64(m->xprev, m->x64, (long)m->nA * m->B, m->s);
-        // inner target: the reduction this pass needs, not below what the
-        // Krylov precision can deliver
-        const double need = 0.5 * std::sqrt(target2 / rir2);
-        const double floor_ = fp32 ? std::max(m->o.inner_rtol, 1e-6) : 1e-15;
-        const double inner = std::max(need, floor_);
-        int it = 0;
-        TRY(inner_solve(m, fp32, ls, kb, inner * inner * bnorm2, bnorm2, &it));
-        total += it;
-        launch_ir_accumulate(m->B, fp32, m->nA, kb, m->s);
-        pi = pbeg(m, PK_IR);
-        launch_ir_residual(m->B, fp32, m->nA, ls, kb, false, m->s);
-        pend(m, pi, m->nA);
-        double now = 0.0;
-        TRY(read_ir(m, &now, &bnorm2));
-        if (fp32 && !(now < 0.81 * rir2)) {
-            // undo the pass and continue in FP64
-            launch_copy_f64(m->x64, m->xprev, (long)m->nA * m->B, m->s);
-            fp32 = false;
-            kb = kbufs(m, false);
-            m->last_fallback = 1;
-            pi = pbeg(m, PK_PRECOND);
-            launch_precond(m->B, false, m->nA, ls, m->dinv, m->At, m->s);
-            pend(m, pi, m->nA);
-            pi = pbeg(m, PK_IR);
-            launch_ir_residual(m->B, false, m->nA, ls, kb, false, m->s);
-            pend(m, pi, m->nA);
-            TRY(read_ir(m, &now, &bnorm2));
-        }
-        rir2 = now;
-    }
-    m->last_kry = total;
-    m->last_refine = passes;
-    m->last_relres = fnorm2 > 0 ? std::sqrt(rir2 / fnorm2) : 0.0;
-    return FIM_OK;
+    if (!m->solo.cap) TRY(table_alloc(m, m->solo, 1));
+    std::vector<fim_model*> one{m};
+    return solve_batch(one, m->solo, m->s);
 }
 
 static bool converged(const fim_model* m, const NStat& ns) {
@@ -362,13 +535,16 @@ static bool converged(const fim_model* m, const NStat& ns) {
 }
 
 // Assembly + solve + update on the current active rows.
-static fim_status local_newton(fim_model* m, fim_iter_stats* it) {
-    const LocalSys ls = lsys(m);
-    int pi = pbeg(m, PK_ASSEMBLE);
-    launch_assemble(m->fk, m->nA, ls, m->g, m->f, m->u, m->st, m->Mn, 1.0 / m->step_dt, m->s);
+// Assembly of the current active rows (launch only).
+static void newton_assemble(fim_model* m) {
+    const int pi = pbeg(m, PK_ASSEMBLE);
+    launch_assemble(m->fk, m->nA, lsys(m), m->g, m->f, m->u, m->st, m->Mn, 1.0 / m->step_dt, m->s);
     pend(m, pi, m->nA);
-    TRY(linear_solve(m));
-    pi = pbeg(m, PK_UPDATE);
+}
+
+// Update after the solve (launch only) and the bookkeeping of the solve.
+static void newton_update(fim_model* m, fim_iter_stats* it) {
+    const int pi = pbeg(m, PK_UPDATE);
     launch_update(m->fk, m->nA, m->l2g, m->x64, m->u, m->st, m->n, m->f, m->o.ds_max,
                   m->dp_abs, m->part, m->ns, m->s);
     pend(m, pi, m->nA);
@@ -387,6 +563,13 @@ static fim_status local_newton(fim_model* m, fim_iter_stats* it) {
     m->sum_active += m->nA;
     m->max_active = std::max(m->max_active, m->nA);
     m->step_kry += m->last_kry;
+}
+
+// Assembly + solve + update on the current active rows.
+static fim_status local_newton(fim_model* m, fim_iter_stats* it) {
+    newton_assemble(m);
+    TRY(linear_solve(m));
+    newton_update(m, it);
     return FIM_OK;
 }
 
@@ -551,6 +734,7 @@ int32_t fim_num_cells(const fim_model* m) { return m ? m->n : 0; }
 int32_t fim_block_size(const fim_model* m) { return m ? m->B : 0; }
 
 static void free_all(fim_model* m) {
+    table_free(m->solo);
     for (const ProfRec& r : m->prof.pend) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -842,10 +1026,10 @@ fim_status fim_get_state(fim_model* m, double* u_out, int8_t* status_out, int me
     return FIM_OK;
 }
 
-static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
-    const bool local = m->step_mode == FIM_LOCAL;
-    TRY(local_newton(m, it));
-    if (local) {
+// After the update of an Algorithm 1 / full iteration: the set update and
+// compaction for the next iteration and the status copies (launch only).
+static fim_status newton_post_launch(fim_model* m) {
+    if (m->step_mode == FIM_LOCAL) {
         const int pi = pbeg(m, PK_SETS);
         launch_fill_i32(m->dint, 1, 0, m->s);
         launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, m->o.eps_loc, m->o.m_layers, m->g,
@@ -855,7 +1039,13 @@ static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
         pend(m, pi, m->n);
     }
     HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
-    TRY(read_int(m));
+    HIPX(hipMemcpyAsync(m->hint, m->dint, 4 * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    return FIM_OK;
+}
+
+// The decisions of the iteration, once the status copies have landed.
+static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it) {
+    const bool local = m->step_mode == FIM_LOCAL;
     const NStat ns = *m->hns;
     m->nu++;
     const bool conv = converged(m, ns);
@@ -900,6 +1090,14 @@ static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
         pend(m, pi, m->nA);
     }
     return FIM_OK;
+}
+
+static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
+    TRY(local_newton(m, it));
+    TRY(newton_post_launch(m));
+    HIPX(hipStreamSynchronize(m->s));
+    pflush(m);
+    return newton_post_finish(m, it);
 }
 
 // one inner iteration of Algorithm 2
@@ -1037,6 +1235,224 @@ fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats*
         todo.insert(todo.begin(), {{h * 0.5, depth + 1}, {h * 0.5, depth + 1}});
     }
     if (st) st->converged = 1;
+    return FIM_OK;
+}
+
+// ---------------------------------------------------------- footprint
+int64_t fim_model_bytes(const fim_model* m) { return m ? (int64_t)m->bytes : 0; }
+
+int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
+    if (!d || d->n_cells <= 0) return -1;
+    (void)o;
+    const size_t n = (size_t)d->n_cells;
+    const size_t B = (size_t)d->fluid.kind;
+    std::vector<int> deg(n, 0);
+    for (int c = 0; c < d->n_conn; c++) {
+        if (d->conn_i[c] < 0 || d->conn_j[c] >= d->n_cells) return -1;
+        deg[d->conn_i[c]]++;
+        deg[d->conn_j[c]]++;
+    }
+    int maxdeg = 0;
+    for (size_t i = 0; i < n; i++) maxdeg = std::max(maxdeg, deg[i]);
+    const size_t nsl = (n + SLICE - 1) / SLICE;
+    const size_t slots = (size_t)(maxdeg + 1) * SLICE * nsl;
+    const size_t nc2 = 2 * (size_t)d->n_conn;
+    size_t b = 0;
+    b += (n + 1) * 4 + nc2 * 12;                  // adjacency
+    b += n * (8 * 4 + 1);                         // pv, depth, wi, bhp, flags
+    b += n * B * 8 * 3 + n * 8 * 2 + n * 2;       // u, un, Mn, dp_abs, last_dp, status
+    b += n * 6;                                   // byte flags
+    b += n * 4 * 4 + (nsl + 1) * 8;               // l2g, g2l (2n each), swidth, sptr
+    b += slots * (4 + B * B * 8 + B * B * 8);     // col, J, A~ (sized for FP64)
+    b += n * B * (8 + B * 8);                     // F, dinv
+    b += n * B * 8 * 3 + n * B * 8 * 9;           // x64, xprev, rir, Krylov vectors
+    b += 4 * (n * B / NT + 2) * 8 + 8 * KB_MAXB * 8;
+    return (int64_t)b;
+}
+
+// ------------------------------------------------------------- batches
+struct fim_batch {
+    std::vector<fim_model*> ms;
+    std::vector<hipEvent_t> ev;   // one per member: stream hand-over
+    hipEvent_t done_ev = nullptr;
+    hipStream_t s = nullptr;
+    bool own_stream = false;
+    SolveTable tab;
+    int B = 0, precision = 0;
+    std::string err;
+};
+
+static thread_local std::string g_batch_err;
+
+static fim_status batch_check(fim_batch* b, fim_model* const* models, int32_t k, std::string& e) {
+    if (!models || k <= 0) { e = "empty batch"; return FIM_E_ARG; }
+    for (int q = 0; q < k; q++) {
+        if (!models[q]) { e = "null model in batch"; return FIM_E_ARG; }
+        for (int r = 0; r < q; r++)
+            if (models[r] == models[q]) { e = "model listed twice"; return FIM_E_ARG; }
+        if (models[q]->B != models[0]->B || models[q]->o.precision != models[0]->o.precision) {
+            e = "batch members need the same block size and Krylov precision";
+            return FIM_E_ARG;
+        }
+    }
+    (void)b;
+    return FIM_OK;
+}
+
+fim_status fim_batch_set(fim_batch* b, fim_model* const* models, int32_t k) {
+    if (!b) return FIM_E_ARG;
+    std::string e;
+    fim_status r = batch_check(b, models, k, e);
+    if (r != FIM_OK) { b->err = e; return r; }
+    fim_model* m = models[0];
+    if (k > b->tab.cap) {
+        table_free(b->tab);
+        TRY(table_alloc(m, b->tab, std::max(k, 2 * b->tab.cap)));
+    }
+    for (hipEvent_t e2 : b->ev) (void)hipEventDestroy(e2);
+    b->ev.assign(k, nullptr);
+    for (int q = 0; q < k; q++) HIPX(hipEventCreateWithFlags(&b->ev[q], hipEventDisableTiming));
+    b->ms.assign(models, models + k);
+    b->B = models[0]->B;
+    b->precision = models[0]->o.precision;
+    return FIM_OK;
+}
+
+fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_stream, fim_batch** out) {
+    if (!out) return FIM_E_ARG;
+    *out = nullptr;
+    std::string e;
+    fim_status r = batch_check(nullptr, models, k, e);
+    if (r != FIM_OK) { g_batch_err = e; return r; }
+    fim_batch* b = new fim_batch();
+    if (hip_stream) {
+        b->s = (hipStream_t)hip_stream;
+    } else if (hipStreamCreate(&b->s) != hipSuccess) {
+        g_batch_err = "hipStreamCreate failed";
+        delete b;
+        return FIM_E_HIP;
+    } else {
+        b->own_stream = true;
+    }
+    if (hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming) != hipSuccess) {
+        g_batch_err = "hipEventCreate failed";
+        if (b->own_stream) (void)hipStreamDestroy(b->s);
+        delete b;
+        return FIM_E_HIP;
+    }
+    r = fim_batch_set(b, models, k);
+    if (r != FIM_OK) {
+        g_batch_err = b->err.empty() ? models[0]->err : b->err;
+        table_free(b->tab);
+        (void)hipEventDestroy(b->done_ev);
+        if (b->own_stream) (void)hipStreamDestroy(b->s);
+        delete b;
+        return r;
+    }
+    *out = b;
+    return FIM_OK;
+}
+
+fim_status fim_batch_destroy(fim_batch* b) {
+    if (!b) return FIM_E_ARG;
+    (void)hipStreamSynchronize(b->s);
+    table_free(b->tab);
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    if (b->done_ev) (void)hipEventDestroy(b->done_ev);
+    if (b->own_stream) (void)hipStreamDestroy(b->s);
+    delete b;
+    return FIM_OK;
+}
+
+const char* fim_batch_last_error(const fim_batch* b) {
+    return b ? b->err.c_str() : g_batch_err.c_str();
+}
+
+// One Newton iteration of every member (Algorithm 1 or full Newton): the
+// per-member set, compaction and assembly launches, then one batched
+// Krylov solve over all members, then the per-member updates, and a single
+// synchronisation for the whole batch.
+fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t* modes,
+                                 fim_iter_stats* stats, int32_t* codes) {
+    if (!b || !dts || !modes || !codes) return FIM_E_ARG;
+    const int K = (int)b->ms.size();
+    for (int q = 0; q < K; q++) {
+        if (modes[q] != FIM_FULL && modes[q] != FIM_LOCAL) {
+            b->err = "batched steps run FIM_FULL or FIM_LOCAL";
+            return FIM_E_ARG;
+        }
+        if (!(dts[q] > 0.0) || !std::isfinite(dts[q])) {
+            b->err = "dt must be positive";
+            return FIM_E_ARG;
+        }
+    }
+    std::vector<hipStream_t> saved(K);
+    // hand the members over to the batch stream
+    for (int q = 0; q < K; q++) {
+        fim_model* m = b->ms[q];
+        saved[q] = m->s;
+        if (m->s != b->s) {
+            if (hipEventRecord(b->ev[q], m->s) != hipSuccess ||
+                hipStreamWaitEvent(b->s, b->ev[q], 0) != hipSuccess) {
+                b->err = "stream hand-over failed";
+                return FIM_E_HIP;
+            }
+        }
+        m->s = b->s;
+        if (stats) std::memset(&stats[q], 0, sizeof(fim_iter_stats));
+        codes[q] = FIM_OK;
+    }
+    auto restore = [&]() {
+        (void)hipEventRecord(b->done_ev, b->s);
+        for (int q = 0; q < K; q++) {
+            b->ms[q]->s = saved[q];
+            if (saved[q] != b->s) (void)hipStreamWaitEvent(saved[q], b->done_ev, 0);
+        }
+    };
+    std::vector<fim_model*> live;
+    std::vector<int> pos;
+    for (int q = 0; q < K; q++) {
+        fim_model* m = b->ms[q];
+        if (m->in_step && (dts[q] != m->step_dt || modes[q] != m->step_mode)) {
+            m->err = "dt or mode changed inside a timestep";
+            codes[q] = FIM_E_STATE;
+            continue;
+        }
+        if (!m->in_step) {
+            fim_status r = begin_step(m, dts[q], modes[q]);
+            if (r != FIM_OK) {
+                codes[q] = r;
+                continue;
+            }
+        }
+        newton_assemble(m);
+        live.push_back(m);
+        pos.push_back(q);
+    }
+    if (!live.empty()) {
+        fim_status r = solve_batch(live, b->tab, b->s);
+        if (r != FIM_OK) {
+            b->err = live[0]->err;
+            restore();
+            return r;
+        }
+        for (size_t t = 0; t < live.size(); t++) {
+            newton_update(live[t], stats ? &stats[pos[t]] : nullptr);
+            fim_status r2 = newton_post_launch(live[t]);
+            if (r2 != FIM_OK) codes[pos[t]] = r2;
+        }
+        if (hipStreamSynchronize(b->s) != hipSuccess) {
+            b->err = "hipStreamSynchronize failed";
+            restore();
+            return FIM_E_HIP;
+        }
+        for (size_t t = 0; t < live.size(); t++) {
+            pflush(live[t]);
+            if (codes[pos[t]] == FIM_OK)
+                codes[pos[t]] = newton_post_finish(live[t], stats ? &stats[pos[t]] : nullptr);
+        }
+    }
+    restore();
     return FIM_OK;
 }
 

@@ -134,18 +134,42 @@ struct KrylovBufs {
     const double* dinv; const void* At;
 };
 int krylov_grid(int nA);
+
+// One model's share of a (batched) Krylov launch.  A launch covers the
+// blocks of every participating model; block q belongs to model
+// blk_seg[q] and is that model's block q - blk0 of nblk.  A model sees the
+// same block partition, the same per-block partial sums and the same
+// reduction order alone and in a batch, so its results are identical.
+struct KSeg {
+    LocalSys ls;
+    KrylovBufs kb;
+    int nA;
+    int blk0, nblk;
+    int active;
+    double tol2;       // stop when |r|^2 <= tol2
+    double bnorm2;     // |b~|^2 of the refinement pass (breakdown scale)
+    int maxit;
+    int pad;
+};
+
 // r64 = -F - J x64, b~ = D^{-1} r64, Krylov initialisation; part_ir holds
 // (|r64|^2, |b~|^2) per block
-void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
-                        const KrylovBufs& kb, bool x_zero, hipStream_t s);
+void launch_ir_residual(int b, bool fp32, const KSeg* segs, const int* blk_seg, int nblk_total,
+                        bool x_zero, hipStream_t s);
 // which: 0 = v = A p (with the p update), 1 = s, t = A s, 2 = x, r update;
-// it = iteration index; tol2 = stop when |r|^2 <= tol2; bnorm2 = |b~|^2
+// it = iteration index (same for every model of the launch)
 // ev0/ev1: optional events stamped with the kernel's own start and end
-void launch_bicg_part(int which, int b, bool fp32, int nA, const LocalSys& ls,
-                      const KrylovBufs& kb, int it, double tol2, double bnorm2, int maxit,
-                      hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
-void launch_ir_accumulate(int b, bool fp32, int nA, const KrylovBufs& kb,
-                          hipStream_t s);
+void launch_bicg_part(int which, int b, bool fp32, const KSeg* segs, const int* blk_seg,
+                      int nblk_total, int it, hipStream_t s, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr);
+void launch_ir_accumulate(int b, bool fp32, const KSeg* segs, const int* blk_seg,
+                          int nblk_total, hipStream_t s);
+
+struct SegStatus {
+    double rir2, bnorm2;
+    int done, iters, breakdown, pad;
+};
+void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s);
 void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);
 
 // update (fim_update.hip)

@@ -29,6 +29,21 @@ struct Vecs {
     T* x; T* r; T* rh; T* p_old; T* v_old; T* p_new; T* v_new; T* s; T* t;
 };
 
+template <int B, typename T>
+__host__ __device__ inline Vecs<B, T> make_vecs(const KrylovBufs& kb, int parity) {
+    Vecs<B, T> V;
+    V.x = (T*)kb.x;
+    V.r = (T*)kb.r;
+    V.rh = (T*)kb.rh;
+    V.p_old = (T*)kb.p[parity];
+    V.v_old = (T*)kb.v[parity];
+    V.p_new = (T*)kb.p[parity ^ 1];
+    V.v_new = (T*)kb.v[parity ^ 1];
+    V.s = (T*)kb.sv;
+    V.t = (T*)kb.t;
+    return V;
+}
+
 // p_new = r + beta (p_old - omega v_old), rounded to T; used for the own
 // row and for every neighbour so both see the same value
 template <typename T>
@@ -154,14 +169,20 @@ static inline int kgrid(long rows) {
 // r = rh = b~.  Partials: ir[q] = (|r64|^2, |b~|^2); pc[q] = ((rh,r), (r,r))
 // so that the first BiCGStab kernel finds rho_0 where it looks for rho.
 template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_ir_residual(int nA, LocalSys ls, KrylovBufs kb,
+__global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ segs,
+                                                       const int* __restrict__ blk_seg,
                                                        int x_zero) {
+    const KSeg& S = segs[blk_seg[blockIdx.x]];
+    if (!S.active) return;
+    const int lb = blockIdx.x - S.blk0, nbk = S.nblk, nA = S.nA;
+    const LocalSys& ls = S.ls;
+    const KrylovBufs& kb = S.kb;
     constexpr int BB = B * B;
     T* xT = (T*)kb.x;
     T* rr = (T*)kb.r;
     T* rh = (T*)kb.rh;
     double part[2] = {0.0, 0.0};
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < nA; r += gridDim.x * blockDim.x) {
+    for (int r = lb * blockDim.x + threadIdx.x; r < nA; r += nbk * blockDim.x) {
         double res[B];
 #pragma unroll
         for (int c = 0; c < B; c++) res[c] = -ls.F[(long)r * B + c];
@@ -199,12 +220,12 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(int nA, LocalSys ls, Kryl
     }
     block_sum<2>(part);
     if (threadIdx.x == 0) {
-        kb.part_ir[2 * blockIdx.x] = part[0];
-        kb.part_ir[2 * blockIdx.x + 1] = part[1];
-        kb.part_c[2 * blockIdx.x] = part[1];
-        kb.part_c[2 * blockIdx.x + 1] = part[1];
+        kb.part_ir[2 * lb] = part[0];
+        kb.part_ir[2 * lb + 1] = part[1];
+        kb.part_c[2 * lb] = part[1];
+        kb.part_c[2 * lb + 1] = part[1];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
         kb.sc->done = 0;
         kb.sc->iters = 0;
         kb.sc->breakdown = 0;
@@ -215,29 +236,37 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(int nA, LocalSys ls, Kryl
 // start: rho_i = (rh, r), |r|^2 from the previous kernel C (or the
 // initialisation); stop if converged or at the iteration cap.
 template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_bicg_a(int nA, LocalSys ls, const T* __restrict__ At,
-                                                  Vecs<B, T> V, KScal* __restrict__ sc,
-                                                  const double* __restrict__ pc,
-                                                  double* __restrict__ pa, int it,
-                                                  double tol2, int maxit) {
+__global__ __launch_bounds__(KB_NT) void k_bicg_a(const KSeg* __restrict__ segs,
+                                                  const int* __restrict__ blk_seg, int it) {
+    const KSeg& S = segs[blk_seg[blockIdx.x]];
+    if (!S.active) return;
+    const int lb = blockIdx.x - S.blk0, nbk = S.nblk, nA = S.nA;
+    const LocalSys& ls = S.ls;
+    const T* __restrict__ At = (const T*)S.kb.At;
+    const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
+    KScal* __restrict__ sc = S.kb.sc;
+    const double* __restrict__ pc = S.kb.part_c;
+    double* __restrict__ pa = S.kb.part_a;
+    const double tol2 = S.tol2;
+    const int maxit = S.maxit;
     const int done = sc->done;
     const double rho_prev = it > 0 ? sc->rho_hist[(it - 1) & 1] : 1.0;
     const double al_prev = sc->alpha, om_prev = sc->omega;
     double red[2] = {0.0, 0.0};
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
+    for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
         red[0] += pc[2 * q];
         red[1] += pc[2 * q + 1];
     }
     if (done) return;
     const T* const src[3] = {V.r, V.p_old, V.v_old};
-    const int r0 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int stride = gridDim.x * blockDim.x;
+    const int r0 = lb * blockDim.x + threadIdx.x;
+    const int stride = nbk * blockDim.x;
     RowRaw<B, T, 3> R;
     if (r0 < nA) fetch_row<B, T, 3>(ls, At, r0, src, R);
     block_sum<2>(red);
     const double rho = red[0], rr = red[1];
     const bool stop = rr <= tol2 || it >= maxit || !isfinite(rr) || (it > 0 && rho == 0.0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
         sc->rho_hist[it & 1] = rho;
         sc->rr = rr;
         if (stop) {
@@ -274,8 +303,8 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_a(int nA, LocalSys ls, const T* 
     }
     block_sum<2>(dot);
     if (threadIdx.x == 0) {
-        pa[2 * blockIdx.x] = dot[0];
-        pa[2 * blockIdx.x + 1] = dot[1];
+        pa[2 * lb] = dot[0];
+        pa[2 * lb + 1] = dot[1];
     }
 }
 
@@ -283,29 +312,37 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_a(int nA, LocalSys ls, const T* 
 // start: sigma = (rh, v); alpha = rho / sigma; a sigma lost against
 // |rh| |v| is a breakdown (stop with the current x).
 template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_bicg_b(int nA, LocalSys ls, const T* __restrict__ At,
-                                                  Vecs<B, T> V, KScal* __restrict__ sc,
-                                                  const double* __restrict__ pa,
-                                                  double* __restrict__ pb, int it, double brk2,
-                                                  double bnorm2) {
+__global__ __launch_bounds__(KB_NT) void k_bicg_b(const KSeg* __restrict__ segs,
+                                                  const int* __restrict__ blk_seg, int it) {
+    const KSeg& S = segs[blk_seg[blockIdx.x]];
+    if (!S.active) return;
+    const int lb = blockIdx.x - S.blk0, nbk = S.nblk, nA = S.nA;
+    const LocalSys& ls = S.ls;
+    const T* __restrict__ At = (const T*)S.kb.At;
+    const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
+    KScal* __restrict__ sc = S.kb.sc;
+    const double* __restrict__ pa = S.kb.part_a;
+    double* __restrict__ pb = S.kb.part_b;
+    const double brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
+    const double brk2 = brk * brk, bnorm2 = S.bnorm2;
     const int done = sc->done;
     const double rho = sc->rho_hist[it & 1];
     double red[2] = {0.0, 0.0};
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
+    for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
         red[0] += pa[2 * q];
         red[1] += pa[2 * q + 1];
     }
     if (done) return;
     const T* const src[2] = {V.r, V.v_new};
-    const int r0 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int stride = gridDim.x * blockDim.x;
+    const int r0 = lb * blockDim.x + threadIdx.x;
+    const int stride = nbk * blockDim.x;
     RowRaw<B, T, 2> R;
     if (r0 < nA) fetch_row<B, T, 2>(ls, At, r0, src, R);
     block_sum<2>(red);
     const double sigma = red[0], vv = red[1];
     const double al = rho / sigma;
     const bool bad = !(sigma * sigma > brk2 * bnorm2 * vv) || !isfinite(al);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
         if (bad) {
             sc->done = 1;
             sc->iters = it;
@@ -339,26 +376,32 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_b(int nA, LocalSys ls, const T* 
     }
     block_sum<2>(dot);
     if (threadIdx.x == 0) {
-        pb[2 * blockIdx.x] = dot[0];
-        pb[2 * blockIdx.x + 1] = dot[1];
+        pb[2 * lb] = dot[0];
+        pb[2 * lb + 1] = dot[1];
     }
 }
 
 // ----------------------- kernel C: x += alpha p + omega s, r = s - omega t
 template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_bicg_c(int nA, Vecs<B, T> V, KScal* __restrict__ sc,
-                                                  const double* __restrict__ pb,
-                                                  double* __restrict__ pc, int it) {
+__global__ __launch_bounds__(KB_NT) void k_bicg_c(const KSeg* __restrict__ segs,
+                                                  const int* __restrict__ blk_seg, int it) {
+    const KSeg& S = segs[blk_seg[blockIdx.x]];
+    if (!S.active) return;
+    const int lb = blockIdx.x - S.blk0, nbk = S.nblk, nA = S.nA;
+    const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
+    KScal* __restrict__ sc = S.kb.sc;
+    const double* __restrict__ pb = S.kb.part_b;
+    double* __restrict__ pc = S.kb.part_c;
     const int done = sc->done;
     const double al = sc->alpha;
     double red[2] = {0.0, 0.0};
-    for (int q = threadIdx.x; q < (int)gridDim.x; q += blockDim.x) {
+    for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
         red[0] += pb[2 * q];
         red[1] += pb[2 * q + 1];
     }
     if (done) return;
-    const int r0 = blockIdx.x * blockDim.x + threadIdx.x;
-    const int stride = gridDim.x * blockDim.x;
+    const int r0 = lb * blockDim.x + threadIdx.x;
+    const int stride = nbk * blockDim.x;
     // prefetch the first row while the partial sums are combined
     T s0[B], t0[B], p0[B], x0[B], h0[B];
     if (r0 < nA) {
@@ -373,7 +416,7 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_c(int nA, Vecs<B, T> V, KScal* _
     // A stops on rho = 0 or converges
     const double om = (red[1] > 0.0) ? red[0] / red[1] : 0.0;
     const bool bad = !isfinite(om);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (lb == 0 && threadIdx.x == 0) {
         sc->omega = om;
         sc->iters = it + 1;
         if (bad) {
@@ -404,16 +447,21 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_c(int nA, Vecs<B, T> V, KScal* _
     }
     block_sum<2>(dot);
     if (threadIdx.x == 0) {
-        pc[2 * blockIdx.x] = dot[0];
-        pc[2 * blockIdx.x + 1] = dot[1];
+        pc[2 * lb] = dot[0];
+        pc[2 * lb + 1] = dot[1];
     }
 }
 
 template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_ir_accumulate(int nA, double* __restrict__ x64,
-                                                         const T* __restrict__ xT) {
-    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < (long)nA * B;
-         q += (long)gridDim.x * blockDim.x)
+__global__ __launch_bounds__(KB_NT) void k_ir_accumulate(const KSeg* __restrict__ segs,
+                                                         const int* __restrict__ blk_seg) {
+    const KSeg& S = segs[blk_seg[blockIdx.x]];
+    if (!S.active) return;
+    const int lb = blockIdx.x - S.blk0, nbk = S.nblk;
+    double* __restrict__ x64 = S.kb.x64;
+    const T* __restrict__ xT = (const T*)S.kb.x;
+    for (long q = (long)lb * blockDim.x + threadIdx.x; q < (long)S.nA * B;
+         q += (long)nbk * blockDim.x)
         x64[q] += (double)xT[q];
 }
 
@@ -427,79 +475,81 @@ void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- launches
-template <int B, typename T>
-static Vecs<B, T> make_vecs(const KrylovBufs& kb, int parity) {
-    Vecs<B, T> V;
-    V.x = (T*)kb.x;
-    V.r = (T*)kb.r;
-    V.rh = (T*)kb.rh;
-    V.p_old = (T*)kb.p[parity];
-    V.v_old = (T*)kb.v[parity];
-    V.p_new = (T*)kb.p[parity ^ 1];
-    V.v_new = (T*)kb.v[parity ^ 1];
-    V.s = (T*)kb.sv;
-    V.t = (T*)kb.t;
-    return V;
-}
 
 // ev0/ev1 (optional): events stamped by the dispatch itself
 // (hipExtLaunchKernelGGL), i.e. the kernel's own start and end
 template <int B, typename T>
-static void part_impl(int which, int nA, const LocalSys& ls, const KrylovBufs& kb, int it,
-                      double tol2, double bnorm2, int maxit, hipStream_t s, hipEvent_t ev0,
-                      hipEvent_t ev1) {
-    const dim3 nb(kgrid(nA)), nt(KB_NT);
-    Vecs<B, T> V = make_vecs<B, T>(kb, it & 1);
-    const double brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
-    const T* At = (const T*)kb.At;
+static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const dim3 nb(nblk_total), nt(KB_NT);
     if (which == 0)
-        hipExtLaunchKernelGGL(k_bicg_a<B, T>, nb, nt, 0, s, ev0, ev1, 0, nA, ls, At, V, kb.sc,
-                              (const double*)kb.part_c, kb.part_a, it, tol2, maxit);
+        hipExtLaunchKernelGGL(k_bicg_a<B, T>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
     else if (which == 1)
-        hipExtLaunchKernelGGL(k_bicg_b<B, T>, nb, nt, 0, s, ev0, ev1, 0, nA, ls, At, V, kb.sc,
-                              (const double*)kb.part_a, kb.part_b, it, brk * brk, bnorm2);
+        hipExtLaunchKernelGGL(k_bicg_b<B, T>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
     else
-        hipExtLaunchKernelGGL(k_bicg_c<B, T>, nb, nt, 0, s, ev0, ev1, 0, nA, V, kb.sc,
-                              (const double*)kb.part_b, kb.part_c, it);
+        hipExtLaunchKernelGGL(k_bicg_c<B, T>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
 }
 
 int krylov_grid(int nA) { return kgrid(nA); }
 
-void launch_ir_residual(int b, bool fp32, int nA, const LocalSys& ls,
-                        const KrylovBufs& kb, bool x_zero, hipStream_t s) {
-    const int nb = kgrid(nA);
-#define IR(BV, TT) k_ir_residual<BV, TT><<<nb, KB_NT, 0, s>>>(nA, ls, kb, x_zero ? 1 : 0)
-    if (fp32) {
-        if (b == 1) IR(1, float); else if (b == 2) IR(2, float); else IR(3, float);
-    } else {
-        if (b == 1) IR(1, double); else if (b == 2) IR(2, double); else IR(3, double);
+// One wave per model: Krylov status and the fixed-order sums of the
+// refinement partials (|r64|^2, |b~|^2) of that model.
+__global__ __launch_bounds__(64) void k_seg_status(const KSeg* __restrict__ segs, int nseg,
+                                                   SegStatus* __restrict__ out) {
+    const int k = blockIdx.x;
+    if (k >= nseg) return;
+    const KSeg& S = segs[k];
+    double a = 0.0, b = 0.0;
+    for (int q = threadIdx.x; q < S.nblk; q += 64) {
+        a += S.kb.part_ir[2 * q];
+        b += S.kb.part_ir[2 * q + 1];
     }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (threadIdx.x == 0) {
+        SegStatus o;
+        o.rir2 = a;
+        o.bnorm2 = b;
+        o.done = S.kb.sc->done;
+        o.iters = S.kb.sc->iters;
+        o.breakdown = S.kb.sc->breakdown;
+        o.pad = 0;
+        out[k] = o;
+    }
+}
+
+void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s) {
+    if (nseg > 0) k_seg_status<<<nseg, 64, 0, s>>>(segs, nseg, out);
+}
+
+#define KDISPATCH(MACRO)                                                        \
+    if (fp32) {                                                                 \
+        if (b == 1) MACRO(1, float); else if (b == 2) MACRO(2, float); else MACRO(3, float);      \
+    } else {                                                                    \
+        if (b == 1) MACRO(1, double); else if (b == 2) MACRO(2, double); else MACRO(3, double);   \
+    }
+
+void launch_ir_residual(int b, bool fp32, const KSeg* segs, const int* blk_seg, int nblk_total,
+                        bool x_zero, hipStream_t s) {
+    if (nblk_total <= 0) return;
+#define IR(BV, TT) k_ir_residual<BV, TT><<<nblk_total, KB_NT, 0, s>>>(segs, blk_seg, x_zero ? 1 : 0)
+    KDISPATCH(IR)
 #undef IR
 }
 
-void launch_bicg_part(int which, int b, bool fp32, int nA, const LocalSys& ls,
-                      const KrylovBufs& kb, int it, double tol2, double bnorm2, int maxit,
-                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (nA <= 0) return;
-#define PI(BV, TT) part_impl<BV, TT>(which, nA, ls, kb, it, tol2, bnorm2, maxit, s, ev0, ev1)
-    if (fp32) {
-        if (b == 1) PI(1, float); else if (b == 2) PI(2, float); else PI(3, float);
-    } else {
-        if (b == 1) PI(1, double); else if (b == 2) PI(2, double); else PI(3, double);
-    }
+void launch_bicg_part(int which, int b, bool fp32, const KSeg* segs, const int* blk_seg,
+                      int nblk_total, int it, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (nblk_total <= 0) return;
+#define PI(BV, TT) part_impl<BV, TT>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1)
+    KDISPATCH(PI)
 #undef PI
 }
 
-void launch_ir_accumulate(int b, bool fp32, int nA, const KrylovBufs& kb,
-                          hipStream_t s) {
-    if (nA <= 0) return;
-    const int nb = kgrid((long)nA * b);
-#define AC(BV, TT) k_ir_accumulate<BV, TT><<<nb, KB_NT, 0, s>>>(nA, kb.x64, (const TT*)kb.x)
-    if (fp32) {
-        if (b == 1) AC(1, float); else if (b == 2) AC(2, float); else AC(3, float);
-    } else {
-        if (b == 1) AC(1, double); else if (b == 2) AC(2, double); else AC(3, double);
-    }
+void launch_ir_accumulate(int b, bool fp32, const KSeg* segs, const int* blk_seg,
+                          int nblk_total, hipStream_t s) {
+    if (nblk_total <= 0) return;
+#define AC(BV, TT) k_ir_accumulate<BV, TT><<<nblk_total, KB_NT, 0, s>>>(segs, blk_seg)
+    KDISPATCH(AC)
 #undef AC
 }
 

@@ -119,6 +119,13 @@ def _load():
         "fim_inspect_sets": (i32, [vp, vp, vp, f64, i32, vp, vp, vp, vp, vp]),
         "fim_inspect_solve": (i32, [vp, vp, vp, vp]),
         "fim_profile_enable": (i32, [vp, i32]),
+        "fim_batch_create": (i32, [vp, i32, vp, vp]),
+        "fim_model_bytes": (C.c_int64, [vp]),
+        "fim_estimate_bytes": (C.c_int64, [vp, vp]),
+        "fim_batch_set": (i32, [vp, vp, i32]),
+        "fim_batch_newton_step": (i32, [vp, vp, vp, vp, vp]),
+        "fim_batch_destroy": (i32, [vp]),
+        "fim_batch_last_error": (C.c_char_p, [vp]),
         "fim_flags_enable": (i32, [vp, i32]),
         "fim_get_flags": (i32, [vp, vp]),
         "fim_profile_read": (i32, [vp, vp, i32]),
@@ -200,28 +207,41 @@ def _stream_handle(stream):
     return None
 
 
+def _describe(model):
+    """fim_model_desc for a model object (and the arrays it points to)."""
+    fl = model.fluid
+    f = _Fluid()
+    f.kind = int(fl["kind"])
+    for name, _ in _Fluid._fields_[1:]:
+        if name in fl:
+            setattr(f, name, float(fl[name]))
+    keep = [_f64(model.pv_ref), _f64(model.depth),
+            np.ascontiguousarray(model.always_active, dtype=np.uint8),
+            _i32(model.conn_i), _i32(model.conn_j), _f64(model.conn_T),
+            _i32(model.perf_cell), _f64(model.perf_wi), _f64(model.perf_bhp)]
+    k = keep
+    d = _Desc(n_cells=int(model.n), n_conn=int(k[3].size), n_perf=int(k[6].size),
+              pv_ref=_ptr(k[0]), depth=_ptr(k[1]), always_active=_ptr(k[2]),
+              conn_i=_ptr(k[3]), conn_j=_ptr(k[4]), conn_T=_ptr(k[5]),
+              perf_cell=_ptr(k[6]), perf_wi=_ptr(k[7]), perf_bhp=_ptr(k[8]),
+              c_r=float(model.rock["c_r"]), p_ref_rock=float(model.rock["p_ref"]),
+              gravity=float(model.gravity), fluid=f)
+    return d, keep
+
+
+def estimate_bytes(model, options: "Options | None" = None) -> int:
+    """Device bytes FimModel(model) would allocate (no allocation)."""
+    d, keep = _describe(model)
+    o = (options or Options())._c()
+    return int(_lib.fim_estimate_bytes(C.byref(d), C.byref(o)))
+
+
 class FimModel:
     """One reservoir model resident on the GPU."""
 
     def __init__(self, model, options: Options | None = None, stream=None):
         self.options = options or Options()
-        fl = model.fluid
-        f = _Fluid()
-        f.kind = int(fl["kind"])
-        for name, _ in _Fluid._fields_[1:]:
-            if name in fl:
-                setattr(f, name, float(fl[name]))
-        self._keep = [_f64(model.pv_ref), _f64(model.depth),
-                      np.ascontiguousarray(model.always_active, dtype=np.uint8),
-                      _i32(model.conn_i), _i32(model.conn_j), _f64(model.conn_T),
-                      _i32(model.perf_cell), _f64(model.perf_wi), _f64(model.perf_bhp)]
-        k = self._keep
-        d = _Desc(n_cells=int(model.n), n_conn=int(k[3].size), n_perf=int(k[6].size),
-                  pv_ref=_ptr(k[0]), depth=_ptr(k[1]), always_active=_ptr(k[2]),
-                  conn_i=_ptr(k[3]), conn_j=_ptr(k[4]), conn_T=_ptr(k[5]),
-                  perf_cell=_ptr(k[6]), perf_wi=_ptr(k[7]), perf_bhp=_ptr(k[8]),
-                  c_r=float(model.rock["c_r"]), p_ref_rock=float(model.rock["p_ref"]),
-                  gravity=float(model.gravity), fluid=f)
+        d, self._keep = _describe(model)
         opts = self.options._c()
         h = C.c_void_p()
         code = _lib.fim_create_model(C.byref(d), C.byref(opts), _stream_handle(stream),
@@ -284,6 +304,9 @@ class FimModel:
     def run(self, schedule, mode=LOCAL):
         """Advance through a schedule; returns the per-step statistics."""
         return [self.solve_timestep(dt, mode).as_dict() for dt in schedule]
+
+    def device_bytes(self):
+        return int(_lib.fim_model_bytes(self._h))
 
     # ---------------------------------------------------------- cell classes
     def record_flags(self, on=True):
@@ -348,6 +371,57 @@ class FimModel:
                self._h)
         return dict(act=ao, bnd=bo, l2g=l2g[:na.value].copy(), n_active=na.value,
                     is_expand=bool(ex.value))
+
+
+class FimBatch:
+    """Several models advanced together: one Newton iteration of every
+    member per call, with one batched Krylov solve over all of them.  A
+    member's result is the same alone and in any batch."""
+
+    def __init__(self, models, stream=None):
+        self._h = None
+        self._models = list(models)
+        arr = (C.c_void_p * len(self._models))(*[m._h.value for m in self._models])
+        h = C.c_void_p()
+        code = _lib.fim_batch_create(arr, len(self._models), _stream_handle(stream), C.byref(h))
+        if code != FIM_OK:
+            raise FimError(code, "fim_batch_create: " + _lib.fim_batch_last_error(None).decode())
+        self._h = h
+
+    @property
+    def models(self):
+        return list(self._models)
+
+    def set_models(self, models):
+        """Replace the membership (between calls)."""
+        self._models = list(models)
+        arr = (C.c_void_p * len(self._models))(*[m._h.value for m in self._models])
+        code = _lib.fim_batch_set(self._h, arr, len(self._models))
+        if code != FIM_OK:
+            raise FimError(code, _lib.fim_batch_last_error(self._h).decode())
+
+    def newton_step(self, dts, modes):
+        """One Newton iteration of every member; returns (stats, codes)."""
+        k = len(self._models)
+        d = np.ascontiguousarray(dts, dtype=np.float64).reshape(k)
+        mo = np.ascontiguousarray(modes, dtype=np.int32).reshape(k)
+        st = (IterStats * k)()
+        codes = np.zeros(k, np.int32)
+        code = _lib.fim_batch_newton_step(self._h, _ptr(d), _ptr(mo), st, _ptr(codes))
+        if code != FIM_OK:
+            raise FimError(code, _lib.fim_batch_last_error(self._h).decode())
+        return [st[i].as_dict() for i in range(k)], codes
+
+    def close(self):
+        if self._h:
+            _lib.fim_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def exported_symbols():

@@ -1,0 +1,108 @@
+"""Batched Newton iterations over several models and the serving loop on
+the GPU: every member's result equals its result alone (bitwise, since
+each member keeps its own block partition and reduction order)."""
+import numpy as np
+import pytest
+
+from fimgen import make_c1, make_c1_variant, make_small_c2
+
+pytestmark = pytest.mark.gpu
+
+
+def _solo(model, opts, mode, dts):
+    import paper_2008_01539_amd as P
+    fm = P.FimModel(model, opts)
+    fm.set_state(model.u0, model.status0)
+    for dt in dts:
+        fm.solve_timestep(dt, mode)
+    u, st = fm.get_state()
+    fm.close()
+    return u, st
+
+
+def _batched(models, opts, mode, nsteps):
+    """Continuous batching: members leave the batch when they finished
+    their steps; each member advances through its own schedule."""
+    import paper_2008_01539_amd as P
+    fms = []
+    for m in models:
+        fm = P.FimModel(m, opts)
+        fm.set_state(m.u0, m.status0)
+        fms.append(fm)
+    step = [0] * len(models)
+    live = list(range(len(models)))
+    bat = P.FimBatch([fms[i] for i in live])
+    sizes = []
+    while live:
+        dts = [models[i].schedule[step[i]] for i in live]
+        stats, codes = bat.newton_step(dts, [mode] * len(live))
+        assert np.all(codes == 0)
+        sizes.append(len(live))
+        nxt = []
+        for i, st in zip(live, stats):
+            if st["converged"]:
+                step[i] += 1
+            if step[i] < nsteps:
+                nxt.append(i)
+        if nxt != live and nxt:
+            bat.set_models([fms[i] for i in nxt])
+        live = nxt
+    out = [fm.get_state() for fm in fms]
+    bat.close()
+    for fm in fms:
+        fm.close()
+    return out, sizes
+
+
+@pytest.mark.parametrize("prec", ["FP64", "MIXED"])
+def test_batch_equals_solo_single_phase(prec):
+    import paper_2008_01539_amd as P
+    models = [make_c1(), make_c1_variant(), make_c1(seed=9, nx=40, ny=30, frac_rows=(5, 25))]
+    opts = P.Options(precision=getattr(P, prec))
+    n = 6
+    got, sizes = _batched(models, opts, P.LOCAL, n)
+    for m, (u, st) in zip(models, got):
+        ref, _ = _solo(m, opts, P.LOCAL, m.schedule[:n])
+        assert np.array_equal(u, ref)
+    assert max(sizes) == 3
+
+
+def test_batch_equals_solo_two_phase_mixed():
+    import paper_2008_01539_amd as P
+    models = [make_small_c2(), make_small_c2(seed=23, nx=30, ny=14, nfrac=20),
+              make_small_c2(seed=24, nx=16, ny=10, nz=3, nfrac=6, nstage=2)]
+    opts = P.Options(precision=P.MIXED)
+    n = 5
+    for mode in (P.LOCAL, P.FULL):
+        got, _ = _batched(models, opts, mode, n)
+        for m, (u, st) in zip(models, got):
+            ref, _ = _solo(m, opts, mode, m.schedule[:n])
+            assert np.array_equal(u, ref)
+
+
+def test_serving_results_same_alone_and_in_the_mix():
+    """Poisson requests over sessions of two block sizes, batched
+    continuously; each session's state after its requests equals the same
+    steps run alone."""
+    import paper_2008_01539_amd as P
+    from paper_2008_01539_amd.serve import GpuExecutor, Server, SessionSpec
+    specs = []
+    for k, m in enumerate([make_c1(), make_c1_variant(), make_small_c2(),
+                           make_small_c2(seed=23, nx=30, ny=14, nfrac=20)]):
+        specs.append(SessionSpec(name=f"s{k}", model=m, options=P.Options(precision=P.MIXED),
+                                 schedule=m.schedule))
+    ex = GpuExecutor()
+    srv = Server(specs, ex, budget_bytes=8 << 30, max_inflight=16,
+                 footprint=lambda s: P.estimate_bytes(s.model, s.options))
+    summ = srv.run_poisson(rate=40.0, duration=1.5, mix=np.array([0.3, 0.3, 0.2, 0.2]), seed=5)
+    assert summ["completed"] == len(srv.done) and summ["failed"] == 0
+    assert max(srv.stats.latencies) > 0
+    for s in srv.sessions:
+        if s.next_step == 0:
+            continue
+        u, _ = s.handle.get_state()
+        sched = s.spec.schedule
+        dts = [sched[k % len(sched)] for k in range(s.next_step)]
+        ref, _ = _solo(s.spec.model, s.spec.options, s.spec.mode, dts)
+        assert np.array_equal(u, ref), s.spec.name
+    ex.close()
