@@ -39,10 +39,11 @@ def algorithmic_bytes(kernel, rec, b, kbytes):
     rec: profile record with rows and nnzb (blocks incl. diagonal)."""
     rows, nnzb = rec["rows"], rec["nnzb"]
     off = max(nnzb - rows, 0.0)
-    if kernel == "bicg_spmv_p":   # col + block per off-diagonal; r,p,v,rh read; p,v written
-        return off * (4 + kbytes * b * b) + rows * (6 * b * kbytes)
-    if kernel == "bicg_spmv_s":   # col + block; r, v read; s, t written
-        return off * (4 + kbytes * b * b) + rows * (4 * b * kbytes)
+    if kernel == "bicg_spmv_p":
+        # col + block per off-diagonal; s, t, p, v, x, rh read; x, r, p, v written
+        return off * (4 + kbytes * b * b) + rows * (10 * b * kbytes)
+    if kernel == "bicg_spmv_s":   # col + block; r, v, rh read; s, t written
+        return off * (4 + kbytes * b * b) + rows * (5 * b * kbytes)
     if kernel == "assemble":
         # per row: l2g 4, state 8b, status 1, pv 8, depth 8, flags 1, old
         # masses 8b, adjacency pointers 8, residual 8b written; per

@@ -93,7 +93,8 @@ typedef struct fim_model_desc {
 
 /* Solver options.  fim_default_options fills the paper's settings
  * (Section 5: eps_p = 0.3 psi cutoff and convergence, m = 2 for
- * Algorithm 1, m = 4 for Algorithm 2). */
+ * Algorithm 1, m = 4 for Algorithm 2) and a linear tolerance of 1e-4
+ * (inexact Newton; the paper does not state one). */
 typedef struct fim_options {
     double  eps_conv;        /* Newton convergence: ||dp||_inf < eps_conv (Pa) */
     double  eps_loc;         /* active/boundary cutoff |dp_i| >= eps_loc (Pa)  */

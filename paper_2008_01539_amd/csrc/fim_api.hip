@@ -19,11 +19,11 @@ using namespace fimk;
 
 // Optional event profiler: hipEvent pairs on the model's stream around each
 // kernel (or kernel group), read back at the next synchronisation.
-enum { PK_ASSEMBLE, PK_PRECOND, PK_IR, PK_BICG_A, PK_BICG_B, PK_BICG_C, PK_UPDATE,
-       PK_SETS, PK_SETUP, PK_N };
-static const char* const kPkName[PK_N] = {"assemble", "precond", "ir_residual",
-                                          "bicg_spmv_p", "bicg_spmv_s", "bicg_update",
-                                          "update", "sets_compact", "step_setup"};
+enum { PK_ASSEMBLE, PK_PRECOND, PK_IR, PK_BICG_A, PK_BICG_B, PK_UPDATE, PK_SETS, PK_SETUP,
+       PK_N };
+static const char* const kPkName[PK_N] = {"assemble", "precond", "ir_residual", "bicg_spmv_p",
+                                          "bicg_spmv_s", "update", "sets_compact",
+                                          "step_setup"};
 struct ProfRec {
     int k;
     hipEvent_t a, b;
@@ -47,8 +47,9 @@ struct Prof {
 struct SolveTable {
     KSeg* dsegs = nullptr;
     int* dblk = nullptr;
-    SegStatus* dstat = nullptr;
+    SegStatus* dstat = nullptr;   // [6][cap]: refinement status, then 2 x 2 Krylov slots
     SegStatus* hstat = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
     int cap = 0;
 };
 
@@ -77,7 +78,7 @@ struct fim_model {
     long slot_cap = 0;
     // Krylov
     double *x64 = nullptr, *xprev = nullptr, *rir = nullptr, *part = nullptr;
-    double* part_ir = nullptr;   // 4 x 2 x KB_MAXB Krylov partials
+    double* part_ir = nullptr;   // Krylov partials: 14 x KB_MAXB
     double* hpart = nullptr;     // pinned copy of the refinement partials
     void* kvec = nullptr;   // 9 vectors of nA b elements in the Krylov precision
     KScal* sc = nullptr;
@@ -227,10 +228,10 @@ static KrylovBufs kbufs(fim_model* m, bool fp32) {
     kb.x64 = m->x64;
     kb.rir = m->rir;
     kb.sc = m->sc;
-    kb.part_ir = m->part_ir;
-    kb.part_a = m->part_ir + 2 * KB_MAXB;
-    kb.part_b = m->part_ir + 4 * KB_MAXB;
-    kb.part_c = m->part_ir + 6 * KB_MAXB;
+    kb.part_ir = m->part_ir;                 // 2 per block
+    kb.part_a = m->part_ir + 2 * KB_MAXB;    // 4 per block
+    kb.part_b = m->part_ir + 6 * KB_MAXB;
+    kb.part_c = m->part_ir + 10 * KB_MAXB;
     kb.dinv = m->dinv;
     kb.At = m->At;
     return kb;
@@ -264,6 +265,8 @@ static fim_status structure(fim_model* m) {
 }
 
 static void table_free(SolveTable& t) {
+    for (hipEvent_t& e : t.ev)
+        if (e) (void)hipEventDestroy(e);
     if (t.dsegs) (void)hipFree(t.dsegs);
     if (t.dblk) (void)hipFree(t.dblk);
     if (t.dstat) (void)hipFree(t.dstat);
@@ -275,11 +278,12 @@ static fim_status table_alloc(fim_model* m, SolveTable& t, int cap) {
     t.cap = cap;
     TRY(dal(m, &t.dsegs, (size_t)2 * cap));
     TRY(dal(m, &t.dblk, (size_t)2 * cap * KB_MAXB));
-    TRY(dal(m, &t.dstat, (size_t)2 * cap));
-    if (hipHostMalloc((void**)&t.hstat, 2 * cap * sizeof(SegStatus)) != hipSuccess) {
+    TRY(dal(m, &t.dstat, (size_t)6 * cap));
+    if (hipHostMalloc((void**)&t.hstat, 6 * cap * sizeof(SegStatus)) != hipSuccess) {
         m->err = "hipHostMalloc failed";
         return FIM_E_NOMEM;
     }
+    for (hipEvent_t& e : t.ev) HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return FIM_OK;
 }
 
@@ -417,36 +421,81 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         }
         if (!nact) break;
         for (int g = 0; g < 2; g++) TRY(upload_group(lead, t, g, G[g], items, s));
-        // ---- BiCGStab in lockstep; finished models return at once
-        int iter = 0, before = 0;
-        const int max_chunks = lead->o.krylov_maxit / check + 2;
-        for (int chunk = 0; chunk < max_chunks; chunk++) {
-            for (int c = 0; c < check; c++, iter++)
-                for (int w = 0; w < 3; w++)
+        // ---- BiCGStab in lockstep; finished models return at once.  The
+        // next block of iterations is queued before the status of the
+        // current one is examined, so the GPU does not idle during the
+        // host check (without profiling, whose records need the stream
+        // drained).
+        const bool ahead = !lead->prof.on;
+        auto queue_chunk = [&](int first_it) {
+            for (int c = 0; c < check; c++)
+                for (int w = 0; w < 2; w++)
                     for (int g = 0; g < 2; g++) {
                         if (!G[g].nblk) continue;
                         const int q = pbeg_ext(lead, PK_BICG_A + w, c);
                         launch_bicg_part(w, b, g == 0, t.dsegs + (size_t)g * t.cap,
-                                         t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk, iter, s,
-                                         q >= 0 ? lead->prof.pend[q].a : nullptr,
+                                         t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk,
+                                         first_it + c, s, q >= 0 ? lead->prof.pend[q].a : nullptr,
                                          q >= 0 ? lead->prof.pend[q].b : nullptr);
                         if (q >= 0) lead->prof.pend[q].rows = lead->nA;
                     }
-            TRY(read_status(lead, t, G, items, s, false));
+        };
+        // status of the queued work into slot sl (2 slots), then an event
+        auto queue_status = [&](int sl) -> fim_status {
+            for (int g = 0; g < 2; g++)
+                if (!G[g].idx.empty())
+                    launch_seg_status(t.dsegs + (size_t)g * t.cap, (int)G[g].idx.size(),
+                                      t.dstat + (size_t)(2 + 2 * sl + g) * t.cap, s);
+            for (int g = 0; g < 2; g++)
+                if (!G[g].idx.empty())
+                    HIPX(hipMemcpyAsync(t.hstat + (size_t)(2 + 2 * sl + g) * t.cap,
+                                        t.dstat + (size_t)(2 + 2 * sl + g) * t.cap,
+                                        G[g].idx.size() * sizeof(SegStatus), hipMemcpyDeviceToHost, s));
+            HIPX(hipEventRecord(t.ev[sl], s));
+            return FIM_OK;
+        };
+        int before = 0;
+        const int max_chunks = lead->o.krylov_maxit / check + 2;
+        queue_chunk(0);
+        TRY(queue_status(0));
+        for (int chunk = 0; chunk < max_chunks; chunk++) {
+            const int sl = chunk & 1;
+            if (ahead && chunk + 1 < max_chunks) {
+                queue_chunk((chunk + 1) * check);
+                TRY(queue_status(sl ^ 1));
+            }
+            HIPX(hipEventSynchronize(t.ev[sl]));
             // the lead model's iteration count tells which of its profiled
             // launches did work (later ones returned at once)
             for (int g = 0; g < 2; g++)
                 for (size_t pos = 0; pos < G[g].idx.size(); pos++)
-                    if (G[g].idx[pos] == 0) {
-                        const int its = status_of(t, G, g, (int)pos).iters;
+                    if (G[g].idx[pos] == 0 && lead->prof.on) {
+                        const int its = t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos].iters;
                         pflush(lead, its - before);
                         before = its;
                     }
             bool all = true;
             for (int g = 0; g < 2; g++)
                 for (size_t pos = 0; pos < G[g].idx.size(); pos++)
-                    if (items[G[g].idx[pos]].active && !status_of(t, G, g, (int)pos).done) all = false;
-            if (all) break;
+                    if (items[G[g].idx[pos]].active &&
+                        !t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos].done)
+                        all = false;
+            if (all) {
+                // final iteration counts
+                for (int g = 0; g < 2; g++)
+                    for (size_t pos = 0; pos < G[g].idx.size(); pos++)
+                        t.hstat[(size_t)g * t.cap + pos] = t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos];
+                break;
+            }
+            if (!ahead && chunk + 1 < max_chunks) {
+                queue_chunk((chunk + 1) * check);
+                TRY(queue_status(sl ^ 1));
+            }
+            if (chunk + 1 == max_chunks) {
+                for (int g = 0; g < 2; g++)
+                    for (size_t pos = 0; pos < G[g].idx.size(); pos++)
+                        t.hstat[(size_t)g * t.cap + pos] = t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos];
+            }
         }
         for (int g = 0; g < 2; g++)
             for (size_t pos = 0; pos < G[g].idx.size(); pos++) {
@@ -720,7 +769,7 @@ void fim_default_options(fim_options* o) {
     o->max_cuts = 8;
     o->ds_max = 0.2;
     o->precision = FIM_FP64;
-    o->lin_rtol = 1e-6;
+    o->lin_rtol = 1e-4;
     o->inner_rtol = 1e-5;
     o->krylov_maxit = 2000;
     o->max_refine = 20;
@@ -940,7 +989,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(dalloc(m, &m->kvec, 9 * nn * B * sizeof(double)));
     CK(dal(m, &m->xprev, nn * B));
     CK(dal(m, &m->sc, 1));
-    CK(dal(m, &m->part_ir, 8 * KB_MAXB));
+    CK(dal(m, &m->part_ir, 14 * KB_MAXB));
     CK(dal(m, &m->ns, 1));
     CK(dal(m, &m->dint, 8));
     CK(dal(m, &m->dsub, 1024));

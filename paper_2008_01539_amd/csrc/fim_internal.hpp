@@ -129,7 +129,7 @@ void launch_precond(int b, bool fp32, int nA, const LocalSys& ls,
 struct KrylovBufs {
     void* x; void* r; void* rh; void* p[2]; void* v[2]; void* sv; void* t;
     double* x64; double* rir; KScal* sc;
-    // per-block partial dot products (2 per block, KB_MAXB blocks)
+    // per-block partial dot products (part_ir 2 per block, the others 4)
     double* part_ir; double* part_a; double* part_b; double* part_c;
     const double* dinv; const void* At;
 };
@@ -156,8 +156,9 @@ struct KSeg {
 // (|r64|^2, |b~|^2) per block
 void launch_ir_residual(int b, bool fp32, const KSeg* segs, const int* blk_seg, int nblk_total,
                         bool x_zero, hipStream_t s);
-// which: 0 = v = A p (with the p update), 1 = s, t = A s, 2 = x, r update;
-// it = iteration index (same for every model of the launch)
+// which: 0 = kernel P (x, r update of iteration it-1; p and v = A p of it),
+// 1 = kernel S (s = r - alpha v, t = A s); it = iteration index (same for
+// every model of the launch)
 // ev0/ev1: optional events stamped with the kernel's own start and end
 void launch_bicg_part(int which, int b, bool fp32, const KSeg* segs, const int* blk_seg,
                       int nblk_total, int it, hipStream_t s, hipEvent_t ev0 = nullptr,

@@ -75,7 +75,7 @@ struct RowRaw {
 
 template <int B, typename T, int NV>
 __device__ inline void fetch_row(const LocalSys& ls, const T* __restrict__ At, int r,
-                                 const T* const (&src)[NV], RowRaw<B, T, NV>& R) {
+                                 const T* const* src, RowRaw<B, T, NV>& R) {
     constexpr int BB = B * B;
     const int s = r / SLICE;
     R.lane = r % SLICE;
@@ -116,7 +116,7 @@ __device__ inline void fetch_row(const LocalSys& ls, const T* __restrict__ At, i
 // slots past the first UNR (wide rows) are loaded here directly
 template <int B, typename T, int NV, class FX>
 __device__ inline void finish_row(const LocalSys& ls, const T* __restrict__ At,
-                                  const T* const (&src)[NV], const RowRaw<B, T, NV>& R,
+                                  const T* const* src, const RowRaw<B, T, NV>& R,
                                   double (&y)[B], FX fx) {
     constexpr int BB = B * B;
 #pragma unroll
@@ -222,8 +222,10 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
     if (threadIdx.x == 0) {
         kb.part_ir[2 * lb] = part[0];
         kb.part_ir[2 * lb + 1] = part[1];
-        kb.part_c[2 * lb] = part[1];
-        kb.part_c[2 * lb + 1] = part[1];
+        kb.part_c[4 * lb] = part[1];      // (rh, r_0) = |b~|^2
+        kb.part_c[4 * lb + 1] = part[1];
+        kb.part_c[4 * lb + 2] = 0.0;
+        kb.part_c[4 * lb + 3] = 0.0;
     }
     if (lb == 0 && threadIdx.x == 0) {
         kb.sc->done = 0;
@@ -232,11 +234,17 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
     }
 }
 
-// ----------------------------------------------- kernel A: v = A p
-// start: rho_i = (rh, r), |r|^2 from the previous kernel C (or the
-// initialisation); stop if converged or at the iteration cap.
-template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_bicg_a(const KSeg* __restrict__ segs,
+// ------------------------------------------------------ kernel P (iter i)
+// Finishes iteration i-1 and starts iteration i:
+//   omega = (t,s)/(t,t), rho_i = (rh,s) - omega (rh,t)   [from kernel S]
+//   x += alpha p + omega s;  r_i = s - omega t           [own rows]
+//   p_i = r_i + beta (p_{i-1} - omega v_{i-1});  v_i = A~ p_i
+// with p_i at the neighbours rebuilt from s, t, p, v on the fly.  Partial
+// sums: (rh, v_i), (v_i, v_i), (r_i, r_i).  At i = 0, p_0 = r_0 (the
+// refinement initialisation).  Stops (after the x, r update) at the
+// iteration cap or when omega = 0.
+template <int B, typename T, bool FIRST>
+__global__ __launch_bounds__(KB_NT) void k_bicg_p(const KSeg* __restrict__ segs,
                                                   const int* __restrict__ blk_seg, int it) {
     const KSeg& S = segs[blk_seg[blockIdx.x]];
     if (!S.active) return;
@@ -245,52 +253,85 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_a(const KSeg* __restrict__ segs,
     const T* __restrict__ At = (const T*)S.kb.At;
     const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
     KScal* __restrict__ sc = S.kb.sc;
-    const double* __restrict__ pc = S.kb.part_c;
+    const double* __restrict__ pin = FIRST ? S.kb.part_c : S.kb.part_b;
     double* __restrict__ pa = S.kb.part_a;
-    const double tol2 = S.tol2;
-    const int maxit = S.maxit;
     const int done = sc->done;
-    const double rho_prev = it > 0 ? sc->rho_hist[(it - 1) & 1] : 1.0;
-    const double al_prev = sc->alpha, om_prev = sc->omega;
-    double red[2] = {0.0, 0.0};
+    const double rho_prev = FIRST ? 1.0 : sc->rho_hist[(it - 1) & 1];
+    const double al_prev = sc->alpha;
+    constexpr int NR = FIRST ? 1 : 4;
+    double red[4] = {0.0, 0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
-        red[0] += pc[2 * q];
-        red[1] += pc[2 * q + 1];
+#pragma unroll
+        for (int k = 0; k < NR; k++) red[k] += pin[(long)q * 4 + k];
     }
     if (done) return;
-    const T* const src[3] = {V.r, V.p_old, V.v_old};
     const int r0 = lb * blockDim.x + threadIdx.x;
     const int stride = nbk * blockDim.x;
-    RowRaw<B, T, 3> R;
-    if (r0 < nA) fetch_row<B, T, 3>(ls, At, r0, src, R);
-    block_sum<2>(red);
-    const double rho = red[0], rr = red[1];
-    const bool stop = rr <= tol2 || it >= maxit || !isfinite(rr) || (it > 0 && rho == 0.0);
+    constexpr int NV = FIRST ? 1 : 4;
+    const T* src[NV];
+    if constexpr (FIRST) {
+        src[0] = V.r;
+    } else {
+        src[0] = V.s;
+        src[1] = V.t;
+        src[2] = V.p_old;
+        src[3] = V.v_old;
+    }
+    RowRaw<B, T, NV> R;
+    if (r0 < nA) fetch_row<B, T, NV>(ls, At, r0, src, R);
+    block_sum<4>(red);
+    double om = 0.0, rho, beta = 0.0;
+    if (FIRST) {
+        rho = red[0];                       // (rh, r_0) = |b~|^2
+    } else {
+        om = (red[1] > 0.0) ? red[0] / red[1] : 0.0;
+        rho = red[2] - om * red[3];
+        beta = (rho / rho_prev) * (al_prev / om);
+    }
+    const bool stop = !FIRST && (it >= S.maxit || om == 0.0 || !isfinite(beta));
     if (lb == 0 && threadIdx.x == 0) {
         sc->rho_hist[it & 1] = rho;
-        sc->rr = rr;
+        sc->omega = om;
+        sc->iters = it;      // iterations completed (x_it is formed here)
         if (stop) {
             sc->done = 1;
-            sc->iters = it;
-            sc->breakdown = (rr <= tol2) ? 0 : 1;
+            sc->breakdown = 1;
         }
     }
-    if (stop) return;
-    const bool first = it == 0;
-    const double beta = first ? 0.0 : (rho / rho_prev) * (al_prev / om_prev);
-    const double om = first ? 0.0 : om_prev;
-    auto fx = [&](const T (&raw)[3][B], double (&x)[B]) {
-#pragma unroll
-        for (int c = 0; c < B; c++) x[c] = p_update<T>(first, raw[0][c], raw[1][c], raw[2][c], beta, om);
-    };
-    double dot[2] = {0.0, 0.0};
+    double dot[4] = {0.0, 0.0, 0.0, 0.0};
     for (int r = r0; r < nA; r += stride) {
-        if (r != r0) fetch_row<B, T, 3>(ls, At, r, src, R);
-        double pi[B], vi[B];
+        if (r != r0) fetch_row<B, T, NV>(ls, At, r, src, R);
+        double ri[B], pi[B], vi[B];
+        if (FIRST) {
+#pragma unroll
+            for (int c = 0; c < B; c++) ri[c] = (double)R.xo[0][c];
+        } else {
+            // tail of iteration i-1 on the own row
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                const long q = (long)r * B + c;
+                const double sv = (double)R.xo[0][c];
+                V.x[q] = (T)((double)V.x[q] + al_prev * (double)R.xo[2][c] + om * sv);
+                ri[c] = (double)(T)(sv - om * (double)R.xo[1][c]);
+                V.r[q] = (T)ri[c];
+            }
+        }
+        if (stop) continue;
+        auto fx = [&](const T (&raw)[NV][B], double (&x)[B]) {
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                if constexpr (FIRST) {
+                    x[c] = (double)raw[0][c];
+                } else {
+                    const double rr_ = (double)(T)((double)raw[0][c] - om * (double)raw[1][c]);
+                    x[c] = (double)(T)(rr_ + beta * ((double)raw[2][c] - om * (double)raw[3][c]));
+                }
+            }
+        };
         fx(R.xo, pi);
 #pragma unroll
         for (int c = 0; c < B; c++) vi[c] = pi[c];
-        finish_row<B, T, 3>(ls, At, src, R, vi, fx);
+        finish_row<B, T, NV>(ls, At, src, R, vi, fx);
 #pragma unroll
         for (int c = 0; c < B; c++) {
             const long q = (long)r * B + c;
@@ -299,20 +340,23 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_a(const KSeg* __restrict__ segs,
             V.v_new[q] = vT;
             dot[0] += (double)V.rh[q] * (double)vT;
             dot[1] += (double)vT * (double)vT;
+            dot[2] += ri[c] * ri[c];
         }
     }
-    block_sum<2>(dot);
+    block_sum<4>(dot);
     if (threadIdx.x == 0) {
-        pa[2 * lb] = dot[0];
-        pa[2 * lb + 1] = dot[1];
+#pragma unroll
+        for (int k = 0; k < 4; k++) pa[4 * lb + k] = dot[k];
     }
 }
 
-// ------------------------------------- kernel B: s = r - alpha v, t = A s
-// start: sigma = (rh, v); alpha = rho / sigma; a sigma lost against
-// |rh| |v| is a breakdown (stop with the current x).
+// ------------------------------------------------------ kernel S (iter i)
+// start: sigma = (rh, v_i), |v_i|^2, |r_i|^2 from kernel P.  Stops when
+// |r_i|^2 <= tol2 (x_i is the answer) or on a breakdown of sigma; else
+// alpha = rho_i / sigma, s = r_i - alpha v_i, t = A~ s (s rebuilt at the
+// neighbours).  Partial sums: (t,s), (t,t), (rh,s), (rh,t).
 template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_bicg_b(const KSeg* __restrict__ segs,
+__global__ __launch_bounds__(KB_NT) void k_bicg_s(const KSeg* __restrict__ segs,
                                                   const int* __restrict__ blk_seg, int it) {
     const KSeg& S = segs[blk_seg[blockIdx.x]];
     if (!S.active) return;
@@ -324,13 +368,12 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_b(const KSeg* __restrict__ segs,
     const double* __restrict__ pa = S.kb.part_a;
     double* __restrict__ pb = S.kb.part_b;
     const double brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
-    const double brk2 = brk * brk, bnorm2 = S.bnorm2;
     const int done = sc->done;
     const double rho = sc->rho_hist[it & 1];
-    double red[2] = {0.0, 0.0};
+    double red[3] = {0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
-        red[0] += pa[2 * q];
-        red[1] += pa[2 * q + 1];
+#pragma unroll
+        for (int k = 0; k < 3; k++) red[k] += pa[(long)q * 4 + k];
     }
     if (done) return;
     const T* const src[2] = {V.r, V.v_new};
@@ -338,25 +381,28 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_b(const KSeg* __restrict__ segs,
     const int stride = nbk * blockDim.x;
     RowRaw<B, T, 2> R;
     if (r0 < nA) fetch_row<B, T, 2>(ls, At, r0, src, R);
-    block_sum<2>(red);
-    const double sigma = red[0], vv = red[1];
+    block_sum<3>(red);
+    const double sigma = red[0], vv = red[1], rr = red[2];
     const double al = rho / sigma;
-    const bool bad = !(sigma * sigma > brk2 * bnorm2 * vv) || !isfinite(al);
+    const bool conv = rr <= S.tol2;
+    const bool bad = !conv && (!(sigma * sigma > brk * brk * S.bnorm2 * vv) || !isfinite(al) ||
+                               !isfinite(rr));
     if (lb == 0 && threadIdx.x == 0) {
-        if (bad) {
+        sc->rr = rr;
+        if (conv || bad) {
             sc->done = 1;
             sc->iters = it;
-            sc->breakdown = 1;
+            sc->breakdown = bad ? 1 : 0;
         } else {
             sc->alpha = al;
         }
     }
-    if (bad) return;
+    if (conv || bad) return;
     auto fx = [&](const T (&raw)[2][B], double (&x)[B]) {
 #pragma unroll
         for (int c = 0; c < B; c++) x[c] = s_update<T>(raw[0][c], raw[1][c], al);
     };
-    double dot[2] = {0.0, 0.0};
+    double dot[4] = {0.0, 0.0, 0.0, 0.0};
     for (int r = r0; r < nA; r += stride) {
         if (r != r0) fetch_row<B, T, 2>(ls, At, r, src, R);
         double si[B], ti[B];
@@ -370,85 +416,17 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_b(const KSeg* __restrict__ segs,
             const T sT = (T)si[c], tT = (T)ti[c];
             V.s[q] = sT;
             V.t[q] = tT;
+            const double h = (double)V.rh[q];
             dot[0] += (double)tT * (double)sT;
             dot[1] += (double)tT * (double)tT;
+            dot[2] += h * (double)sT;
+            dot[3] += h * (double)tT;
         }
     }
-    block_sum<2>(dot);
+    block_sum<4>(dot);
     if (threadIdx.x == 0) {
-        pb[2 * lb] = dot[0];
-        pb[2 * lb + 1] = dot[1];
-    }
-}
-
-// ----------------------- kernel C: x += alpha p + omega s, r = s - omega t
-template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_bicg_c(const KSeg* __restrict__ segs,
-                                                  const int* __restrict__ blk_seg, int it) {
-    const KSeg& S = segs[blk_seg[blockIdx.x]];
-    if (!S.active) return;
-    const int lb = blockIdx.x - S.blk0, nbk = S.nblk, nA = S.nA;
-    const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
-    KScal* __restrict__ sc = S.kb.sc;
-    const double* __restrict__ pb = S.kb.part_b;
-    double* __restrict__ pc = S.kb.part_c;
-    const int done = sc->done;
-    const double al = sc->alpha;
-    double red[2] = {0.0, 0.0};
-    for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
-        red[0] += pb[2 * q];
-        red[1] += pb[2 * q + 1];
-    }
-    if (done) return;
-    const int r0 = lb * blockDim.x + threadIdx.x;
-    const int stride = nbk * blockDim.x;
-    // prefetch the first row while the partial sums are combined
-    T s0[B], t0[B], p0[B], x0[B], h0[B];
-    if (r0 < nA) {
 #pragma unroll
-        for (int c = 0; c < B; c++) {
-            const long q = (long)r0 * B + c;
-            s0[c] = V.s[q]; t0[c] = V.t[q]; p0[c] = V.p_new[q]; x0[c] = V.x[q]; h0[c] = V.rh[q];
-        }
-    }
-    block_sum<2>(red);
-    // omega = 0 (t orthogonal to s): x += alpha p, r = s; the next kernel
-    // A stops on rho = 0 or converges
-    const double om = (red[1] > 0.0) ? red[0] / red[1] : 0.0;
-    const bool bad = !isfinite(om);
-    if (lb == 0 && threadIdx.x == 0) {
-        sc->omega = om;
-        sc->iters = it + 1;
-        if (bad) {
-            sc->done = 1;
-            sc->breakdown = 1;
-        }
-    }
-    if (bad) return;
-    double dot[2] = {0.0, 0.0};
-    for (int r = r0; r < nA; r += stride) {
-        if (r != r0) {
-#pragma unroll
-            for (int c = 0; c < B; c++) {
-                const long q = (long)r * B + c;
-                s0[c] = V.s[q]; t0[c] = V.t[q]; p0[c] = V.p_new[q]; x0[c] = V.x[q]; h0[c] = V.rh[q];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < B; c++) {
-            const long q = (long)r * B + c;
-            const double sv = (double)s0[c];
-            V.x[q] = (T)((double)x0[c] + al * (double)p0[c] + om * sv);
-            const T rT = (T)(sv - om * (double)t0[c]);
-            V.r[q] = rT;
-            dot[0] += (double)h0[c] * (double)rT;
-            dot[1] += (double)rT * (double)rT;
-        }
-    }
-    block_sum<2>(dot);
-    if (threadIdx.x == 0) {
-        pc[2 * lb] = dot[0];
-        pc[2 * lb + 1] = dot[1];
+        for (int k = 0; k < 4; k++) pb[4 * lb + k] = dot[k];
     }
 }
 
@@ -482,12 +460,14 @@ template <int B, typename T>
 static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 nb(nblk_total), nt(KB_NT);
-    if (which == 0)
-        hipExtLaunchKernelGGL(k_bicg_a<B, T>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
-    else if (which == 1)
-        hipExtLaunchKernelGGL(k_bicg_b<B, T>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
-    else
-        hipExtLaunchKernelGGL(k_bicg_c<B, T>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
+    if (which == 0) {
+        if (it == 0)
+            hipExtLaunchKernelGGL(k_bicg_p<B, T, true>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
+        else
+            hipExtLaunchKernelGGL(k_bicg_p<B, T, false>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
+    } else {
+        hipExtLaunchKernelGGL(k_bicg_s<B, T>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
+    }
 }
 
 int krylov_grid(int nA) { return kgrid(nA); }

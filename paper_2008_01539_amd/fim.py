@@ -155,7 +155,7 @@ class Options:
     max_cuts: int = 8
     ds_max: float = 0.2
     precision: int = FP64
-    lin_rtol: float = 1e-6
+    lin_rtol: float = 1e-4
     inner_rtol: float = 1e-5
     krylov_maxit: int = 2000
     max_refine: int = 20
