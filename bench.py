@@ -147,9 +147,166 @@ def _cpu_name():
     return platform.processor()
 
 
+# ------------------------------------------------------------- other workloads
+def _member(k):
+    from fimgen import make_c4_member
+    return make_c4_member(k)
+
+
+def _pool_models(fn, ids, procs=16):
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(min(procs, len(ids))) as pool:
+        return pool.map(fn, ids)
+
+
+def run_c4(members, steps):
+    """Batched ensemble: `members` config-4 models advanced together, one
+    Newton iteration of every live member per batched call, each member
+    through its own schedule; then the same members one after another."""
+    import numpy as np
+    import torch
+    import paper_2008_01539_amd as P
+    log(f"generating {members} ensemble members")
+    models = _pool_models(_member, list(range(members)))
+    ncell = sum(m.n for m in models)
+    log(f"total cells {ncell}")
+    opts = P.Options(precision=P.MIXED)
+    fms = [P.FimModel(m, opts) for m in models]
+    for fm, m in zip(fms, models):
+        fm.set_state(m.u0, m.status0)
+    log(f"device bytes {sum(fm.device_bytes() for fm in fms) / 2**30:.1f} GiB")
+    step = [0] * members
+    live = list(range(members))
+    bat = P.FimBatch([fms[i] for i in live])
+    lat, act = [], 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while live:
+        dts = [models[i].schedule[step[i]] for i in live]
+        t1 = time.perf_counter()
+        stats, codes = bat.newton_step(dts, [P.LOCAL] * len(live))
+        lat.append(time.perf_counter() - t1)
+        nxt = []
+        for i, st, c in zip(live, stats, codes):
+            act += st["n_active"]
+            if st["converged"]:
+                step[i] += 1
+            if c == 0 and step[i] < steps:
+                nxt.append(i)
+        if nxt != live and nxt:
+            bat.set_models([fms[i] for i in nxt])
+        live = nxt
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bat.close()
+    u_batch = [fm.get_state()[0] for fm in fms]
+    for fm in fms:
+        fm.close()
+    log(f"batched: {len(lat)} calls, wall {wall:.2f}s")
+    # the same members one after another
+    t0 = time.perf_counter()
+    same = True
+    for i, m in enumerate(models):
+        fm = P.FimModel(m, opts)
+        fm.set_state(m.u0, m.status0)
+        for dt in m.schedule[:steps]:
+            fm.solve_timestep(dt, P.LOCAL)
+        same = same and bool(np.array_equal(fm.get_state()[0], u_batch[i]))
+        fm.close()
+    torch.cuda.synchronize()
+    wall_seq = time.perf_counter() - t0
+    log(f"sequential: wall {wall_seq:.2f}s, identical results {same}")
+    lat_ms = np.array(lat) * 1e3
+    return {
+        "metric": "active-cell Newton updates/s, batched ensemble (1 GPU); p50/p99 batched-call latency",
+        "value": act / wall, "unit": "active-cell Newton updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": 0, "higher_is_better": True, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"config 4: {members} water/dead-oil members (seeds 4000+k, "
+                               f"5k-200k cells each, {ncell} cells), first {steps} timesteps of "
+                               "each member's schedule, localized Newton, one Newton iteration "
+                               "of every live member per batched call", "members": members},
+        "batched_wall_s": wall, "sequential_wall_s": wall_seq,
+        "batching_speedup": wall_seq / wall, "batch_equals_solo_bitwise": same,
+        "call_ms_p50": float(np.percentile(lat_ms, 50)),
+        "call_ms_p99": float(np.percentile(lat_ms, 99)), "calls": len(lat),
+    }
+
+
+def _c5_session(args):
+    kind, k = args
+    from fimgen import make_c1, make_small_c2, make_small_c3
+    if kind == 1:
+        return make_c1(seed=5000 + k)
+    if kind == 2:
+        return make_small_c2(seed=6000 + k, nx=60, ny=30, nz=10, nfrac=180, nstage=6)
+    return make_small_c3(seed=7000 + k, nx=40, ny=20, nz=8, nfrac=60, nstage=4)
+
+
+def run_c5(seconds, n1, n2, n3, budget_gib, rate=50.0):
+    """Serving: Poisson timestep requests at `rate`/s over sessions of
+    config-1, -2 and -3 recipes (50/40/10 % of requests)."""
+    import numpy as np
+    import paper_2008_01539_amd as P
+    from paper_2008_01539_amd.serve import GpuExecutor, Server, SessionSpec
+    log(f"generating sessions {n1}/{n2}/{n3}")
+    ids = [(1, k) for k in range(n1)] + [(2, k) for k in range(n2)] + [(3, k) for k in range(n3)]
+    models = _pool_models(_c5_session, ids)
+    specs = [SessionSpec(name=f"{kind}-{k}", model=m, options=P.Options(precision=P.MIXED),
+                         schedule=m.schedule) for (kind, k), m in zip(ids, models)]
+    mix = np.array([0.5 / n1] * n1 + [0.4 / n2] * n2 + [0.1 / n3] * n3)
+    ex = GpuExecutor()
+    srv = Server(specs, ex, budget_bytes=int(budget_gib * 2**30), max_inflight=64,
+                 footprint=lambda sp: P.estimate_bytes(sp.model, sp.options))
+    log(f"serving {seconds}s at {rate}/s, budget {budget_gib} GiB")
+    summ = srv.run_poisson(rate=rate, duration=seconds, mix=mix, seed=5)
+    ex.close()
+    return {
+        "metric": "served timestep requests/s and p50/p99 request latency (1 GPU)",
+        "value": summ["throughput_rps"], "unit": "requests/s", "n_gpus": 1,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"config 5: Poisson arrivals at {rate}/s for {seconds}s, "
+                               f"50/40/10 % of requests over {n1} config-1, {n2} config-2-recipe "
+                               f"(60x30x10) and {n3} config-3-recipe (40x20x8) sessions, "
+                               f"HBM budget {budget_gib} GiB, continuous batching",
+                   "rate": rate, "seconds": seconds},
+        "serving": summ,
+    }
+
+
+def run_c3(steps, warmup):
+    import numpy as np
+    import paper_2008_01539_amd as P
+    from fimgen import make_c3
+    log("building config 3")
+    model = make_c3()
+    log(f"n={model.n}")
+    opts = P.Options(precision=P.MIXED)
+    loc = run_gpu(model, opts, P.LOCAL, steps, warmup)
+    full = run_gpu(model, opts, P.FULL, steps, warmup)
+    return {
+        "metric": "active-cell Newton updates/s, local vs full Newton (1 GPU); p50/p99 step latency",
+        "value": loc["active"] / loc["wall"], "unit": "active-cell Newton updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"config 3: black oil (bubble point 3500 psi, Sg/Rs switching), "
+                               f"400x200x8 + 5000-fracture DFN ({model.n} cells), 3x3 blocks, "
+                               f"timesteps {warmup}..{warmup + steps - 1} of 40, localized Newton, "
+                               "FP32 Krylov in FP64 refinement"},
+        "local": {k: loc[k] for k in ("iters", "krylov", "wall", "p50", "p99")},
+        "full": {"updates_per_s": full["active"] / full["wall"], "wall": full["wall"]},
+        "speedup_local_vs_full": full["wall"] / loc["wall"],
+        "max_dp_local_vs_full_psi": float(np.abs(full["u"][0] - loc["u"][0]).max() / 6894.757293168),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--members", type=int, default=256)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--budget-gib", type=float, default=64.0)
     ap.add_argument("--steps", type=int, default=18)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
@@ -167,6 +324,15 @@ def main():
     torch.cuda.set_device(0)
     from fimgen import PSI, make_c2
     import paper_2008_01539_amd as P
+    if args.workload == "c4":
+        print(json.dumps(run_c4(args.members, max(1, args.steps))), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(run_c5(args.serve_seconds, 64, 16, 4, args.budget_gib)), flush=True)
+        return
+    if args.workload == "c3":
+        print(json.dumps(run_c3(args.steps, args.warmup)), flush=True)
+        return
 
     log("building the config-2 model")
     model = make_c2()
