@@ -149,8 +149,10 @@ void fim_default_options(fim_options* o);
 
 /* Uploads the model (Section 4.3, the index set V and the connection
  * graph).  hip_stream: a hipStream_t or NULL.  Errors: FIM_E_ARG on an
- * invalid description, FIM_E_NOMEM / FIM_E_HIP on device failures; *out
- * is NULL then. */
+ * invalid description or when the Jacobian blocks of the whole grid would
+ * pass 4 GiB (64 (max degree + 1) ceil(n/64) b^2 8 bytes; about 40 M
+ * cells at b = 3 and degree 10), FIM_E_NOMEM / FIM_E_HIP on device
+ * failures; *out is NULL then. */
 fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
                             void* hip_stream, fim_model** out);
 

@@ -71,7 +71,7 @@ struct fim_model {
     uint8_t *act = nullptr, *act2 = nullptr, *supp = nullptr, *bnd = nullptr, *vt = nullptr,
             *outer = nullptr;
     // local system
-    int *l2g = nullptr, *g2l = nullptr, *swidth = nullptr, *sptr = nullptr, *blk = nullptr;
+    int *l2g = nullptr, *g2l = nullptr, *swidth = nullptr, *blk = nullptr;
     int *col = nullptr;
     double *J = nullptr, *F = nullptr, *dinv = nullptr;
     void* At = nullptr;
@@ -241,7 +241,9 @@ static LocalSys lsys(fim_model* m) {
     LocalSys ls;
     ls.l2g = m->l2g;
     ls.g2l = m->g2l;
-    ls.sptr = m->sptr;
+    ls.swidth = m->swidth;
+    ls.wcap = m->max_deg + 1;
+    ls.pad = 0;
     ls.col = m->col;
     ls.J = m->J;
     ls.F = m->F;
@@ -259,8 +261,7 @@ static fim_status read_int(fim_model* m) {
 }
 
 static fim_status structure(fim_model* m) {
-    launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, m->sptr, m->blk, &m->dint[4],
-                     m->s);
+    launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, &m->dint[4], m->s);
     return FIM_OK;
 }
 
@@ -354,6 +355,12 @@ static fim_status read_status(fim_model* lead, SolveTable& t, Group* G, std::vec
     return FIM_OK;
 }
 
+// a launch over group g covers a single model
+static bool solo_of(SolveTable& t, Group* G, int g) {
+    (void)t;
+    return G[g].idx.size() == 1;
+}
+
 static const SegStatus& status_of(SolveTable& t, Group* G, int g, int pos) {
     return t.hstat[(size_t)g * t.cap + pos];
 }
@@ -384,8 +391,8 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
     for (int g = 0; g < 2; g++) TRY(upload_group(lead, t, g, G[g], items, s));
     int pi = pbeg(lead, PK_IR);
     for (int g = 0; g < 2; g++)
-        launch_ir_residual(b, g == 0, t.dsegs + (size_t)g * t.cap, t.dblk + (size_t)g * t.cap * KB_MAXB,
-                           G[g].nblk, true, s);
+        launch_ir_residual(b, g == 0, solo_of(t, G, g), t.dsegs + (size_t)g * t.cap,
+                           t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk, true, s);
     pend(lead, pi, lead->nA);
     if (lead->prof.on)
         HIPX(hipMemcpyAsync(&lead->hint[4], &lead->dint[4], sizeof(int), hipMemcpyDeviceToHost, s));
@@ -433,7 +440,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                     for (int g = 0; g < 2; g++) {
                         if (!G[g].nblk) continue;
                         const int q = pbeg_ext(lead, PK_BICG_A + w, c);
-                        launch_bicg_part(w, b, g == 0, t.dsegs + (size_t)g * t.cap,
+                        launch_bicg_part(w, b, g == 0, solo_of(t, G, g), t.dsegs + (size_t)g * t.cap,
                                          t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk,
                                          first_it + c, s, q >= 0 ? lead->prof.pend[q].a : nullptr,
                                          q >= 0 ? lead->prof.pend[q].b : nullptr);
@@ -504,9 +511,9 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
             }
         pi = pbeg(lead, PK_IR);
         for (int g = 0; g < 2; g++) {
-            launch_ir_accumulate(b, g == 0, t.dsegs + (size_t)g * t.cap,
+            launch_ir_accumulate(b, g == 0, solo_of(t, G, g), t.dsegs + (size_t)g * t.cap,
                                  t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk, s);
-            launch_ir_residual(b, g == 0, t.dsegs + (size_t)g * t.cap,
+            launch_ir_residual(b, g == 0, solo_of(t, G, g), t.dsegs + (size_t)g * t.cap,
                                t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk, false, s);
         }
         pend(lead, pi, lead->nA);
@@ -547,8 +554,8 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
             G[0].idx = keep32;
             for (SolveItem& it : items) it.active = it.fallback == 1 && !it.fp32 && it.active;
             for (int g = 0; g < 2; g++) TRY(upload_group(lead, t, g, G[g], items, s));
-            launch_ir_residual(b, false, t.dsegs + (size_t)t.cap, t.dblk + (size_t)t.cap * KB_MAXB,
-                               G[1].nblk, false, s);
+            launch_ir_residual(b, false, solo_of(t, G, 1), t.dsegs + (size_t)t.cap,
+                               t.dblk + (size_t)t.cap * KB_MAXB, G[1].nblk, false, s);
             TRY(read_status(lead, t, G, items, s));
             for (size_t pos = 0; pos < G[1].idx.size(); pos++) {
                 SolveItem& it = items[G[1].idx[pos]];
@@ -791,7 +798,7 @@ static void free_all(fim_model* m) {
     for (hipEvent_t e : m->prof.pool) (void)hipEventDestroy(e);
     void* ptrs[] = {m->adj_ptr, m->adj_nbr, m->adj_T, m->pv, m->depth, m->wi, m->bhp, m->flags,
                     m->u, m->un, m->Mn, m->dp_abs, m->last_dp, m->st, m->stn, m->act, m->act2,
-                    m->supp, m->bnd, m->vt, m->outer, m->l2g, m->g2l, m->swidth, m->sptr,
+                    m->supp, m->bnd, m->vt, m->outer, m->l2g, m->g2l, m->swidth,
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
                     m->part_ir, m->classes};
@@ -950,6 +957,13 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     const size_t nsl = (nn + SLICE - 1) / SLICE;
     m->slot_cap = (long)(m->max_deg + 1) * SLICE * (long)nsl;
     const int B = m->B;
+    // the Krylov kernels address the matrix blocks with 32-bit byte offsets
+    if ((double)m->slot_cap * B * B * sizeof(double) >= 4294967296.0) {
+        g_create_err = "model too large: the matrix blocks would exceed 4 GiB";
+        if (m->own_stream) (void)hipStreamDestroy(m->s);
+        delete m;
+        return FIM_E_ARG;
+    }
     const size_t ntile = std::max((nn + TILE - 1) / TILE, (nsl + TILE - 1) / TILE) + 1;
     CK(dal(m, &m->adj_ptr, nn + 1));
     CK(dal(m, &m->adj_nbr, nbr.size()));
@@ -975,7 +989,6 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(dal(m, &m->l2g, 2 * nn));
     CK(dal(m, &m->g2l, 2 * nn));
     CK(dal(m, &m->swidth, nsl + 1));
-    CK(dal(m, &m->sptr, nsl + 1));
     CK(dal(m, &m->blk, ntile));
     CK(dal(m, &m->col, (size_t)m->slot_cap));
     CK(dal(m, &m->J, (size_t)m->slot_cap * B * B));
@@ -1311,7 +1324,7 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     b += n * (8 * 4 + 1);                         // pv, depth, wi, bhp, flags
     b += n * B * 8 * 3 + n * 8 * 2 + n * 2;       // u, un, Mn, dp_abs, last_dp, status
     b += n * 6;                                   // byte flags
-    b += n * 4 * 4 + (nsl + 1) * 8;               // l2g, g2l (2n each), swidth, sptr
+    b += n * 4 * 4 + nsl * 4;                     // l2g, g2l (2n each), swidth
     b += slots * (4 + B * B * 8 + B * B * 8);     // col, J, A~ (sized for FP64)
     b += n * B * (8 + B * 8);                     // F, dinv
     b += n * B * 8 * 3 + n * B * 8 * 9;           // x64, xprev, rir, Krylov vectors
@@ -1586,10 +1599,10 @@ fim_status fim_inspect_assemble(fim_model* m, const double* u_old, const double*
     launch_assemble(m->fk, m->nA, ls, m->g, m->f, m->u, m->st, m->Mn, 1.0 / dt, m->s);
     const int nA = m->nA, B = m->B, BB = B * B;
     const int nsl = (nA + SLICE - 1) / SLICE;
-    std::vector<int> sptr(nsl + 1), hl2g(nA);
-    HIPX(hipMemcpyAsync(sptr.data(), m->sptr, (nsl + 1) * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    std::vector<int> swidth(nsl), hl2g(nA);
+    HIPX(hipMemcpyAsync(swidth.data(), m->swidth, nsl * sizeof(int), hipMemcpyDeviceToHost, m->s));
     HIPX(hipStreamSynchronize(m->s));
-    const long slots = nA ? sptr[nsl] : 0;
+    const long slots = (long)nsl * SLICE * ls.wcap;
     std::vector<int> hcol(slots);
     std::vector<double> hJ(slots * BB);
     HIPX(hipMemcpyAsync(hl2g.data(), m->l2g, nA * sizeof(int), hipMemcpyDeviceToHost, m->s));
@@ -1602,10 +1615,9 @@ fim_status fim_inspect_assemble(fim_model* m, const double* u_old, const double*
     long nz = 0;
     row_ptr[0] = 0;
     for (int r = 0; r < nA; r++) {
-        const int s = r / SLICE, lane = r % SLICE;
-        const int w = (sptr[s + 1] - sptr[s]) / SLICE;
+        const int w = swidth[r / SLICE];
         for (int k = 0; k < w; k++) {
-            const long pos = sptr[s] + (long)k * SLICE + lane;
+            const long pos = slot_of(ls, r, k);
             if (k > 0 && hcol[pos] == r) break;   // padding
             if (nz >= cap_blocks) {
                 m->err = "cap_blocks too small";

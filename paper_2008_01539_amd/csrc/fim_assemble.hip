@@ -44,9 +44,8 @@ __global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, D
     if (r >= nA) return;
     const int n = g.n;
     const int i = ls.l2g[r];
-    const int s = r / SLICE, lane = r % SLICE;
-    const int base = ls.sptr[s];
-    const int width = (ls.sptr[s + 1] - base) / SLICE;
+    const long base = slot_of(ls, r, 0);   // slot k at base + 64 k
+    const int width = ls.swidth[r / SLICE];
 
     double ui[B];
 #pragma unroll
@@ -121,7 +120,7 @@ __global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, D
             }
         }
         if (lj >= 0) {
-            const long pos = (long)base + (long)k * SLICE + lane;
+            const long pos = base + (long)k * SLICE;
             ls.col[pos] = lj;
             double* out = ls.J + pos * BB;
 #pragma unroll
@@ -148,7 +147,7 @@ __global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, D
     }
     // diagonal block and residual
     {
-        const long pos = (long)base + lane;
+        const long pos = base;
         ls.col[pos] = r;
         double* out = ls.J + pos * BB;
 #pragma unroll
@@ -157,7 +156,7 @@ __global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, D
             for (int v = 0; v < B; v++) out[c * B + v] = Jd[c][v];
     }
     for (; k < width; k++) {
-        const long pos = (long)base + (long)k * SLICE + lane;
+        const long pos = base + (long)k * SLICE;
         ls.col[pos] = r;
         double* out = ls.J + pos * BB;
 #pragma unroll
@@ -234,18 +233,17 @@ __global__ __launch_bounds__(NT) void k_precond(int nA, LocalSys ls, double* __r
     constexpr int BB = B * B;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nA) return;
-    const int s = r / SLICE, lane = r % SLICE;
-    const int base = ls.sptr[s];
-    const int width = (ls.sptr[s + 1] - base) / SLICE;
+    const long base = slot_of(ls, r, 0);
+    const int width = ls.swidth[r / SLICE];
     double d[BB], di[BB];
     const double* J = ls.J;
 #pragma unroll
-    for (int q = 0; q < BB; q++) d[q] = J[((long)base + lane) * BB + q];
+    for (int q = 0; q < BB; q++) d[q] = J[base * BB + q];
     invert_block<B>(d, di);
 #pragma unroll
     for (int q = 0; q < BB; q++) dinv[(long)r * BB + q] = di[q];
     for (int k = 1; k < width; k++) {
-        const long pos = (long)base + (long)k * SLICE + lane;
+        const long pos = base + (long)k * SLICE;
         double a[BB];
 #pragma unroll
         for (int q = 0; q < BB; q++) a[q] = J[pos * BB + q];

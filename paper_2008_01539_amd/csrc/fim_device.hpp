@@ -98,4 +98,25 @@ __device__ inline bool last_block(unsigned* counter) {
 
 inline int nblocks(long n, int nt = NT) { return (int)((n + nt - 1) / nt); }
 
+// The dispatcher hands workgroups to the XCDs round robin (workgroup g to
+// XCD g mod 8), and each XCD has its own L2.  For a segment of nbk
+// workgroups starting at g0, xcd_tile maps workgroup g to a tile index in
+// [0, nbk) such that the workgroups of one XCD take consecutive tiles:
+// each XCD then works on one contiguous range of rows, and the neighbour
+// rows its gathers touch mostly sit in its own L2.  A bijection for any
+// g0 and nbk; tile t covers the same rows whichever workgroup runs it.
+constexpr int N_XCD = 8;
+__host__ __device__ inline int xcd_tile(int g0, int nbk, int g) {
+    const int off = g0 % N_XCD;          // XCD slot of the first workgroup
+    const int q = g - g0 + off;          // position from an aligned start
+    const int x = q % N_XCD, end = off + nbk;
+    int t = 0;
+    for (int y = 0; y < x; y++) {
+        const int f = y >= off ? y : y + N_XCD;   // first position on XCD y
+        if (f < end) t += (end - f + N_XCD - 1) / N_XCD;
+    }
+    const int f = x >= off ? x : x + N_XCD;
+    return t + (q - f) / N_XCD;
+}
+
 } // namespace fimk

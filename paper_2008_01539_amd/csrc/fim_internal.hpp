@@ -41,17 +41,27 @@ struct Graph {
     const double* bhp;      // [n]
 };
 
-// Local (compacted) block system in sliced-ELL form: slice s holds rows
-// 64s..64s+63; slot (row r, k) sits at sptr[s] + 64 k + (r - 64 s); slot
-// k = 0 is the diagonal block; padding slots have col = r and zero value.
+// Local (compacted) block system in sliced-ELL form with a fixed slice
+// stride: slice s holds rows 64s..64s+63 in slots 64 wcap s .. 64 wcap
+// (s+1) - 1 (wcap = the largest row width of the grid, max degree + 1);
+// slot (row r, k) sits at 64 (wcap s + k) + (r - 64 s) for k < swidth[s];
+// slot k = 0 is the diagonal block; padding slots below the slice width
+// have col = r and zero value, slots at or past it are never read for
+// arithmetic.  The fixed stride puts a slot's address one step from the
+// row index (no slice-pointer load in front of the column loads).
 struct LocalSys {
     const int* l2g;         // [nA]
     const int* g2l;         // [n], -1 = inactive
-    const int* sptr;        // [nslices+1]
+    const int* swidth;      // [nslices] slots per row in slice s
+    int wcap;               // slice stride / 64
+    int pad;
     int* col;               // [slots]
     double* J;              // [slots b b] FP64 Jacobian blocks
     double* F;              // [nA b]
 };
+__host__ __device__ inline long slot_of(const LocalSys& ls, int r, int k) {
+    return ((long)(r / SLICE) * ls.wcap + k) * SLICE + (r % SLICE);
+}
 
 // Scalars of the BiCGStab iteration, recorded by block 0 of each kernel
 // for the kernels that follow and for the host.
@@ -77,7 +87,7 @@ void launch_compact(const uint8_t* act, int n, int* blk_cnt, int* l2g,
                     int* g2l, int* n_out, hipStream_t s);
 // also writes the number of blocks of the local matrix (diagonal included)
 void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
-                      int* swidth, int* sptr, int* blk, int* nnzb, hipStream_t s);
+                      int* swidth, int* nnzb, hipStream_t s);
 void launch_boundary(int nA, const int* l2g, const int* g2l, const Graph& g,
                      uint8_t* bnd, int* count, hipStream_t s);
 void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
@@ -154,16 +164,18 @@ struct KSeg {
 
 // r64 = -F - J x64, b~ = D^{-1} r64, Krylov initialisation; part_ir holds
 // (|r64|^2, |b~|^2) per block
-void launch_ir_residual(int b, bool fp32, const KSeg* segs, const int* blk_seg, int nblk_total,
-                        bool x_zero, hipStream_t s);
+// solo: the launch covers one model (segs[0]); its blocks then skip the
+// block-to-model lookup
+void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
+                        int nblk_total, bool x_zero, hipStream_t s);
 // which: 0 = kernel P (x, r update of iteration it-1; p and v = A p of it),
 // 1 = kernel S (s = r - alpha v, t = A s); it = iteration index (same for
 // every model of the launch)
 // ev0/ev1: optional events stamped with the kernel's own start and end
-void launch_bicg_part(int which, int b, bool fp32, const KSeg* segs, const int* blk_seg,
-                      int nblk_total, int it, hipStream_t s, hipEvent_t ev0 = nullptr,
-                      hipEvent_t ev1 = nullptr);
-void launch_ir_accumulate(int b, bool fp32, const KSeg* segs, const int* blk_seg,
+void launch_bicg_part(int which, int b, bool fp32, bool solo, const KSeg* segs,
+                      const int* blk_seg, int nblk_total, int it, hipStream_t s,
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
                           int nblk_total, hipStream_t s);
 
 struct SegStatus {

@@ -35,126 +35,159 @@ __host__ __device__ inline Vecs<B, T> make_vecs(const KrylovBufs& kb, int parity
     V.x = (T*)kb.x;
     V.r = (T*)kb.r;
     V.rh = (T*)kb.rh;
-    V.p_old = (T*)kb.p[parity];
-    V.v_old = (T*)kb.v[parity];
-    V.p_new = (T*)kb.p[parity ^ 1];
-    V.v_new = (T*)kb.v[parity ^ 1];
+    // selects, not indexing: kb may be a kernel argument
+    V.p_old = (T*)(parity ? kb.p[1] : kb.p[0]);
+    V.v_old = (T*)(parity ? kb.v[1] : kb.v[0]);
+    V.p_new = (T*)(parity ? kb.p[0] : kb.p[1]);
+    V.v_new = (T*)(parity ? kb.v[0] : kb.v[1]);
     V.s = (T*)kb.sv;
     V.t = (T*)kb.t;
     return V;
 }
 
-// p_new = r + beta (p_old - omega v_old), rounded to T; used for the own
-// row and for every neighbour so both see the same value
-template <typename T>
-__device__ inline double p_update(bool first, T r, T p, T v, double beta, double om) {
-    const double x = first ? (double)r : (double)r + beta * ((double)p - om * (double)v);
-    return (double)(T)x;
+// Loads and stores through the global address space with 32-bit byte
+// offsets from a wave-uniform base: the compiler then issues global (not
+// flat) memory instructions, which do not hold up LDS waits, and shares
+// one offset register between arrays indexed alike.  Every array these
+// kernels address this way stays below 4 GiB (checked at model creation).
+#define FIM_GLOBAL __attribute__((address_space(1)))
+template <typename V>
+__device__ inline V ldg(const void* base, unsigned off) {
+    return *(const FIM_GLOBAL V*)((const FIM_GLOBAL char*)base + off);
 }
-template <typename T>
-__device__ inline double s_update(T r, T v, double al) {
-    return (double)(T)((double)r - al * (double)v);
+template <typename V>
+__device__ inline void stg(void* base, unsigned off, V v) {
+    *(FIM_GLOBAL V*)((FIM_GLOBAL char*)base + off) = v;
+}
+template <int B, typename T>
+__device__ inline void ldv(T (&d)[B], const void* base, unsigned off) {
+#pragma unroll
+    for (int c = 0; c < B; c++) d[c] = ldg<T>(base, off + c * (unsigned)sizeof(T));
+}
+template <int B, typename T>
+__device__ inline void stv(void* base, unsigned off, const T (&v)[B]) {
+#pragma unroll
+    for (int c = 0; c < B; c++) stg<T>(base, off + c * (unsigned)sizeof(T), v[c]);
 }
 
-// Raw operands of one row of a product kernel: the slice geometry, the
-// column indices and blocks of the first UNR off-diagonal slots and the
-// values of NV source vectors at the row itself and at those neighbours.
-// They are fetched before the iteration's scalars are known, so the
-// fetches overlap the reduction of the previous kernel's partial sums; a
-// row then waits for about two memory round trips (columns, then gathers
-// and blocks) instead of two per slot.
-constexpr int UNR = 8;
+// Neighbour slots fetched together: enough to keep the raw operands of a
+// chunk within about 104 VGPRs (column offsets, blocks and NV gathered
+// vectors per slot), at most 8.
 template <int B, typename T, int NV>
-struct RowRaw {
-    int base, width, lane;
-    int cl[UNR];
-    T a[UNR][B * B];
-    T xn[NV][UNR][B];
-    T xo[NV][B];
+constexpr int chunk_slots() {
+    constexpr int w = (int)sizeof(T) / 4;
+    constexpr int per = 1 + (B * B + NV * B) * w;
+    constexpr int u = 104 / per;
+    return u < 2 ? 2 : (u > 8 ? 8 : u);
+}
+
+// Waves per SIMD the product kernels are compiled for (a VGPR cap of
+// 512 / waves): three, except FP64 3x3 blocks, whose first chunk needs
+// more registers than that leaves.
+template <int B, typename T>
+constexpr int kb_waves() { return (B == 3 && sizeof(T) == 8) ? 2 : 3; }
+
+// Slot geometry of row r: slot k at base + 64 k; width slots are in use,
+// cap (the slice stride) bounds the slots that may be read at all.
+struct RowGeo {
+    unsigned base, width, cap;
+};
+__device__ inline RowGeo row_geo(const LocalSys& ls, int r) {
+    RowGeo g;
+    g.base = (unsigned)slot_of(ls, r, 0);
+    g.width = (unsigned)ldg<int>(ls.swidth, 4u * (unsigned)(r / SLICE));
+    g.cap = (unsigned)ls.wcap;
+    return g;
+}
+
+// The segment a block works on: the first of the table for a
+// single-model launch (no block-to-model lookup in front of it), else
+// looked up by block.
+template <bool SOLO>
+__device__ inline const KSeg& seg_of(const KSeg* segs, const int* blk_seg) {
+    if constexpr (SOLO) return segs[0];
+    else return segs[blk_seg[blockIdx.x]];
+}
+
+// Raw operands of U off-diagonal slots k0 .. k0+U-1 of one row: the blocks
+// of A~ and the values of NV source vectors at the neighbours.  The column
+// indices of every slot below the slice stride are loaded at once,
+// together with the slice width (their addresses follow from the row index
+// alone); the blocks and gathers of the slots below the width follow, so a
+// chunk costs about two memory round trips.  Column words at or past the
+// width (stale memory) are never used.
+template <int B, typename T, int NV, int U>
+struct Chunk {
+    T a[U][B * B];
+    T xn[NV][U][B];
 };
 
-template <int B, typename T, int NV>
-__device__ inline void fetch_row(const LocalSys& ls, const T* __restrict__ At, int r,
-                                 const T* const* src, RowRaw<B, T, NV>& R) {
-    constexpr int BB = B * B;
-    const int s = r / SLICE;
-    R.lane = r % SLICE;
-    R.base = ls.sptr[s];
-    R.width = (ls.sptr[s + 1] - R.base) / SLICE;
+template <int B, typename T, int NV, int U>
+__device__ inline void fetch_chunk(const LocalSys& ls, const T* At, const RowGeo& g, unsigned k0,
+                                   const T* const (&src)[NV], Chunk<B, T, NV, U>& ch) {
+    constexpr unsigned BB = B * B, RB = B * sizeof(T);
+    unsigned cl[U];
 #pragma unroll
-    for (int v = 0; v < NV; v++)
-#pragma unroll
-        for (int c = 0; c < B; c++) R.xo[v][c] = src[v][(long)r * B + c];
-#pragma unroll
-    for (int u = 0; u < UNR; u++) {
-        const int k = 1 + u;   // k < width is uniform over the wave (one slice)
-        R.cl[u] = (k < R.width) ? ls.col[(long)R.base + (long)k * SLICE + R.lane] : r;
+    for (int u = 0; u < U; u++) {
+        const unsigned k = k0 + u;
+        cl[u] = 0;
+        if (k < g.cap) cl[u] = (unsigned)ldg<int>(ls.col, 4u * (g.base + k * SLICE));
     }
 #pragma unroll
-    for (int u = 0; u < UNR; u++) {
-        const int k = 1 + u;
-        if (k < R.width) {
-            const T* ap = At + ((long)R.base + (long)k * SLICE + R.lane) * BB;
+    for (int u = 0; u < U; u++) {
+        const unsigned k = k0 + u;
+        if (k < g.width) {
+            const unsigned ab = (g.base + k * SLICE) * (BB * (unsigned)sizeof(T));
 #pragma unroll
-            for (int q = 0; q < BB; q++) R.a[u][q] = ap[q];
+            for (unsigned q = 0; q < BB; q++) ch.a[u][q] = ldg<T>(At, ab + q * (unsigned)sizeof(T));
 #pragma unroll
-            for (int v = 0; v < NV; v++)
-#pragma unroll
-                for (int c = 0; c < B; c++) R.xn[v][u][c] = src[v][(long)R.cl[u] * B + c];
+            for (int v = 0; v < NV; v++) ldv<B, T>(ch.xn[v][u], src[v], cl[u] * RB);
         } else {
 #pragma unroll
-            for (int q = 0; q < BB; q++) R.a[u][q] = (T)0;
+            for (unsigned q = 0; q < BB; q++) ch.a[u][q] = (T)0;
 #pragma unroll
             for (int v = 0; v < NV; v++)
 #pragma unroll
-                for (int c = 0; c < B; c++) R.xn[v][u][c] = (T)0;
+                for (int c = 0; c < B; c++) ch.xn[v][u][c] = (T)0;
         }
     }
 }
 
-// y += sum_k A~_rk x_k with x_k = f(raw source values at neighbour k);
-// slots past the first UNR (wide rows) are loaded here directly
-template <int B, typename T, int NV, class FX>
-__device__ inline void finish_row(const LocalSys& ls, const T* __restrict__ At,
-                                  const T* const* src, const RowRaw<B, T, NV>& R,
-                                  double (&y)[B], FX fx) {
-    constexpr int BB = B * B;
+// y += sum over the chunk of A~_rk f(raw values at neighbour k), in FP64
+template <int B, typename T, int NV, int U, class FX>
+__device__ inline void apply_chunk(const Chunk<B, T, NV, U>& ch, unsigned k0, unsigned width,
+                                   double (&y)[B], FX fx) {
 #pragma unroll
-    for (int u = 0; u < UNR; u++) {
-        if (1 + u >= R.width) break;
+    for (int u = 0; u < U; u++) {
+        if (k0 + u >= width) break;
         T raw[NV][B];
 #pragma unroll
         for (int v = 0; v < NV; v++)
 #pragma unroll
-            for (int c = 0; c < B; c++) raw[v][c] = R.xn[v][u][c];
+            for (int c = 0; c < B; c++) raw[v][c] = ch.xn[v][u][c];
         double xj[B];
         fx(raw, xj);
 #pragma unroll
         for (int c = 0; c < B; c++) {
             double acc = 0.0;
 #pragma unroll
-            for (int v = 0; v < B; v++) acc += (double)R.a[u][c * B + v] * xj[v];
+            for (int v = 0; v < B; v++) acc += (double)ch.a[u][c * B + v] * xj[v];
             y[c] += acc;
         }
     }
-    for (int k = 1 + UNR; k < R.width; k++) {
-        const long pos = (long)R.base + (long)k * SLICE + R.lane;
-        const int cl = ls.col[pos];
-        T raw[NV][B];
-#pragma unroll
-        for (int v = 0; v < NV; v++)
-#pragma unroll
-            for (int c = 0; c < B; c++) raw[v][c] = src[v][(long)cl * B + c];
-        double xj[B];
-        fx(raw, xj);
-        const T* ap = At + pos * BB;
-#pragma unroll
-        for (int c = 0; c < B; c++) {
-            double acc = 0.0;
-#pragma unroll
-            for (int v = 0; v < B; v++) acc += (double)ap[c * B + v] * xj[v];
-            y[c] += acc;
-        }
+}
+
+// all off-diagonal slots of a row: the first chunk is already in ch (it
+// was fetched early); wider rows reuse ch for the following chunks, so the
+// operands of one chunk at a time are live
+template <int B, typename T, int NV, int U, class FX>
+__device__ inline void row_product(const LocalSys& ls, const T* At, const RowGeo& g,
+                                   const T* const (&src)[NV], Chunk<B, T, NV, U>& ch,
+                                   double (&y)[B], FX fx) {
+#pragma unroll 1
+    for (unsigned k0 = 1; k0 < g.width; k0 += U) {
+        if (k0 > 1) fetch_chunk<B, T, NV, U>(ls, At, g, k0, src, ch);
+        apply_chunk<B, T, NV, U>(ch, k0, g.width, y, fx);
     }
 }
 
@@ -168,13 +201,13 @@ static inline int kgrid(long rows) {
 // r64 = -F - J x64 (x64 skipped when zero), b~ = D^{-1} r64; x = 0,
 // r = rh = b~.  Partials: ir[q] = (|r64|^2, |b~|^2); pc[q] = ((rh,r), (r,r))
 // so that the first BiCGStab kernel finds rho_0 where it looks for rho.
-template <int B, typename T>
+template <int B, typename T, bool SOLO>
 __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ segs,
                                                        const int* __restrict__ blk_seg,
                                                        int x_zero) {
-    const KSeg& S = segs[blk_seg[blockIdx.x]];
+    const KSeg& S = seg_of<SOLO>(segs, blk_seg);
     if (!S.active) return;
-    const int lb = blockIdx.x - S.blk0, nbk = S.nblk, nA = S.nA;
+    const int nbk = S.nblk, nA = S.nA, lb = xcd_tile(S.blk0, nbk, blockIdx.x);
     const LocalSys& ls = S.ls;
     const KrylovBufs& kb = S.kb;
     constexpr int BB = B * B;
@@ -187,11 +220,10 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
 #pragma unroll
         for (int c = 0; c < B; c++) res[c] = -ls.F[(long)r * B + c];
         if (!x_zero) {
-            const int s = r / SLICE, lane = r % SLICE;
-            const int base = ls.sptr[s];
-            const int width = (ls.sptr[s + 1] - base) / SLICE;
+            const long base = slot_of(ls, r, 0);
+            const int width = ls.swidth[r / SLICE];
             for (int k = 0; k < width; k++) {
-                const long pos = (long)base + (long)k * SLICE + lane;
+                const long pos = base + (long)k * SLICE;
                 const int cl = ls.col[pos];
                 const double* a = ls.J + pos * BB;
 #pragma unroll
@@ -239,18 +271,23 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
 //   omega = (t,s)/(t,t), rho_i = (rh,s) - omega (rh,t)   [from kernel S]
 //   x += alpha p + omega s;  r_i = s - omega t           [own rows]
 //   p_i = r_i + beta (p_{i-1} - omega v_{i-1});  v_i = A~ p_i
-// with p_i at the neighbours rebuilt from s, t, p, v on the fly.  Partial
-// sums: (rh, v_i), (v_i, v_i), (r_i, r_i).  At i = 0, p_0 = r_0 (the
-// refinement initialisation).  Stops (after the x, r update) at the
-// iteration cap or when omega = 0.
-template <int B, typename T, bool FIRST>
-__global__ __launch_bounds__(KB_NT) void k_bicg_p(const KSeg* __restrict__ segs,
-                                                  const int* __restrict__ blk_seg, int it) {
-    const KSeg& S = segs[blk_seg[blockIdx.x]];
+// with p_i at the neighbours rebuilt from s, t, p, v on the fly (the same
+// expression as on the own row, so both see the same value).  Vectors are
+// stored in T; all arithmetic is FP64.
+// Partial sums: (rh, v_i), (v_i, v_i), (r_i, r_i).  At i = 0, p_0 = r_0
+// (the refinement initialisation) and x = 0 stays.  Stops (after the x, r
+// update) at the iteration cap or when omega = 0.  The own-row operands
+// and the first chunk of neighbour slots are fetched before the previous
+// kernel's partial sums are reduced, so those loads overlap the reduction.
+template <int B, typename T, bool FIRST, bool SOLO>
+__global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_p(const KSeg* __restrict__ segs,
+                                                                      const int* __restrict__ blk_seg,
+                                                                      int it) {
+    const KSeg& S = seg_of<SOLO>(segs, blk_seg);
     if (!S.active) return;
-    const int lb = blockIdx.x - S.blk0, nbk = S.nblk, nA = S.nA;
+    const int nbk = S.nblk, nA = S.nA, lb = xcd_tile(S.blk0, nbk, blockIdx.x);
     const LocalSys& ls = S.ls;
-    const T* __restrict__ At = (const T*)S.kb.At;
+    const T* At = (const T*)S.kb.At;
     const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
     KScal* __restrict__ sc = S.kb.sc;
     const double* __restrict__ pin = FIRST ? S.kb.part_c : S.kb.part_b;
@@ -268,6 +305,8 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_p(const KSeg* __restrict__ segs,
     const int r0 = lb * blockDim.x + threadIdx.x;
     const int stride = nbk * blockDim.x;
     constexpr int NV = FIRST ? 1 : 4;
+    constexpr int U = chunk_slots<B, T, NV>();
+    constexpr unsigned RB = B * sizeof(T);
     const T* src[NV];
     if constexpr (FIRST) {
         src[0] = V.r;
@@ -277,8 +316,19 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_p(const KSeg* __restrict__ segs,
         src[2] = V.p_old;
         src[3] = V.v_old;
     }
-    RowRaw<B, T, NV> R;
-    if (r0 < nA) fetch_row<B, T, NV>(ls, At, r0, src, R);
+    RowGeo g{0, 0, 0};
+    T own[NV][B] = {}, ox[B] = {}, orh[B] = {};
+    Chunk<B, T, NV, U> ch{};
+    auto fetch = [&](int r) {
+        g = row_geo(ls, r);
+        const unsigned ro = (unsigned)r * RB;
+#pragma unroll
+        for (int v = 0; v < NV; v++) ldv<B, T>(own[v], src[v], ro);
+        if constexpr (!FIRST) ldv<B, T>(ox, V.x, ro);
+        ldv<B, T>(orh, V.rh, ro);
+        fetch_chunk<B, T, NV, U>(ls, At, g, 1, src, ch);
+    };
+    if (r0 < nA) fetch(r0);
     block_sum<4>(red);
     double om = 0.0, rho, beta = 0.0;
     if (FIRST) {
@@ -298,50 +348,64 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_p(const KSeg* __restrict__ segs,
             sc->breakdown = 1;
         }
     }
-    double dot[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r = r0; r < nA; r += stride) {
-        if (r != r0) fetch_row<B, T, NV>(ls, At, r, src, R);
-        double ri[B], pi[B], vi[B];
-        if (FIRST) {
-#pragma unroll
-            for (int c = 0; c < B; c++) ri[c] = (double)R.xo[0][c];
-        } else {
-            // tail of iteration i-1 on the own row
-#pragma unroll
-            for (int c = 0; c < B; c++) {
-                const long q = (long)r * B + c;
-                const double sv = (double)R.xo[0][c];
-                V.x[q] = (T)((double)V.x[q] + al_prev * (double)R.xo[2][c] + om * sv);
-                ri[c] = (double)(T)(sv - om * (double)R.xo[1][c]);
-                V.r[q] = (T)ri[c];
-            }
-        }
-        if (stop) continue;
-        auto fx = [&](const T (&raw)[NV][B], double (&x)[B]) {
-#pragma unroll
-            for (int c = 0; c < B; c++) {
-                if constexpr (FIRST) {
-                    x[c] = (double)raw[0][c];
-                } else {
-                    const double rr_ = (double)(T)((double)raw[0][c] - om * (double)raw[1][c]);
-                    x[c] = (double)(T)(rr_ + beta * ((double)raw[2][c] - om * (double)raw[3][c]));
-                }
-            }
-        };
-        fx(R.xo, pi);
-#pragma unroll
-        for (int c = 0; c < B; c++) vi[c] = pi[c];
-        finish_row<B, T, NV>(ls, At, src, R, vi, fx);
+    // p_i from the raw (s, t, p_{i-1}, v_{i-1}) of a row: FP64 arithmetic,
+    // r_i and p_i rounded to T as they are stored
+    auto fx = [&](const T (&raw)[NV][B], double (&x)[B]) {
 #pragma unroll
         for (int c = 0; c < B; c++) {
-            const long q = (long)r * B + c;
-            V.p_new[q] = (T)pi[c];
-            const T vT = (T)vi[c];
-            V.v_new[q] = vT;
-            dot[0] += (double)V.rh[q] * (double)vT;
-            dot[1] += (double)vT * (double)vT;
-            dot[2] += ri[c] * ri[c];
+            if constexpr (FIRST) {
+                x[c] = (double)raw[0][c];
+            } else {
+                const double rr_ = (double)(T)((double)raw[0][c] - om * (double)raw[1][c]);
+                x[c] = (double)(T)(rr_ + beta * ((double)raw[2][c] - om * (double)raw[3][c]));
+            }
         }
+    };
+    double dot[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int r = r0; r < nA; r += stride) {
+        const unsigned ro = (unsigned)r * RB;
+        T ri[B];
+        double pi[B], vi[B];
+        if constexpr (FIRST) {
+#pragma unroll
+            for (int c = 0; c < B; c++) ri[c] = own[0][c];
+        } else {
+            // tail of iteration i-1 on the own row
+            T xn[B];
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                const double sv = (double)own[0][c];
+                xn[c] = (T)((double)ox[c] + al_prev * (double)own[2][c] + om * sv);
+                ri[c] = (T)(sv - om * (double)own[1][c]);
+            }
+            stv<B, T>(V.x, ro, xn);
+            stv<B, T>(V.r, ro, ri);
+        }
+        if (stop) {
+            if (r + stride < nA) fetch(r + stride);
+            continue;
+        }
+        fx(own, pi);
+#pragma unroll
+        for (int c = 0; c < B; c++) vi[c] = pi[c];      // diagonal block of A~ is I
+        row_product<B, T, NV, U>(ls, At, g, src, ch, vi, fx);
+        T pT[B], vT[B];
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            pT[c] = (T)pi[c];
+            vT[c] = (T)vi[c];
+        }
+        stv<B, T>(V.p_new, ro, pT);
+        stv<B, T>(V.v_new, ro, vT);
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            dot[0] += (double)orh[c] * (double)vT[c];
+            dot[1] += (double)vT[c] * (double)vT[c];
+            dot[2] += (double)ri[c] * (double)ri[c];
+        }
+        // (fetched here, not at the top of the loop, so that the first
+        // chunk's registers are dead during the rest of the row)
+        if (r + stride < nA) fetch(r + stride);
     }
     block_sum<4>(dot);
     if (threadIdx.x == 0) {
@@ -355,14 +419,15 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_p(const KSeg* __restrict__ segs,
 // |r_i|^2 <= tol2 (x_i is the answer) or on a breakdown of sigma; else
 // alpha = rho_i / sigma, s = r_i - alpha v_i, t = A~ s (s rebuilt at the
 // neighbours).  Partial sums: (t,s), (t,t), (rh,s), (rh,t).
-template <int B, typename T>
-__global__ __launch_bounds__(KB_NT) void k_bicg_s(const KSeg* __restrict__ segs,
-                                                  const int* __restrict__ blk_seg, int it) {
-    const KSeg& S = segs[blk_seg[blockIdx.x]];
+template <int B, typename T, bool SOLO>
+__global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_s(const KSeg* __restrict__ segs,
+                                                                      const int* __restrict__ blk_seg,
+                                                                      int it) {
+    const KSeg& S = seg_of<SOLO>(segs, blk_seg);
     if (!S.active) return;
-    const int lb = blockIdx.x - S.blk0, nbk = S.nblk, nA = S.nA;
+    const int nbk = S.nblk, nA = S.nA, lb = xcd_tile(S.blk0, nbk, blockIdx.x);
     const LocalSys& ls = S.ls;
-    const T* __restrict__ At = (const T*)S.kb.At;
+    const T* At = (const T*)S.kb.At;
     const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
     KScal* __restrict__ sc = S.kb.sc;
     const double* __restrict__ pa = S.kb.part_a;
@@ -376,11 +441,24 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_s(const KSeg* __restrict__ segs,
         for (int k = 0; k < 3; k++) red[k] += pa[(long)q * 4 + k];
     }
     if (done) return;
-    const T* const src[2] = {V.r, V.v_new};
+    constexpr int NV = 2;
+    constexpr int U = chunk_slots<B, T, NV>();
+    constexpr unsigned RB = B * sizeof(T);
+    const T* const src[NV] = {V.r, V.v_new};
     const int r0 = lb * blockDim.x + threadIdx.x;
     const int stride = nbk * blockDim.x;
-    RowRaw<B, T, 2> R;
-    if (r0 < nA) fetch_row<B, T, 2>(ls, At, r0, src, R);
+    RowGeo g{0, 0, 0};
+    T own[NV][B] = {}, orh[B] = {};
+    Chunk<B, T, NV, U> ch{};
+    auto fetch = [&](int r) {
+        g = row_geo(ls, r);
+        const unsigned ro = (unsigned)r * RB;
+#pragma unroll
+        for (int v = 0; v < NV; v++) ldv<B, T>(own[v], src[v], ro);
+        ldv<B, T>(orh, V.rh, ro);
+        fetch_chunk<B, T, NV, U>(ls, At, g, 1, src, ch);
+    };
+    if (r0 < nA) fetch(r0);
     block_sum<3>(red);
     const double sigma = red[0], vv = red[1], rr = red[2];
     const double al = rho / sigma;
@@ -398,30 +476,35 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_s(const KSeg* __restrict__ segs,
         }
     }
     if (conv || bad) return;
-    auto fx = [&](const T (&raw)[2][B], double (&x)[B]) {
+    auto fx = [&](const T (&raw)[NV][B], double (&x)[B]) {
 #pragma unroll
-        for (int c = 0; c < B; c++) x[c] = s_update<T>(raw[0][c], raw[1][c], al);
+        for (int c = 0; c < B; c++) x[c] = (double)(T)((double)raw[0][c] - al * (double)raw[1][c]);
     };
     double dot[4] = {0.0, 0.0, 0.0, 0.0};
     for (int r = r0; r < nA; r += stride) {
-        if (r != r0) fetch_row<B, T, 2>(ls, At, r, src, R);
+        const unsigned ro = (unsigned)r * RB;
         double si[B], ti[B];
-        fx(R.xo, si);
+        fx(own, si);
 #pragma unroll
         for (int c = 0; c < B; c++) ti[c] = si[c];
-        finish_row<B, T, 2>(ls, At, src, R, ti, fx);
+        row_product<B, T, NV, U>(ls, At, g, src, ch, ti, fx);
+        T sT[B], tT[B];
 #pragma unroll
         for (int c = 0; c < B; c++) {
-            const long q = (long)r * B + c;
-            const T sT = (T)si[c], tT = (T)ti[c];
-            V.s[q] = sT;
-            V.t[q] = tT;
-            const double h = (double)V.rh[q];
-            dot[0] += (double)tT * (double)sT;
-            dot[1] += (double)tT * (double)tT;
-            dot[2] += h * (double)sT;
-            dot[3] += h * (double)tT;
+            sT[c] = (T)si[c];
+            tT[c] = (T)ti[c];
         }
+        stv<B, T>(V.s, ro, sT);
+        stv<B, T>(V.t, ro, tT);
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            const double sd = (double)sT[c], td = (double)tT[c], h = (double)orh[c];
+            dot[0] += td * sd;
+            dot[1] += td * td;
+            dot[2] += h * sd;
+            dot[3] += h * td;
+        }
+        if (r + stride < nA) fetch(r + stride);
     }
     block_sum<4>(dot);
     if (threadIdx.x == 0) {
@@ -430,12 +513,12 @@ __global__ __launch_bounds__(KB_NT) void k_bicg_s(const KSeg* __restrict__ segs,
     }
 }
 
-template <int B, typename T>
+template <int B, typename T, bool SOLO>
 __global__ __launch_bounds__(KB_NT) void k_ir_accumulate(const KSeg* __restrict__ segs,
                                                          const int* __restrict__ blk_seg) {
-    const KSeg& S = segs[blk_seg[blockIdx.x]];
+    const KSeg& S = seg_of<SOLO>(segs, blk_seg);
     if (!S.active) return;
-    const int lb = blockIdx.x - S.blk0, nbk = S.nblk;
+    const int nbk = S.nblk, lb = xcd_tile(S.blk0, nbk, blockIdx.x);
     double* __restrict__ x64 = S.kb.x64;
     const T* __restrict__ xT = (const T*)S.kb.x;
     for (long q = (long)lb * blockDim.x + threadIdx.x; q < (long)S.nA * B;
@@ -456,17 +539,19 @@ void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s) {
 
 // ev0/ev1 (optional): events stamped by the dispatch itself
 // (hipExtLaunchKernelGGL), i.e. the kernel's own start and end
-template <int B, typename T>
+template <int B, typename T, bool SOLO>
 static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 nb(nblk_total), nt(KB_NT);
     if (which == 0) {
         if (it == 0)
-            hipExtLaunchKernelGGL(k_bicg_p<B, T, true>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
+            hipExtLaunchKernelGGL(k_bicg_p<B, T, true, SOLO>, nb, nt, 0, s, ev0, ev1, 0, segs,
+                                  blk_seg, it);
         else
-            hipExtLaunchKernelGGL(k_bicg_p<B, T, false>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
+            hipExtLaunchKernelGGL(k_bicg_p<B, T, false, SOLO>, nb, nt, 0, s, ev0, ev1, 0, segs,
+                                  blk_seg, it);
     } else {
-        hipExtLaunchKernelGGL(k_bicg_s<B, T>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
+        hipExtLaunchKernelGGL(k_bicg_s<B, T, SOLO>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
     }
 }
 
@@ -509,26 +594,47 @@ void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s
         if (b == 1) MACRO(1, double); else if (b == 2) MACRO(2, double); else MACRO(3, double);   \
     }
 
-void launch_ir_residual(int b, bool fp32, const KSeg* segs, const int* blk_seg, int nblk_total,
-                        bool x_zero, hipStream_t s) {
+void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
+                        int nblk_total, bool x_zero, hipStream_t s) {
     if (nblk_total <= 0) return;
-#define IR(BV, TT) k_ir_residual<BV, TT><<<nblk_total, KB_NT, 0, s>>>(segs, blk_seg, x_zero ? 1 : 0)
+#define IR(BV, TT)                                                                         \
+    do {                                                                                   \
+        if (solo)                                                                          \
+            k_ir_residual<BV, TT, true><<<nblk_total, KB_NT, 0, s>>>(segs, blk_seg,        \
+                                                                     x_zero ? 1 : 0);      \
+        else                                                                               \
+            k_ir_residual<BV, TT, false><<<nblk_total, KB_NT, 0, s>>>(segs, blk_seg,       \
+                                                                      x_zero ? 1 : 0);     \
+    } while (0)
     KDISPATCH(IR)
 #undef IR
 }
 
-void launch_bicg_part(int which, int b, bool fp32, const KSeg* segs, const int* blk_seg,
-                      int nblk_total, int it, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+void launch_bicg_part(int which, int b, bool fp32, bool solo, const KSeg* segs,
+                      const int* blk_seg, int nblk_total, int it, hipStream_t s, hipEvent_t ev0,
+                      hipEvent_t ev1) {
     if (nblk_total <= 0) return;
-#define PI(BV, TT) part_impl<BV, TT>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1)
+#define PI(BV, TT)                                                                          \
+    do {                                                                                    \
+        if (solo)                                                                           \
+            part_impl<BV, TT, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1);      \
+        else                                                                                \
+            part_impl<BV, TT, false>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1);     \
+    } while (0)
     KDISPATCH(PI)
 #undef PI
 }
 
-void launch_ir_accumulate(int b, bool fp32, const KSeg* segs, const int* blk_seg,
+void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
                           int nblk_total, hipStream_t s) {
     if (nblk_total <= 0) return;
-#define AC(BV, TT) k_ir_accumulate<BV, TT><<<nblk_total, KB_NT, 0, s>>>(segs, blk_seg)
+#define AC(BV, TT)                                                                          \
+    do {                                                                                    \
+        if (solo)                                                                           \
+            k_ir_accumulate<BV, TT, true><<<nblk_total, KB_NT, 0, s>>>(segs, blk_seg);       \
+        else                                                                                \
+            k_ir_accumulate<BV, TT, false><<<nblk_total, KB_NT, 0, s>>>(segs, blk_seg);      \
+    } while (0)
     KDISPATCH(AC)
 #undef AC
 }

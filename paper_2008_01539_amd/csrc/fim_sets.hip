@@ -131,63 +131,11 @@ __global__ __launch_bounds__(NT) void k_slice_width(int nA, const int* __restric
     if ((threadIdx.x % WAVE) == 0 && r < nA) swidth[r / SLICE] = cnt;
 }
 
-// exclusive scan of swidth (x SLICE) into sptr[0..ns]; tiles of NT*16
-__global__ __launch_bounds__(NT) void k_scan_count(const int* __restrict__ a, int ns,
-                                                   int* __restrict__ blk) {
-    const int base = blockIdx.x * TILE + threadIdx.x * PER;
-    int c = 0;
-#pragma unroll
-    for (int q = 0; q < PER; q++)
-        if (base + q < ns) c += a[base + q];
-    c = block_sum_i(c);
-    if (threadIdx.x == 0) blk[blockIdx.x] = c;
-}
-
-__global__ __launch_bounds__(NT) void k_scan_apply(const int* __restrict__ a, int ns,
-                                                   const int* __restrict__ blk,
-                                                   int* __restrict__ sptr) {
-    __shared__ int wsum[NT / WAVE];
-    int off = 0;
-    for (int t = threadIdx.x; t < (int)blockIdx.x; t += NT) off += blk[t];
-    off = block_sum_i(off);
-    const int base = blockIdx.x * TILE + threadIdx.x * PER;
-    int v[PER];
-    int c = 0;
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-        v[q] = (base + q < ns) ? a[base + q] : 0;
-        c += v[q];
-    }
-    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    int inc = c;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        int y = __shfl_up(inc, o, WAVE);
-        if (lane >= o) inc += y;
-    }
-    __syncthreads();
-    if (lane == WAVE - 1) wsum[w] = inc;
-    __syncthreads();
-    int wo = 0;
-    for (int q = 0; q < w; q++) wo += wsum[q];
-    int pos = off + wo + inc - c;
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-        if (base + q < ns) sptr[base + q] = pos * SLICE;
-        pos += v[q];
-    }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == NT - 1) sptr[ns] = pos * SLICE;
-}
-
 void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
-                      int* swidth, int* sptr, int* blk, int* nnzb, hipStream_t s) {
+                      int* swidth, int* nnzb, hipStream_t s) {
     launch_fill_i32(nnzb, 1, 0, s);
     if (nA <= 0) return;
-    const int ns = (nA + SLICE - 1) / SLICE;
     k_slice_width<<<nblocks(nA), NT, 0, s>>>(nA, l2g, g2l, g, swidth, nnzb);
-    const int nt = (ns + TILE - 1) / TILE;
-    k_scan_count<<<nt, NT, 0, s>>>(swidth, ns, blk);
-    k_scan_apply<<<nt, NT, 0, s>>>(swidth, ns, blk, sptr);
 }
 
 // -------------------------------------------------------------- boundary
