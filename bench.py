@@ -235,20 +235,23 @@ def run_c4(members, steps):
 
 def _c5_session(args):
     kind, k = args
-    from fimgen import make_c1, make_small_c2, make_small_c3
+    from fimgen import make_c1, make_c2, make_c3
     if kind == 1:
         return make_c1(seed=5000 + k)
     if kind == 2:
-        return make_small_c2(seed=6000 + k, nx=60, ny=30, nz=10, nfrac=180, nstage=6)
-    return make_small_c3(seed=7000 + k, nx=40, ny=20, nz=8, nfrac=60, nstage=4)
+        return make_c2(seed=6000 + k)
+    return make_c3(seed=7000 + k)
 
 
-def run_c5(seconds, n1, n2, n3, budget_gib, rate=50.0):
-    """Serving: Poisson timestep requests at `rate`/s over sessions of
-    config-1, -2 and -3 recipes (50/40/10 % of requests)."""
+def run_c5(seconds, pool, budget_gib, rate=50.0):
+    """Serving: Poisson timestep requests at `rate`/s over a pool of
+    config-1, -2 and -3 sessions (50/40/10 % of requests); sessions are
+    admitted up to the HBM budget before the clock starts, the rest on
+    demand (evicting idle ones)."""
     import numpy as np
     import paper_2008_01539_amd as P
     from paper_2008_01539_amd.serve import GpuExecutor, Server, SessionSpec
+    n1, n2, n3 = pool
     log(f"generating sessions {n1}/{n2}/{n3}")
     ids = [(1, k) for k in range(n1)] + [(2, k) for k in range(n2)] + [(3, k) for k in range(n3)]
     models = _pool_models(_c5_session, ids)
@@ -258,18 +261,25 @@ def run_c5(seconds, n1, n2, n3, budget_gib, rate=50.0):
     ex = GpuExecutor()
     srv = Server(specs, ex, budget_bytes=int(budget_gib * 2**30), max_inflight=64,
                  footprint=lambda sp: P.estimate_bytes(sp.model, sp.options))
-    log(f"serving {seconds}s at {rate}/s, budget {budget_gib} GiB")
-    summ = srv.run_poisson(rate=rate, duration=seconds, mix=mix, seed=5)
+    t0 = time.perf_counter()
+    res = srv.warm()
+    log(f"warm: {res} sessions resident ({srv.used / 2**30:.1f} GiB) in "
+        f"{time.perf_counter() - t0:.1f}s; serving {seconds}s at {rate}/s")
+    summ = srv.run_poisson(
+        rate=rate, duration=seconds, mix=mix, seed=5,
+        progress=lambda t, st: log(f"t={t:.0f}s completed {st.completed} ticks {st.ticks} "
+                                   f"queued {len(srv.queue)} inflight {len(srv.inflight)}"))
     ex.close()
     return {
         "metric": "served timestep requests/s and p50/p99 request latency (1 GPU)",
         "value": summ["throughput_rps"], "unit": "requests/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"config 5: Poisson arrivals at {rate}/s for {seconds}s, "
-                               f"50/40/10 % of requests over {n1} config-1, {n2} config-2-recipe "
-                               f"(60x30x10) and {n3} config-3-recipe (40x20x8) sessions, "
-                               f"HBM budget {budget_gib} GiB, continuous batching",
-                   "rate": rate, "seconds": seconds},
+                               f"50/40/10 % of requests over {n1} config-1, {n2} config-2 and "
+                               f"{n3} config-3 sessions (full sizes; seeds 5000+k, 6000+k, "
+                               f"7000+k), HBM budget {budget_gib} GiB, continuous batching",
+                   "rate": rate, "seconds": seconds, "pool": list(pool),
+                   "budget_gib": budget_gib},
         "serving": summ,
     }
 
@@ -307,6 +317,8 @@ def main():
     ap.add_argument("--members", type=int, default=256)
     ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--pool", default="256,64,16",
+                    help="serving: config-1,2,3 session counts")
     ap.add_argument("--steps", type=int, default=18)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
@@ -328,7 +340,8 @@ def main():
         print(json.dumps(run_c4(args.members, max(1, args.steps))), flush=True)
         return
     if args.workload == "c5":
-        print(json.dumps(run_c5(args.serve_seconds, 64, 16, 4, args.budget_gib)), flush=True)
+        pool = tuple(int(v) for v in args.pool.split(","))
+        print(json.dumps(run_c5(args.serve_seconds, pool, args.budget_gib)), flush=True)
         return
     if args.workload == "c3":
         print(json.dumps(run_c3(args.steps, args.warmup)), flush=True)

@@ -75,7 +75,10 @@ typedef struct fim_fluid {
  * the caller keeps ownership).  Connections need conn_i < conn_j, no
  * duplicates, T >= 0; pore volumes > 0; at most one perforation per cell.
  * Pore volume is pv_ref (1 + c_r (p - p_ref_rock)).  always_active may be
- * NULL (no cell always active); the paper keeps fracture cells active. */
+ * NULL (no cell always active); the paper keeps fracture cells active.
+ * frac_id may be NULL; else the fracture (>= 0) each cell belongs to, -1
+ * for matrix cells: the linear solver's fracture-block preconditioner
+ * groups cells of one fracture that are consecutive in the cell order. */
 typedef struct fim_model_desc {
     int32_t n_cells, n_conn, n_perf;
     const double*  pv_ref;        /* [n] m^3                               */
@@ -89,7 +92,16 @@ typedef struct fim_model_desc {
     const double*  perf_bhp;      /* [n_perf] Pa                           */
     double c_r, p_ref_rock, gravity;
     fim_fluid fluid;
+    const int32_t* frac_id;       /* [n] or NULL                           */
 } fim_model_desc;
+
+/* Preconditioners of the local linear solve (the paper names none). */
+enum {
+    FIM_PC_JACOBI = 0,     /* block Jacobi over the b x b cell blocks          */
+    FIM_PC_FRACTURE = 1    /* plus exact inverses of fracture blocks: runs of
+                              up to 128/b consecutive rows of one fracture
+                              inside a 256-row tile, applied on the left      */
+};
 
 /* Solver options.  fim_default_options fills the paper's settings
  * (Section 5: eps_p = 0.3 psi cutoff and convergence, m = 2 for
@@ -113,6 +125,8 @@ typedef struct fim_options {
     int32_t krylov_maxit;    /* BiCGStab iterations per refinement pass        */
     int32_t max_refine;      /* refinement passes                              */
     int32_t check_every;     /* BiCGStab iterations between host checks        */
+    int32_t precond;         /* FIM_PC_JACOBI or FIM_PC_FRACTURE (default;
+                                Jacobi when the model has no frac_id)          */
 } fim_options;
 
 typedef struct fim_iter_stats {

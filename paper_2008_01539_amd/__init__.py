@@ -4,10 +4,11 @@ ctypes binding.
 
     from paper_2008_01539_amd import FimModel, Options, LOCAL
 """
-from .fim import (DD, DEVICE, FP64, FULL, HOST, LIB_PATH, LOCAL, MIXED, FimBatch, FimError,
-                  FimModel, IterStats, NotConverged, Options, StepStats,
+from .fim import (DD, DEVICE, FP64, FULL, HOST, LIB_PATH, LOCAL, MIXED, PC_FRACTURE, PC_JACOBI,
+                  FimBatch, FimError, FimModel, IterStats, NotConverged, Options, StepStats,
                   estimate_bytes, exported_symbols)
 
 __all__ = ["FimModel", "FimBatch", "Options", "FimError", "NotConverged", "IterStats",
-           "StepStats", "FULL", "LOCAL", "DD", "FP64", "MIXED", "HOST", "DEVICE",
+           "StepStats", "FULL", "LOCAL", "DD", "FP64", "MIXED", "HOST", "DEVICE", "PC_JACOBI",
+           "PC_FRACTURE",
            "LIB_PATH", "estimate_bytes", "exported_symbols"]

@@ -12,8 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libfim.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["fim_api.hip", "fim_assemble.hip", "fim_krylov.hip", "fim_sets.hip",
-           "fim_update.hip"]
+SOURCES = ["fim_api.hip", "fim_assemble.hip", "fim_fracpc.hip", "fim_krylov.hip",
+           "fim_sets.hip", "fim_update.hip"]
 ARCH = os.environ.get("FIM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -20,10 +20,11 @@ using namespace fimk;
 // Optional event profiler: hipEvent pairs on the model's stream around each
 // kernel (or kernel group), read back at the next synchronisation.
 enum { PK_ASSEMBLE, PK_PRECOND, PK_IR, PK_BICG_A, PK_BICG_B, PK_UPDATE, PK_SETS, PK_SETUP,
-       PK_N };
+       PK_PCINV, PK_PCV_A, PK_PCV_B, PK_N };
 static const char* const kPkName[PK_N] = {"assemble", "precond", "ir_residual", "bicg_spmv_p",
                                           "bicg_spmv_s", "update", "sets_compact",
-                                          "step_setup"};
+                                          "step_setup", "frac_invert", "frac_apply_p",
+                                          "frac_apply_s"};
 struct ProfRec {
     int k;
     hipEvent_t a, b;
@@ -76,9 +77,14 @@ struct fim_model {
     double *J = nullptr, *F = nullptr, *dinv = nullptr;
     void* At = nullptr;
     long slot_cap = 0;
+    // fracture-block preconditioner (use_pc false: block Jacobi only)
+    bool use_pc = false;
+    int pc_cap = 0;                 // rows per block
+    int *frac_id = nullptr, *ford = nullptr, *pcinfo = nullptr, *pcoff = nullptr;
+    float* pcM = nullptr;           // FP32 inverses
     // Krylov
     double *x64 = nullptr, *xprev = nullptr, *rir = nullptr, *part = nullptr;
-    double* part_ir = nullptr;   // Krylov partials: 14 x KB_MAXB
+    double* part_ir = nullptr;   // Krylov partials: 22 x KB_MAXB
     double* hpart = nullptr;     // pinned copy of the refinement partials
     void* kvec = nullptr;   // 9 vectors of nA b elements in the Krylov precision
     KScal* sc = nullptr;
@@ -234,6 +240,11 @@ static KrylovBufs kbufs(fim_model* m, bool fp32) {
     kb.part_c = m->part_ir + 10 * KB_MAXB;
     kb.dinv = m->dinv;
     kb.At = m->At;
+    kb.pcinfo = m->pcinfo;
+    kb.pcoff = m->pcoff;
+    kb.pcM = m->use_pc ? m->pcM : nullptr;
+    kb.part_a2 = m->part_ir + 14 * KB_MAXB;
+    kb.part_b2 = m->part_ir + 18 * KB_MAXB;
     return kb;
 }
 
@@ -262,6 +273,9 @@ static fim_status read_int(fim_model* m) {
 
 static fim_status structure(fim_model* m) {
     launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, &m->dint[4], m->s);
+    if (m->use_pc)
+        launch_pc_blocks(m->nA, m->l2g, m->frac_id, m->ford, m->pc_cap,
+                         m->pc_cap * m->B * m->B, m->pcinfo, m->pcoff, m->s);
     return FIM_OK;
 }
 
@@ -303,6 +317,7 @@ struct SolveItem {
 struct Group {
     std::vector<int> idx;   // items in this group
     int nblk = 0;
+    bool pc = false;        // some model uses fracture blocks
 };
 
 static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
@@ -329,6 +344,8 @@ static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
         segs.push_back(k);
     }
     G.nblk = off;
+    G.pc = false;
+    for (int q : G.idx) G.pc = G.pc || items[q].m->use_pc;
     if (segs.empty()) return fim_status(FIM_OK);
     fim_model* m = lead;
     HIPX(hipMemcpyAsync(t.dsegs + (size_t)g * t.cap, segs.data(), segs.size() * sizeof(KSeg),
@@ -384,6 +401,12 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         const int pi = pbeg(lead, PK_PRECOND);
         launch_precond(mq->B, it.fp32, mq->nA, lsys(mq), mq->dinv, mq->At, s);
         pend(lead, pi, mq->nA);
+        if (mq->use_pc) {
+            const int pv = pbeg(lead, PK_PCINV);
+            launch_pc_invert(mq->B, mq->nA, lsys(mq), mq->dinv, mq->pcinfo, mq->pcoff,
+                             mq->pcM, s);
+            pend(lead, pv, mq->nA);
+        }
         launch_fill_f64(mq->x64, (long)mq->nA * mq->B, 0.0, s);
         G[it.fp32 ? 0 : 1].idx.push_back(q);
     }
@@ -445,6 +468,16 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                                          first_it + c, s, q >= 0 ? lead->prof.pend[q].a : nullptr,
                                          q >= 0 ? lead->prof.pend[q].b : nullptr);
                         if (q >= 0) lead->prof.pend[q].rows = lead->nA;
+                        if (G[g].pc) {
+                            const int qv = pbeg_ext(lead, PK_PCV_A + w, c);
+                            launch_pc_vec(w, b, g == 0, solo_of(t, G, g),
+                                          t.dsegs + (size_t)g * t.cap,
+                                          t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk,
+                                          first_it + c, s,
+                                          qv >= 0 ? lead->prof.pend[qv].a : nullptr,
+                                          qv >= 0 ? lead->prof.pend[qv].b : nullptr);
+                            if (qv >= 0) lead->prof.pend[qv].rows = lead->nA;
+                        }
                     }
         };
         // status of the queued work into slot sl (2 slots), then an event
@@ -781,6 +814,7 @@ void fim_default_options(fim_options* o) {
     o->krylov_maxit = 2000;
     o->max_refine = 20;
     o->check_every = 8;
+    o->precond = FIM_PC_FRACTURE;
 }
 
 static thread_local std::string g_create_err;
@@ -801,7 +835,8 @@ static void free_all(fim_model* m) {
                     m->supp, m->bnd, m->vt, m->outer, m->l2g, m->g2l, m->swidth,
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
-                    m->part_ir, m->classes};
+                    m->part_ir, m->classes, m->frac_id, m->ford, m->pcinfo, m->pcoff,
+                    m->pcM};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (m->hsc) (void)hipHostFree(m->hsc);
@@ -842,6 +877,9 @@ static fim_status validate(const fim_model_desc* d, std::string& e) {
             return FIM_E_ARG;
         }
     }
+    if (d->frac_id)
+        for (int i = 0; i < n; i++)
+            if (d->frac_id[i] < -1) { e = "frac_id must be >= -1"; return FIM_E_ARG; }
     std::vector<uint8_t> seen(n, 0);
     for (int p = 0; p < d->n_perf; p++) {
         const int c = d->perf_cell[p];
@@ -1001,8 +1039,31 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(dal(m, &m->part, 4 * ((nn * B + NT - 1) / NT + 1)));
     CK(dalloc(m, &m->kvec, 9 * nn * B * sizeof(double)));
     CK(dal(m, &m->xprev, nn * B));
+    std::vector<int> ford;   // fracture-cell ordinal per cell, -1 elsewhere
+    if (d->frac_id && m->o.precond == FIM_PC_FRACTURE) {
+        ford.assign(n, -1);
+        int nfc = 0;
+        for (int i = 0; i < n; i++)
+            if (d->frac_id[i] >= 0) ford[i] = nfc++;
+        if (nfc > 0) {
+            m->pc_cap = PC_DOF / B;
+            const double store = (double)nfc * m->pc_cap * B * B * sizeof(float);
+            if (store >= 4294967296.0) {
+                g_create_err = "model too large: fracture-block inverses would exceed 4 GiB";
+                free_all(m);
+                delete m;
+                return FIM_E_ARG;
+            }
+            CK(dal(m, &m->frac_id, nn));
+            CK(dal(m, &m->ford, nn));
+            CK(dal(m, &m->pcinfo, nn));
+            CK(dal(m, &m->pcoff, nn));
+            CK(dal(m, &m->pcM, (size_t)nfc * m->pc_cap * B * B));
+            m->use_pc = true;
+        }
+    }
     CK(dal(m, &m->sc, 1));
-    CK(dal(m, &m->part_ir, 14 * KB_MAXB));
+    CK(dal(m, &m->part_ir, 22 * KB_MAXB));
     CK(dal(m, &m->ns, 1));
     CK(dal(m, &m->dint, 8));
     CK(dal(m, &m->dsub, 1024));
@@ -1027,6 +1088,10 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(up(m->wi, wi.data(), nn * sizeof(double)));
     CK(up(m->bhp, bh.data(), nn * sizeof(double)));
     CK(up(m->flags, fl.data(), nn));
+    if (m->use_pc) {
+        CK(up(m->frac_id, d->frac_id, nn * sizeof(int)));
+        CK(up(m->ford, ford.data(), nn * sizeof(int)));
+    }
     // zero the counters and state
     std::vector<char> z(std::max(sizeof(KScal), sizeof(NStat)), 0);
     CK(up(m->sc, z.data(), sizeof(KScal)));
@@ -1305,7 +1370,6 @@ int64_t fim_model_bytes(const fim_model* m) { return m ? (int64_t)m->bytes : 0; 
 
 int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     if (!d || d->n_cells <= 0) return -1;
-    (void)o;
     const size_t n = (size_t)d->n_cells;
     const size_t B = (size_t)d->fluid.kind;
     std::vector<int> deg(n, 0);
@@ -1329,6 +1393,12 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     b += n * B * (8 + B * 8);                     // F, dinv
     b += n * B * 8 * 3 + n * B * 8 * 9;           // x64, xprev, rir, Krylov vectors
     b += 4 * (n * B / NT + 2) * 8 + 8 * KB_MAXB * 8;
+    const int pc = o ? o->precond : FIM_PC_FRACTURE;
+    if (d->frac_id && pc == FIM_PC_FRACTURE) {
+        size_t nfc = 0;
+        for (size_t i = 0; i < n; i++) nfc += d->frac_id[i] >= 0 ? 1 : 0;
+        if (nfc) b += n * 16 + nfc * (size_t)(PC_DOF / B) * B * B * 4;
+    }
     return (int64_t)b;
 }
 

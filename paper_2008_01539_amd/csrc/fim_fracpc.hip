@@ -1,0 +1,188 @@
+// Fracture-block preconditioner for the local linear solve (Section 4.3
+// leaves the solver open).  The hard part of these systems is the
+// fracture network: fracture cells couple to each other through
+// transmissibilities orders of magnitude above the matrix ones, while
+// matrix rows are strongly diagonally dominant.  On top of the b x b
+// block-Jacobi scaling (A~ = D^{-1} J), each run of consecutive local rows
+// that belong to one fracture is grouped into a block of at most
+// PC_DOF / b rows that never crosses a 256-row Krylov tile; the exact
+// inverse of A~ restricted to the block is formed once per Newton
+// iteration and applied on the left after each Krylov product (a short
+// kernel over the fracture rows, see fim_krylov.hip).  Matrix rows and
+// rows of one-row blocks keep the plain scaling.
+#include "fim_device.hpp"
+
+namespace fimk {
+
+// Block layout of one local system, one workgroup per 256-row tile:
+//   pcinfo[r] = (first row of r's block - tile base) << 16 | block rows
+//   pcoff[r]  = element offset of the block's inverse in the inverse
+//               store (N x N column-major, N = rows * b); the block's
+//               first fracture cell ordinal times cap * b * b, so the
+//               blocks of one system never overlap.
+__global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restrict__ l2g,
+                                                     const int* __restrict__ frac_id,
+                                                     const int* __restrict__ ford, int cap,
+                                                     int cell_stride, int* __restrict__ pcinfo,
+                                                     int* __restrict__ pcoff) {
+    __shared__ int sf[KB_NT];   // fracture id of each row (-1 matrix, -2 past nA)
+    __shared__ int ss[KB_NT];   // block start of each row
+    const int t = threadIdx.x, base = blockIdx.x * KB_NT, r = base + t;
+    const bool valid = r < nA;
+    const int f = valid ? frac_id[l2g[r]] : -2;
+    sf[t] = f;
+    __syncthreads();
+    int run = t;
+    if (f >= 0)
+        while (run > 0 && sf[run - 1] == f) run--;
+    const int bs = f >= 0 ? run + ((t - run) / cap) * cap : t;
+    ss[t] = bs;
+    __syncthreads();
+    int size = 1;
+    if (f >= 0) {
+        int e = bs;
+        while (e + 1 < KB_NT && ss[e + 1] == bs) e++;
+        size = e - bs + 1;
+    }
+    if (valid) {
+        pcinfo[r] = (bs << 16) | size;
+        pcoff[r] = (size > 1) ? ford[l2g[base + bs]] * cell_stride : 0;
+    }
+}
+
+void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
+                      int cell_stride, int* pcinfo, int* pcoff, hipStream_t s) {
+    if (nA <= 0) return;
+    k_pc_blocks<<<(nA + KB_NT - 1) / KB_NT, KB_NT, 0, s>>>(nA, l2g, frac_id, ford, cap,
+                                                            cell_stride, pcinfo, pcoff);
+}
+
+// Inverse of every multi-row block of a tile, one wave per block, stored
+// in FP32 (the same inverse serves the FP32 and FP64 Krylov; 8-bit
+// mantissas are not enough for nearly singular blocks): the block of
+// A~ = D^{-1} J (FP64 products, FP32 from here on) is assembled
+// in LDS, padded to 64 x 64 with the identity, and each lane takes one
+// row into registers.  Gauss-Jordan elimination then runs 64 steps
+// without pivoting (the scaled blocks have unit diagonal blocks and are
+// diagonally dominant in practice); every step takes column 0 as the
+// pivot column, broadcasts the pivot row through LDS, and shifts the
+// columns left by one, appending the new column of the inverse at the end,
+// so that all register indices are compile-time constants and after 64
+// steps the registers hold the inverse in the original column order.  A
+// pivot below 1e-20 in magnitude or a non-finite one, or an inverse entry
+// above 1e8, leaves the identity for that block (plain block Jacobi on its
+// rows).
+constexpr int PCI_NT = 128;   // threads per workgroup of the inversion
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int B>
+__global__ __launch_bounds__(PCI_NT) void k_pc_invert(int nA, LocalSys ls,
+                                                      const double* __restrict__ dinv,
+                                                      const int* __restrict__ pcinfo,
+                                                      const int* __restrict__ pcoff,
+                                                      float* __restrict__ pcM) {
+    constexpr int BB = B * B;
+    constexpr int NW = PCI_NT / WAVE;
+    __shared__ __align__(16) float Ab[NW][PC_DOF * PC_DOF];
+    __shared__ int list[KB_NT];
+    __shared__ int nlist;
+    const int base = blockIdx.x * KB_NT;
+    if (threadIdx.x == 0) nlist = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < KB_NT; t += PCI_NT) {
+        const int r = base + t;
+        if (r < nA) {
+            const int info = pcinfo[r];
+            if ((info & 0xffff) > 1 && (info >> 16) == t) list[atomicAdd(&nlist, 1)] = t;
+        }
+    }
+    __syncthreads();
+    const int nb = nlist;
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    float* M = Ab[w];
+    for (int q = w; q < nb; q += NW) {
+        const int bs = list[q];
+        const int size = pcinfo[base + bs] & 0xffff;
+        const int N = size * B;
+        for (int e = lane; e < N * N; e += WAVE) M[e] = 0.0f;
+        wave_sync();
+        if (lane < size) {
+            const int r = base + bs + lane;
+            const long s0 = slot_of(ls, r, 0);
+            const int width = ls.swidth[r / SLICE];
+            const double* di = dinv + (long)r * BB;
+            for (int k = 0; k < width; k++) {
+                const long pos = s0 + (long)k * SLICE;
+                const int jl = ls.col[pos] - (base + bs);
+                if (jl < 0 || jl >= size) continue;
+                const double* a = ls.J + pos * BB;
+#pragma unroll
+                for (int i = 0; i < B; i++)
+#pragma unroll
+                    for (int j = 0; j < B; j++) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int m = 0; m < B; m++) acc += di[i * B + m] * a[m * B + j];
+                        // padding slots (col = r, zero block) add nothing
+                        M[(lane * B + i) * N + jl * B + j] += (float)acc;
+                    }
+            }
+        }
+        wave_sync();
+        float a[PC_DOF];
+#pragma unroll
+        for (int c = 0; c < PC_DOF; c++)
+            a[c] = (lane < N && c < N) ? M[lane * N + c] : (c == lane ? 1.0f : 0.0f);
+        wave_sync();
+        bool bad = false;
+        for (int step = 0; step < PC_DOF; step++) {
+            if (lane == step) {
+#pragma unroll
+                for (int c = 0; c < PC_DOF; c++) M[c] = a[c];
+            }
+            wave_sync();
+            float pr[PC_DOF];
+#pragma unroll
+            for (int c = 0; c < PC_DOF; c++) pr[c] = M[c];
+            wave_sync();
+            const float p = pr[0];
+            bad = bad || !(fabsf(p) > 1e-20f) || !isfinite(p);
+            const float ip = 1.0f / p;
+            const float f = a[0];
+            const bool me = lane == step;
+#pragma unroll
+            for (int c = 1; c < PC_DOF; c++) {
+                const float sc = pr[c] * ip;
+                a[c - 1] = me ? sc : a[c] - f * sc;
+            }
+            a[PC_DOF - 1] = me ? ip : -f * ip;
+        }
+        bool big = false;
+#pragma unroll
+        for (int c = 0; c < PC_DOF; c++)
+            if (lane < N && c < N && !(fabsf(a[c]) <= 1e8f)) big = true;
+        bad = bad || __any(big);
+        float* out = pcM + pcoff[base + bs];
+        if (lane < N) {
+#pragma unroll
+            for (int c = 0; c < PC_DOF; c++)
+                if (c < N) out[c * N + lane] = bad ? (c == lane ? 1.0f : 0.0f) : a[c];
+        }
+        wave_sync();
+    }
+}
+
+void launch_pc_invert(int b, int nA, const LocalSys& ls, const double* dinv,
+                      const int* pcinfo, const int* pcoff, float* pcM, hipStream_t s) {
+    if (nA <= 0) return;
+    const int nb = (nA + KB_NT - 1) / KB_NT;
+    if (b == 1) k_pc_invert<1><<<nb, PCI_NT, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
+    else if (b == 2) k_pc_invert<2><<<nb, PCI_NT, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
+    else k_pc_invert<3><<<nb, PCI_NT, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
+}
+
+} // namespace fimk

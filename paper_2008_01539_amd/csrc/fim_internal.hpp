@@ -16,6 +16,7 @@ constexpr int MAX_LAYERS = 8;   // deepest neighbourhood the marker walks
 constexpr int MAX_SUBS = 64;    // Algorithm 2 subdomains per timestep
 constexpr int KB_NT = 256;      // threads per block of the Krylov kernels
 constexpr int KB_MAXB = 1024;   // blocks per Krylov launch (grid-stride above)
+constexpr int PC_DOF = 64;      // unknowns per fracture preconditioner block
 
 // per-cell flag bits
 enum : uint8_t { CF_FRAC = 1, CF_PERF = 2, CF_AA = 4 };
@@ -142,6 +143,10 @@ struct KrylovBufs {
     // per-block partial dot products (part_ir 2 per block, the others 4)
     double* part_ir; double* part_a; double* part_b; double* part_c;
     const double* dinv; const void* At;
+    // fracture-block preconditioner (pcM NULL: block Jacobi only); its
+    // kernels' partial sums after P (a2) and after S (b2), 4 per block
+    const int* pcinfo; const int* pcoff; const float* pcM;   // FP32 inverses
+    double* part_a2; double* part_b2;
 };
 int krylov_grid(int nA);
 
@@ -177,6 +182,10 @@ void launch_bicg_part(int which, int b, bool fp32, bool solo, const KSeg* segs,
                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
                           int nblk_total, hipStream_t s);
+// fracture-block step after kernel P (which = 0) or S (which = 1)
+void launch_pc_vec(int which, int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
+                   int nblk_total, int it, hipStream_t s, hipEvent_t ev0 = nullptr,
+                   hipEvent_t ev1 = nullptr);
 
 struct SegStatus {
     double rir2, bnorm2;
@@ -184,6 +193,12 @@ struct SegStatus {
 };
 void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s);
 void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);
+
+// fracture-block preconditioner (fim_fracpc.hip)
+void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
+                      int cell_stride, int* pcinfo, int* pcoff, hipStream_t s);
+void launch_pc_invert(int b, int nA, const LocalSys& ls, const double* dinv,
+                      const int* pcinfo, const int* pcoff, float* pcM, hipStream_t s);
 
 // update (fim_update.hip)
 void launch_update(int fk, int nA, const int* l2g, const double* x64,

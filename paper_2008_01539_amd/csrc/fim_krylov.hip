@@ -6,7 +6,11 @@
 //   solve A~ d = D^{-1} r64     (BiCGStab in precision T: float or double)
 //   x64 += d                    until ||r64|| <= lin_rtol ||F||.
 //
-// One BiCGStab iteration is three kernels.  Each writes per-block partial
+// With fracture blocks (fim_fracpc.hip) BiCGStab runs on M^{-1} A~, M the
+// block diagonal of A~ over fracture blocks: every product kernel is
+// followed by a short kernel that applies M^{-1} on the fracture rows.
+//
+// One BiCGStab iteration is two kernels (four with fracture blocks).  Each writes per-block partial
 // dot products; the next kernel's blocks each reduce those partials in the
 // same fixed order (so every block derives the same scalar, and the result
 // is deterministic) before doing their rows.  No fences, atomics or extra
@@ -85,7 +89,9 @@ constexpr int chunk_slots() {
 // 512 / waves): three, except FP64 3x3 blocks, whose first chunk needs
 // more registers than that leaves.
 template <int B, typename T>
-constexpr int kb_waves() { return (B == 3 && sizeof(T) == 8) ? 2 : 3; }
+constexpr int kbp_waves() { return (B == 3 && sizeof(T) == 8) ? 2 : 3; }
+template <int B, typename T>
+constexpr int kbs_waves() { return kbp_waves<B, T>(); }
 
 // Slot geometry of row r: slot k at base + 64 k; width slots are in use,
 // cap (the slice stride) bounds the slots that may be read at all.
@@ -191,6 +197,53 @@ __device__ inline void row_product(const LocalSys& ls, const T* At, const RowGeo
     }
 }
 
+constexpr int PC_BATCH = 8;
+
+// Left application of the fracture-block inverses (see fim_fracpc.hip) to
+// the products y of one tile, one row per thread; y enters and leaves in
+// FP64, the inverses are stored in T.  Called by every thread of the block
+// (two barriers); act marks the threads that hold a row.
+template <int B, typename T>
+__device__ inline void pc_apply(const KrylovBufs& kb, bool act, int info, int off,
+                                double (&y)[B]) {
+    __shared__ double yb[KB_NT * B];
+    const int t = threadIdx.x;
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < B; c++) yb[t * B + c] = y[c];
+    }
+    __syncthreads();
+    const int size = info & 0xffff;
+    if (act && size > 1) {
+        const int bs = info >> 16, N = size * B, rl = t - bs;
+        const unsigned m0 = (unsigned)(off + rl * B) * 4u;
+        const unsigned col = (unsigned)N * 4u;
+        double acc[B];
+#pragma unroll
+        for (int c = 0; c < B; c++) acc[c] = 0.0;
+        // PC_BATCH columns per round of loads (coalesced over the block's rows)
+        for (int j0 = 0; j0 < N; j0 += PC_BATCH) {
+            float mv[PC_BATCH][B];
+#pragma unroll
+            for (int q = 0; q < PC_BATCH; q++) {
+#pragma unroll
+                for (int c = 0; c < B; c++)
+                    mv[q][c] = (j0 + q < N) ? ldg<float>(kb.pcM, m0 + (j0 + q) * col + 4u * c)
+                                            : 0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < PC_BATCH; q++) {
+                const double yj = (j0 + q < N) ? yb[bs * B + j0 + q] : 0.0;
+#pragma unroll
+                for (int c = 0; c < B; c++) acc[c] += (double)mv[q][c] * yj;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < B; c++) y[c] = acc[c];
+    }
+    __syncthreads();
+}
+
 static inline int kgrid(long rows) {
     long g = (rows + KB_NT - 1) / KB_NT;
     if (g < 1) g = 1;
@@ -215,39 +268,60 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
     T* rr = (T*)kb.r;
     T* rh = (T*)kb.rh;
     double part[2] = {0.0, 0.0};
-    for (int r = lb * blockDim.x + threadIdx.x; r < nA; r += nbk * blockDim.x) {
-        double res[B];
+    const bool pc = kb.pcM != nullptr;
+    // whole tiles per pass, so that the preconditioner's barriers are uniform
+    for (int tb = lb * KB_NT; tb < nA; tb += nbk * KB_NT) {
+        const int r = tb + threadIdx.x;
+        const bool act = r < nA;
+        double bt[B];
+        int pinfo = 0, poff = 0;
 #pragma unroll
-        for (int c = 0; c < B; c++) res[c] = -ls.F[(long)r * B + c];
-        if (!x_zero) {
-            const long base = slot_of(ls, r, 0);
-            const int width = ls.swidth[r / SLICE];
-            for (int k = 0; k < width; k++) {
-                const long pos = base + (long)k * SLICE;
-                const int cl = ls.col[pos];
-                const double* a = ls.J + pos * BB;
+        for (int c = 0; c < B; c++) bt[c] = 0.0;
+        if (act) {
+            double res[B];
 #pragma unroll
-                for (int c = 0; c < B; c++) {
-                    double acc = 0.0;
+            for (int c = 0; c < B; c++) res[c] = -ls.F[(long)r * B + c];
+            if (!x_zero) {
+                const long base = slot_of(ls, r, 0);
+                const int width = ls.swidth[r / SLICE];
+                for (int k = 0; k < width; k++) {
+                    const long pos = base + (long)k * SLICE;
+                    const int cl = ls.col[pos];
+                    const double* a = ls.J + pos * BB;
 #pragma unroll
-                    for (int v = 0; v < B; v++) acc += a[c * B + v] * kb.x64[(long)cl * B + v];
-                    res[c] -= acc;
+                    for (int c = 0; c < B; c++) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int v = 0; v < B; v++) acc += a[c * B + v] * kb.x64[(long)cl * B + v];
+                        res[c] -= acc;
+                    }
                 }
             }
+            const double* di = kb.dinv + (long)r * BB;
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                kb.rir[(long)r * B + c] = res[c];
+                part[0] += res[c] * res[c];
+                double s_ = 0.0;
+#pragma unroll
+                for (int v = 0; v < B; v++) s_ += di[c * B + v] * res[v];
+                bt[c] = s_;
+            }
+            if (pc) {
+                pinfo = kb.pcinfo[r];
+                poff = kb.pcoff[r];
+            }
         }
-        const double* di = kb.dinv + (long)r * BB;
+        if (pc) pc_apply<B, T>(kb, act, pinfo, poff, bt);
+        if (act) {
 #pragma unroll
-        for (int c = 0; c < B; c++) {
-            kb.rir[(long)r * B + c] = res[c];
-            part[0] += res[c] * res[c];
-            double bt = 0.0;
-#pragma unroll
-            for (int v = 0; v < B; v++) bt += di[c * B + v] * res[v];
-            const T btT = (T)bt;
-            xT[(long)r * B + c] = (T)0;
-            rr[(long)r * B + c] = btT;
-            rh[(long)r * B + c] = btT;
-            part[1] += (double)btT * (double)btT;
+            for (int c = 0; c < B; c++) {
+                const T btT = (T)bt[c];
+                xT[(long)r * B + c] = (T)0;
+                rr[(long)r * B + c] = btT;
+                rh[(long)r * B + c] = btT;
+                part[1] += (double)btT * (double)btT;
+            }
         }
     }
     block_sum<2>(part);
@@ -280,7 +354,7 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
 // and the first chunk of neighbour slots are fetched before the previous
 // kernel's partial sums are reduced, so those loads overlap the reduction.
 template <int B, typename T, bool FIRST, bool SOLO>
-__global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_p(const KSeg* __restrict__ segs,
+__global__ __launch_bounds__(KB_NT, (kbp_waves<B, T>())) void k_bicg_p(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
                                                                       int it) {
     const KSeg& S = seg_of<SOLO>(segs, blk_seg);
@@ -296,10 +370,18 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_p(const KSeg
     const double rho_prev = FIRST ? 1.0 : sc->rho_hist[(it - 1) & 1];
     const double al_prev = sc->alpha;
     constexpr int NR = FIRST ? 1 : 4;
+    const bool pc = S.kb.pcM != nullptr;
     double red[4] = {0.0, 0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
 #pragma unroll
         for (int k = 0; k < NR; k++) red[k] += pin[(long)q * 4 + k];
+    }
+    if (!FIRST && pc) {
+        // the fracture rows' share, from the preconditioner step after S
+        for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) red[k] += S.kb.part_b2[(long)q * 4 + k];
+        }
     }
     if (done) return;
     const int r0 = lb * blockDim.x + threadIdx.x;
@@ -319,6 +401,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_p(const KSeg
     RowGeo g{0, 0, 0};
     T own[NV][B] = {}, ox[B] = {}, orh[B] = {};
     Chunk<B, T, NV, U> ch{};
+    bool inblk = false;   // row of a multi-row fracture block
     auto fetch = [&](int r) {
         g = row_geo(ls, r);
         const unsigned ro = (unsigned)r * RB;
@@ -326,6 +409,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_p(const KSeg
         for (int v = 0; v < NV; v++) ldv<B, T>(own[v], src[v], ro);
         if constexpr (!FIRST) ldv<B, T>(ox, V.x, ro);
         ldv<B, T>(orh, V.rh, ro);
+        inblk = pc && (ldg<int>(S.kb.pcinfo, 4u * (unsigned)r) & 0xffff) > 1;
         fetch_chunk<B, T, NV, U>(ls, At, g, 1, src, ch);
     };
     if (r0 < nA) fetch(r0);
@@ -396,11 +480,16 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_p(const KSeg
             vT[c] = (T)vi[c];
         }
         stv<B, T>(V.p_new, ro, pT);
+        // rows of fracture blocks hold A~ p here; the preconditioner step
+        // replaces it by M^{-1} A~ p and adds their (rh, v), (v, v)
         stv<B, T>(V.v_new, ro, vT);
+        const bool own_v = !inblk;
 #pragma unroll
         for (int c = 0; c < B; c++) {
-            dot[0] += (double)orh[c] * (double)vT[c];
-            dot[1] += (double)vT[c] * (double)vT[c];
+            if (own_v) {
+                dot[0] += (double)orh[c] * (double)vT[c];
+                dot[1] += (double)vT[c] * (double)vT[c];
+            }
             dot[2] += (double)ri[c] * (double)ri[c];
         }
         // (fetched here, not at the top of the loop, so that the first
@@ -420,7 +509,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_p(const KSeg
 // alpha = rho_i / sigma, s = r_i - alpha v_i, t = A~ s (s rebuilt at the
 // neighbours).  Partial sums: (t,s), (t,t), (rh,s), (rh,t).
 template <int B, typename T, bool SOLO>
-__global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_s(const KSeg* __restrict__ segs,
+__global__ __launch_bounds__(KB_NT, (kbs_waves<B, T>())) void k_bicg_s(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
                                                                       int it) {
     const KSeg& S = seg_of<SOLO>(segs, blk_seg);
@@ -435,10 +524,18 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_s(const KSeg
     const double brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
     const int done = sc->done;
     const double rho = sc->rho_hist[it & 1];
+    const bool pc = S.kb.pcM != nullptr;
     double red[3] = {0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
 #pragma unroll
         for (int k = 0; k < 3; k++) red[k] += pa[(long)q * 4 + k];
+    }
+    if (pc) {
+        // the fracture rows' share, from the preconditioner step after P
+        for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) red[k] += S.kb.part_a2[(long)q * 4 + k];
+        }
     }
     if (done) return;
     constexpr int NV = 2;
@@ -450,12 +547,14 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_s(const KSeg
     RowGeo g{0, 0, 0};
     T own[NV][B] = {}, orh[B] = {};
     Chunk<B, T, NV, U> ch{};
+    bool inblk = false;   // row of a multi-row fracture block
     auto fetch = [&](int r) {
         g = row_geo(ls, r);
         const unsigned ro = (unsigned)r * RB;
 #pragma unroll
         for (int v = 0; v < NV; v++) ldv<B, T>(own[v], src[v], ro);
         ldv<B, T>(orh, V.rh, ro);
+        inblk = pc && (ldg<int>(S.kb.pcinfo, 4u * (unsigned)r) & 0xffff) > 1;
         fetch_chunk<B, T, NV, U>(ls, At, g, 1, src, ch);
     };
     if (r0 < nA) fetch(r0);
@@ -495,14 +594,19 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_s(const KSeg
             tT[c] = (T)ti[c];
         }
         stv<B, T>(V.s, ro, sT);
+        // rows of fracture blocks hold A~ s here; the preconditioner step
+        // replaces it and adds their (t, s), (t, t), (rh, t)
         stv<B, T>(V.t, ro, tT);
+        const bool own_t = !inblk;
 #pragma unroll
         for (int c = 0; c < B; c++) {
             const double sd = (double)sT[c], td = (double)tT[c], h = (double)orh[c];
-            dot[0] += td * sd;
-            dot[1] += td * td;
+            if (own_t) {
+                dot[0] += td * sd;
+                dot[1] += td * td;
+                dot[3] += h * td;
+            }
             dot[2] += h * sd;
-            dot[3] += h * td;
         }
         if (r + stride < nA) fetch(r + stride);
     }
@@ -510,6 +614,99 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T>())) void k_bicg_s(const KSeg
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < 4; k++) pb[4 * lb + k] = dot[k];
+    }
+}
+
+// ------------------------------------------ fracture-block step (W = 0, 1)
+// After kernel P (W = 0) the rows of multi-row fracture blocks hold
+// y = A~ p in v, after kernel S (W = 1) y = A~ s in t.  This kernel
+// replaces y by M^{-1} y on those rows (M: the block diagonal of A~ over
+// the blocks, inverses from fim_fracpc.hip) and writes those rows' share of
+// the dot products in the slots the next kernel reduces: W = 0: (rh, v),
+// (v, v); W = 1: (t, s), (t, t), -, (rh, t).  Same tiles as the product
+// kernels; thread t of a tile pass works on unknowns t, t + 256, ... of
+// the tile (one row of M^{-1} each, up to 64 values loaded at once,
+// coalesced over the block's unknowns).
+template <int B, typename T, bool SOLO, int W>
+__global__ __launch_bounds__(KB_NT) void k_pc_vec(const KSeg* __restrict__ segs,
+                                                  const int* __restrict__ blk_seg, int it) {
+    const KSeg& S = seg_of<SOLO>(segs, blk_seg);
+    if (!S.active || S.kb.pcM == nullptr) return;
+    const int done = S.kb.sc->done;   // checked once the first loads are out
+    const int nbk = S.nblk, nA = S.nA, lb = xcd_tile(S.blk0, nbk, blockIdx.x);
+    const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
+    T* y = W == 0 ? V.v_new : V.t;
+    double* __restrict__ part = W == 0 ? S.kb.part_a2 : S.kb.part_b2;
+    __shared__ double yb[KB_NT * B];
+    __shared__ int info_s[KB_NT], off_s[KB_NT];
+    const int t = threadIdx.x;
+    double dot[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int tb = lb * KB_NT; tb < nA; tb += nbk * KB_NT) {
+        // one round of loads for everything indexed by row or unknown
+        const int r = tb + t;
+        const bool act = r < nA;
+        int info = 1, off = 0;
+        double yo[B], hu[B], su[B];
+#pragma unroll
+        for (int c = 0; c < B; c++) yo[c] = hu[c] = su[c] = 0.0;
+        if (act) {
+            info = S.kb.pcinfo[r];
+            off = S.kb.pcoff[r];
+#pragma unroll
+            for (int c = 0; c < B; c++) yo[c] = (double)y[(long)r * B + c];
+        }
+#pragma unroll
+        for (int h = 0; h < B; h++) {
+            const long q = (long)tb * B + h * KB_NT + t;   // this thread's unknowns
+            if (q < (long)nA * B) {
+                hu[h] = (double)V.rh[q];
+                if (W == 1) su[h] = (double)V.s[q];
+            }
+        }
+        if (done) return;   // uniform
+        info_s[t] = info;
+        off_s[t] = off;
+#pragma unroll
+        for (int c = 0; c < B; c++) yb[t * B + c] = yo[c];
+        if (!__syncthreads_or((info & 0xffff) > 1)) continue;
+#pragma unroll
+        for (int h = 0; h < B; h++) {
+            const int R = h * KB_NT + t;          // unknown of the tile
+            const int rl = R / B, ci = R - rl * B;
+            const int row = tb + rl;
+            const int inf = info_s[rl];
+            const int size = inf & 0xffff;
+            if (row < nA && size > 1) {
+                const int bs = inf >> 16, N = size * B, ri = (rl - bs) * B + ci;
+                const unsigned m0 = (unsigned)(off_s[rl] + ri) * 4u;
+                const unsigned colb = (unsigned)N * 4u;
+                float mv[PC_DOF];
+#pragma unroll
+                for (int j = 0; j < PC_DOF; j++)   // (index clamped: every load in bounds)
+                    mv[j] = ldg<float>(S.kb.pcM, m0 + (unsigned)min(j, N - 1) * colb);
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < PC_DOF; j++)
+                    if (j < N) acc += (double)mv[j] * yb[bs * B + j];
+                const T o = (T)acc;
+                y[(long)row * B + ci] = o;
+                const double od = (double)o;
+                if (W == 0) {
+                    dot[0] += hu[h] * od;
+                    dot[1] += od * od;
+                } else {
+                    dot[0] += od * su[h];
+                    dot[1] += od * od;
+                    dot[3] += hu[h] * od;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    block_sum<4>(dot);
+    if (t == 0) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) part[4 * lb + k] = dot[k];
     }
 }
 
@@ -623,6 +820,32 @@ void launch_bicg_part(int which, int b, bool fp32, bool solo, const KSeg* segs,
     } while (0)
     KDISPATCH(PI)
 #undef PI
+}
+
+void launch_pc_vec(int which, int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
+                   int nblk_total, int it, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (nblk_total <= 0) return;
+    const dim3 nb(nblk_total), nt(KB_NT);
+#define PVEC(BV, TT)                                                                            \
+    do {                                                                                        \
+        if (solo) {                                                                             \
+            if (which == 0)                                                                     \
+                hipExtLaunchKernelGGL(k_pc_vec<BV, TT, true, 0>, nb, nt, 0, s, ev0, ev1, 0,     \
+                                      segs, blk_seg, it);                                       \
+            else                                                                                \
+                hipExtLaunchKernelGGL(k_pc_vec<BV, TT, true, 1>, nb, nt, 0, s, ev0, ev1, 0,     \
+                                      segs, blk_seg, it);                                       \
+        } else {                                                                                \
+            if (which == 0)                                                                     \
+                hipExtLaunchKernelGGL(k_pc_vec<BV, TT, false, 0>, nb, nt, 0, s, ev0, ev1, 0,    \
+                                      segs, blk_seg, it);                                       \
+            else                                                                                \
+                hipExtLaunchKernelGGL(k_pc_vec<BV, TT, false, 1>, nb, nt, 0, s, ev0, ev1, 0,    \
+                                      segs, blk_seg, it);                                       \
+        }                                                                                       \
+    } while (0)
+    KDISPATCH(PVEC)
+#undef PVEC
 }
 
 void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,

@@ -20,6 +20,7 @@ FIM_E_ARG, FIM_E_NOMEM, FIM_E_HIP, FIM_E_STATE, FIM_E_NONFINITE = -1, -2, -3, -4
 FULL, LOCAL, DD = 0, 1, 2
 FP64, MIXED = 0, 1
 HOST, DEVICE = 0, 1
+PC_JACOBI, PC_FRACTURE = 0, 1
 PSI = 6894.757293168
 
 
@@ -52,7 +53,7 @@ class _Desc(C.Structure):
                 ("perf_cell", C.c_void_p), ("perf_wi", C.c_void_p),
                 ("perf_bhp", C.c_void_p), ("c_r", C.c_double),
                 ("p_ref_rock", C.c_double), ("gravity", C.c_double),
-                ("fluid", _Fluid)]
+                ("fluid", _Fluid), ("frac_id", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -62,7 +63,8 @@ class _Opts(C.Structure):
                 ("auto_cut", C.c_int32), ("max_cuts", C.c_int32), ("ds_max", C.c_double),
                 ("precision", C.c_int32), ("lin_rtol", C.c_double),
                 ("inner_rtol", C.c_double), ("krylov_maxit", C.c_int32),
-                ("max_refine", C.c_int32), ("check_every", C.c_int32)]
+                ("max_refine", C.c_int32), ("check_every", C.c_int32),
+                ("precond", C.c_int32)]
 
 
 class IterStats(C.Structure):
@@ -160,6 +162,7 @@ class Options:
     krylov_maxit: int = 2000
     max_refine: int = 20
     check_every: int = 8
+    precond: int = PC_FRACTURE
 
     @staticmethod
     def tight_mode(**kw):
@@ -219,13 +222,19 @@ def _describe(model):
             np.ascontiguousarray(model.always_active, dtype=np.uint8),
             _i32(model.conn_i), _i32(model.conn_j), _f64(model.conn_T),
             _i32(model.perf_cell), _f64(model.perf_wi), _f64(model.perf_bhp)]
+    fid = (model.grid or {}).get("fid")
+    frac = None
+    if fid is not None and len(fid) == model.n - model.n_matrix:
+        frac = np.full(model.n, -1, np.int32)
+        frac[model.n_matrix:] = fid
+    keep.append(frac)
     k = keep
     d = _Desc(n_cells=int(model.n), n_conn=int(k[3].size), n_perf=int(k[6].size),
               pv_ref=_ptr(k[0]), depth=_ptr(k[1]), always_active=_ptr(k[2]),
               conn_i=_ptr(k[3]), conn_j=_ptr(k[4]), conn_T=_ptr(k[5]),
               perf_cell=_ptr(k[6]), perf_wi=_ptr(k[7]), perf_bhp=_ptr(k[8]),
               c_r=float(model.rock["c_r"]), p_ref_rock=float(model.rock["p_ref"]),
-              gravity=float(model.gravity), fluid=f)
+              gravity=float(model.gravity), fluid=f, frac_id=_ptr(frac))
     return d, keep
 
 
@@ -378,10 +387,16 @@ class FimBatch:
     member per call, with one batched Krylov solve over all of them.  A
     member's result is the same alone and in any batch."""
 
+    @staticmethod
+    def _handles(models):
+        if any(m._h is None for m in models):
+            raise FimError(FIM_E_ARG, "a batch member has been closed")
+        return (C.c_void_p * len(models))(*[m._h.value for m in models])
+
     def __init__(self, models, stream=None):
         self._h = None
         self._models = list(models)
-        arr = (C.c_void_p * len(self._models))(*[m._h.value for m in self._models])
+        arr = self._handles(self._models)
         h = C.c_void_p()
         code = _lib.fim_batch_create(arr, len(self._models), _stream_handle(stream), C.byref(h))
         if code != FIM_OK:
@@ -394,14 +409,15 @@ class FimBatch:
 
     def set_models(self, models):
         """Replace the membership (between calls)."""
+        arr = self._handles(list(models))
         self._models = list(models)
-        arr = (C.c_void_p * len(self._models))(*[m._h.value for m in self._models])
         code = _lib.fim_batch_set(self._h, arr, len(self._models))
         if code != FIM_OK:
             raise FimError(code, _lib.fim_batch_last_error(self._h).decode())
 
     def newton_step(self, dts, modes):
         """One Newton iteration of every member; returns (stats, codes)."""
+        self._handles(self._models)
         k = len(self._models)
         d = np.ascontiguousarray(dts, dtype=np.float64).reshape(k)
         mo = np.ascontiguousarray(modes, dtype=np.int32).reshape(k)

@@ -124,8 +124,12 @@ class GpuExecutor:
         return fm
 
     def evict(self, session):
-        u, st = session.handle.get_state()
-        session.handle.close()
+        fm = session.handle
+        u, st = fm.get_state()
+        # a batch that holds the model must not outlive it
+        for key in [k for k, b in self._batches.items() if any(m is fm for m in b.models)]:
+            self._batches.pop(key).close()
+        fm.close()
         return (u, st)
 
     def tick(self, members):
@@ -140,7 +144,7 @@ class GpuExecutor:
             if bat is None:
                 bat = self.P.FimBatch(models, stream=self.stream)
                 self._batches[key] = bat
-            elif [m._h.value for m in bat.models] != [m._h.value for m in models]:
+            elif len(bat.models) != len(models) or any(a is not b for a, b in zip(bat.models, models)):
                 bat.set_models(models)
             dts = [members[p][1].dt for p in poss]
             modes = [members[p][0].spec.mode for p in poss]
@@ -167,17 +171,23 @@ class ServeStats:
     evictions: int = 0
     admissions: int = 0
     latencies: list = field(default_factory=list)
+    by_family: dict = field(default_factory=dict)   # family -> latencies
     cell_updates: float = 0.0
     wall: float = 0.0
+    max_batch: int = 0
 
     def summary(self):
         lat = np.array(self.latencies) if self.latencies else np.zeros(1)
+        fam = {f: dict(n=len(v), p50_ms=float(np.percentile(v, 50) * 1e3),
+                       p99_ms=float(np.percentile(v, 99) * 1e3))
+               for f, v in sorted(self.by_family.items())}
         return dict(completed=self.completed, failed=self.failed, ticks=self.ticks,
                     evictions=self.evictions, admissions=self.admissions,
                     throughput_rps=self.completed / self.wall if self.wall else 0.0,
                     cell_updates_per_s=self.cell_updates / self.wall if self.wall else 0.0,
                     p50_ms=float(np.percentile(lat, 50) * 1e3),
-                    p99_ms=float(np.percentile(lat, 99) * 1e3), wall_s=self.wall)
+                    p99_ms=float(np.percentile(lat, 99) * 1e3), wall_s=self.wall,
+                    max_batch=self.max_batch, by_family=fam)
 
 
 class Server:
@@ -234,6 +244,15 @@ class Server:
         self.stats.admissions += 1
         return True
 
+    def warm(self, order=None):
+        """Admit sessions (in `order`, default all) while they fit the
+        budget without evicting; returns how many are resident."""
+        for idx in (range(len(self.sessions)) if order is None else order):
+            s = self.sessions[idx]
+            if s.handle is None and self._fits(s.footprint):
+                self._admit(idx)
+        return len(self.resident)
+
     # ----------------------------------------------------------- requests
     def submit(self, req: Request):
         self.queue.append(req)
@@ -264,6 +283,7 @@ class Server:
         members = [(self.sessions[i], r) for i, r in self.inflight]
         res = self.ex.tick(members)
         self.stats.ticks += 1
+        self.stats.max_batch = max(self.stats.max_batch, len(members))
         now = self.ex.now()
         still = []
         for (i, r), (conv, failed, n_act) in zip(self.inflight, res):
@@ -278,6 +298,8 @@ class Server:
                     s.next_step += 1
                     self.stats.completed += 1
                     self.stats.latencies.append(r.finish - r.arrival)
+                    fam = s.spec.name.split("-")[0]
+                    self.stats.by_family.setdefault(fam, []).append(r.finish - r.arrival)
                 else:
                     self.stats.failed += 1
                 self.done.append(r)
@@ -286,10 +308,12 @@ class Server:
         self.inflight = still
         return True
 
-    def run_poisson(self, rate, duration, mix, seed=5, max_ticks=10 ** 7):
+    def run_poisson(self, rate, duration, mix, seed=5, max_ticks=10 ** 7, progress=None,
+                    every=10.0):
         """Poisson arrivals at `rate`/s for `duration` s of the executor's
         clock; `mix[k]` is the probability that a request targets session
-        k.  Returns the statistics."""
+        k.  `progress(elapsed, stats)` is called about every `every`
+        seconds.  Returns the statistics."""
         rng = np.random.default_rng(seed)
         t0 = self.ex.now()
         t = 0.0
@@ -302,8 +326,12 @@ class Server:
         heapq.heapify(arrivals)
         rid = 0
         ticks = 0
+        next_report = every
         while (arrivals or self.queue or self.inflight) and ticks < max_ticks:
             now = self.ex.now() - t0
+            if progress is not None and now >= next_report:
+                progress(now, self.stats)
+                next_report += every
             while arrivals and arrivals[0][0] <= now:
                 ta, sidx = heapq.heappop(arrivals)
                 self.submit(Request(rid=rid, session=sidx, arrival=t0 + ta))
