@@ -72,7 +72,7 @@ void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* for
 // pivot below 1e-20 in magnitude or a non-finite one, or an inverse entry
 // above 1e8, leaves the identity for that block (plain block Jacobi on its
 // rows).
-constexpr int PCI_NT = 128;   // threads per workgroup of the inversion
+constexpr int PCI_SUB = 8;    // single-wave workgroups per tile
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -80,31 +80,32 @@ __device__ inline void wave_sync() {
 }
 
 template <int B>
-__global__ __launch_bounds__(PCI_NT) void k_pc_invert(int nA, LocalSys ls,
-                                                      const double* __restrict__ dinv,
-                                                      const int* __restrict__ pcinfo,
-                                                      const int* __restrict__ pcoff,
-                                                      float* __restrict__ pcM) {
+__global__ __launch_bounds__(WAVE) void k_pc_invert(int nA, LocalSys ls,
+                                                    const double* __restrict__ dinv,
+                                                    const int* __restrict__ pcinfo,
+                                                    const int* __restrict__ pcoff,
+                                                    float* __restrict__ pcM) {
     constexpr int BB = B * B;
-    constexpr int NW = PCI_NT / WAVE;
-    __shared__ __align__(16) float Ab[NW][PC_DOF * PC_DOF];
+    __shared__ __align__(16) float M[PC_DOF * PC_DOF];
     __shared__ int list[KB_NT];
-    __shared__ int nlist;
-    const int base = blockIdx.x * KB_NT;
-    if (threadIdx.x == 0) nlist = 0;
-    __syncthreads();
-    for (int t = threadIdx.x; t < KB_NT; t += PCI_NT) {
-        const int r = base + t;
+    const int tile = blockIdx.x / PCI_SUB, sub = blockIdx.x % PCI_SUB;
+    const int base = tile * KB_NT, lane = threadIdx.x;
+    // the tile's multi-row blocks in row order (the same list in every
+    // workgroup of the tile; workgroup sub takes blocks sub, sub + 8, ...)
+    int nb = 0;
+    for (int k = 0; k < KB_NT / WAVE; k++) {
+        const int t = k * WAVE + lane, r = base + t;
+        bool lead = false;
         if (r < nA) {
             const int info = pcinfo[r];
-            if ((info & 0xffff) > 1 && (info >> 16) == t) list[atomicAdd(&nlist, 1)] = t;
+            lead = (info & 0xffff) > 1 && (info >> 16) == t;
         }
+        const unsigned long long bal = __ballot(lead);
+        if (lead) list[nb + __popcll(bal & ((1ull << lane) - 1ull))] = t;
+        nb += __popcll(bal);
     }
-    __syncthreads();
-    const int nb = nlist;
-    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    float* M = Ab[w];
-    for (int q = w; q < nb; q += NW) {
+    wave_sync();
+    for (int q = sub; q < nb; q += PCI_SUB) {
         const int bs = list[q];
         const int size = pcinfo[base + bs] & 0xffff;
         const int N = size * B;
@@ -139,7 +140,9 @@ __global__ __launch_bounds__(PCI_NT) void k_pc_invert(int nA, LocalSys ls,
             a[c] = (lane < N && c < N) ? M[lane * N + c] : (c == lane ? 1.0f : 0.0f);
         wave_sync();
         bool bad = false;
-        for (int step = 0; step < PC_DOF; step++) {
+        // N steps; afterwards columns 64 - N .. 63 of rows 0 .. N-1 hold the
+        // inverse (the identity padding is never a pivot)
+        for (int step = 0; step < N; step++) {
             if (lane == step) {
 #pragma unroll
                 for (int c = 0; c < PC_DOF; c++) M[c] = a[c];
@@ -161,16 +164,20 @@ __global__ __launch_bounds__(PCI_NT) void k_pc_invert(int nA, LocalSys ls,
             }
             a[PC_DOF - 1] = me ? ip : -f * ip;
         }
+        const int c0 = PC_DOF - N;
         bool big = false;
 #pragma unroll
         for (int c = 0; c < PC_DOF; c++)
-            if (lane < N && c < N && !(fabsf(a[c]) <= 1e8f)) big = true;
+            if (lane < N && c >= c0 && !(fabsf(a[c]) <= 1e8f)) big = true;
         bad = bad || __any(big);
         float* out = pcM + pcoff[base + bs];
         if (lane < N) {
 #pragma unroll
             for (int c = 0; c < PC_DOF; c++)
-                if (c < N) out[c * N + lane] = bad ? (c == lane ? 1.0f : 0.0f) : a[c];
+                if (c >= c0) {
+                    const int j = c - c0;
+                    out[j * N + lane] = bad ? (j == lane ? 1.0f : 0.0f) : a[c];
+                }
         }
         wave_sync();
     }
@@ -179,10 +186,10 @@ __global__ __launch_bounds__(PCI_NT) void k_pc_invert(int nA, LocalSys ls,
 void launch_pc_invert(int b, int nA, const LocalSys& ls, const double* dinv,
                       const int* pcinfo, const int* pcoff, float* pcM, hipStream_t s) {
     if (nA <= 0) return;
-    const int nb = (nA + KB_NT - 1) / KB_NT;
-    if (b == 1) k_pc_invert<1><<<nb, PCI_NT, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
-    else if (b == 2) k_pc_invert<2><<<nb, PCI_NT, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
-    else k_pc_invert<3><<<nb, PCI_NT, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
+    const int nb = (nA + KB_NT - 1) / KB_NT * PCI_SUB;
+    if (b == 1) k_pc_invert<1><<<nb, WAVE, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
+    else if (b == 2) k_pc_invert<2><<<nb, WAVE, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
+    else k_pc_invert<3><<<nb, WAVE, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
 }
 
 } // namespace fimk

@@ -197,49 +197,54 @@ __device__ inline void row_product(const LocalSys& ls, const T* At, const RowGeo
     }
 }
 
-constexpr int PC_BATCH = 8;
-
-// Left application of the fracture-block inverses (see fim_fracpc.hip) to
-// the products y of one tile, one row per thread; y enters and leaves in
-// FP64, the inverses are stored in T.  Called by every thread of the block
-// (two barriers); act marks the threads that hold a row.
-template <int B, typename T>
+// Left application of the fracture-block inverses (see fim_fracpc.hip)
+// to one tile of values y (one row per thread, FP64), used by the
+// refinement kernel.  Every thread of the block calls it (barriers); act
+// marks the threads that hold a row, info / off are the row's block
+// layout words.  Thread t computes unknowns t, t + 256, ... of the tile,
+// each from one row of the block inverse (up to 64 values, one round of
+// loads, coalesced over the block's unknowns).
+template <int B>
 __device__ inline void pc_apply(const KrylovBufs& kb, bool act, int info, int off,
                                 double (&y)[B]) {
     __shared__ double yb[KB_NT * B];
+    __shared__ int info_s[KB_NT], off_s[KB_NT];
     const int t = threadIdx.x;
-    if (act) {
+    info_s[t] = act ? info : 1;
+    off_s[t] = off;
 #pragma unroll
-        for (int c = 0; c < B; c++) yb[t * B + c] = y[c];
+    for (int c = 0; c < B; c++) yb[t * B + c] = act ? y[c] : 0.0;
+    __syncthreads();
+    double z[B];
+#pragma unroll
+    for (int h = 0; h < B; h++) {
+        const int R = h * KB_NT + t;
+        const int rl = R / B, ci = R - rl * B;
+        const int inf = info_s[rl];
+        const int size = inf & 0xffff;
+        z[h] = yb[R];
+        if (size > 1) {
+            const int bs = inf >> 16, N = size * B, ri = (rl - bs) * B + ci;
+            const unsigned m0 = (unsigned)(off_s[rl] + ri) * 4u;
+            const unsigned colb = (unsigned)N * 4u;
+            float mv[PC_DOF];
+#pragma unroll
+            for (int j = 0; j < PC_DOF; j++)   // (index clamped: every load in bounds)
+                mv[j] = ldg<float>(kb.pcM, m0 + (unsigned)min(j, N - 1) * colb);
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < PC_DOF; j++)
+                if (j < N) acc += (double)mv[j] * yb[bs * B + j];
+            z[h] = acc;
+        }
     }
     __syncthreads();
-    const int size = info & 0xffff;
-    if (act && size > 1) {
-        const int bs = info >> 16, N = size * B, rl = t - bs;
-        const unsigned m0 = (unsigned)(off + rl * B) * 4u;
-        const unsigned col = (unsigned)N * 4u;
-        double acc[B];
 #pragma unroll
-        for (int c = 0; c < B; c++) acc[c] = 0.0;
-        // PC_BATCH columns per round of loads (coalesced over the block's rows)
-        for (int j0 = 0; j0 < N; j0 += PC_BATCH) {
-            float mv[PC_BATCH][B];
+    for (int h = 0; h < B; h++) yb[h * KB_NT + t] = z[h];
+    __syncthreads();
+    if (act) {
 #pragma unroll
-            for (int q = 0; q < PC_BATCH; q++) {
-#pragma unroll
-                for (int c = 0; c < B; c++)
-                    mv[q][c] = (j0 + q < N) ? ldg<float>(kb.pcM, m0 + (j0 + q) * col + 4u * c)
-                                            : 0.0f;
-            }
-#pragma unroll
-            for (int q = 0; q < PC_BATCH; q++) {
-                const double yj = (j0 + q < N) ? yb[bs * B + j0 + q] : 0.0;
-#pragma unroll
-                for (int c = 0; c < B; c++) acc[c] += (double)mv[q][c] * yj;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < B; c++) y[c] = acc[c];
+        for (int c = 0; c < B; c++) y[c] = yb[t * B + c];
     }
     __syncthreads();
 }
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
                 poff = kb.pcoff[r];
             }
         }
-        if (pc) pc_apply<B, T>(kb, act, pinfo, poff, bt);
+        if (pc) pc_apply<B>(kb, act, pinfo, poff, bt);
         if (act) {
 #pragma unroll
             for (int c = 0; c < B; c++) {
