@@ -32,18 +32,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel, rec, b, kbytes):
+def algorithmic_bytes(kernel, rec, b, kbytes, pc=True):
     """Bytes a kernel must move per the work it did (one active row = one
     unit): every array entry it reads or writes once, neighbour gathers
     counted once (cache reuse), padding of the sliced-ELL matrix excluded.
-    rec: profile record with rows and nnzb (blocks incl. diagonal)."""
+    rec: profile record with rows and nnzb (blocks incl. diagonal; for the
+    fracture-block steps the entries of the block inverses read)."""
     rows, nnzb = rec["rows"], rec["nnzb"]
     off = max(nnzb - rows, 0.0)
+    blk = 4 if pc else 0   # block layout word per row
     if kernel == "bicg_spmv_p":
         # col + block per off-diagonal; s, t, p, v, x, rh read; x, r, p, v written
-        return off * (4 + kbytes * b * b) + rows * (10 * b * kbytes)
+        return off * (4 + kbytes * b * b) + rows * (10 * b * kbytes + blk)
     if kernel == "bicg_spmv_s":   # col + block; r, v, rh read; s, t written
-        return off * (4 + kbytes * b * b) + rows * (5 * b * kbytes)
+        return off * (4 + kbytes * b * b) + rows * (5 * b * kbytes + blk)
+    if kernel in ("frac_apply_p", "frac_apply_s"):
+        # FP32 inverse entries; per row: layout words 8, y and rh (and s
+        # after S) read; the fracture rows' results written (not counted)
+        nvec = 2 if kernel == "frac_apply_p" else 3
+        return 4 * nnzb + rows * (8 + nvec * b * kbytes)
     if kernel == "assemble":
         # per row: l2g 4, state 8b, status 1, pv 8, depth 8, flags 1, old
         # masses 8b, adjacency pointers 8, residual 8b written; per
@@ -51,6 +58,34 @@ def algorithmic_bytes(kernel, rec, b, kbytes):
         # block: 8 b^2 values + 4 col written
         return rows * (30 + 24 * b) + off * 16 + nnzb * (8 * b * b + 4)
     raise KeyError(kernel)
+
+
+PROFILE_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                               "c2_local_kernels.md")
+KERNEL_SOURCES = ["fim_krylov.hip", "fim_fracpc.hip", "fim_internal.hpp", "fim_device.hpp"]
+
+
+def measured_traffic_per_row():
+    """HBM bytes per row of each kernel from the committed rocprofv3 counter
+    summary, or {} when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        text = open(PROFILE_SUMMARY).read()
+    except OSError:
+        return {}
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2008_01539_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(fh.read())
+    out, ok = {}, False
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 2 and parts[0] == "sources_sha256":
+            ok = parts[1] == h.hexdigest()
+        elif len(parts) == 3 and parts[0] == "traffic_bytes_per_row":
+            out[parts[1]] = float(parts[2])
+    return out if ok else {}
 
 
 def run_gpu(model, opts, mode, steps, warmup, profile=False):
@@ -323,6 +358,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-full", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device to device once (a plain copy "
+                         "kernel of known size for scaling memory counters)")
     ap.add_argument("--profile", type=int, default=1,
                     help="record per-kernel hipEvents during the timed local run")
     args = ap.parse_args()
@@ -387,8 +425,9 @@ def main():
             "workload": "config 2: water/dead-oil, 200x100x10 grid + seeded 2000-fracture "
                         "DFN + 10-stage horizontal well (258096 cells, 722225 connections), "
                         "20-step schedule to 71.6 d; localized Newton (Algorithm 1, "
-                        "eps_p 0.3 psi, m 2); FP64 assembly/update, FP32 BiCGStab with "
-                        "block-Jacobi inside FP64 refinement",
+                        "eps_p 0.3 psi, m 2); FP64 assembly/update, FP32 BiCGStab "
+                        "(block-Jacobi scaling + fracture-block inverses) inside FP64 "
+                        "refinement",
             "n_cells": model.n,
             "krylov_dtype": "f32",
             "parallelism": "1 GPU",
@@ -410,19 +449,35 @@ def main():
     prof = prof_run["prof"] if prof_run else None
     if prof:
         cands = {k: v for k, v in prof.items()
-                 if k in ("assemble", "bicg_spmv_p", "bicg_spmv_s") and v["launches"]}
+                 if k in ("assemble", "bicg_spmv_p", "bicg_spmv_s", "frac_apply_p",
+                          "frac_apply_s") and v["launches"]}
         dom = max(cands, key=lambda k: cands[k]["total_ms"])
         rec = cands[dom]
         avg_s = rec["total_ms"] / rec["launches"] * 1e-3
         byt = algorithmic_bytes(dom, rec, model.b, 4) / rec["launches"]
         ach = byt / avg_s / 1e9
+        per_row = measured_traffic_per_row().get(dom)
+        rows_pl = rec["rows"] / rec["launches"]
         out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach,
                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                           "traffic": None, "avg_launch_us": avg_s * 1e6,
-                           "bytes_per_launch": byt,
-                           "rows_per_launch": rec["rows"] / rec["launches"]}
+                           # counter-measured bytes per launch (FETCH_SIZE + WRITE_SIZE
+                           # scaled by a plain copy, per row, times this run's rows per
+                           # launch); None once the kernels changed since the counters
+                           "traffic": per_row * rows_pl if per_row else None,
+                           "avg_launch_us": avg_s * 1e6,
+                           "bytes_per_launch": byt, "rows_per_launch": rows_pl}
         out["kernel_profile_local"] = prof
         out["roofline"]["profiled_wall_s"] = prof_run["wall"]
+    if args.calibrate_copy:
+        # one plain device-to-device copy of known size (memory-counter scale)
+        n_el = args.calibrate_copy * 2**20 // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = n_el * 4
+        del src, dst
     if not args.no_cpu:
         log("oracle CPU baseline")
         out["cpu_baseline"] = cpu_baseline(log)

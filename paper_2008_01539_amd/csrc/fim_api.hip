@@ -112,6 +112,7 @@ struct fim_model {
     double last_relres = 0.0;
     bool inspect_ready = false;
     int cur_nnzb = 0;   // blocks of the current local matrix (profiling)
+    double cur_pcn2 = 0.0;   // sum of N^2 over its fracture blocks (profiling)
     bool flags_on = false;
     SolveTable solo;
     size_t bytes = 0;   // device bytes held
@@ -144,7 +145,7 @@ static int pbeg(fim_model* m, int k, int tag = -1) {
 // record for a launch whose events the dispatch stamps (hipExtLaunchKernel)
 static int pbeg_ext(fim_model* m, int k, int tag) {
     if (!m->prof.on) return -1;
-    const bool mat = k == PK_BICG_A || k == PK_BICG_B;
+    const bool mat = k == PK_BICG_A || k == PK_BICG_B || k == PK_PCV_A || k == PK_PCV_B;
     ProfRec r{k, ev_take(m), ev_take(m), 0.0, mat, tag};
     m->prof.pend.push_back(r);
     return (int)m->prof.pend.size() - 1;
@@ -168,7 +169,11 @@ static void pflush(fim_model* m, int keep_tag = INT_MAX) {
                 m->prof.ms[r.k] += ms;
                 m->prof.cnt[r.k] += 1;
                 m->prof.rows[r.k] += r.rows;
-                if (r.matrix) m->prof.nnzb[r.k] += m->cur_nnzb;
+                // matrix launches: blocks of the local matrix; fracture-block
+                // steps: entries of the block inverses
+                if (r.matrix)
+                    m->prof.nnzb[r.k] += (r.k == PK_PCV_A || r.k == PK_PCV_B) ? m->cur_pcn2
+                                                                             : m->cur_nnzb;
             }
         }
         m->prof.pool.push_back(r.a);
@@ -275,7 +280,7 @@ static fim_status structure(fim_model* m) {
     launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, &m->dint[4], m->s);
     if (m->use_pc)
         launch_pc_blocks(m->nA, m->l2g, m->frac_id, m->ford, m->pc_cap,
-                         m->pc_cap * m->B * m->B, m->pcinfo, m->pcoff, m->s);
+                         m->pc_cap * m->B * m->B, m->pcinfo, m->pcoff, &m->dint[5], m->s);
     return FIM_OK;
 }
 
@@ -418,9 +423,13 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                            t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk, true, s);
     pend(lead, pi, lead->nA);
     if (lead->prof.on)
-        HIPX(hipMemcpyAsync(&lead->hint[4], &lead->dint[4], sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPX(hipMemcpyAsync(&lead->hint[4], &lead->dint[4], 2 * sizeof(int), hipMemcpyDeviceToHost,
+                            s));
     TRY(read_status(lead, t, G, items, s));
-    if (lead->prof.on) lead->cur_nnzb = lead->hint[4];
+    if (lead->prof.on) {
+        lead->cur_nnzb = lead->hint[4];
+        lead->cur_pcn2 = lead->use_pc ? (double)lead->hint[5] * lead->B * lead->B : 0.0;
+    }
     for (int g = 0; g < 2; g++)
         for (size_t pos = 0; pos < G[g].idx.size(); pos++) {
             SolveItem& it = items[G[g].idx[pos]];

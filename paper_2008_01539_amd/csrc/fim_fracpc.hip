@@ -24,7 +24,8 @@ __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restri
                                                      const int* __restrict__ frac_id,
                                                      const int* __restrict__ ford, int cap,
                                                      int cell_stride, int* __restrict__ pcinfo,
-                                                     int* __restrict__ pcoff) {
+                                                     int* __restrict__ pcoff,
+                                                     int* __restrict__ rows2) {
     __shared__ int sf[KB_NT];   // fracture id of each row (-1 matrix, -2 past nA)
     __shared__ int ss[KB_NT];   // block start of each row
     const int t = threadIdx.x, base = blockIdx.x * KB_NT, r = base + t;
@@ -47,14 +48,16 @@ __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restri
     if (valid) {
         pcinfo[r] = (bs << 16) | size;
         pcoff[r] = (size > 1) ? ford[l2g[base + bs]] * cell_stride : 0;
+        if (size > 1 && bs == t) atomicAdd(rows2, size * size);   // sum of block rows^2
     }
 }
 
 void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
-                      int cell_stride, int* pcinfo, int* pcoff, hipStream_t s) {
+                      int cell_stride, int* pcinfo, int* pcoff, int* rows2, hipStream_t s) {
+    launch_fill_i32(rows2, 1, 0, s);
     if (nA <= 0) return;
     k_pc_blocks<<<(nA + KB_NT - 1) / KB_NT, KB_NT, 0, s>>>(nA, l2g, frac_id, ford, cap,
-                                                            cell_stride, pcinfo, pcoff);
+                                                            cell_stride, pcinfo, pcoff, rows2);
 }
 
 // Inverse of every multi-row block of a tile, one wave per block, stored

@@ -195,8 +195,9 @@ void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s
 void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);
 
 // fracture-block preconditioner (fim_fracpc.hip)
+// rows2 receives the sum over multi-row blocks of (block rows)^2
 void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
-                      int cell_stride, int* pcinfo, int* pcoff, hipStream_t s);
+                      int cell_stride, int* pcinfo, int* pcoff, int* rows2, hipStream_t s);
 void launch_pc_invert(int b, int nA, const LocalSys& ls, const double* dinv,
                       const int* pcinfo, const int* pcoff, float* pcM, hipStream_t s);
 

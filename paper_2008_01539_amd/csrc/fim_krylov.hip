@@ -197,6 +197,32 @@ __device__ inline void row_product(const LocalSys& ls, const T* At, const RowGeo
     }
 }
 
+// One row of a fracture-block inverse times the block's values y (in
+// LDS): sum_j M[row][j] y[j], j < N; M column-major from byte offset m0,
+// colb bytes per column.  Loads and LDS reads are clamped to the block
+// (every address valid) and masked, with no branch per term, so that all
+// of them are in flight together; two halves of 32 keep registers in check.
+template <int B>
+__device__ __attribute__((always_inline)) inline double block_row_dot(const float* M, unsigned m0,
+                                                                      unsigned colb, int N,
+                                       const double* y) {
+    double acc = 0.0;
+#pragma unroll
+    for (int h = 0; h < PC_DOF; h += 32) {
+        float mv[32];
+        double yv[32];
+#pragma unroll
+        for (int q = 0; q < 32; q++) {
+            const int j = min(h + q, N - 1);
+            mv[q] = ldg<float>(M, m0 + (unsigned)j * colb);
+            yv[q] = y[j];
+        }
+#pragma unroll
+        for (int q = 0; q < 32; q++) acc += (h + q < N) ? (double)mv[q] * yv[q] : 0.0;
+    }
+    return acc;
+}
+
 // Left application of the fracture-block inverses (see fim_fracpc.hip)
 // to one tile of values y (one row per thread, FP64), used by the
 // refinement kernel.  Every thread of the block calls it (barriers); act
@@ -227,15 +253,7 @@ __device__ inline void pc_apply(const KrylovBufs& kb, bool act, int info, int of
             const int bs = inf >> 16, N = size * B, ri = (rl - bs) * B + ci;
             const unsigned m0 = (unsigned)(off_s[rl] + ri) * 4u;
             const unsigned colb = (unsigned)N * 4u;
-            float mv[PC_DOF];
-#pragma unroll
-            for (int j = 0; j < PC_DOF; j++)   // (index clamped: every load in bounds)
-                mv[j] = ldg<float>(kb.pcM, m0 + (unsigned)min(j, N - 1) * colb);
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j < PC_DOF; j++)
-                if (j < N) acc += (double)mv[j] * yb[bs * B + j];
-            z[h] = acc;
+            z[h] = block_row_dot<B>(kb.pcM, m0, colb, N, yb + bs * B);
         }
     }
     __syncthreads();
@@ -685,14 +703,7 @@ __global__ __launch_bounds__(KB_NT) void k_pc_vec(const KSeg* __restrict__ segs,
                 const int bs = inf >> 16, N = size * B, ri = (rl - bs) * B + ci;
                 const unsigned m0 = (unsigned)(off_s[rl] + ri) * 4u;
                 const unsigned colb = (unsigned)N * 4u;
-                float mv[PC_DOF];
-#pragma unroll
-                for (int j = 0; j < PC_DOF; j++)   // (index clamped: every load in bounds)
-                    mv[j] = ldg<float>(S.kb.pcM, m0 + (unsigned)min(j, N - 1) * colb);
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < PC_DOF; j++)
-                    if (j < N) acc += (double)mv[j] * yb[bs * B + j];
+                const double acc = block_row_dot<B>(S.kb.pcM, m0, colb, N, yb + bs * B);
                 const T o = (T)acc;
                 y[(long)row * B + ci] = o;
                 const double od = (double)o;
