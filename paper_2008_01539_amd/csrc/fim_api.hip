@@ -466,8 +466,8 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         // host check (without profiling, whose records need the stream
         // drained).
         const bool ahead = !lead->prof.on;
-        auto queue_chunk = [&](int first_it) {
-            for (int c = 0; c < check; c++)
+        auto queue_chunk = [&](int first_it, int len) {
+            for (int c = 0; c < len; c++)
                 for (int w = 0; w < 2; w++)
                     for (int g = 0; g < 2; g++) {
                         if (!G[g].nblk) continue;
@@ -503,14 +503,54 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
             HIPX(hipEventRecord(t.ev[sl], s));
             return FIM_OK;
         };
+        // Iterations queued so far, and the length of the next block: near
+        // convergence the block shrinks to what the observed residual
+        // decay predicts (plus a margin), so that few launches run after
+        // the solve has finished.  Blocks are never shorter than 2.
+        int queued = 0;
+        int next_len = check;
+        std::vector<double> rr_seen(K, -1.0);
+        std::vector<int> its_seen(K, -1);
+        auto plan_next = [&](int sl) {
+            double need = 0.0;
+            bool unknown = false;
+            for (int g = 0; g < 2; g++)
+                for (size_t pos = 0; pos < G[g].idx.size(); pos++) {
+                    const int q = G[g].idx[pos];
+                    if (!items[q].active) continue;
+                    const SegStatus& st = t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos];
+                    if (st.done) continue;
+                    const double rr = st.rr, tol2 = items[q].tol2;
+                    if (its_seen[q] >= 0 && st.iters > its_seen[q] && rr > 0.0 &&
+                        rr_seen[q] > 0.0 && tol2 > 0.0) {
+                        const double rate = std::pow(rr / rr_seen[q], 1.0 / (st.iters - its_seen[q]));
+                        if (rate < 0.999) {
+                            const double rem = std::log(tol2 / rr) / std::log(rate);
+                            need = std::max(need, rem - (queued - st.iters));
+                        } else {
+                            unknown = true;
+                        }
+                    } else {
+                        unknown = true;
+                    }
+                    rr_seen[q] = rr;
+                    its_seen[q] = st.iters;
+                }
+            next_len = unknown ? check : std::max(2, std::min(check, (int)std::ceil(need) + 2));
+        };
         int before = 0;
-        const int max_chunks = lead->o.krylov_maxit / check + 2;
-        queue_chunk(0);
+        const int max_chunks = lead->o.krylov_maxit + 4;   // blocks are >= 1 iteration
+        const int max_queued = lead->o.krylov_maxit + 2 * check;
+        queue_chunk(0, check);
+        queued = check;
         TRY(queue_status(0));
         for (int chunk = 0; chunk < max_chunks; chunk++) {
             const int sl = chunk & 1;
-            if (ahead && chunk + 1 < max_chunks) {
-                queue_chunk((chunk + 1) * check);
+            const bool more = queued < max_queued;
+            if (ahead && more) {
+                const int len = next_len;
+                queue_chunk(queued, len);
+                queued += len;
                 TRY(queue_status(sl ^ 1));
             }
             HIPX(hipEventSynchronize(t.ev[sl]));
@@ -529,21 +569,20 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                     if (items[G[g].idx[pos]].active &&
                         !t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos].done)
                         all = false;
-            if (all) {
-                // final iteration counts
+            if (all || !more) {
+                // final iteration counts.  Without more work queued, the
+                // status just read covers everything queued, and the
+                // iteration cap has stopped every model inside it.
                 for (int g = 0; g < 2; g++)
                     for (size_t pos = 0; pos < G[g].idx.size(); pos++)
                         t.hstat[(size_t)g * t.cap + pos] = t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos];
                 break;
             }
-            if (!ahead && chunk + 1 < max_chunks) {
-                queue_chunk((chunk + 1) * check);
+            if (ahead) plan_next(sl);
+            if (!ahead && more) {
+                queue_chunk(queued, check);
+                queued += check;
                 TRY(queue_status(sl ^ 1));
-            }
-            if (chunk + 1 == max_chunks) {
-                for (int g = 0; g < 2; g++)
-                    for (size_t pos = 0; pos < G[g].idx.size(); pos++)
-                        t.hstat[(size_t)g * t.cap + pos] = t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos];
             }
         }
         for (int g = 0; g < 2; g++)

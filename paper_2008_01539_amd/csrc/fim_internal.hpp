@@ -189,6 +189,7 @@ void launch_pc_vec(int which, int b, bool fp32, bool solo, const KSeg* segs, con
 
 struct SegStatus {
     double rir2, bnorm2;
+    double rr;              // BiCGStab |r|^2 at the last completed iteration
     int done, iters, breakdown, pad;
 };
 void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s);

@@ -788,6 +788,7 @@ __global__ __launch_bounds__(64) void k_seg_status(const KSeg* __restrict__ segs
         SegStatus o;
         o.rir2 = a;
         o.bnorm2 = b;
+        o.rr = S.kb.sc->rr;
         o.done = S.kb.sc->done;
         o.iters = S.kb.sc->iters;
         o.breakdown = S.kb.sc->breakdown;
