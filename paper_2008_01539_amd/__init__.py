@@ -3,6 +3,9 @@ MI355X (gfx950): HIP kernels behind the C ABI of include/fim.h, with a thin
 ctypes binding.
 
     from paper_2008_01539_amd import FimModel, Options, LOCAL
+
+Also: ``FimBatch`` (several models per batched call), ``serve`` (the
+continuous-batching serving loop), ``trace`` (per-iteration JSONL log).
 """
 from .fim import (DD, DEVICE, FP64, FULL, HOST, LIB_PATH, LOCAL, MIXED, PC_FRACTURE, PC_JACOBI,
                   FimBatch, FimError, FimModel, IterStats, NotConverged, Options, StepStats,

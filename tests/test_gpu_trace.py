@@ -1,0 +1,35 @@
+"""Instrumentation on the GPU path: one JSONL record per Newton iteration
+with M_A = n_A / n (Sections 5.2.1 and 5.2.3), the cell classes of each
+iteration consistent with its active-set size."""
+import json
+
+import numpy as np
+import pytest
+
+from fimgen import make_c1
+
+pytestmark = pytest.mark.gpu
+
+
+def test_iteration_log_matches_step_statistics(tmp_path):
+    from paper_2008_01539_amd import LOCAL, FimModel, Options
+    from paper_2008_01539_amd.trace import IterationLog, unrle
+    model = make_c1()
+    fm = FimModel(model, Options())
+    fm.set_state(model.u0, model.status0)
+    log = IterationLog(str(tmp_path / "c1.jsonl"), n_cells=model.n, classes_every=1)
+    recs = log.run(fm, model.schedule[:6], LOCAL)
+    log.close()
+    fm.close()
+    lines = [json.loads(s) for s in (tmp_path / "c1.jsonl").read_text().splitlines()]
+    assert len(lines) == len(recs) >= 6
+    assert sum(r["converged"] for r in lines) == 6
+    for r in lines:
+        assert r["m_a"] == r["n_active"] / model.n
+        cls = unrle(r["classes_rle"])
+        assert cls.size == model.n
+        assert int(((cls & 1) != 0).sum()) == r["n_active"]
+        # boundary and large-update classes only on active cells
+        assert not np.any((cls & 6) & ~((cls & 1) * 7))
+    s = log.summary()
+    assert abs(s["m_a_average"] * s["iterations"] - s["m_a_total"]) < 1e-12
