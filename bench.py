@@ -412,11 +412,16 @@ def main():
         prof_run = run_gpu(model, opts, P.LOCAL, args.steps, args.warmup, profile=True)
         log(f"local (events): wall {prof_run['wall']:.3f}s")
     full = None
+    dd = None
     if not args.no_full:
         log("full Newton on the same steps")
         full = run_gpu(model, opts, P.FULL, args.steps, args.warmup)
         log(f"full: {full['iters']} iterations, wall {full['wall']:.3f}s, "
             f"krylov {full['krylov']}")
+        log("Algorithm 2 (adaptive localized DD) on the same steps")
+        dd = run_gpu(model, opts, P.DD, args.steps, args.warmup)
+        log(f"dd: {dd['iters']} inner iterations, wall {dd['wall']:.3f}s, "
+            f"krylov {dd['krylov']}")
     value = loc["active"] / loc["wall"]
     out = {
         "metric": "active-cell Newton updates/s, local vs full Newton (1 GPU); "
@@ -457,6 +462,13 @@ def main():
                        "newton_step_ms_p50": full["p50"], "newton_step_ms_p99": full["p99"]}
         out["speedup_local_vs_full"] = full["wall"] / loc["wall"]
         out["max_dp_local_vs_full_psi"] = dp / PSI
+    if dd is not None:
+        out["dd"] = {"inner_iterations": dd["iters"], "sum_active": dd["active"],
+                     "updates_per_s": dd["active"] / dd["wall"], "krylov_iters": dd["krylov"],
+                     "wall_s": dd["wall"], "newton_step_ms_p50": dd["p50"],
+                     "newton_step_ms_p99": dd["p99"],
+                     "speedup_vs_full": full["wall"] / dd["wall"],
+                     "max_dp_vs_full_psi": float(np.abs(full["u"][0] - dd["u"][0]).max()) / PSI}
     # roofline of the dominant matrix kernel (local run, events on its stream)
     prof = prof_run["prof"] if prof_run else None
     if prof:

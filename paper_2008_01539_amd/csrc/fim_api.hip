@@ -408,7 +408,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         pend(lead, pi, mq->nA);
         if (mq->use_pc) {
             const int pv = pbeg(lead, PK_PCINV);
-            launch_pc_invert(mq->B, mq->nA, lsys(mq), mq->dinv, mq->pcinfo, mq->pcoff,
+            launch_pc_invert(mq->B, it.fp32, mq->nA, lsys(mq), mq->At, mq->pcinfo, mq->pcoff,
                              mq->pcM, s);
             pend(lead, pv, mq->nA);
         }

@@ -61,9 +61,9 @@ void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* for
 }
 
 // Inverse of every multi-row block of a tile, one wave per block, stored
-// in FP32 (the same inverse serves the FP32 and FP64 Krylov; 8-bit
-// mantissas are not enough for nearly singular blocks): the block of
-// A~ = D^{-1} J (FP64 products, FP32 from here on) is assembled
+// in FP32 (8-bit mantissas are not enough for nearly singular blocks): the
+// block of A~ = D^{-1} J (the scaled blocks k_precond wrote, in the
+// Krylov precision; FP32 from here on) is assembled
 // in LDS, padded to 64 x 64 with the identity, and each lane takes one
 // row into registers.  Gauss-Jordan elimination then runs 64 steps
 // without pivoting (the scaled blocks have unit diagonal blocks and are
@@ -82,9 +82,9 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-template <int B>
+template <int B, typename T>
 __global__ __launch_bounds__(WAVE) void k_pc_invert(int nA, LocalSys ls,
-                                                    const double* __restrict__ dinv,
+                                                    const T* __restrict__ At,
                                                     const int* __restrict__ pcinfo,
                                                     const int* __restrict__ pcoff,
                                                     float* __restrict__ pcM) {
@@ -115,25 +115,39 @@ __global__ __launch_bounds__(WAVE) void k_pc_invert(int nA, LocalSys ls,
         for (int e = lane; e < N * N; e += WAVE) M[e] = 0.0f;
         wave_sync();
         if (lane < size) {
+            // the row of A~: identity diagonal block, off-diagonal blocks
+            // as scaled by k_precond (At, Krylov precision).  Columns of a
+            // group of slots are loaded together, then their blocks.
             const int r = base + bs + lane;
             const long s0 = slot_of(ls, r, 0);
             const int width = ls.swidth[r / SLICE];
-            const double* di = dinv + (long)r * BB;
-            for (int k = 0; k < width; k++) {
-                const long pos = s0 + (long)k * SLICE;
-                const int jl = ls.col[pos] - (base + bs);
-                if (jl < 0 || jl >= size) continue;
-                const double* a = ls.J + pos * BB;
 #pragma unroll
-                for (int i = 0; i < B; i++)
+            for (int i = 0; i < B; i++) M[(lane * B + i) * N + lane * B + i] = 1.0f;
+            for (int k0 = 1; k0 < width; k0 += 8) {
+                int jl[8];
 #pragma unroll
-                    for (int j = 0; j < B; j++) {
-                        double acc = 0.0;
+                for (int u = 0; u < 8; u++) {
+                    const int k = k0 + u;
+                    jl[u] = k < width ? ls.col[s0 + (long)k * SLICE] - (base + bs) : -1;
+                }
+                T blk[8][BB];
 #pragma unroll
-                        for (int m = 0; m < B; m++) acc += di[i * B + m] * a[m * B + j];
-                        // padding slots (col = r, zero block) add nothing
-                        M[(lane * B + i) * N + jl * B + j] += (float)acc;
-                    }
+                for (int u = 0; u < 8; u++) {
+                    const bool in = jl[u] >= 0 && jl[u] < size && jl[u] != lane;
+#pragma unroll
+                    for (int e = 0; e < BB; e++)
+                        blk[u][e] = in ? At[(s0 + (long)min(k0 + u, width - 1) * SLICE) * BB + e]
+                                       : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    if (!(jl[u] >= 0 && jl[u] < size && jl[u] != lane)) continue;
+#pragma unroll
+                    for (int i = 0; i < B; i++)
+#pragma unroll
+                        for (int j = 0; j < B; j++)
+                            M[(lane * B + i) * N + jl[u] * B + j] = (float)blk[u][i * B + j];
+                }
             }
         }
         wave_sync();
@@ -186,13 +200,18 @@ __global__ __launch_bounds__(WAVE) void k_pc_invert(int nA, LocalSys ls,
     }
 }
 
-void launch_pc_invert(int b, int nA, const LocalSys& ls, const double* dinv,
+void launch_pc_invert(int b, bool fp32, int nA, const LocalSys& ls, const void* At,
                       const int* pcinfo, const int* pcoff, float* pcM, hipStream_t s) {
     if (nA <= 0) return;
     const int nb = (nA + KB_NT - 1) / KB_NT * PCI_SUB;
-    if (b == 1) k_pc_invert<1><<<nb, WAVE, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
-    else if (b == 2) k_pc_invert<2><<<nb, WAVE, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
-    else k_pc_invert<3><<<nb, WAVE, 0, s>>>(nA, ls, dinv, pcinfo, pcoff, pcM);
+#define PV(BV, TT) \
+    k_pc_invert<BV, TT><<<nb, WAVE, 0, s>>>(nA, ls, (const TT*)At, pcinfo, pcoff, pcM)
+    if (fp32) {
+        if (b == 1) PV(1, float); else if (b == 2) PV(2, float); else PV(3, float);
+    } else {
+        if (b == 1) PV(1, double); else if (b == 2) PV(2, double); else PV(3, double);
+    }
+#undef PV
 }
 
 } // namespace fimk

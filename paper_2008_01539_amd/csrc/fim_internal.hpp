@@ -199,7 +199,8 @@ void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);
 // rows2 receives the sum over multi-row blocks of (block rows)^2
 void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
                       int cell_stride, int* pcinfo, int* pcoff, int* rows2, hipStream_t s);
-void launch_pc_invert(int b, int nA, const LocalSys& ls, const double* dinv,
+// At: the scaled blocks in the Krylov precision (fp32: float, else double)
+void launch_pc_invert(int b, bool fp32, int nA, const LocalSys& ls, const void* At,
                       const int* pcinfo, const int* pcoff, float* pcM, hipStream_t s);
 
 // update (fim_update.hip)

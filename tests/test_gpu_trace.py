@@ -33,3 +33,18 @@ def test_iteration_log_matches_step_statistics(tmp_path):
         assert not np.any((cls & 6) & ~((cls & 1) * 7))
     s = log.summary()
     assert abs(s["m_a_average"] * s["iterations"] - s["m_a_total"]) < 1e-12
+
+
+def test_autotune_probes_on_the_gpu(tmp_path):
+    from paper_2008_01539_amd import MIXED, Options
+    from paper_2008_01539_amd.autotune import tune
+    from fimgen import make_small_c2
+    model = make_small_c2()
+    cache = tmp_path / "tune.json"
+    o = tune(model, Options(precision=MIXED), probe_steps=1, cache_path=str(cache))
+    rec = json.loads(cache.read_text())
+    (key, entry), = rec.items()
+    assert entry["choice"] in entry["candidates"]
+    assert all(t > 0 for t in entry["times_s"])
+    assert (o.check_every, o.precond) == (entry["choice"]["check_every"],
+                                          entry["choice"]["precond"])
