@@ -36,21 +36,18 @@ def algorithmic_bytes(kernel, rec, b, kbytes, pc=True):
     """Bytes a kernel must move per the work it did (one active row = one
     unit): every array entry it reads or writes once, neighbour gathers
     counted once (cache reuse), padding of the sliced-ELL matrix excluded.
-    rec: profile record with rows and nnzb (blocks incl. diagonal; for the
-    fracture-block steps the entries of the block inverses read)."""
+    rec: profile record with rows, nnzb (blocks incl. diagonal) and aux
+    (FP32 fracture-block inverse entries applied by the product kernels)."""
     rows, nnzb = rec["rows"], rec["nnzb"]
     off = max(nnzb - rows, 0.0)
-    blk = 4 if pc else 0   # block layout word per row
+    aux = rec.get("aux", 0.0)
+    blk = 8 if (pc and aux > 0) else 0   # block layout words per row
     if kernel == "bicg_spmv_p":
-        # col + block per off-diagonal; s, t, p, v, x, rh read; x, r, p, v written
-        return off * (4 + kbytes * b * b) + rows * (10 * b * kbytes + blk)
+        # col + block per off-diagonal; s, t, p, v, x, rh read; x, r, p, v
+        # written; the inverse entries of the fracture blocks
+        return off * (4 + kbytes * b * b) + rows * (10 * b * kbytes + blk) + 4 * aux
     if kernel == "bicg_spmv_s":   # col + block; r, v, rh read; s, t written
-        return off * (4 + kbytes * b * b) + rows * (5 * b * kbytes + blk)
-    if kernel in ("frac_apply_p", "frac_apply_s"):
-        # FP32 inverse entries; per row: layout words 8, y and rh (and s
-        # after S) read; the fracture rows' results written (not counted)
-        nvec = 2 if kernel == "frac_apply_p" else 3
-        return 4 * nnzb + rows * (8 + nvec * b * kbytes)
+        return off * (4 + kbytes * b * b) + rows * (5 * b * kbytes + blk) + 4 * aux
     if kernel == "assemble":
         # per row: l2g 4, state 8b, status 1, pv 8, depth 8, flags 1, old
         # masses 8b, adjacency pointers 8, residual 8b written; per
@@ -473,8 +470,7 @@ def main():
     prof = prof_run["prof"] if prof_run else None
     if prof:
         cands = {k: v for k, v in prof.items()
-                 if k in ("assemble", "bicg_spmv_p", "bicg_spmv_s", "frac_apply_p",
-                          "frac_apply_s") and v["launches"]}
+                 if k in ("assemble", "bicg_spmv_p", "bicg_spmv_s") and v["launches"]}
         dom = max(cands, key=lambda k: cands[k]["total_ms"])
         rec = cands[dom]
         avg_s = rec["total_ms"] / rec["launches"] * 1e-3

@@ -257,19 +257,20 @@ fim_status fim_get_flags(fim_model* m, uint8_t* out);
 /* Per-kernel timing with hipEvents recorded on the model's stream around
  * each launch (kernel classes: assemble, precond, ir_residual,
  * bicg_spmv_p, bicg_spmv_s, update, sets_compact, step_setup,
- * frac_invert, frac_apply_p, frac_apply_s).  BiCGStab launches queued
- * after the solve converged return at once and are not counted.  rows =
- * sum over launches of the active rows the launch processed, nnzb = sum of
- * the blocks (diagonal included) of the local matrix for the kernels that
- * read or write it, and for frac_apply_* the entries of the fracture-block
- * inverses they read.  Profiling adds event records and one extra
- * synchronisation per linear solve and is off by default. */
+ * frac_invert).  BiCGStab launches queued after the solve converged return
+ * at once and are not counted.  rows = sum over launches of the active
+ * rows the launch processed, nnzb = sum of the blocks (diagonal included)
+ * of the local matrix for the kernels that read or write it, aux = sum of
+ * the fracture-block inverse entries that the product kernels applied
+ * (zero without fracture blocks).  Profiling adds event records and one
+ * extra synchronisation per linear solve and is off by default. */
 typedef struct fim_kernel_profile {
     char    name[32];
     int64_t launches;
     double  total_ms;
     double  rows;
     double  nnzb;
+    double  aux;
 } fim_kernel_profile;
 
 /* on != 0 clears the counters and starts recording; 0 stops. */

@@ -39,6 +39,7 @@ struct Prof {
     double ms[PK_N] = {};
     double rows[PK_N] = {};
     double nnzb[PK_N] = {};
+    double aux[PK_N] = {};
     long cnt[PK_N] = {};
 };
 
@@ -145,7 +146,7 @@ static int pbeg(fim_model* m, int k, int tag = -1) {
 // record for a launch whose events the dispatch stamps (hipExtLaunchKernel)
 static int pbeg_ext(fim_model* m, int k, int tag) {
     if (!m->prof.on) return -1;
-    const bool mat = k == PK_BICG_A || k == PK_BICG_B || k == PK_PCV_A || k == PK_PCV_B;
+    const bool mat = k == PK_BICG_A || k == PK_BICG_B;
     ProfRec r{k, ev_take(m), ev_take(m), 0.0, mat, tag};
     m->prof.pend.push_back(r);
     return (int)m->prof.pend.size() - 1;
@@ -169,11 +170,12 @@ static void pflush(fim_model* m, int keep_tag = INT_MAX) {
                 m->prof.ms[r.k] += ms;
                 m->prof.cnt[r.k] += 1;
                 m->prof.rows[r.k] += r.rows;
-                // matrix launches: blocks of the local matrix; fracture-block
-                // steps: entries of the block inverses
-                if (r.matrix)
-                    m->prof.nnzb[r.k] += (r.k == PK_PCV_A || r.k == PK_PCV_B) ? m->cur_pcn2
-                                                                             : m->cur_nnzb;
+                // matrix launches: blocks of the local matrix and entries of
+                // the fracture-block inverses
+                if (r.matrix) {
+                    m->prof.nnzb[r.k] += m->cur_nnzb;
+                    m->prof.aux[r.k] += m->cur_pcn2;   // the product kernels apply them
+                }
             }
         }
         m->prof.pool.push_back(r.a);
@@ -472,21 +474,12 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                     for (int g = 0; g < 2; g++) {
                         if (!G[g].nblk) continue;
                         const int q = pbeg_ext(lead, PK_BICG_A + w, c);
-                        launch_bicg_part(w, b, g == 0, solo_of(t, G, g), t.dsegs + (size_t)g * t.cap,
+                        launch_bicg_part(w, b, g == 0, solo_of(t, G, g), G[g].pc,
+                                         t.dsegs + (size_t)g * t.cap,
                                          t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk,
                                          first_it + c, s, q >= 0 ? lead->prof.pend[q].a : nullptr,
                                          q >= 0 ? lead->prof.pend[q].b : nullptr);
                         if (q >= 0) lead->prof.pend[q].rows = lead->nA;
-                        if (G[g].pc) {
-                            const int qv = pbeg_ext(lead, PK_PCV_A + w, c);
-                            launch_pc_vec(w, b, g == 0, solo_of(t, G, g),
-                                          t.dsegs + (size_t)g * t.cap,
-                                          t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk,
-                                          first_it + c, s,
-                                          qv >= 0 ? lead->prof.pend[qv].a : nullptr,
-                                          qv >= 0 ? lead->prof.pend[qv].b : nullptr);
-                            if (qv >= 0) lead->prof.pend[qv].rows = lead->nA;
-                        }
                     }
         };
         // status of the queued work into slot sl (2 slots), then an event
@@ -1668,6 +1661,7 @@ fim_status fim_profile_enable(fim_model* m, int32_t on) {
         m->prof.ms[k] = 0.0;
         m->prof.rows[k] = 0.0;
         m->prof.nnzb[k] = 0.0;
+        m->prof.aux[k] = 0.0;
         m->prof.cnt[k] = 0;
     }
     return FIM_OK;
@@ -1684,6 +1678,7 @@ int32_t fim_profile_read(fim_model* m, fim_kernel_profile* out, int32_t cap) {
         out[k].total_ms = m->prof.ms[k];
         out[k].rows = m->prof.rows[k];
         out[k].nnzb = m->prof.nnzb[k];
+        out[k].aux = m->prof.aux[k];
     }
     return k;
 }

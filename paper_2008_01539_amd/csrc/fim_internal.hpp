@@ -176,8 +176,10 @@ void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int
 // which: 0 = kernel P (x, r update of iteration it-1; p and v = A p of it),
 // 1 = kernel S (s = r - alpha v, t = A s); it = iteration index (same for
 // every model of the launch)
+// pc: some model of the launch has fracture blocks (the kernels then apply
+// their inverses to the product on the fracture rows)
 // ev0/ev1: optional events stamped with the kernel's own start and end
-void launch_bicg_part(int which, int b, bool fp32, bool solo, const KSeg* segs,
+void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSeg* segs,
                       const int* blk_seg, int nblk_total, int it, hipStream_t s,
                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,

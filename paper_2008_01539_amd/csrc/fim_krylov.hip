@@ -7,10 +7,11 @@
 //   x64 += d                    until ||r64|| <= lin_rtol ||F||.
 //
 // With fracture blocks (fim_fracpc.hip) BiCGStab runs on M^{-1} A~, M the
-// block diagonal of A~ over fracture blocks: every product kernel is
-// followed by a short kernel that applies M^{-1} on the fracture rows.
+// block diagonal of A~ over fracture blocks: each product kernel applies
+// M^{-1} to its tile's fracture rows before writing them (the blocks of a
+// tile are local to its workgroup).
 //
-// One BiCGStab iteration is two kernels (four with fracture blocks).  Each writes per-block partial
+// One BiCGStab iteration is two kernels.  Each writes per-block partial
 // dot products; the next kernel's blocks each reduce those partials in the
 // same fixed order (so every block derives the same scalar, and the result
 // is deterministic) before doing their rows.  No fences, atomics or extra
@@ -90,8 +91,9 @@ constexpr int chunk_slots() {
 // more registers than that leaves.
 template <int B, typename T>
 constexpr int kbp_waves() { return (B == 3 && sizeof(T) == 8) ? 2 : 3; }
-template <int B, typename T>
-constexpr int kbs_waves() { return kbp_waves<B, T>(); }
+// with the fracture-block step fused in (PC), two waves per SIMD
+template <int B, typename T, bool PC>
+constexpr int kb_waves() { return PC ? 2 : kbp_waves<B, T>(); }
 
 // Slot geometry of row r: slot k at base + 64 k; width slots are in use,
 // cap (the slice stride) bounds the slots that may be read at all.
@@ -221,6 +223,61 @@ __device__ __attribute__((always_inline)) inline double block_row_dot(const floa
         for (int q = 0; q < 32; q++) acc += (h + q < N) ? (double)mv[q] * yv[q] : 0.0;
     }
     return acc;
+}
+
+// Left application of the fracture-block inverses inside the product
+// kernels: y holds this thread's row of A~ x; rows of multi-row fracture
+// blocks get the block's M^{-1} applied (the block's other rows are in the
+// same tile, exchanged through LDS in the stored precision T, the values
+// the unpreconditioned product would have written).  Every thread of the
+// workgroup calls it; tiles without such blocks return after one barrier.
+// The block's columns are taken 16 at a time (B loads and one LDS read per
+// column, all in flight together), so the register cost stays bounded
+// whatever the block size.
+template <int B, typename T>
+__device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off,
+                               double (&y)[B]) {
+    __shared__ T yb[KB_NT * B];
+    constexpr int Q = (B == 3 && sizeof(T) == 8) ? 8 : 16;
+    const int t = threadIdx.x;
+    const bool blk = act && (info & 0xffff) > 1;
+    if (!__syncthreads_or(blk)) return;
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < B; c++) yb[t * B + c] = (T)y[c];
+    }
+    __syncthreads();
+    if (blk) {
+        const int size = info & 0xffff, bs = info >> 16, N = size * B;
+        const unsigned colb = (unsigned)N * 4u;
+        const unsigned m0 = (unsigned)(off + (t - bs) * B) * 4u;
+        const T* yv = yb + bs * B;
+        double acc[B];
+#pragma unroll
+        for (int c = 0; c < B; c++) acc[c] = 0.0;
+#pragma unroll 1
+        for (int h = 0; h < N; h += Q) {
+            float mv[Q][B];
+            T ys[Q];
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+                const int j = min(h + q, N - 1);
+                ys[q] = yv[j];
+#pragma unroll
+                for (int c = 0; c < B; c++)
+                    mv[q][c] = ldg<float>(kb.pcM, m0 + 4u * c + (unsigned)j * colb);
+            }
+#pragma unroll
+            for (int q = 0; q < Q; q++) {
+                const double w = (h + q < N) ? (double)ys[q] : 0.0;
+#pragma unroll
+                for (int c = 0; c < B; c++) acc[c] += (double)mv[q][c] * w;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < B; c++) y[c] = acc[c];
+    }
+    __syncthreads();   // yb is reused by the next tile pass
 }
 
 // Left application of the fracture-block inverses (see fim_fracpc.hip)
@@ -376,8 +433,8 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
 // update) at the iteration cap or when omega = 0.  The own-row operands
 // and the first chunk of neighbour slots are fetched before the previous
 // kernel's partial sums are reduced, so those loads overlap the reduction.
-template <int B, typename T, bool FIRST, bool SOLO>
-__global__ __launch_bounds__(KB_NT, (kbp_waves<B, T>())) void k_bicg_p(const KSeg* __restrict__ segs,
+template <int B, typename T, bool FIRST, bool SOLO, bool PC>
+__global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
                                                                       int it) {
     const KSeg& S = seg_of<SOLO>(segs, blk_seg);
@@ -393,18 +450,11 @@ __global__ __launch_bounds__(KB_NT, (kbp_waves<B, T>())) void k_bicg_p(const KSe
     const double rho_prev = FIRST ? 1.0 : sc->rho_hist[(it - 1) & 1];
     const double al_prev = sc->alpha;
     constexpr int NR = FIRST ? 1 : 4;
-    const bool pc = S.kb.pcM != nullptr;
+    const bool pc = PC && S.kb.pcM != nullptr;   // uniform over the launch's segment
     double red[4] = {0.0, 0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
 #pragma unroll
         for (int k = 0; k < NR; k++) red[k] += pin[(long)q * 4 + k];
-    }
-    if (!FIRST && pc) {
-        // the fracture rows' share, from the preconditioner step after S
-        for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
-#pragma unroll
-            for (int k = 0; k < 4; k++) red[k] += S.kb.part_b2[(long)q * 4 + k];
-        }
     }
     if (done) return;
     const int r0 = lb * blockDim.x + threadIdx.x;
@@ -424,7 +474,7 @@ __global__ __launch_bounds__(KB_NT, (kbp_waves<B, T>())) void k_bicg_p(const KSe
     RowGeo g{0, 0, 0};
     T own[NV][B] = {}, ox[B] = {}, orh[B] = {};
     Chunk<B, T, NV, U> ch{};
-    bool inblk = false;   // row of a multi-row fracture block
+    int pinfo = 1, poff = 0;   // fracture-block layout of the row
     auto fetch = [&](int r) {
         g = row_geo(ls, r);
         const unsigned ro = (unsigned)r * RB;
@@ -432,7 +482,10 @@ __global__ __launch_bounds__(KB_NT, (kbp_waves<B, T>())) void k_bicg_p(const KSe
         for (int v = 0; v < NV; v++) ldv<B, T>(own[v], src[v], ro);
         if constexpr (!FIRST) ldv<B, T>(ox, V.x, ro);
         ldv<B, T>(orh, V.rh, ro);
-        inblk = pc && (ldg<int>(S.kb.pcinfo, 4u * (unsigned)r) & 0xffff) > 1;
+        if (pc) {
+            pinfo = ldg<int>(S.kb.pcinfo, 4u * (unsigned)r);
+            poff = ldg<int>(S.kb.pcoff, 4u * (unsigned)r);
+        }
         fetch_chunk<B, T, NV, U>(ls, At, g, 1, src, ch);
     };
     if (r0 < nA) fetch(r0);
@@ -469,55 +522,65 @@ __global__ __launch_bounds__(KB_NT, (kbp_waves<B, T>())) void k_bicg_p(const KSe
         }
     };
     double dot[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r = r0; r < nA; r += stride) {
+    // whole tiles per pass (r - threadIdx.x is the tile base), and the
+    // fracture-block step outside every per-row branch: its barriers are
+    // reached by all waves of the workgroup the same number of times
+    for (int r = r0; r - (int)threadIdx.x < nA; r += stride) {
+        const bool act = r < nA;
         const unsigned ro = (unsigned)r * RB;
-        T ri[B];
-        double pi[B], vi[B];
-        if constexpr (FIRST) {
+        double vi[B];
 #pragma unroll
-            for (int c = 0; c < B; c++) ri[c] = own[0][c];
-        } else {
-            // tail of iteration i-1 on the own row
-            T xn[B];
+        for (int c = 0; c < B; c++) vi[c] = 0.0;
+        if (act) {
+            T ri[B];
+            if constexpr (FIRST) {
 #pragma unroll
-            for (int c = 0; c < B; c++) {
-                const double sv = (double)own[0][c];
-                xn[c] = (T)((double)ox[c] + al_prev * (double)own[2][c] + om * sv);
-                ri[c] = (T)(sv - om * (double)own[1][c]);
+                for (int c = 0; c < B; c++) ri[c] = own[0][c];
+            } else {
+                // tail of iteration i-1 on the own row
+                T xn[B];
+#pragma unroll
+                for (int c = 0; c < B; c++) {
+                    const double sv = (double)own[0][c];
+                    xn[c] = (T)((double)ox[c] + al_prev * (double)own[2][c] + om * sv);
+                    ri[c] = (T)(sv - om * (double)own[1][c]);
+                }
+                stv<B, T>(V.x, ro, xn);
+                stv<B, T>(V.r, ro, ri);
             }
-            stv<B, T>(V.x, ro, xn);
-            stv<B, T>(V.r, ro, ri);
+            if (!stop) {
+                double pi[B];
+                fx(own, pi);
+#pragma unroll
+                for (int c = 0; c < B; c++) vi[c] = pi[c];      // diagonal block of A~ is I
+                row_product<B, T, NV, U>(ls, At, g, src, ch, vi, fx);
+                T pT[B];
+#pragma unroll
+                for (int c = 0; c < B; c++) {
+                    pT[c] = (T)pi[c];
+                    dot[2] += (double)ri[c] * (double)ri[c];
+                }
+                stv<B, T>(V.p_new, ro, pT);
+            }
         }
-        if (stop) {
-            if (r + stride < nA) fetch(r + stride);
+        if (stop) {   // uniform: x and r only
+            if (act && r + stride < nA) fetch(r + stride);
             continue;
         }
-        fx(own, pi);
+        if (pc) pc_rows<B, T>(S.kb, act, pinfo, poff, vi);   // v = M^{-1} A~ p
+        if (act) {
+            T vT[B];
 #pragma unroll
-        for (int c = 0; c < B; c++) vi[c] = pi[c];      // diagonal block of A~ is I
-        row_product<B, T, NV, U>(ls, At, g, src, ch, vi, fx);
-        T pT[B], vT[B];
-#pragma unroll
-        for (int c = 0; c < B; c++) {
-            pT[c] = (T)pi[c];
-            vT[c] = (T)vi[c];
-        }
-        stv<B, T>(V.p_new, ro, pT);
-        // rows of fracture blocks hold A~ p here; the preconditioner step
-        // replaces it by M^{-1} A~ p and adds their (rh, v), (v, v)
-        stv<B, T>(V.v_new, ro, vT);
-        const bool own_v = !inblk;
-#pragma unroll
-        for (int c = 0; c < B; c++) {
-            if (own_v) {
+            for (int c = 0; c < B; c++) {
+                vT[c] = (T)vi[c];
                 dot[0] += (double)orh[c] * (double)vT[c];
                 dot[1] += (double)vT[c] * (double)vT[c];
             }
-            dot[2] += (double)ri[c] * (double)ri[c];
+            stv<B, T>(V.v_new, ro, vT);
+            // (fetched here, not at the top of the loop, so that the first
+            // chunk's registers are dead during the rest of the row)
+            if (r + stride < nA) fetch(r + stride);
         }
-        // (fetched here, not at the top of the loop, so that the first
-        // chunk's registers are dead during the rest of the row)
-        if (r + stride < nA) fetch(r + stride);
     }
     block_sum<4>(dot);
     if (threadIdx.x == 0) {
@@ -531,8 +594,8 @@ __global__ __launch_bounds__(KB_NT, (kbp_waves<B, T>())) void k_bicg_p(const KSe
 // |r_i|^2 <= tol2 (x_i is the answer) or on a breakdown of sigma; else
 // alpha = rho_i / sigma, s = r_i - alpha v_i, t = A~ s (s rebuilt at the
 // neighbours).  Partial sums: (t,s), (t,t), (rh,s), (rh,t).
-template <int B, typename T, bool SOLO>
-__global__ __launch_bounds__(KB_NT, (kbs_waves<B, T>())) void k_bicg_s(const KSeg* __restrict__ segs,
+template <int B, typename T, bool SOLO, bool PC>
+__global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
                                                                       int it) {
     const KSeg& S = seg_of<SOLO>(segs, blk_seg);
@@ -547,18 +610,11 @@ __global__ __launch_bounds__(KB_NT, (kbs_waves<B, T>())) void k_bicg_s(const KSe
     const double brk = sizeof(T) == 4 ? 1e-6 : 1e-14;
     const int done = sc->done;
     const double rho = sc->rho_hist[it & 1];
-    const bool pc = S.kb.pcM != nullptr;
+    const bool pc = PC && S.kb.pcM != nullptr;
     double red[3] = {0.0, 0.0, 0.0};
     for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
 #pragma unroll
         for (int k = 0; k < 3; k++) red[k] += pa[(long)q * 4 + k];
-    }
-    if (pc) {
-        // the fracture rows' share, from the preconditioner step after P
-        for (int q = threadIdx.x; q < nbk; q += blockDim.x) {
-#pragma unroll
-            for (int k = 0; k < 3; k++) red[k] += S.kb.part_a2[(long)q * 4 + k];
-        }
     }
     if (done) return;
     constexpr int NV = 2;
@@ -570,14 +626,17 @@ __global__ __launch_bounds__(KB_NT, (kbs_waves<B, T>())) void k_bicg_s(const KSe
     RowGeo g{0, 0, 0};
     T own[NV][B] = {}, orh[B] = {};
     Chunk<B, T, NV, U> ch{};
-    bool inblk = false;   // row of a multi-row fracture block
+    int pinfo = 1, poff = 0;   // fracture-block layout of the row
     auto fetch = [&](int r) {
         g = row_geo(ls, r);
         const unsigned ro = (unsigned)r * RB;
 #pragma unroll
         for (int v = 0; v < NV; v++) ldv<B, T>(own[v], src[v], ro);
         ldv<B, T>(orh, V.rh, ro);
-        inblk = pc && (ldg<int>(S.kb.pcinfo, 4u * (unsigned)r) & 0xffff) > 1;
+        if (pc) {
+            pinfo = ldg<int>(S.kb.pcinfo, 4u * (unsigned)r);
+            poff = ldg<int>(S.kb.pcoff, 4u * (unsigned)r);
+        }
         fetch_chunk<B, T, NV, U>(ls, At, g, 1, src, ch);
     };
     if (r0 < nA) fetch(r0);
@@ -603,35 +662,45 @@ __global__ __launch_bounds__(KB_NT, (kbs_waves<B, T>())) void k_bicg_s(const KSe
         for (int c = 0; c < B; c++) x[c] = (double)(T)((double)raw[0][c] - al * (double)raw[1][c]);
     };
     double dot[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r = r0; r < nA; r += stride) {
+    // whole tiles per pass, the fracture-block step outside every per-row
+    // branch (its barriers are uniform over the workgroup)
+    for (int r = r0; r - (int)threadIdx.x < nA; r += stride) {
+        const bool act = r < nA;
         const unsigned ro = (unsigned)r * RB;
-        double si[B], ti[B];
-        fx(own, si);
-#pragma unroll
-        for (int c = 0; c < B; c++) ti[c] = si[c];
-        row_product<B, T, NV, U>(ls, At, g, src, ch, ti, fx);
-        T sT[B], tT[B];
+        double ti[B];
+        T sT[B];
 #pragma unroll
         for (int c = 0; c < B; c++) {
-            sT[c] = (T)si[c];
-            tT[c] = (T)ti[c];
+            ti[c] = 0.0;
+            sT[c] = (T)0;
         }
-        stv<B, T>(V.s, ro, sT);
-        // rows of fracture blocks hold A~ s here; the preconditioner step
-        // replaces it and adds their (t, s), (t, t), (rh, t)
-        stv<B, T>(V.t, ro, tT);
-        const bool own_t = !inblk;
+        if (act) {
+            double si[B];
+            fx(own, si);
 #pragma unroll
-        for (int c = 0; c < B; c++) {
-            const double sd = (double)sT[c], td = (double)tT[c], h = (double)orh[c];
-            if (own_t) {
+            for (int c = 0; c < B; c++) ti[c] = si[c];
+            row_product<B, T, NV, U>(ls, At, g, src, ch, ti, fx);
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                sT[c] = (T)si[c];
+                dot[2] += (double)orh[c] * (double)sT[c];
+            }
+            stv<B, T>(V.s, ro, sT);
+        }
+        if (pc) pc_rows<B, T>(S.kb, act, pinfo, poff, ti);   // t = M^{-1} A~ s
+        if (act) {
+            T tT[B];
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                tT[c] = (T)ti[c];
+                const double sd = (double)sT[c], td = (double)tT[c], h = (double)orh[c];
                 dot[0] += td * sd;
                 dot[1] += td * td;
                 dot[3] += h * td;
             }
-            dot[2] += h * sd;
+            stv<B, T>(V.t, ro, tT);
+            if (r + stride < nA) fetch(r + stride);
         }
-        if (r + stride < nA) fetch(r + stride);
     }
     block_sum<4>(dot);
     if (threadIdx.x == 0) {
@@ -752,19 +821,20 @@ void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s) {
 
 // ev0/ev1 (optional): events stamped by the dispatch itself
 // (hipExtLaunchKernelGGL), i.e. the kernel's own start and end
-template <int B, typename T, bool SOLO>
+template <int B, typename T, bool SOLO, bool PC>
 static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 nb(nblk_total), nt(KB_NT);
     if (which == 0) {
         if (it == 0)
-            hipExtLaunchKernelGGL(k_bicg_p<B, T, true, SOLO>, nb, nt, 0, s, ev0, ev1, 0, segs,
+            hipExtLaunchKernelGGL(k_bicg_p<B, T, true, SOLO, PC>, nb, nt, 0, s, ev0, ev1, 0, segs,
                                   blk_seg, it);
         else
-            hipExtLaunchKernelGGL(k_bicg_p<B, T, false, SOLO>, nb, nt, 0, s, ev0, ev1, 0, segs,
-                                  blk_seg, it);
+            hipExtLaunchKernelGGL(k_bicg_p<B, T, false, SOLO, PC>, nb, nt, 0, s, ev0, ev1, 0,
+                                  segs, blk_seg, it);
     } else {
-        hipExtLaunchKernelGGL(k_bicg_s<B, T, SOLO>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg, it);
+        hipExtLaunchKernelGGL(k_bicg_s<B, T, SOLO, PC>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg,
+                              it);
     }
 }
 
@@ -824,16 +894,26 @@ void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int
 #undef IR
 }
 
-void launch_bicg_part(int which, int b, bool fp32, bool solo, const KSeg* segs,
+void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSeg* segs,
                       const int* blk_seg, int nblk_total, int it, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1) {
     if (nblk_total <= 0) return;
-#define PI(BV, TT)                                                                          \
-    do {                                                                                    \
-        if (solo)                                                                           \
-            part_impl<BV, TT, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1);      \
-        else                                                                                \
-            part_impl<BV, TT, false>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1);     \
+#define PI(BV, TT)                                                                             \
+    do {                                                                                       \
+        if (solo) {                                                                            \
+            if (pc)                                                                            \
+                part_impl<BV, TT, true, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1); \
+            else                                                                               \
+                part_impl<BV, TT, true, false>(which, segs, blk_seg, nblk_total, it, s, ev0,   \
+                                               ev1);                                           \
+        } else {                                                                               \
+            if (pc)                                                                            \
+                part_impl<BV, TT, false, true>(which, segs, blk_seg, nblk_total, it, s, ev0,   \
+                                               ev1);                                           \
+            else                                                                               \
+                part_impl<BV, TT, false, false>(which, segs, blk_seg, nblk_total, it, s, ev0,  \
+                                                ev1);                                          \
+        }                                                                                      \
     } while (0)
     KDISPATCH(PI)
 #undef PI

@@ -82,7 +82,8 @@ class IterStats(C.Structure):
 
 class KernelProfile(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("launches", C.c_int64),
-                ("total_ms", C.c_double), ("rows", C.c_double), ("nnzb", C.c_double)]
+                ("total_ms", C.c_double), ("rows", C.c_double), ("nnzb", C.c_double),
+                ("aux", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -334,7 +335,8 @@ class FimModel:
         arr = (KernelProfile * 16)()
         k = _lib.fim_profile_read(self._h, arr, 16)
         return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
-                                           rows=arr[i].rows, nnzb=arr[i].nnzb)
+                                           rows=arr[i].rows, nnzb=arr[i].nnzb,
+                                           aux=arr[i].aux)
                 for i in range(k)}
 
     # ------------------------------------------------------------ inspection
