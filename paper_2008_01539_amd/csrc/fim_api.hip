@@ -85,7 +85,7 @@ struct fim_model {
     float* pcM = nullptr;           // FP32 inverses
     // Krylov
     double *x64 = nullptr, *xprev = nullptr, *rir = nullptr, *part = nullptr;
-    double* part_ir = nullptr;   // Krylov partials: 22 x KB_MAXB
+    double* part_ir = nullptr;   // Krylov partials: 14 x KB_MAXB
     double* hpart = nullptr;     // pinned copy of the refinement partials
     void* kvec = nullptr;   // 9 vectors of nA b elements in the Krylov precision
     KScal* sc = nullptr;
@@ -250,8 +250,6 @@ static KrylovBufs kbufs(fim_model* m, bool fp32) {
     kb.pcinfo = m->pcinfo;
     kb.pcoff = m->pcoff;
     kb.pcM = m->use_pc ? m->pcM : nullptr;
-    kb.part_a2 = m->part_ir + 14 * KB_MAXB;
-    kb.part_b2 = m->part_ir + 18 * KB_MAXB;
     return kb;
 }
 
@@ -282,7 +280,7 @@ static fim_status structure(fim_model* m) {
     launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, &m->dint[4], m->s);
     if (m->use_pc)
         launch_pc_blocks(m->nA, m->l2g, m->frac_id, m->ford, m->pc_cap,
-                         m->pc_cap * m->B * m->B, m->pcinfo, m->pcoff, &m->dint[5], m->s);
+                         pc_cell_stride(m->B), m->pcinfo, m->pcoff, &m->dint[5], m->s);
     return FIM_OK;
 }
 
@@ -1088,7 +1086,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             if (d->frac_id[i] >= 0) ford[i] = nfc++;
         if (nfc > 0) {
             m->pc_cap = PC_DOF / B;
-            const double store = (double)nfc * m->pc_cap * B * B * sizeof(float);
+            const double store = (double)nfc * pc_cell_stride(B) * sizeof(float);
             if (store >= 4294967296.0) {
                 g_create_err = "model too large: fracture-block inverses would exceed 4 GiB";
                 free_all(m);
@@ -1099,12 +1097,12 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             CK(dal(m, &m->ford, nn));
             CK(dal(m, &m->pcinfo, nn));
             CK(dal(m, &m->pcoff, nn));
-            CK(dal(m, &m->pcM, (size_t)nfc * m->pc_cap * B * B));
+            CK(dal(m, &m->pcM, (size_t)nfc * pc_cell_stride(B)));
             m->use_pc = true;
         }
     }
     CK(dal(m, &m->sc, 1));
-    CK(dal(m, &m->part_ir, 22 * KB_MAXB));
+    CK(dal(m, &m->part_ir, 14 * KB_MAXB));
     CK(dal(m, &m->ns, 1));
     CK(dal(m, &m->dint, 8));
     CK(dal(m, &m->dsub, 1024));
@@ -1438,7 +1436,7 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     if (d->frac_id && pc == FIM_PC_FRACTURE) {
         size_t nfc = 0;
         for (size_t i = 0; i < n; i++) nfc += d->frac_id[i] >= 0 ? 1 : 0;
-        if (nfc) b += n * 16 + nfc * (size_t)(PC_DOF / B) * B * B * 4;
+        if (nfc) b += n * 16 + nfc * (size_t)pc_cell_stride(B) * 4;
     }
     return (int64_t)b;
 }

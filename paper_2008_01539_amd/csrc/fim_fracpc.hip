@@ -7,9 +7,9 @@
 // that belong to one fracture is grouped into a block of at most
 // PC_DOF / b rows that never crosses a 256-row Krylov tile; the exact
 // inverse of A~ restricted to the block is formed once per Newton
-// iteration and applied on the left after each Krylov product (a short
-// kernel over the fracture rows, see fim_krylov.hip).  Matrix rows and
-// rows of one-row blocks keep the plain scaling.
+// iteration and applied on the left inside each Krylov product kernel
+// (fim_krylov.hip).  Matrix rows and rows of one-row blocks keep the plain
+// scaling.
 #include "fim_device.hpp"
 
 namespace fimk {
@@ -17,8 +17,8 @@ namespace fimk {
 // Block layout of one local system, one workgroup per 256-row tile:
 //   pcinfo[r] = (first row of r's block - tile base) << 16 | block rows
 //   pcoff[r]  = element offset of the block's inverse in the inverse
-//               store (N x N column-major, N = rows * b); the block's
-//               first fracture cell ordinal times cap * b * b, so the
+//               store (grouped layout of fim_internal.hpp); the block's
+//               first fracture cell ordinal times cell_stride, so the
 //               blocks of one system never overlap.
 __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restrict__ l2g,
                                                      const int* __restrict__ frac_id,
@@ -187,14 +187,19 @@ __global__ __launch_bounds__(WAVE) void k_pc_invert(int nA, LocalSys ls,
         for (int c = 0; c < PC_DOF; c++)
             if (lane < N && c >= c0 && !(fabsf(a[c]) <= 1e8f)) big = true;
         bad = bad || __any(big);
+        // grouped store (see fim_internal.hpp): lane = unknown rr b + ci
+        constexpr int K = pc_group_cols(B), W = B * K;
         float* out = pcM + pcoff[base + bs];
+        const int rr = lane / B, ci = lane - rr * B;
+        const int rowo = rr * W + ci * K, grp = size * W;
         if (lane < N) {
 #pragma unroll
             for (int c = 0; c < PC_DOF; c++)
                 if (c >= c0) {
                     const int j = c - c0;
-                    out[j * N + lane] = bad ? (j == lane ? 1.0f : 0.0f) : a[c];
+                    out[(j / K) * grp + rowo + j % K] = bad ? (j == lane ? 1.0f : 0.0f) : a[c];
                 }
+            for (int j = N; j % K != 0; j++) out[(j / K) * grp + rowo + j % K] = 0.0f;
         }
         wave_sync();
     }

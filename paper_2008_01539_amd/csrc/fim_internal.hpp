@@ -18,6 +18,17 @@ constexpr int KB_NT = 256;      // threads per block of the Krylov kernels
 constexpr int KB_MAXB = 1024;   // blocks per Krylov launch (grid-stride above)
 constexpr int PC_DOF = 64;      // unknowns per fracture preconditioner block
 
+// Fracture-block inverse store.  A block of R rows (N = R b unknowns) at
+// element offset off keeps entry (unknown u = rr b + c, column j) at
+//   off + ((j / K) R + rr) W + c K + j % K,  K = pc_group_cols(b), W = b K:
+// the columns in groups of K, and inside a group the b K entries of one row
+// contiguous (a multiple of 16 bytes, read as 4-float vectors by the
+// thread of that row); the last group is padded with zeros.  Each fracture
+// cell reserves b PC_DOF entries, so a block whose first cell has fracture
+// ordinal f fits before the next block's first ordinal (>= f + R).
+constexpr int pc_group_cols(int b) { return b == 2 ? 2 : 4; }
+constexpr int pc_cell_stride(int b) { return b * PC_DOF; }
+
 // per-cell flag bits
 enum : uint8_t { CF_FRAC = 1, CF_PERF = 2, CF_AA = 4 };
 
@@ -143,10 +154,8 @@ struct KrylovBufs {
     // per-block partial dot products (part_ir 2 per block, the others 4)
     double* part_ir; double* part_a; double* part_b; double* part_c;
     const double* dinv; const void* At;
-    // fracture-block preconditioner (pcM NULL: block Jacobi only); its
-    // kernels' partial sums after P (a2) and after S (b2), 4 per block
+    // fracture-block preconditioner (pcM NULL: block Jacobi only)
     const int* pcinfo; const int* pcoff; const float* pcM;   // FP32 inverses
-    double* part_a2; double* part_b2;
 };
 int krylov_grid(int nA);
 
@@ -184,10 +193,6 @@ void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSe
                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
                           int nblk_total, hipStream_t s);
-// fracture-block step after kernel P (which = 0) or S (which = 1)
-void launch_pc_vec(int which, int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
-                   int nblk_total, int it, hipStream_t s, hipEvent_t ev0 = nullptr,
-                   hipEvent_t ev1 = nullptr);
 
 struct SegStatus {
     double rir2, bnorm2;

@@ -200,14 +200,18 @@ __device__ inline void row_product(const LocalSys& ls, const T* At, const RowGeo
 }
 
 // One row of a fracture-block inverse times the block's values y (in
-// LDS): sum_j M[row][j] y[j], j < N; M column-major from byte offset m0,
-// colb bytes per column.  Loads and LDS reads are clamped to the block
-// (every address valid) and masked, with no branch per term, so that all
-// of them are in flight together; two halves of 32 keep registers in check.
+// LDS): sum_j M[u][j] y[j], j < N, for the unknown u = rr b + ci of a block
+// of `size` rows stored from element offset off (grouped layout of
+// fim_internal.hpp).  Loads and LDS reads are clamped to the block (every
+// address valid) and masked, with no branch per term, so that all of them
+// are in flight together; two halves of 32 keep registers in check.
 template <int B>
-__device__ __attribute__((always_inline)) inline double block_row_dot(const float* M, unsigned m0,
-                                                                      unsigned colb, int N,
-                                       const double* y) {
+__device__ __attribute__((always_inline)) inline double pc_unknown_dot(const float* M, int off,
+                                                                       int rr, int ci, int size,
+                                                                       int N, const double* y) {
+    constexpr int K = pc_group_cols(B), W = B * K;
+    const unsigned row0 = (unsigned)(off + rr * W + ci * K) * 4u;
+    const unsigned grpb = (unsigned)(size * W) * 4u;
     double acc = 0.0;
 #pragma unroll
     for (int h = 0; h < PC_DOF; h += 32) {
@@ -216,7 +220,7 @@ __device__ __attribute__((always_inline)) inline double block_row_dot(const floa
 #pragma unroll
         for (int q = 0; q < 32; q++) {
             const int j = min(h + q, N - 1);
-            mv[q] = ldg<float>(M, m0 + (unsigned)j * colb);
+            mv[q] = ldg<float>(M, row0 + (unsigned)(j / K) * grpb + 4u * (unsigned)(j % K));
             yv[q] = y[j];
         }
 #pragma unroll
@@ -225,20 +229,23 @@ __device__ __attribute__((always_inline)) inline double block_row_dot(const floa
     return acc;
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 // Left application of the fracture-block inverses inside the product
 // kernels: y holds this thread's row of A~ x; rows of multi-row fracture
 // blocks get the block's M^{-1} applied (the block's other rows are in the
 // same tile, exchanged through LDS in the stored precision T, the values
 // the unpreconditioned product would have written).  Every thread of the
 // workgroup calls it; tiles without such blocks return after one barrier.
-// The block's columns are taken 16 at a time (B loads and one LDS read per
-// column, all in flight together), so the register cost stays bounded
-// whatever the block size.
+// The thread of block row rr reads its b rows of M^{-1} as 16-byte vectors
+// (the grouped layout keeps them contiguous per group of K columns), 16
+// columns per round with all loads of a round in flight together.
 template <int B, typename T>
 __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off,
                                double (&y)[B]) {
     __shared__ T yb[KB_NT * B];
-    constexpr int Q = (B == 3 && sizeof(T) == 8) ? 8 : 16;
+    constexpr int K = pc_group_cols(B), W = B * K, NV4 = W / 4;
+    constexpr int QG = (B == 3 && sizeof(T) == 8) ? 2 : 16 / K;   // column groups per round
     const int t = threadIdx.x;
     const bool blk = act && (info & 0xffff) > 1;
     if (!__syncthreads_or(blk)) return;
@@ -249,29 +256,38 @@ __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off
     __syncthreads();
     if (blk) {
         const int size = info & 0xffff, bs = info >> 16, N = size * B;
-        const unsigned colb = (unsigned)N * 4u;
-        const unsigned m0 = (unsigned)(off + (t - bs) * B) * 4u;
+        const int G = (N + K - 1) / K;
+        const unsigned row0 = (unsigned)(off + (t - bs) * W) * 4u;
+        const unsigned grpb = (unsigned)(size * W) * 4u;
         const T* yv = yb + bs * B;
         double acc[B];
 #pragma unroll
         for (int c = 0; c < B; c++) acc[c] = 0.0;
 #pragma unroll 1
-        for (int h = 0; h < N; h += Q) {
-            float mv[Q][B];
-            T ys[Q];
+        for (int g0 = 0; g0 < G; g0 += QG) {
+            f4v mv[QG][NV4];
+            T ys[QG][K];
 #pragma unroll
-            for (int q = 0; q < Q; q++) {
-                const int j = min(h + q, N - 1);
-                ys[q] = yv[j];
+            for (int q = 0; q < QG; q++) {
+                const int gq = min(g0 + q, G - 1);
 #pragma unroll
-                for (int c = 0; c < B; c++)
-                    mv[q][c] = ldg<float>(kb.pcM, m0 + 4u * c + (unsigned)j * colb);
+                for (int v = 0; v < NV4; v++)
+                    mv[q][v] = ldg<f4v>(kb.pcM, row0 + (unsigned)gq * grpb + 16u * v);
+#pragma unroll
+                for (int k = 0; k < K; k++) ys[q][k] = yv[min(gq * K + k, N - 1)];
             }
 #pragma unroll
-            for (int q = 0; q < Q; q++) {
-                const double w = (h + q < N) ? (double)ys[q] : 0.0;
+            for (int q = 0; q < QG; q++) {
 #pragma unroll
-                for (int c = 0; c < B; c++) acc[c] += (double)mv[q][c] * w;
+                for (int k = 0; k < K; k++) {
+                    const int j = (g0 + q) * K + k;   // past N: padding or a clamped repeat
+                    const double w = j < N ? (double)ys[q][k] : 0.0;
+#pragma unroll
+                    for (int c = 0; c < B; c++) {
+                        const int e = c * K + k;
+                        acc[c] += (double)mv[q][e / 4][e % 4] * w;
+                    }
+                }
             }
         }
 #pragma unroll
@@ -307,10 +323,9 @@ __device__ inline void pc_apply(const KrylovBufs& kb, bool act, int info, int of
         const int size = inf & 0xffff;
         z[h] = yb[R];
         if (size > 1) {
-            const int bs = inf >> 16, N = size * B, ri = (rl - bs) * B + ci;
-            const unsigned m0 = (unsigned)(off_s[rl] + ri) * 4u;
-            const unsigned colb = (unsigned)N * 4u;
-            z[h] = block_row_dot<B>(kb.pcM, m0, colb, N, yb + bs * B);
+            const int bs = inf >> 16;
+            z[h] = pc_unknown_dot<B>(kb.pcM, off_s[rl], rl - bs, ci, size, size * B,
+                                     yb + bs * B);
         }
     }
     __syncthreads();
@@ -709,92 +724,6 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const 
     }
 }
 
-// ------------------------------------------ fracture-block step (W = 0, 1)
-// After kernel P (W = 0) the rows of multi-row fracture blocks hold
-// y = A~ p in v, after kernel S (W = 1) y = A~ s in t.  This kernel
-// replaces y by M^{-1} y on those rows (M: the block diagonal of A~ over
-// the blocks, inverses from fim_fracpc.hip) and writes those rows' share of
-// the dot products in the slots the next kernel reduces: W = 0: (rh, v),
-// (v, v); W = 1: (t, s), (t, t), -, (rh, t).  Same tiles as the product
-// kernels; thread t of a tile pass works on unknowns t, t + 256, ... of
-// the tile (one row of M^{-1} each, up to 64 values loaded at once,
-// coalesced over the block's unknowns).
-template <int B, typename T, bool SOLO, int W>
-__global__ __launch_bounds__(KB_NT) void k_pc_vec(const KSeg* __restrict__ segs,
-                                                  const int* __restrict__ blk_seg, int it) {
-    const KSeg& S = seg_of<SOLO>(segs, blk_seg);
-    if (!S.active || S.kb.pcM == nullptr) return;
-    const int done = S.kb.sc->done;   // checked once the first loads are out
-    const int nbk = S.nblk, nA = S.nA, lb = xcd_tile(S.blk0, nbk, blockIdx.x);
-    const Vecs<B, T> V = make_vecs<B, T>(S.kb, it & 1);
-    T* y = W == 0 ? V.v_new : V.t;
-    double* __restrict__ part = W == 0 ? S.kb.part_a2 : S.kb.part_b2;
-    __shared__ double yb[KB_NT * B];
-    __shared__ int info_s[KB_NT], off_s[KB_NT];
-    const int t = threadIdx.x;
-    double dot[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int tb = lb * KB_NT; tb < nA; tb += nbk * KB_NT) {
-        // one round of loads for everything indexed by row or unknown
-        const int r = tb + t;
-        const bool act = r < nA;
-        int info = 1, off = 0;
-        double yo[B], hu[B], su[B];
-#pragma unroll
-        for (int c = 0; c < B; c++) yo[c] = hu[c] = su[c] = 0.0;
-        if (act) {
-            info = S.kb.pcinfo[r];
-            off = S.kb.pcoff[r];
-#pragma unroll
-            for (int c = 0; c < B; c++) yo[c] = (double)y[(long)r * B + c];
-        }
-#pragma unroll
-        for (int h = 0; h < B; h++) {
-            const long q = (long)tb * B + h * KB_NT + t;   // this thread's unknowns
-            if (q < (long)nA * B) {
-                hu[h] = (double)V.rh[q];
-                if (W == 1) su[h] = (double)V.s[q];
-            }
-        }
-        if (done) return;   // uniform
-        info_s[t] = info;
-        off_s[t] = off;
-#pragma unroll
-        for (int c = 0; c < B; c++) yb[t * B + c] = yo[c];
-        if (!__syncthreads_or((info & 0xffff) > 1)) continue;
-#pragma unroll
-        for (int h = 0; h < B; h++) {
-            const int R = h * KB_NT + t;          // unknown of the tile
-            const int rl = R / B, ci = R - rl * B;
-            const int row = tb + rl;
-            const int inf = info_s[rl];
-            const int size = inf & 0xffff;
-            if (row < nA && size > 1) {
-                const int bs = inf >> 16, N = size * B, ri = (rl - bs) * B + ci;
-                const unsigned m0 = (unsigned)(off_s[rl] + ri) * 4u;
-                const unsigned colb = (unsigned)N * 4u;
-                const double acc = block_row_dot<B>(S.kb.pcM, m0, colb, N, yb + bs * B);
-                const T o = (T)acc;
-                y[(long)row * B + ci] = o;
-                const double od = (double)o;
-                if (W == 0) {
-                    dot[0] += hu[h] * od;
-                    dot[1] += od * od;
-                } else {
-                    dot[0] += od * su[h];
-                    dot[1] += od * od;
-                    dot[3] += hu[h] * od;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    block_sum<4>(dot);
-    if (t == 0) {
-#pragma unroll
-        for (int k = 0; k < 4; k++) part[4 * lb + k] = dot[k];
-    }
-}
-
 template <int B, typename T, bool SOLO>
 __global__ __launch_bounds__(KB_NT) void k_ir_accumulate(const KSeg* __restrict__ segs,
                                                          const int* __restrict__ blk_seg) {
@@ -917,32 +846,6 @@ void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSe
     } while (0)
     KDISPATCH(PI)
 #undef PI
-}
-
-void launch_pc_vec(int which, int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
-                   int nblk_total, int it, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (nblk_total <= 0) return;
-    const dim3 nb(nblk_total), nt(KB_NT);
-#define PVEC(BV, TT)                                                                            \
-    do {                                                                                        \
-        if (solo) {                                                                             \
-            if (which == 0)                                                                     \
-                hipExtLaunchKernelGGL(k_pc_vec<BV, TT, true, 0>, nb, nt, 0, s, ev0, ev1, 0,     \
-                                      segs, blk_seg, it);                                       \
-            else                                                                                \
-                hipExtLaunchKernelGGL(k_pc_vec<BV, TT, true, 1>, nb, nt, 0, s, ev0, ev1, 0,     \
-                                      segs, blk_seg, it);                                       \
-        } else {                                                                                \
-            if (which == 0)                                                                     \
-                hipExtLaunchKernelGGL(k_pc_vec<BV, TT, false, 0>, nb, nt, 0, s, ev0, ev1, 0,    \
-                                      segs, blk_seg, it);                                       \
-            else                                                                                \
-                hipExtLaunchKernelGGL(k_pc_vec<BV, TT, false, 1>, nb, nt, 0, s, ev0, ev1, 0,    \
-                                      segs, blk_seg, it);                                       \
-        }                                                                                       \
-    } while (0)
-    KDISPATCH(PVEC)
-#undef PVEC
 }
 
 void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
