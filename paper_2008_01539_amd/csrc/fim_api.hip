@@ -81,6 +81,7 @@ struct fim_model {
     // fracture-block preconditioner (use_pc false: block Jacobi only)
     bool use_pc = false;
     int pc_cap = 0;                 // rows per block
+    int pc_grid = KB_MAXB;          // Krylov workgroups with fracture blocks (2 per CU)
     int *frac_id = nullptr, *ford = nullptr, *pcinfo = nullptr, *pcoff = nullptr;
     float* pcM = nullptr;           // FP32 inverses
     // Krylov
@@ -338,7 +339,7 @@ static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
         k.kb = kbufs(m, g == 0);
         k.nA = m->nA;
         k.blk0 = off;
-        k.nblk = krylov_grid(m->nA);
+        k.nblk = krylov_grid(m->nA, m->use_pc ? m->pc_grid : KB_MAXB);
         k.active = it.active ? 1 : 0;
         k.tol2 = it.tol2;
         k.bnorm2 = it.bnorm2;
@@ -947,6 +948,16 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     if (o) m->o = *o;
     else fim_default_options(&m->o);
     if (m->o.check_every <= 0) m->o.check_every = 8;
+    {
+        // the fused fracture-block product kernels keep two workgroups per
+        // CU resident; more tiles than that are looped over inside them
+        // rather than launched as a second round of workgroups
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            m->pc_grid = std::min(KB_MAXB, 2 * cus);
+    }
     if (m->o.m_layers < 0 || m->o.m_layers > MAX_LAYERS || m->o.m_layers_dd < 0 ||
         m->o.m_layers_dd > MAX_LAYERS) {
         g_create_err = "neighbour layers must be in [0, 8]";

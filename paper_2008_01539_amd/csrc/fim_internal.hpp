@@ -157,7 +157,9 @@ struct KrylovBufs {
     // fracture-block preconditioner (pcM NULL: block Jacobi only)
     const int* pcinfo; const int* pcoff; const float* pcM;   // FP32 inverses
 };
-int krylov_grid(int nA);
+// workgroups of a Krylov launch over nA rows: one per 256-row tile, at most
+// cap (the kernels loop over further tiles)
+int krylov_grid(int nA, int cap);
 
 // One model's share of a (batched) Krylov launch.  A launch covers the
 // blocks of every participating model; block q belongs to model

@@ -767,7 +767,7 @@ static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_
     }
 }
 
-int krylov_grid(int nA) { return kgrid(nA); }
+int krylov_grid(int nA, int cap) { return std::min(kgrid(nA), std::max(1, cap)); }
 
 // One wave per model: Krylov status and the fixed-order sums of the
 // refinement partials (|r64|^2, |b~|^2) of that model.
