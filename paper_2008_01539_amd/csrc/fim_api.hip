@@ -83,6 +83,9 @@ struct fim_model {
     int pc_cap = 0;                 // rows per block
     int pc_grid = KB_MAXB;          // Krylov workgroups with fracture blocks (2 per CU)
     int *frac_id = nullptr, *ford = nullptr, *pcinfo = nullptr, *pcoff = nullptr;
+    int* pclist = nullptr;          // multi-row blocks: (first row, rows) pairs
+    int pc_inv_grid = 0;            // workgroups of the inversion launch
+    int cus = 256;                  // compute units of the device
     float* pcM = nullptr;           // FP32 inverses
     // Krylov
     double *x64 = nullptr, *xprev = nullptr, *rir = nullptr, *part = nullptr;
@@ -281,7 +284,8 @@ static fim_status structure(fim_model* m) {
     launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, &m->dint[4], m->s);
     if (m->use_pc)
         launch_pc_blocks(m->nA, m->l2g, m->frac_id, m->ford, m->pc_cap,
-                         pc_cell_stride(m->B), m->pcinfo, m->pcoff, &m->dint[5], m->s);
+                         pc_cell_stride(m->B), m->pcinfo, m->pcoff, m->pclist, &m->dint[5],
+                         m->s);
     return FIM_OK;
 }
 
@@ -409,8 +413,8 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         pend(lead, pi, mq->nA);
         if (mq->use_pc) {
             const int pv = pbeg(lead, PK_PCINV);
-            launch_pc_invert(mq->B, it.fp32, mq->nA, lsys(mq), mq->At, mq->pcinfo, mq->pcoff,
-                             mq->pcM, s);
+            launch_pc_invert(mq->B, it.fp32, mq->pc_inv_grid, lsys(mq), mq->At, mq->pclist,
+                             &mq->dint[6], mq->pcoff, mq->pcM, s);
             pend(lead, pv, mq->nA);
         }
         launch_fill_f64(mq->x64, (long)mq->nA * mq->B, 0.0, s);
@@ -876,7 +880,7 @@ static void free_all(fim_model* m) {
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
                     m->part_ir, m->classes, m->frac_id, m->ford, m->pcinfo, m->pcoff,
-                    m->pcM};
+                    m->pcM, m->pclist};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (m->hsc) (void)hipHostFree(m->hsc);
@@ -955,8 +959,10 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-            cus > 0)
+            cus > 0) {
             m->pc_grid = std::min(KB_MAXB, 2 * cus);
+            m->cus = cus;
+        }
     }
     if (m->o.m_layers < 0 || m->o.m_layers > MAX_LAYERS || m->o.m_layers_dd < 0 ||
         m->o.m_layers_dd > MAX_LAYERS) {
@@ -1109,6 +1115,10 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             CK(dal(m, &m->pcinfo, nn));
             CK(dal(m, &m->pcoff, nn));
             CK(dal(m, &m->pcM, (size_t)nfc * pc_cell_stride(B)));
+            // blocks have >= 2 rows, all fracture cells
+            CK(dal(m, &m->pclist, 2 * (nfc / 2 + 1)));
+            // about as many single-wave workgroups as fit at once (LDS)
+            m->pc_inv_grid = std::min(nfc / 2 + 1, 8 * m->cus);
             m->use_pc = true;
         }
     }
@@ -1447,7 +1457,7 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     if (d->frac_id && pc == FIM_PC_FRACTURE) {
         size_t nfc = 0;
         for (size_t i = 0; i < n; i++) nfc += d->frac_id[i] >= 0 ? 1 : 0;
-        if (nfc) b += n * 16 + nfc * (size_t)pc_cell_stride(B) * 4;
+        if (nfc) b += n * 16 + nfc * (size_t)pc_cell_stride(B) * 4 + (nfc / 2 + 1) * 8;
     }
     return (int64_t)b;
 }

@@ -20,12 +20,15 @@ namespace fimk {
 //               store (grouped layout of fim_internal.hpp); the block's
 //               first fracture cell ordinal times cell_stride, so the
 //               blocks of one system never overlap.
+// and the list of multi-row blocks, (first row, rows) pairs in no
+// particular order: cnt[1] entries; cnt[0] = sum of rows^2.
 __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restrict__ l2g,
                                                      const int* __restrict__ frac_id,
                                                      const int* __restrict__ ford, int cap,
                                                      int cell_stride, int* __restrict__ pcinfo,
                                                      int* __restrict__ pcoff,
-                                                     int* __restrict__ rows2) {
+                                                     int* __restrict__ list,
+                                                     int* __restrict__ cnt) {
     __shared__ int sf[KB_NT];   // fracture id of each row (-1 matrix, -2 past nA)
     __shared__ int ss[KB_NT];   // block start of each row
     const int t = threadIdx.x, base = blockIdx.x * KB_NT, r = base + t;
@@ -48,169 +51,218 @@ __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restri
     if (valid) {
         pcinfo[r] = (bs << 16) | size;
         pcoff[r] = (size > 1) ? ford[l2g[base + bs]] * cell_stride : 0;
-        if (size > 1 && bs == t) atomicAdd(rows2, size * size);   // sum of block rows^2
+        if (size > 1 && bs == t) {
+            atomicAdd(&cnt[0], size * size);
+            const int q = atomicAdd(&cnt[1], 1);
+            list[2 * q] = r;
+            list[2 * q + 1] = size;
+        }
     }
 }
 
 void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
-                      int cell_stride, int* pcinfo, int* pcoff, int* rows2, hipStream_t s) {
-    launch_fill_i32(rows2, 1, 0, s);
+                      int cell_stride, int* pcinfo, int* pcoff, int* list, int* cnt,
+                      hipStream_t s) {
+    launch_fill_i32(cnt, 2, 0, s);
     if (nA <= 0) return;
     k_pc_blocks<<<(nA + KB_NT - 1) / KB_NT, KB_NT, 0, s>>>(nA, l2g, frac_id, ford, cap,
-                                                            cell_stride, pcinfo, pcoff, rows2);
+                                                            cell_stride, pcinfo, pcoff, list, cnt);
 }
 
-// Inverse of every multi-row block of a tile, one wave per block, stored
+// Inverse of every multi-row block of the list, one wave per block, stored
 // in FP32 (8-bit mantissas are not enough for nearly singular blocks): the
 // block of A~ = D^{-1} J (the scaled blocks k_precond wrote, in the
-// Krylov precision; FP32 from here on) is assembled
-// in LDS, padded to 64 x 64 with the identity, and each lane takes one
-// row into registers.  Gauss-Jordan elimination then runs 64 steps
-// without pivoting (the scaled blocks have unit diagonal blocks and are
-// diagonally dominant in practice); every step takes column 0 as the
-// pivot column, broadcasts the pivot row through LDS, and shifts the
-// columns left by one, appending the new column of the inverse at the end,
-// so that all register indices are compile-time constants and after 64
-// steps the registers hold the inverse in the original column order.  A
+// Krylov precision; FP32 from here on) is assembled in LDS, padded to
+// 64 x 64 with the identity, and each lane takes one row into registers.
+// Gauss-Jordan elimination then runs N steps (N = the block's unknowns; the
+// identity padding never pivots) without pivoting (the scaled blocks have
+// unit diagonal blocks and are diagonally dominant in practice); every
+// step takes column 0 as the pivot column, broadcasts the pivot row
+// through LDS, and shifts the columns left by one, appending the new column
+// of the inverse at the end, so that all register indices are compile-time
+// constants and after N steps columns 64 - N .. 63 hold the inverse.  Rows
+// are eliminated with multiplier (entry / pivot) and the pivot row is left
+// unscaled (one FMA per entry and step); each row is divided by its own
+// pivot once at the end.  A
 // pivot below 1e-20 in magnitude or a non-finite one, or an inverse entry
 // above 1e8, leaves the identity for that block (plain block Jacobi on its
 // rows).
-constexpr int PCI_SUB = 8;    // single-wave workgroups per tile
 
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 template <int B, typename T>
-__global__ __launch_bounds__(WAVE) void k_pc_invert(int nA, LocalSys ls,
-                                                    const T* __restrict__ At,
-                                                    const int* __restrict__ pcinfo,
+__global__ __launch_bounds__(WAVE) void k_pc_invert(LocalSys ls, const T* __restrict__ At,
+                                                    const int* __restrict__ list,
+                                                    const int* __restrict__ cnt,
                                                     const int* __restrict__ pcoff,
                                                     float* __restrict__ pcM) {
     constexpr int BB = B * B;
-    __shared__ __align__(16) float M[PC_DOF * PC_DOF];
-    __shared__ int list[KB_NT];
-    const int tile = blockIdx.x / PCI_SUB, sub = blockIdx.x % PCI_SUB;
-    const int base = tile * KB_NT, lane = threadIdx.x;
-    // the tile's multi-row blocks in row order (the same list in every
-    // workgroup of the tile; workgroup sub takes blocks sub, sub + 8, ...)
-    int nb = 0;
-    for (int k = 0; k < KB_NT / WAVE; k++) {
-        const int t = k * WAVE + lane, r = base + t;
-        bool lead = false;
-        if (r < nA) {
-            const int info = pcinfo[r];
-            lead = (info & 0xffff) > 1 && (info >> 16) == t;
-        }
-        const unsigned long long bal = __ballot(lead);
-        if (lead) list[nb + __popcll(bal & ((1ull << lane) - 1ull))] = t;
-        nb += __popcll(bal);
-    }
-    wave_sync();
-    for (int q = sub; q < nb; q += PCI_SUB) {
-        const int bs = list[q];
-        const int size = pcinfo[base + bs] & 0xffff;
+    // the block in LDS, row stride MS (16-byte rows, offset banks per row)
+    constexpr int MS = PC_DOF + 4;
+    __shared__ __align__(16) float M[PC_DOF * MS];
+    const int lane = threadIdx.x;
+    const int nblk = *cnt;
+    // Loops stay rolled where they run once per block: each wave runs this
+    // code about once per launch, so its size (instruction fetch) costs
+    // more than loop overhead.  One block per workgroup (single wave) at a
+    // time, from the list k_pc_blocks wrote.
+    for (int q = blockIdx.x; q < nblk; q += gridDim.x) {
+        const int r0 = list[2 * q], size = list[2 * q + 1];
         const int N = size * B;
-        for (int e = lane; e < N * N; e += WAVE) M[e] = 0.0f;
+
+        // slot widths of the (at most two) slices the block's rows are in
+        const int sl0 = r0 / SLICE, sl1 = (r0 + size - 1) / SLICE;
+        const int w0 = ls.swidth[sl0], w1 = ls.swidth[sl1];
+        // identity: the diagonal blocks of A~ and the padding to 64 x 64
+        {
+            f4v* row = (f4v*)&M[lane * MS];
+#pragma unroll 1
+            for (int c = 0; c < PC_DOF / 4; c++) {
+                f4v z = {0.0f, 0.0f, 0.0f, 0.0f};
+                if (c == lane / 4) z[lane % 4] = 1.0f;
+                row[c] = z;
+            }
+        }
         wave_sync();
-        if (lane < size) {
-            // the row of A~: identity diagonal block, off-diagonal blocks
-            // as scaled by k_precond (At, Krylov precision).  Columns of a
-            // group of slots are loaded together, then their blocks.
-            const int r = base + bs + lane;
-            const long s0 = slot_of(ls, r, 0);
-            const int width = ls.swidth[r / SLICE];
+        // off-diagonal blocks inside the block, from the scaled blocks
+        // k_precond wrote (At, Krylov precision): the (slot, row) pairs
+        // of the block are spread over the lanes, FU per lane at a time,
+        // the column loads first, then the blocks that couple two rows
+        constexpr int FU = 4;
+        const int items = size * (max(w0, w1) - 1);
+#pragma unroll 1
+        for (int i0 = 0; i0 < items; i0 += WAVE * FU) {
+            int jl[FU], rl[FU];
+            long ps[FU];
 #pragma unroll
-            for (int i = 0; i < B; i++) M[(lane * B + i) * N + lane * B + i] = 1.0f;
-            for (int k0 = 1; k0 < width; k0 += 8) {
-                int jl[8];
+            for (int u = 0; u < FU; u++) {
+                const int i = i0 + u * WAVE + lane;
+                const int k = 1 + i / size, rr = i - (k - 1) * size, r = r0 + rr;
+                const bool ok = i < items && k < ((r / SLICE == sl0) ? w0 : w1);
+                rl[u] = rr;
+                ps[u] = ok ? slot_of(ls, r, k) : 0;
+                jl[u] = ok ? ls.col[ps[u]] - r0 : -1;
+            }
+            T blk[FU][BB];
 #pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    const int k = k0 + u;
-                    jl[u] = k < width ? ls.col[s0 + (long)k * SLICE] - (base + bs) : -1;
-                }
-                T blk[8][BB];
+            for (int u = 0; u < FU; u++) {
+                const bool in = jl[u] >= 0 && jl[u] < size && jl[u] != rl[u];
 #pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    const bool in = jl[u] >= 0 && jl[u] < size && jl[u] != lane;
+                for (int e = 0; e < BB; e++) blk[u][e] = in ? At[ps[u] * BB + e] : (T)0;
+            }
 #pragma unroll
-                    for (int e = 0; e < BB; e++)
-                        blk[u][e] = in ? At[(s0 + (long)min(k0 + u, width - 1) * SLICE) * BB + e]
-                                       : (T)0;
-                }
+            for (int u = 0; u < FU; u++) {
+                if (!(jl[u] >= 0 && jl[u] < size && jl[u] != rl[u])) continue;
 #pragma unroll
-                for (int u = 0; u < 8; u++) {
-                    if (!(jl[u] >= 0 && jl[u] < size && jl[u] != lane)) continue;
+                for (int i = 0; i < B; i++)
 #pragma unroll
-                    for (int i = 0; i < B; i++)
-#pragma unroll
-                        for (int j = 0; j < B; j++)
-                            M[(lane * B + i) * N + jl[u] * B + j] = (float)blk[u][i * B + j];
-                }
+                    for (int j = 0; j < B; j++)
+                        M[(rl[u] * B + i) * MS + jl[u] * B + j] = (float)blk[u][i * B + j];
             }
         }
         wave_sync();
         float a[PC_DOF];
+        {
+            const f4v* row = (const f4v*)&M[lane * MS];
 #pragma unroll
-        for (int c = 0; c < PC_DOF; c++)
-            a[c] = (lane < N && c < N) ? M[lane * N + c] : (c == lane ? 1.0f : 0.0f);
+            for (int c = 0; c < PC_DOF / 4; c++) {
+                const f4v v = row[c];
+                a[4 * c] = v[0];
+                a[4 * c + 1] = v[1];
+                a[4 * c + 2] = v[2];
+                a[4 * c + 3] = v[3];
+            }
+        }
         wave_sync();
         bool bad = false;
+        float myip = 1.0f;   // 1 / this row's pivot
         // N steps; afterwards columns 64 - N .. 63 of rows 0 .. N-1 hold the
-        // inverse (the identity padding is never a pivot)
+        // inverse, each row still times its pivot (the identity padding is
+        // never a pivot)
         for (int step = 0; step < N; step++) {
             if (lane == step) {
+                f4v* row = (f4v*)M;
 #pragma unroll
-                for (int c = 0; c < PC_DOF; c++) M[c] = a[c];
+                for (int c = 0; c < PC_DOF / 4; c++)
+                    row[c] = f4v{a[4 * c], a[4 * c + 1], a[4 * c + 2], a[4 * c + 3]};
             }
             wave_sync();
             float pr[PC_DOF];
+            {
+                const f4v* row = (const f4v*)M;
 #pragma unroll
-            for (int c = 0; c < PC_DOF; c++) pr[c] = M[c];
+                for (int c = 0; c < PC_DOF / 4; c++) {
+                    const f4v v = row[c];
+                    pr[4 * c] = v[0];
+                    pr[4 * c + 1] = v[1];
+                    pr[4 * c + 2] = v[2];
+                    pr[4 * c + 3] = v[3];
+                }
+            }
             wave_sync();
             const float p = pr[0];
             bad = bad || !(fabsf(p) > 1e-20f) || !isfinite(p);
             const float ip = 1.0f / p;
-            const float f = a[0];
             const bool me = lane == step;
+            // the pivot row is not normalised here (one FMA per entry with
+            // the multiplier f / p); the pivot lane only shifts its row
+            if (me) myip = ip;
+            const float f = me ? 0.0f : a[0] * ip;
 #pragma unroll
-            for (int c = 1; c < PC_DOF; c++) {
-                const float sc = pr[c] * ip;
-                a[c - 1] = me ? sc : a[c] - f * sc;
-            }
-            a[PC_DOF - 1] = me ? ip : -f * ip;
+            for (int c = 1; c < PC_DOF; c++) a[c - 1] = fmaf(-f, pr[c], a[c]);
+            a[PC_DOF - 1] = me ? 1.0f : -f;
         }
+#pragma unroll
+        for (int c = 0; c < PC_DOF; c++) a[c] *= myip;
+        // the inverse back to LDS (row lane), checked, then stored in the
+        // grouped layout (see fim_internal.hpp): lane = unknown rr b + ci,
+        // K consecutive columns per store, zero padding past column N
+        {
+            f4v* row = (f4v*)&M[lane * MS];
+#pragma unroll
+            for (int c = 0; c < PC_DOF / 4; c++)
+                row[c] = f4v{a[4 * c], a[4 * c + 1], a[4 * c + 2], a[4 * c + 3]};
+        }
+        wave_sync();
         const int c0 = PC_DOF - N;
         bool big = false;
-#pragma unroll
-        for (int c = 0; c < PC_DOF; c++)
-            if (lane < N && c >= c0 && !(fabsf(a[c]) <= 1e8f)) big = true;
+        if (lane < N) {
+#pragma unroll 1
+            for (int j = 0; j < N; j++) big = big || !(fabsf(M[lane * MS + c0 + j]) <= 1e8f);
+        }
         bad = bad || __any(big);
-        // grouped store (see fim_internal.hpp): lane = unknown rr b + ci
         constexpr int K = pc_group_cols(B), W = B * K;
-        float* out = pcM + pcoff[base + bs];
+        typedef float kv __attribute__((ext_vector_type(K)));
+        float* out = pcM + pcoff[r0];
         const int rr = lane / B, ci = lane - rr * B;
         const int rowo = rr * W + ci * K, grp = size * W;
         if (lane < N) {
+#pragma unroll 1
+            for (int g = 0; g * K < N; g++) {
+                kv v;
 #pragma unroll
-            for (int c = 0; c < PC_DOF; c++)
-                if (c >= c0) {
-                    const int j = c - c0;
-                    out[(j / K) * grp + rowo + j % K] = bad ? (j == lane ? 1.0f : 0.0f) : a[c];
+                for (int k = 0; k < K; k++) {
+                    const int j = g * K + k;
+                    v[k] = j >= N ? 0.0f : bad ? (j == lane ? 1.0f : 0.0f) : M[lane * MS + c0 + j];
                 }
-            for (int j = N; j % K != 0; j++) out[(j / K) * grp + rowo + j % K] = 0.0f;
+                *(kv*)(out + g * grp + rowo) = v;
+            }
         }
         wave_sync();
     }
 }
 
-void launch_pc_invert(int b, bool fp32, int nA, const LocalSys& ls, const void* At,
-                      const int* pcinfo, const int* pcoff, float* pcM, hipStream_t s) {
-    if (nA <= 0) return;
-    const int nb = (nA + KB_NT - 1) / KB_NT * PCI_SUB;
+void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void* At,
+                      const int* list, const int* cnt, const int* pcoff, float* pcM,
+                      hipStream_t s) {
+    if (grid <= 0) return;
 #define PV(BV, TT) \
-    k_pc_invert<BV, TT><<<nb, WAVE, 0, s>>>(nA, ls, (const TT*)At, pcinfo, pcoff, pcM)
+    k_pc_invert<BV, TT><<<grid, WAVE, 0, s>>>(ls, (const TT*)At, list, cnt, pcoff, pcM)
     if (fp32) {
         if (b == 1) PV(1, float); else if (b == 2) PV(2, float); else PV(3, float);
     } else {

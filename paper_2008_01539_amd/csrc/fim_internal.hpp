@@ -205,12 +205,16 @@ void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s
 void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);
 
 // fracture-block preconditioner (fim_fracpc.hip)
-// rows2 receives the sum over multi-row blocks of (block rows)^2
+// list: (first row, rows) of each multi-row block (room for nA / 2
+// blocks); cnt[0] = sum over them of rows^2, cnt[1] = their number
 void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
-                      int cell_stride, int* pcinfo, int* pcoff, int* rows2, hipStream_t s);
-// At: the scaled blocks in the Krylov precision (fp32: float, else double)
-void launch_pc_invert(int b, bool fp32, int nA, const LocalSys& ls, const void* At,
-                      const int* pcinfo, const int* pcoff, float* pcM, hipStream_t s);
+                      int cell_stride, int* pcinfo, int* pcoff, int* list, int* cnt,
+                      hipStream_t s);
+// At: the scaled blocks in the Krylov precision (fp32: float, else double);
+// grid single-wave workgroups share the listed blocks
+void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void* At,
+                      const int* list, const int* cnt, const int* pcoff, float* pcM,
+                      hipStream_t s);
 
 // update (fim_update.hip)
 void launch_update(int fk, int nA, const int* l2g, const double* x64,
