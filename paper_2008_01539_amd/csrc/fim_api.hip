@@ -20,11 +20,10 @@ using namespace fimk;
 // Optional event profiler: hipEvent pairs on the model's stream around each
 // kernel (or kernel group), read back at the next synchronisation.
 enum { PK_ASSEMBLE, PK_PRECOND, PK_IR, PK_BICG_A, PK_BICG_B, PK_UPDATE, PK_SETS, PK_SETUP,
-       PK_PCINV, PK_PCV_A, PK_PCV_B, PK_N };
+       PK_PCINV, PK_N };
 static const char* const kPkName[PK_N] = {"assemble", "precond", "ir_residual", "bicg_spmv_p",
                                           "bicg_spmv_s", "update", "sets_compact",
-                                          "step_setup", "frac_invert", "frac_apply_p",
-                                          "frac_apply_s"};
+                                          "step_setup", "frac_invert"};
 struct ProfRec {
     int k;
     hipEvent_t a, b;
