@@ -48,7 +48,10 @@ struct Prof {
 struct SolveTable {
     KSeg* dsegs = nullptr;
     int* dblk = nullptr;
-    SegStatus* dstat = nullptr;   // [6][cap]: refinement status, then 2 x 2 Krylov slots
+    // [6][cap]: refinement status, then 2 x 2 Krylov slots, in pinned host
+    // memory that k_seg_status writes directly (hstat_dev: its device
+    // address), so no copy runs between the Krylov kernels
+    SegStatus* hstat_dev = nullptr;
     SegStatus* hstat = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     int cap = 0;
@@ -293,7 +296,6 @@ static void table_free(SolveTable& t) {
         if (e) (void)hipEventDestroy(e);
     if (t.dsegs) (void)hipFree(t.dsegs);
     if (t.dblk) (void)hipFree(t.dblk);
-    if (t.dstat) (void)hipFree(t.dstat);
     if (t.hstat) (void)hipHostFree(t.hstat);
     t = SolveTable();
 }
@@ -302,9 +304,10 @@ static fim_status table_alloc(fim_model* m, SolveTable& t, int cap) {
     t.cap = cap;
     TRY(dal(m, &t.dsegs, (size_t)2 * cap));
     TRY(dal(m, &t.dblk, (size_t)2 * cap * KB_MAXB));
-    TRY(dal(m, &t.dstat, (size_t)6 * cap));
-    if (hipHostMalloc((void**)&t.hstat, 6 * cap * sizeof(SegStatus)) != hipSuccess) {
-        m->err = "hipHostMalloc failed";
+    if (hipHostMalloc((void**)&t.hstat, 6 * cap * sizeof(SegStatus),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&t.hstat_dev, t.hstat, 0) != hipSuccess) {
+        m->err = "pinned status buffer not available";
         return FIM_E_NOMEM;
     }
     for (hipEvent_t& e : t.ev) HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -370,11 +373,7 @@ static fim_status read_status(fim_model* lead, SolveTable& t, Group* G, std::vec
     for (int g = 0; g < 2; g++)
         if (!G[g].idx.empty())
             launch_seg_status(t.dsegs + (size_t)g * t.cap, (int)G[g].idx.size(),
-                              t.dstat + (size_t)g * t.cap, s);
-    for (int g = 0; g < 2; g++)
-        if (!G[g].idx.empty())
-            HIPX(hipMemcpyAsync(t.hstat + (size_t)g * t.cap, t.dstat + (size_t)g * t.cap,
-                                G[g].idx.size() * sizeof(SegStatus), hipMemcpyDeviceToHost, s));
+                              t.hstat_dev + (size_t)g * t.cap, s);
     HIPX(hipStreamSynchronize(s));
     if (flush) pflush(lead);
     (void)items;
@@ -489,12 +488,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
             for (int g = 0; g < 2; g++)
                 if (!G[g].idx.empty())
                     launch_seg_status(t.dsegs + (size_t)g * t.cap, (int)G[g].idx.size(),
-                                      t.dstat + (size_t)(2 + 2 * sl + g) * t.cap, s);
-            for (int g = 0; g < 2; g++)
-                if (!G[g].idx.empty())
-                    HIPX(hipMemcpyAsync(t.hstat + (size_t)(2 + 2 * sl + g) * t.cap,
-                                        t.dstat + (size_t)(2 + 2 * sl + g) * t.cap,
-                                        G[g].idx.size() * sizeof(SegStatus), hipMemcpyDeviceToHost, s));
+                                      t.hstat_dev + (size_t)(2 + 2 * sl + g) * t.cap, s);
             HIPX(hipEventRecord(t.ev[sl], s));
             return FIM_OK;
         };

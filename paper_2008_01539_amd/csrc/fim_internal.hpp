@@ -201,6 +201,7 @@ struct SegStatus {
     double rr;              // BiCGStab |r|^2 at the last completed iteration
     int done, iters, breakdown, pad;
 };
+// out: nseg records; may be the device address of coherent pinned host memory
 void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s);
 void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);
 
