@@ -469,39 +469,39 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         // host check (without profiling, whose records need the stream
         // drained).
         const bool ahead = !lead->prof.on;
-        auto queue_chunk = [&](int first_it, int len) {
+        // a block of len iterations; its last kernel S writes every model's
+        // Krylov status into slot sl (2 slots) of the pinned status table
+        auto queue_chunk = [&](int first_it, int len, int sl) {
             for (int c = 0; c < len; c++)
                 for (int w = 0; w < 2; w++)
                     for (int g = 0; g < 2; g++) {
                         if (!G[g].nblk) continue;
                         const int q = pbeg_ext(lead, PK_BICG_A + w, c);
+                        SegStatus* rec = (w == 1 && c == len - 1)
+                                             ? t.hstat_dev + (size_t)(2 + 2 * sl + g) * t.cap
+                                             : nullptr;
                         launch_bicg_part(w, b, g == 0, solo_of(t, G, g), G[g].pc,
                                          t.dsegs + (size_t)g * t.cap,
                                          t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk,
                                          first_it + c, s, q >= 0 ? lead->prof.pend[q].a : nullptr,
-                                         q >= 0 ? lead->prof.pend[q].b : nullptr);
+                                         q >= 0 ? lead->prof.pend[q].b : nullptr, rec);
                         if (q >= 0) lead->prof.pend[q].rows = lead->nA;
                     }
         };
-        // status of the queued work into slot sl (2 slots), then an event
+        // the event that tells the host slot sl is written
         auto queue_status = [&](int sl) -> fim_status {
-            for (int g = 0; g < 2; g++)
-                if (!G[g].idx.empty())
-                    launch_seg_status(t.dsegs + (size_t)g * t.cap, (int)G[g].idx.size(),
-                                      t.hstat_dev + (size_t)(2 + 2 * sl + g) * t.cap, s);
             HIPX(hipEventRecord(t.ev[sl], s));
             return FIM_OK;
         };
         // Iterations queued so far, and the length of the next block: near
         // convergence the block shrinks to what the observed residual
-        // decay predicts (plus a margin), so that few launches run after
-        // the solve has finished.  Blocks are never shorter than 2.
+        // decay predicts (plus a margin), and none is queued while the
+        // work in flight is predicted to suffice, so that few launches run
+        // after the solve has finished.  Blocks are never shorter than 2.
         int queued = 0;
         int next_len = check;
-        std::vector<double> rr_seen(K, -1.0);
-        std::vector<int> its_seen(K, -1);
         auto plan_next = [&](int sl) {
-            double need = 0.0;
+            double need = -1e30;   // iterations still to queue, over the models
             bool unknown = false;
             for (int g = 0; g < 2; g++)
                 for (size_t pos = 0; pos < G[g].idx.size(); pos++) {
@@ -509,10 +509,12 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                     if (!items[q].active) continue;
                     const SegStatus& st = t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos];
                     if (st.done) continue;
-                    const double rr = st.rr, tol2 = items[q].tol2;
-                    if (its_seen[q] >= 0 && st.iters > its_seen[q] && rr > 0.0 &&
-                        rr_seen[q] > 0.0 && tol2 > 0.0) {
-                        const double rate = std::pow(rr / rr_seen[q], 1.0 / (st.iters - its_seen[q]));
+                    const double rr = st.rr, tol2 = items[q].tol2, r0 = items[q].bnorm2;
+                    // average decay per iteration since the start of the pass
+                    // (x0 = 0, so |r_0|^2 = |b~|^2): BiCGStab residuals are
+                    // too erratic from one check to the next
+                    if (st.iters > 0 && rr > 0.0 && r0 > 0.0 && tol2 > 0.0) {
+                        const double rate = std::pow(rr / r0, 1.0 / st.iters);
                         if (rate < 0.999) {
                             const double rem = std::log(tol2 / rr) / std::log(rate);
                             need = std::max(need, rem - (queued - st.iters));
@@ -522,26 +524,37 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                     } else {
                         unknown = true;
                     }
-                    rr_seen[q] = rr;
-                    its_seen[q] = st.iters;
                 }
-            next_len = unknown ? check : std::max(2, std::min(check, (int)std::ceil(need) + 2));
+            // nothing more while the queued work is predicted to finish the
+            // solve with an iteration to spare: launches queued past
+            // convergence return at once but still cost a dispatch each
+            next_len = unknown ? check
+                       : need <= -1.0 ? 0
+                                      : std::max(2, std::min(check, (int)std::ceil(need) + 2));
         };
         int before = 0;
         const int max_chunks = lead->o.krylov_maxit + 4;   // blocks are >= 1 iteration
         const int max_queued = lead->o.krylov_maxit + 2 * check;
-        queue_chunk(0, check);
-        queued = check;
-        TRY(queue_status(0));
+        // blocks whose status is queued and not yet read (their slots, in
+        // order; at most two, in alternating slots)
+        int inflight[2] = {0, 0}, npend = 0, slot_next = 0;
+        auto issue = [&](int len) -> fim_status {
+            queue_chunk(queued, len, slot_next);
+            queued += len;
+            TRY(queue_status(slot_next));
+            inflight[npend++] = slot_next;
+            slot_next ^= 1;
+            return FIM_OK;
+        };
+        TRY(issue(check));
         for (int chunk = 0; chunk < max_chunks; chunk++) {
-            const int sl = chunk & 1;
             const bool more = queued < max_queued;
-            if (ahead && more) {
-                const int len = next_len;
-                queue_chunk(queued, len);
-                queued += len;
-                TRY(queue_status(sl ^ 1));
-            }
+            if (more && (npend == 0 || (ahead && npend < 2 && next_len > 0)))
+                TRY(issue(npend == 0 ? std::max(2, next_len) : next_len));
+            if (npend == 0) break;   // (not reached: the cap ends the loop below)
+            const int sl = inflight[0];
+            inflight[0] = inflight[1];
+            npend--;
             HIPX(hipEventSynchronize(t.ev[sl]));
             // the lead model's iteration count tells which of its profiled
             // launches did work (later ones returned at once)
@@ -558,7 +571,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                     if (items[G[g].idx[pos]].active &&
                         !t.hstat[(size_t)(2 + 2 * sl + g) * t.cap + pos].done)
                         all = false;
-            if (all || !more) {
+            if (all || (!more && npend == 0)) {
                 // final iteration counts.  Without more work queued, the
                 // status just read covers everything queued, and the
                 // iteration cap has stopped every model inside it.
@@ -568,11 +581,6 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                 break;
             }
             if (ahead) plan_next(sl);
-            if (!ahead && more) {
-                queue_chunk(queued, check);
-                queued += check;
-                TRY(queue_status(sl ^ 1));
-            }
         }
         for (int g = 0; g < 2; g++)
             for (size_t pos = 0; pos < G[g].idx.size(); pos++) {

@@ -190,9 +190,15 @@ void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int
 // pc: some model of the launch has fracture blocks (the kernels then apply
 // their inverses to the product on the fracture rows)
 // ev0/ev1: optional events stamped with the kernel's own start and end
+// rec (kernel S only, optional): one SegStatus per model of the launch with
+// the Krylov status after this kernel (rr, done, iters, breakdown; the
+// refinement sums zero); may be the device address of coherent pinned host
+// memory
+struct SegStatus;
 void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSeg* segs,
                       const int* blk_seg, int nblk_total, int it, hipStream_t s,
-                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                      hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                      SegStatus* rec = nullptr);
 void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
                           int nblk_total, hipStream_t s);
 

@@ -435,6 +435,16 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
     }
 }
 
+__device__ inline void put_status(SegStatus* o, double rr, int done, int iters, int brk) {
+    o->rir2 = 0.0;
+    o->bnorm2 = 0.0;
+    o->rr = rr;
+    o->done = done;
+    o->iters = iters;
+    o->breakdown = brk;
+    o->pad = 0;
+}
+
 // ------------------------------------------------------ kernel P (iter i)
 // Finishes iteration i-1 and starts iteration i:
 //   omega = (t,s)/(t,t), rho_i = (rh,s) - omega (rh,t)   [from kernel S]
@@ -612,7 +622,8 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const 
 template <int B, typename T, bool SOLO, bool PC>
 __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
-                                                                      int it) {
+                                                                      int it,
+                                                                      SegStatus* __restrict__ rec) {
     const KSeg& S = seg_of<SOLO>(segs, blk_seg);
     if (!S.active) return;
     const int nbk = S.nblk, nA = S.nA, lb = xcd_tile(S.blk0, nbk, blockIdx.x);
@@ -631,7 +642,14 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const 
 #pragma unroll
         for (int k = 0; k < 3; k++) red[k] += pa[(long)q * 4 + k];
     }
-    if (done) return;
+    // rec (the last kernel S of a block of iterations): each model's
+    // Krylov status after this kernel, for the host's check
+    const int segi = SOLO ? 0 : blk_seg[blockIdx.x];
+    if (done) {
+        if (rec && lb == 0 && threadIdx.x == 0)
+            put_status(rec + segi, sc->rr, 1, sc->iters, sc->breakdown);
+        return;
+    }
     constexpr int NV = 2;
     constexpr int U = chunk_slots<B, T, NV>();
     constexpr unsigned RB = B * sizeof(T);
@@ -670,6 +688,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const 
         } else {
             sc->alpha = al;
         }
+        if (rec) put_status(rec + segi, rr, (conv || bad) ? 1 : 0, it, bad ? 1 : 0);
     }
     if (conv || bad) return;
     auto fx = [&](const T (&raw)[NV][B], double (&x)[B]) {
@@ -752,7 +771,7 @@ void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s) {
 // (hipExtLaunchKernelGGL), i.e. the kernel's own start and end
 template <int B, typename T, bool SOLO, bool PC>
 static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
-                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, SegStatus* rec) {
     const dim3 nb(nblk_total), nt(KB_NT);
     if (which == 0) {
         if (it == 0)
@@ -763,7 +782,7 @@ static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_
                                   segs, blk_seg, it);
     } else {
         hipExtLaunchKernelGGL(k_bicg_s<B, T, SOLO, PC>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg,
-                              it);
+                              it, rec);
     }
 }
 
@@ -825,23 +844,23 @@ void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int
 
 void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSeg* segs,
                       const int* blk_seg, int nblk_total, int it, hipStream_t s, hipEvent_t ev0,
-                      hipEvent_t ev1) {
+                      hipEvent_t ev1, SegStatus* rec) {
     if (nblk_total <= 0) return;
 #define PI(BV, TT)                                                                             \
     do {                                                                                       \
         if (solo) {                                                                            \
             if (pc)                                                                            \
-                part_impl<BV, TT, true, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1); \
+                part_impl<BV, TT, true, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1, rec); \
             else                                                                               \
                 part_impl<BV, TT, true, false>(which, segs, blk_seg, nblk_total, it, s, ev0,   \
-                                               ev1);                                           \
+                                               ev1, rec);                                           \
         } else {                                                                               \
             if (pc)                                                                            \
                 part_impl<BV, TT, false, true>(which, segs, blk_seg, nblk_total, it, s, ev0,   \
-                                               ev1);                                           \
+                                               ev1, rec);                                           \
             else                                                                               \
                 part_impl<BV, TT, false, false>(which, segs, blk_seg, nblk_total, it, s, ev0,  \
-                                                ev1);                                          \
+                                                ev1, rec);                                          \
         }                                                                                      \
     } while (0)
     KDISPATCH(PI)
