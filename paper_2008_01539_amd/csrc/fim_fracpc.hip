@@ -29,35 +29,71 @@ __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restri
                                                      int* __restrict__ pcoff,
                                                      int* __restrict__ list,
                                                      int* __restrict__ cnt) {
-    __shared__ int sf[KB_NT];   // fracture id of each row (-1 matrix, -2 past nA)
-    __shared__ int ss[KB_NT];   // block start of each row
-    const int t = threadIdx.x, base = blockIdx.x * KB_NT, r = base + t;
+    constexpr int NW = KB_NT / WAVE;
+    __shared__ int sf[KB_NT];              // fracture id of each row (-1 matrix, -2 past nA)
+    __shared__ int wfirst[NW], wlast[NW];  // first / last run start in each wave
+    __shared__ int nlead[NW], sq[NW + 1], base_q;
+    const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
+    const int base = blockIdx.x * KB_NT, r = base + t;
     const bool valid = r < nA;
     const int f = valid ? frac_id[l2g[r]] : -2;
     sf[t] = f;
     __syncthreads();
-    int run = t;
-    if (f >= 0)
-        while (run > 0 && sf[run - 1] == f) run--;
-    const int bs = f >= 0 ? run + ((t - run) / cap) * cap : t;
-    ss[t] = bs;
-    __syncthreads();
-    int size = 1;
-    if (f >= 0) {
-        int e = bs;
-        while (e + 1 < KB_NT && ss[e + 1] == bs) e++;
-        size = e - bs + 1;
+    // runs of equal fracture id: the run around row t starts at the last
+    // run start at or before t and ends before the first one after t
+    const bool start = t == 0 || sf[t - 1] != f;
+    const unsigned long long m = __ballot(start);
+    if (lane == 0) {
+        wfirst[w] = m ? w * WAVE + __ffsll((long long)m) - 1 : KB_NT;
+        wlast[w] = m ? w * WAVE + 63 - __clzll((long long)m) : -1;
     }
+    __syncthreads();
+    const unsigned long long upto = (2ull << lane) - 1ull;   // lanes 0 .. lane
+    int run = 0, rend = KB_NT;
+    if (m & upto) {
+        run = w * WAVE + 63 - __clzll((long long)(m & upto));
+    } else {
+        for (int v = w - 1; v >= 0; v--)
+            if (wlast[v] >= 0) { run = wlast[v]; break; }
+    }
+    if (m & ~upto) {
+        rend = w * WAVE + __ffsll((long long)(m & ~upto)) - 1;
+    } else {
+        for (int v = w + 1; v < NW; v++)
+            if (wfirst[v] < KB_NT) { rend = wfirst[v]; break; }
+    }
+    // fracture runs split into blocks of at most cap rows; matrix rows
+    // (and rows past nA) are blocks of one row
+    const int bs = f >= 0 ? run + ((t - run) / cap) * cap : t;
+    const int size = f >= 0 ? min(bs + cap, rend) - bs : 1;
+    const bool lead = valid && size > 1 && bs == t;
+    // list slots: one atomic per workgroup
+    const unsigned long long lm = __ballot(lead);
+    if (lane == 0) nlead[w] = __popcll(lm);
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int v = 0; v < NW; v++) {
+            sq[v] = acc;
+            acc += nlead[v];
+        }
+        sq[NW] = acc;
+        base_q = acc ? atomicAdd(&cnt[1], acc) : 0;
+    }
+    __syncthreads();
     if (valid) {
         pcinfo[r] = (bs << 16) | size;
         pcoff[r] = (size > 1) ? ford[l2g[base + bs]] * cell_stride : 0;
-        if (size > 1 && bs == t) {
-            atomicAdd(&cnt[0], size * size);
-            const int q = atomicAdd(&cnt[1], 1);
-            list[2 * q] = r;
-            list[2 * q + 1] = size;
-        }
     }
+    if (lead) {
+        const int q = base_q + sq[w] + __popcll(lm & (upto >> 1));
+        list[2 * q] = r;
+        list[2 * q + 1] = size;
+    }
+    // sum of rows^2 over the blocks (profiling): one atomic per wave
+    int s2 = lead ? size * size : 0;
+    for (int o = WAVE / 2; o > 0; o /= 2) s2 += __shfl_xor(s2, o);
+    if (lane == 0 && s2) atomicAdd(&cnt[0], s2);
 }
 
 void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
