@@ -6,10 +6,30 @@
 
 namespace fimk {
 
+// One DPP move of a double (both halves with the same control); lanes
+// that the row mask leaves out, or whose source is out of range, read 0.
+template <int CTRL, int ROWS = 0xf>
+__device__ inline double dpp_f64(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, true),
+                            __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xf, true));
+}
+
+// Sum over the wave, returned in every lane; fixed order (deterministic).
+// Cross-lane steps are DPP register moves (no LDS round trips): swaps of
+// neighbours and pairs inside each quad, mirrors inside each half-row and
+// row (every lane then holds its 16-lane row sum), then rows 0+1 and 2+3
+// (row broadcast of lane 15) and all four (row broadcast of lane 31) into
+// row 3; lane 63 holds the total.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
+    v += dpp_f64<0xB1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);          // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);         // row_half_mirror
+    v += dpp_f64<0x140>(v);         // row_mirror
+    v += dpp_f64<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
 }
 
 __device__ inline double wave_max(double v) {
