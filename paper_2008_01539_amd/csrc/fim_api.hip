@@ -63,6 +63,7 @@ struct fim_model {
     DevFluid f{};
     hipStream_t s = nullptr;
     bool own_stream = false;
+    hipEvent_t sync_ev = nullptr;   // see spin_sync
     Graph g{};
     // static data
     int *adj_ptr = nullptr, *adj_nbr = nullptr;
@@ -223,10 +224,26 @@ static fim_status dal(fim_model* m, P** p, size_t count) {
 }
 
 
+// Waits for an event by polling rather than sleeping.  These waits sit
+// between dependent launches on the host's critical path (status checks of
+// the Newton and Krylov loops), where an interrupt-driven wake-up leaves the
+// GPU idle for tens of microseconds.
+static hipError_t spin_event(hipEvent_t e) {
+    for (;;) {
+        const hipError_t r = hipEventQuery(e);
+        if (r != hipErrorNotReady) return r;
+    }
+}
+// All work queued on s so far, through the model's own event
+static hipError_t spin_sync(fim_model* m, hipStream_t s) {
+    const hipError_t r = hipEventRecord(m->sync_ev, s);
+    return r == hipSuccess ? spin_event(m->sync_ev) : r;
+}
+
 static fim_status sync_read(fim_model* m, void* host, const void* dev, size_t bytes,
                             int keep_tag = INT_MAX) {
     HIPX(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, m->s));
-    HIPX(hipStreamSynchronize(m->s));
+    HIPX(spin_sync(m, m->s));
     pflush(m, keep_tag);
     return FIM_OK;
 }
@@ -374,7 +391,7 @@ static fim_status read_status(fim_model* lead, SolveTable& t, Group* G, std::vec
         if (!G[g].idx.empty())
             launch_seg_status(t.dsegs + (size_t)g * t.cap, (int)G[g].idx.size(),
                               t.hstat_dev + (size_t)g * t.cap, s);
-    HIPX(hipStreamSynchronize(s));
+    HIPX(spin_sync(lead, s));
     if (flush) pflush(lead);
     (void)items;
     return FIM_OK;
@@ -555,7 +572,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
             const int sl = inflight[0];
             inflight[0] = inflight[1];
             npend--;
-            HIPX(hipEventSynchronize(t.ev[sl]));
+            HIPX(spin_event(t.ev[sl]));
             // the lead model's iteration count tells which of its profiled
             // launches did work (later ones returned at once)
             for (int g = 0; g < 2; g++)
@@ -889,6 +906,7 @@ static void free_all(fim_model* m) {
     if (m->hint) (void)hipHostFree(m->hint);
     if (m->hsub) (void)hipHostFree(m->hsub);
     if (m->hpart) (void)hipHostFree(m->hpart);
+    if (m->sync_ev) (void)hipEventDestroy(m->sync_ev);
     if (m->own_stream && m->s) (void)hipStreamDestroy(m->s);
 }
 
@@ -1002,6 +1020,12 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
         }
         m->own_stream = true;
     }
+    if (hipEventCreateWithFlags(&m->sync_ev, hipEventDisableTiming) != hipSuccess) {
+        g_create_err = "hipEventCreate failed";
+        if (m->own_stream) (void)hipStreamDestroy(m->s);
+        delete m;
+        return FIM_E_HIP;
+    }
     // host-side adjacency (both directions, neighbours ascending)
     std::vector<int> deg(n + 1, 0);
     for (int c = 0; c < d->n_conn; c++) {
@@ -1029,7 +1053,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             for (size_t q = 0; q < row.size(); q++) {
                 if (q && row[q].first == row[q - 1].first) {
                     g_create_err = "duplicate connection";
-                    if (m->own_stream) (void)hipStreamDestroy(m->s);
+                    free_all(m);
                     delete m;
                     return FIM_E_ARG;
                 }
@@ -1055,7 +1079,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     // the Krylov kernels address the matrix blocks with 32-bit byte offsets
     if ((double)m->slot_cap * B * B * sizeof(double) >= 4294967296.0) {
         g_create_err = "model too large: the matrix blocks would exceed 4 GiB";
-        if (m->own_stream) (void)hipStreamDestroy(m->s);
+        free_all(m);
         delete m;
         return FIM_E_ARG;
     }
@@ -1283,7 +1307,7 @@ static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it) {
 static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
     TRY(local_newton(m, it));
     TRY(newton_post_launch(m));
-    HIPX(hipStreamSynchronize(m->s));
+    HIPX(spin_sync(m, m->s));
     pflush(m);
     return newton_post_finish(m, it);
 }
@@ -1350,7 +1374,7 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
         TRY(local_newton(m, it));
         launch_copy_masked(m->nA, m->l2g, m->dp_abs, m->last_dp, m->s);
         HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
-        HIPX(hipStreamSynchronize(m->s));
+        HIPX(spin_sync(m, m->s));
         m->nu++;
         const NStat ns = *m->hns;
         if (it) { it->dp_max = ns.dp_max; it->ds_max = ns.ds_max; it->nonfinite = ns.nonfinite; }
