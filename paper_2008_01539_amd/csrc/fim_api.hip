@@ -54,6 +54,10 @@ struct SolveTable {
     SegStatus* hstat_dev = nullptr;
     SegStatus* hstat = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // batched fracture-block inversion: [2][cap] systems (FP32, FP64 Krylov)
+    // and [2][cap + 1] running block counts
+    PcSeg* dpc = nullptr;
+    int* dpref = nullptr;
     int cap = 0;
 };
 
@@ -313,12 +317,16 @@ static void table_free(SolveTable& t) {
         if (e) (void)hipEventDestroy(e);
     if (t.dsegs) (void)hipFree(t.dsegs);
     if (t.dblk) (void)hipFree(t.dblk);
+    if (t.dpc) (void)hipFree(t.dpc);
+    if (t.dpref) (void)hipFree(t.dpref);
     if (t.hstat) (void)hipHostFree(t.hstat);
     t = SolveTable();
 }
 
 static fim_status table_alloc(fim_model* m, SolveTable& t, int cap) {
     t.cap = cap;
+    TRY(dal(m, &t.dpc, (size_t)2 * cap));
+    TRY(dal(m, &t.dpref, (size_t)2 * (cap + 1)));
     TRY(dal(m, &t.dsegs, (size_t)2 * cap));
     TRY(dal(m, &t.dblk, (size_t)2 * cap * KB_MAXB));
     if (hipHostMalloc((void**)&t.hstat, 6 * cap * sizeof(SegStatus),
@@ -426,7 +434,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         const int pi = pbeg(lead, PK_PRECOND);
         launch_precond(mq->B, it.fp32, mq->nA, lsys(mq), mq->dinv, mq->At, s);
         pend(lead, pi, mq->nA);
-        if (mq->use_pc) {
+        if (mq->use_pc && K == 1) {
             const int pv = pbeg(lead, PK_PCINV);
             launch_pc_invert(mq->B, it.fp32, mq->pc_inv_grid, lsys(mq), mq->At, mq->pclist,
                              &mq->dint[6], mq->pcoff, mq->pcM, s);
@@ -434,6 +442,28 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         }
         launch_fill_f64(mq->x64, (long)mq->nA * mq->B, 0.0, s);
         G[it.fp32 ? 0 : 1].idx.push_back(q);
+    }
+    if (K > 1) {
+        // the fracture blocks of all members in one launch per precision
+        // (each member's inversion alone is a few waves and latency-bound)
+        for (int g = 0; g < 2; g++) {
+            std::vector<PcSeg> pcs;
+            for (int q : G[g].idx) {
+                fim_model* mq = ms[q];
+                if (mq->use_pc)
+                    pcs.push_back(PcSeg{lsys(mq), mq->At, mq->pclist, &mq->dint[6], mq->pcoff,
+                                        mq->pcM});
+            }
+            if (pcs.empty()) continue;
+            PcSeg* dpc = t.dpc + (size_t)g * t.cap;
+            int* dpref = t.dpref + (size_t)g * (t.cap + 1);
+            HIPX(hipMemcpyAsync(dpc, pcs.data(), pcs.size() * sizeof(PcSeg),
+                                hipMemcpyHostToDevice, s));
+            const int pv = pbeg(lead, PK_PCINV);
+            launch_pc_invert_batch(lead->B, g == 0, 8 * lead->cus, dpc, (int)pcs.size(), dpref,
+                                   s);
+            pend(lead, pv, lead->nA);
+        }
     }
     const int b = lead->B;
     for (int g = 0; g < 2; g++) TRY(upload_group(lead, t, g, G[g], items, s));

@@ -131,23 +131,21 @@ __device__ inline void wave_sync() {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// the block in LDS, row stride MS (16-byte rows, offset banks per row)
+constexpr int PCI_MS = PC_DOF + 4;
+
+// Block q of one system's list, by one wave; M: PC_DOF x PCI_MS floats of
+// LDS.  Loops stay rolled where they run once per block: each wave runs
+// this code about once per launch, so its size (instruction fetch) costs
+// more than loop overhead.
 template <int B, typename T>
-__global__ __launch_bounds__(WAVE) void k_pc_invert(LocalSys ls, const T* __restrict__ At,
-                                                    const int* __restrict__ list,
-                                                    const int* __restrict__ cnt,
-                                                    const int* __restrict__ pcoff,
-                                                    float* __restrict__ pcM) {
+__device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
+                             const int* __restrict__ list, const int* __restrict__ pcoff,
+                             float* __restrict__ pcM, int q, float* M) {
     constexpr int BB = B * B;
-    // the block in LDS, row stride MS (16-byte rows, offset banks per row)
-    constexpr int MS = PC_DOF + 4;
-    __shared__ __align__(16) float M[PC_DOF * MS];
+    constexpr int MS = PCI_MS;
     const int lane = threadIdx.x;
-    const int nblk = *cnt;
-    // Loops stay rolled where they run once per block: each wave runs this
-    // code about once per launch, so its size (instruction fetch) costs
-    // more than loop overhead.  One block per workgroup (single wave) at a
-    // time, from the list k_pc_blocks wrote.
-    for (int q = blockIdx.x; q < nblk; q += gridDim.x) {
+    {
         const int r0 = list[2 * q], size = list[2 * q + 1];
         const int N = size * B;
 
@@ -293,12 +291,70 @@ __global__ __launch_bounds__(WAVE) void k_pc_invert(LocalSys ls, const T* __rest
     }
 }
 
+// One system: workgroup w takes blocks w, w + grid, ... of its list.
+template <int B, typename T>
+__global__ __launch_bounds__(WAVE) void k_pc_invert(LocalSys ls, const T* __restrict__ At,
+                                                    const int* __restrict__ list,
+                                                    const int* __restrict__ cnt,
+                                                    const int* __restrict__ pcoff,
+                                                    float* __restrict__ pcM) {
+    __shared__ __align__(16) float M[PC_DOF * PCI_MS];
+    const int nblk = *cnt;
+    for (int q = blockIdx.x; q < nblk; q += gridDim.x)
+        invert_block<B, T>(ls, At, list, pcoff, pcM, q, M);
+}
+
+// Many systems (a batch): the blocks of all lists in one sequence; pref
+// holds the running block counts (pref[k] = blocks of systems 0 .. k-1).
+__global__ __launch_bounds__(64) void k_pc_prefix(const PcSeg* __restrict__ segs, int nseg,
+                                                  int* __restrict__ pref) {
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int k = 0; k < nseg; k++) {
+            pref[k] = acc;
+            acc += *segs[k].cnt;
+        }
+        pref[nseg] = acc;
+    }
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(WAVE) void k_pc_invert_batch(const PcSeg* __restrict__ segs,
+                                                          int nseg,
+                                                          const int* __restrict__ pref) {
+    __shared__ __align__(16) float M[PC_DOF * PCI_MS];
+    const int total = pref[nseg];
+    for (int q = blockIdx.x; q < total; q += gridDim.x) {
+        int lo = 0, hi = nseg - 1;   // the system k with pref[k] <= q < pref[k + 1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (pref[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const PcSeg& S = segs[lo];
+        invert_block<B, T>(S.ls, (const T*)S.At, S.list, S.pcoff, S.pcM, q - pref[lo], M);
+    }
+}
+
 void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void* At,
                       const int* list, const int* cnt, const int* pcoff, float* pcM,
                       hipStream_t s) {
     if (grid <= 0) return;
 #define PV(BV, TT) \
     k_pc_invert<BV, TT><<<grid, WAVE, 0, s>>>(ls, (const TT*)At, list, cnt, pcoff, pcM)
+    if (fp32) {
+        if (b == 1) PV(1, float); else if (b == 2) PV(2, float); else PV(3, float);
+    } else {
+        if (b == 1) PV(1, double); else if (b == 2) PV(2, double); else PV(3, double);
+    }
+#undef PV
+}
+
+void launch_pc_invert_batch(int b, bool fp32, int grid, const PcSeg* segs, int nseg, int* pref,
+                            hipStream_t s) {
+    if (grid <= 0 || nseg <= 0) return;
+    k_pc_prefix<<<1, 64, 0, s>>>(segs, nseg, pref);
+#define PV(BV, TT) k_pc_invert_batch<BV, TT><<<grid, WAVE, 0, s>>>(segs, nseg, pref)
     if (fp32) {
         if (b == 1) PV(1, float); else if (b == 2) PV(2, float); else PV(3, float);
     } else {

@@ -222,6 +222,19 @@ void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* for
 void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void* At,
                       const int* list, const int* cnt, const int* pcoff, float* pcM,
                       hipStream_t s);
+// one system of a batched inversion (device table entry)
+struct PcSeg {
+    LocalSys ls;
+    const void* At;
+    const int* list;
+    const int* cnt;
+    const int* pcoff;
+    float* pcM;
+};
+// the blocks of nseg systems (same b and Krylov precision) in one launch of
+// grid single-wave workgroups; pref: nseg + 1 ints of device scratch
+void launch_pc_invert_batch(int b, bool fp32, int grid, const PcSeg* segs, int nseg, int* pref,
+                            hipStream_t s);
 
 // update (fim_update.hip)
 void launch_update(int fk, int nA, const int* l2g, const double* x64,

@@ -22,11 +22,13 @@ def _solo(model, opts, mode, dts):
 
 def _batched(models, opts, mode, nsteps):
     """Continuous batching: members leave the batch when they finished
-    their steps; each member advances through its own schedule."""
+    their steps; each member advances through its own schedule.  opts may
+    be one Options for all members or one per member."""
     import paper_2008_01539_amd as P
     fms = []
-    for m in models:
-        fm = P.FimModel(m, opts)
+    per = opts if isinstance(opts, (list, tuple)) else [opts] * len(models)
+    for m, o in zip(models, per):
+        fm = P.FimModel(m, o)
         fm.set_state(m.u0, m.status0)
         fms.append(fm)
     step = [0] * len(models)
@@ -106,3 +108,31 @@ def test_serving_results_same_alone_and_in_the_mix():
         ref, _ = _solo(s.spec.model, s.spec.options, s.spec.mode, dts)
         assert np.array_equal(u, ref), s.spec.name
     ex.close()
+
+
+def test_batch_two_phase_fp64_equals_solo():
+    """FP64 Krylov members with fracture blocks (the batched inversion reads
+    FP64 scaled blocks): every member keeps its solo bits."""
+    import paper_2008_01539_amd as P
+    models = [make_small_c2(seed=31, nx=24, ny=12, nfrac=14),
+              make_small_c2(seed=32, nx=20, ny=16, nfrac=18),
+              make_small_c2(seed=33, nx=18, ny=10, nz=3, nfrac=8, nstage=2)]
+    opts = P.Options(precision=P.FP64)
+    n = 4
+    got, sizes = _batched(models, opts, P.LOCAL, n)
+    for m, (u, st) in zip(models, got):
+        ref, ref_st = _solo(m, opts, P.LOCAL, m.schedule[:n])
+        assert np.array_equal(u, ref)
+        assert np.array_equal(st, ref_st)
+    assert max(sizes) == 3
+
+
+def test_batch_rejects_mixed_precisions():
+    import paper_2008_01539_amd as P
+    from paper_2008_01539_amd.fim import FimError
+    a = P.FimModel(make_small_c2(seed=34), P.Options(precision=P.FP64))
+    b = P.FimModel(make_small_c2(seed=35), P.Options(precision=P.MIXED))
+    with pytest.raises(FimError):
+        P.FimBatch([a, b])
+    a.close()
+    b.close()
