@@ -1518,12 +1518,20 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
 }
 
 // ------------------------------------------------------------- batches
+constexpr int BATCH_AUX = 4;   // streams for the members' own small kernels
+
 struct fim_batch {
     std::vector<fim_model*> ms;
     std::vector<hipEvent_t> ev;   // one per member: stream hand-over
     hipEvent_t done_ev = nullptr;
     hipStream_t s = nullptr;
     bool own_stream = false;
+    // the members' set, compaction, assembly and update launches are a few
+    // small kernels each; member q issues them on aux[q % BATCH_AUX] so that
+    // those of different members overlap; fork / join order them against
+    // the batch stream, which runs the batched solve
+    hipStream_t aux[BATCH_AUX] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[BATCH_AUX] = {};
     SolveTable tab;
     int B = 0, precision = 0;
     std::string err;
@@ -1581,19 +1589,20 @@ fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_strea
     } else {
         b->own_stream = true;
     }
-    if (hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming) != hipSuccess) {
-        g_batch_err = "hipEventCreate failed";
-        if (b->own_stream) (void)hipStreamDestroy(b->s);
-        delete b;
+    bool ok = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < BATCH_AUX && ok; i++)
+        ok = hipStreamCreate(&b->aux[i]) == hipSuccess &&
+             hipEventCreateWithFlags(&b->join_ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        g_batch_err = "hipStreamCreate / hipEventCreate failed";
+        (void)fim_batch_destroy(b);
         return FIM_E_HIP;
     }
     r = fim_batch_set(b, models, k);
     if (r != FIM_OK) {
         g_batch_err = b->err.empty() ? models[0]->err : b->err;
-        table_free(b->tab);
-        (void)hipEventDestroy(b->done_ev);
-        if (b->own_stream) (void)hipStreamDestroy(b->s);
-        delete b;
+        (void)fim_batch_destroy(b);
         return r;
     }
     *out = b;
@@ -1602,12 +1611,37 @@ fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_strea
 
 fim_status fim_batch_destroy(fim_batch* b) {
     if (!b) return FIM_E_ARG;
-    (void)hipStreamSynchronize(b->s);
+    if (b->s) (void)hipStreamSynchronize(b->s);
+    for (int i = 0; i < BATCH_AUX; i++) {
+        if (b->aux[i]) {
+            (void)hipStreamSynchronize(b->aux[i]);
+            (void)hipStreamDestroy(b->aux[i]);
+        }
+        if (b->join_ev[i]) (void)hipEventDestroy(b->join_ev[i]);
+    }
     table_free(b->tab);
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     if (b->done_ev) (void)hipEventDestroy(b->done_ev);
-    if (b->own_stream) (void)hipStreamDestroy(b->s);
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    if (b->own_stream && b->s) (void)hipStreamDestroy(b->s);
     delete b;
+    return FIM_OK;
+}
+
+// aux streams after everything queued on the batch stream so far
+static fim_status batch_fork(fim_batch* b) {
+    if (hipEventRecord(b->fork_ev, b->s) != hipSuccess) return FIM_E_HIP;
+    for (int i = 0; i < BATCH_AUX; i++)
+        if (hipStreamWaitEvent(b->aux[i], b->fork_ev, 0) != hipSuccess) return FIM_E_HIP;
+    return FIM_OK;
+}
+
+// the batch stream after everything queued on the aux streams so far
+static fim_status batch_join(fim_batch* b) {
+    for (int i = 0; i < BATCH_AUX; i++)
+        if (hipEventRecord(b->join_ev[i], b->aux[i]) != hipSuccess ||
+            hipStreamWaitEvent(b->s, b->join_ev[i], 0) != hipSuccess)
+            return FIM_E_HIP;
     return FIM_OK;
 }
 
@@ -1650,16 +1684,23 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
         codes[q] = FIM_OK;
     }
     auto restore = [&]() {
+        (void)batch_join(b);
         (void)hipEventRecord(b->done_ev, b->s);
         for (int q = 0; q < K; q++) {
             b->ms[q]->s = saved[q];
             if (saved[q] != b->s) (void)hipStreamWaitEvent(saved[q], b->done_ev, 0);
         }
     };
+    if (batch_fork(b) != FIM_OK) {
+        b->err = "stream fork failed";
+        restore();
+        return FIM_E_HIP;
+    }
     std::vector<fim_model*> live;
     std::vector<int> pos;
     for (int q = 0; q < K; q++) {
         fim_model* m = b->ms[q];
+        m->s = b->aux[q % BATCH_AUX];
         if (m->in_step && (dts[q] != m->step_dt || modes[q] != m->step_mode)) {
             m->err = "dt or mode changed inside a timestep";
             codes[q] = FIM_E_STATE;
@@ -1677,18 +1718,30 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
         pos.push_back(q);
     }
     if (!live.empty()) {
+        if (batch_join(b) != FIM_OK) {
+            b->err = "stream join failed";
+            restore();
+            return FIM_E_HIP;
+        }
+        for (fim_model* m : live) m->s = b->s;
         fim_status r = solve_batch(live, b->tab, b->s);
         if (r != FIM_OK) {
             b->err = live[0]->err;
             restore();
             return r;
         }
+        if (batch_fork(b) != FIM_OK) {
+            b->err = "stream fork failed";
+            restore();
+            return FIM_E_HIP;
+        }
         for (size_t t = 0; t < live.size(); t++) {
+            live[t]->s = b->aux[pos[t] % BATCH_AUX];
             newton_update(live[t], stats ? &stats[pos[t]] : nullptr);
             fim_status r2 = newton_post_launch(live[t]);
             if (r2 != FIM_OK) codes[pos[t]] = r2;
         }
-        if (hipStreamSynchronize(b->s) != hipSuccess) {
+        if (batch_join(b) != FIM_OK || hipStreamSynchronize(b->s) != hipSuccess) {
             b->err = "hipStreamSynchronize failed";
             restore();
             return FIM_E_HIP;
