@@ -58,6 +58,11 @@ struct SolveTable {
     // and [2][cap + 1] running block counts
     PcSeg* dpc = nullptr;
     int* dpref = nullptr;
+    // pinned staging of the uploads ([2][cap] descriptors, [2][cap * KB_MAXB]
+    // block map): asynchronous copies; the host rewrites them only after a
+    // synchronisation that follows the previous copy
+    KSeg* hsegs = nullptr;
+    int* hblk = nullptr;
     int cap = 0;
 };
 
@@ -320,6 +325,8 @@ static void table_free(SolveTable& t) {
     if (t.dpc) (void)hipFree(t.dpc);
     if (t.dpref) (void)hipFree(t.dpref);
     if (t.hstat) (void)hipHostFree(t.hstat);
+    if (t.hsegs) (void)hipHostFree(t.hsegs);
+    if (t.hblk) (void)hipHostFree(t.hblk);
     t = SolveTable();
 }
 
@@ -329,6 +336,11 @@ static fim_status table_alloc(fim_model* m, SolveTable& t, int cap) {
     TRY(dal(m, &t.dpref, (size_t)2 * (cap + 1)));
     TRY(dal(m, &t.dsegs, (size_t)2 * cap));
     TRY(dal(m, &t.dblk, (size_t)2 * cap * KB_MAXB));
+    if (hipHostMalloc((void**)&t.hsegs, 2 * cap * sizeof(KSeg)) != hipSuccess ||
+        hipHostMalloc((void**)&t.hblk, (size_t)2 * cap * KB_MAXB * sizeof(int)) != hipSuccess) {
+        m->err = "hipHostMalloc failed";
+        return FIM_E_NOMEM;
+    }
     if (hipHostMalloc((void**)&t.hstat, 6 * cap * sizeof(SegStatus),
                       hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
         hipHostGetDevicePointer((void**)&t.hstat_dev, t.hstat, 0) != hipSuccess) {
@@ -385,10 +397,16 @@ static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
     for (int q : G.idx) G.pc = G.pc || items[q].m->use_pc;
     if (segs.empty()) return fim_status(FIM_OK);
     fim_model* m = lead;
-    HIPX(hipMemcpyAsync(t.dsegs + (size_t)g * t.cap, segs.data(), segs.size() * sizeof(KSeg),
+    KSeg* hs = t.hsegs + (size_t)g * t.cap;
+    std::memcpy(hs, segs.data(), segs.size() * sizeof(KSeg));
+    HIPX(hipMemcpyAsync(t.dsegs + (size_t)g * t.cap, hs, segs.size() * sizeof(KSeg),
                         hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(t.dblk + (size_t)g * t.cap * KB_MAXB, blk.data(), blk.size() * sizeof(int),
-                        hipMemcpyHostToDevice, s));
+    if (segs.size() > 1) {   // one-model launches do not read the block map
+        int* hb = t.hblk + (size_t)g * t.cap * KB_MAXB;
+        std::memcpy(hb, blk.data(), blk.size() * sizeof(int));
+        HIPX(hipMemcpyAsync(t.dblk + (size_t)g * t.cap * KB_MAXB, hb, blk.size() * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+    }
     return FIM_OK;
 }
 
