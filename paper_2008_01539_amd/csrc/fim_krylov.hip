@@ -199,36 +199,6 @@ __device__ inline void row_product(const LocalSys& ls, const T* At, const RowGeo
     }
 }
 
-// One row of a fracture-block inverse times the block's values y (in
-// LDS): sum_j M[u][j] y[j], j < N, for the unknown u = rr b + ci of a block
-// of `size` rows stored from element offset off (grouped layout of
-// fim_internal.hpp).  Loads and LDS reads are clamped to the block (every
-// address valid) and masked, with no branch per term, so that all of them
-// are in flight together; two halves of 32 keep registers in check.
-template <int B>
-__device__ __attribute__((always_inline)) inline double pc_unknown_dot(const float* M, int off,
-                                                                       int rr, int ci, int size,
-                                                                       int N, const double* y) {
-    constexpr int K = pc_group_cols(B), W = B * K;
-    const unsigned row0 = (unsigned)(off + rr * W + ci * K) * 4u;
-    const unsigned grpb = (unsigned)(size * W) * 4u;
-    double acc = 0.0;
-#pragma unroll
-    for (int h = 0; h < PC_DOF; h += 32) {
-        float mv[32];
-        double yv[32];
-#pragma unroll
-        for (int q = 0; q < 32; q++) {
-            const int j = min(h + q, N - 1);
-            mv[q] = ldg<float>(M, row0 + (unsigned)(j / K) * grpb + 4u * (unsigned)(j % K));
-            yv[q] = y[j];
-        }
-#pragma unroll
-        for (int q = 0; q < 32; q++) acc += (h + q < N) ? (double)mv[q] * yv[q] : 0.0;
-    }
-    return acc;
-}
-
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 // Left application of the fracture-block inverses inside the product
@@ -294,49 +264,6 @@ __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off
         for (int c = 0; c < B; c++) y[c] = acc[c];
     }
     __syncthreads();   // yb is reused by the next tile pass
-}
-
-// Left application of the fracture-block inverses (see fim_fracpc.hip)
-// to one tile of values y (one row per thread, FP64), used by the
-// refinement kernel.  Every thread of the block calls it (barriers); act
-// marks the threads that hold a row, info / off are the row's block
-// layout words.  Thread t computes unknowns t, t + 256, ... of the tile,
-// each from one row of the block inverse (up to 64 values, one round of
-// loads, coalesced over the block's unknowns).
-template <int B>
-__device__ inline void pc_apply(const KrylovBufs& kb, bool act, int info, int off,
-                                double (&y)[B]) {
-    __shared__ double yb[KB_NT * B];
-    __shared__ int info_s[KB_NT], off_s[KB_NT];
-    const int t = threadIdx.x;
-    info_s[t] = act ? info : 1;
-    off_s[t] = off;
-#pragma unroll
-    for (int c = 0; c < B; c++) yb[t * B + c] = act ? y[c] : 0.0;
-    __syncthreads();
-    double z[B];
-#pragma unroll
-    for (int h = 0; h < B; h++) {
-        const int R = h * KB_NT + t;
-        const int rl = R / B, ci = R - rl * B;
-        const int inf = info_s[rl];
-        const int size = inf & 0xffff;
-        z[h] = yb[R];
-        if (size > 1) {
-            const int bs = inf >> 16;
-            z[h] = pc_unknown_dot<B>(kb.pcM, off_s[rl], rl - bs, ci, size, size * B,
-                                     yb + bs * B);
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < B; h++) yb[h * KB_NT + t] = z[h];
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int c = 0; c < B; c++) y[c] = yb[t * B + c];
-    }
-    __syncthreads();
 }
 
 static inline int kgrid(long rows) {
@@ -407,7 +334,7 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
                 poff = kb.pcoff[r];
             }
         }
-        if (pc) pc_apply<B>(kb, act, pinfo, poff, bt);
+        if (pc) pc_rows<B, double>(kb, act, pinfo, poff, bt);
         if (act) {
 #pragma unroll
             for (int c = 0; c < B; c++) {
