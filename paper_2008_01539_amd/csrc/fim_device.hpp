@@ -1,5 +1,5 @@
-// Device helpers: deterministic block reductions and the last-block
-// pattern used to finish grid-wide reductions without an extra launch.
+// Device helpers: deterministic wave and block reductions, and the
+// XCD-aware workgroup-to-tile map.
 #pragma once
 
 #include "fim_internal.hpp"
@@ -99,21 +99,6 @@ __device__ inline int block_sum_i(int v) {
     int r = 0;
     for (int q = 0; q < (int)(blockDim.x / WAVE); q++) r += sh[q];
     return r;
-}
-
-// Thread 0 has written this block's partials; returns true in every thread
-// of the block that finishes last (all partials of the grid are visible).
-__device__ inline bool last_block(unsigned* counter) {
-    __shared__ int last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned t = atomicAdd(counter, 1u);
-        last = (t == gridDim.x - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
 }
 
 inline int nblocks(long n, int nt = NT) { return (int)((n + nt - 1) / nt); }
