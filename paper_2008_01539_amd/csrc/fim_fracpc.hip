@@ -113,8 +113,9 @@ void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* for
 // Gauss-Jordan elimination then runs N steps (N = the block's unknowns; the
 // identity padding never pivots) without pivoting (the scaled blocks have
 // unit diagonal blocks and are diagonally dominant in practice); every
-// step takes column 0 as the pivot column, broadcasts the pivot row
-// through LDS, and shifts the columns left by one, appending the new column
+// step takes column 0 as the pivot column, broadcasts the pivot row from
+// the pivot lane's registers (lane reads, no LDS round trip), and shifts the
+// columns left by one, appending the new column
 // of the inverse at the end, so that all register indices are compile-time
 // constants and after N steps columns 64 - N .. 63 hold the inverse.  Rows
 // are eliminated with multiplier (entry / pivot) and the pivot row is left
@@ -219,26 +220,11 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
         // inverse, each row still times its pivot (the identity padding is
         // never a pivot)
         for (int step = 0; step < N; step++) {
-            if (lane == step) {
-                f4v* row = (f4v*)M;
-#pragma unroll
-                for (int c = 0; c < PC_DOF / 4; c++)
-                    row[c] = f4v{a[4 * c], a[4 * c + 1], a[4 * c + 2], a[4 * c + 3]};
-            }
-            wave_sync();
+            // the pivot row, broadcast from the pivot lane's registers
             float pr[PC_DOF];
-            {
-                const f4v* row = (const f4v*)M;
 #pragma unroll
-                for (int c = 0; c < PC_DOF / 4; c++) {
-                    const f4v v = row[c];
-                    pr[4 * c] = v[0];
-                    pr[4 * c + 1] = v[1];
-                    pr[4 * c + 2] = v[2];
-                    pr[4 * c + 3] = v[3];
-                }
-            }
-            wave_sync();
+            for (int c = 0; c < PC_DOF; c++)
+                pr[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[c]), step));
             const float p = pr[0];
             bad = bad || !(fabsf(p) > 1e-20f) || !isfinite(p);
             const float ip = 1.0f / p;
