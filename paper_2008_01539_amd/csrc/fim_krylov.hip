@@ -209,13 +209,54 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // workgroup calls it; tiles without such blocks return after one barrier.
 // The thread of block row rr reads its b rows of M^{-1} as 16-byte vectors
 // (the grouped layout keeps them contiguous per group of K columns), 16
-// columns per round with all loads of a round in flight together.
+// columns per round with all loads of a round in flight together.  For
+// b <= 2 the first round does not wait for the product: pc_first issues it
+// before the row's product, pc_rows consumes it.
+template <int B, typename T>
+struct PcShape {
+    static constexpr int K = pc_group_cols(B), W = B * K, NV4 = W / 4;
+    static constexpr int QG = (B == 3 && sizeof(T) == 8) ? 2 : 16 / K;   // groups per round
+    static constexpr bool PRE = B <= 2;                                   // first round early
+};
+
+template <int B, typename T>
+using PcRound = f4v[PcShape<B, T>::QG][PcShape<B, T>::NV4];
+
+// the inverse entries of round g0 of this thread's block row
+template <int B, typename T>
+__device__ inline void pc_load(const float* pcM, unsigned row0, unsigned grpb, int G, int g0,
+                               PcRound<B, T>& mv) {
+    using Sh = PcShape<B, T>;
+#pragma unroll
+    for (int q = 0; q < Sh::QG; q++) {
+        const int gq = min(g0 + q, G - 1);
+#pragma unroll
+        for (int v = 0; v < Sh::NV4; v++) mv[q][v] = ldg<f4v>(pcM, row0 + (unsigned)gq * grpb + 16u * v);
+    }
+}
+
+// first round of the row with layout words (info, off), if it is in a
+// multi-row block (called with the row's tile pass current)
+template <int B, typename T>
+__device__ inline void pc_first(const KrylovBufs& kb, int info, int off, PcRound<B, T>& pm) {
+    using Sh = PcShape<B, T>;
+    if constexpr (Sh::PRE) {
+        const int size = info & 0xffff;
+        if (size > 1) {
+            const int bs = info >> 16, N = size * B;
+            const unsigned row0 = (unsigned)(off + ((int)threadIdx.x - bs) * Sh::W) * 4u;
+            pc_load<B, T>(kb.pcM, row0, (unsigned)(size * Sh::W) * 4u, (N + Sh::K - 1) / Sh::K, 0,
+                          pm);
+        }
+    }
+}
+
 template <int B, typename T>
 __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off,
-                               double (&y)[B]) {
+                               double (&y)[B], const PcRound<B, T>& pm) {
+    using Sh = PcShape<B, T>;
+    constexpr int K = Sh::K, W = Sh::W, QG = Sh::QG;
     __shared__ T yb[KB_NT * B];
-    constexpr int K = pc_group_cols(B), W = B * K, NV4 = W / 4;
-    constexpr int QG = (B == 3 && sizeof(T) == 8) ? 2 : 16 / K;   // column groups per round
     const int t = threadIdx.x;
     const bool blk = act && (info & 0xffff) > 1;
     if (!__syncthreads_or(blk)) return;
@@ -233,16 +274,11 @@ __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off
         double acc[B];
 #pragma unroll
         for (int c = 0; c < B; c++) acc[c] = 0.0;
-#pragma unroll 1
-        for (int g0 = 0; g0 < G; g0 += QG) {
-            f4v mv[QG][NV4];
+        auto round = [&](int g0, const PcRound<B, T>& mv) {
             T ys[QG][K];
 #pragma unroll
             for (int q = 0; q < QG; q++) {
                 const int gq = min(g0 + q, G - 1);
-#pragma unroll
-                for (int v = 0; v < NV4; v++)
-                    mv[q][v] = ldg<f4v>(kb.pcM, row0 + (unsigned)gq * grpb + 16u * v);
 #pragma unroll
                 for (int k = 0; k < K; k++) ys[q][k] = yv[min(gq * K + k, N - 1)];
             }
@@ -259,6 +295,17 @@ __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off
                     }
                 }
             }
+        };
+        int g0 = 0;
+        if constexpr (Sh::PRE) {
+            round(0, pm);
+            g0 = QG;
+        }
+#pragma unroll 1
+        for (; g0 < G; g0 += QG) {
+            PcRound<B, T> mv;
+            pc_load<B, T>(kb.pcM, row0, grpb, G, g0, mv);
+            round(g0, mv);
         }
 #pragma unroll
         for (int c = 0; c < B; c++) y[c] = acc[c];
@@ -334,7 +381,9 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
                 poff = kb.pcoff[r];
             }
         }
-        if (pc) pc_rows<B, double>(kb, act, pinfo, poff, bt);
+        PcRound<B, double> pm;
+        if (pc && act) pc_first<B, double>(kb, pinfo, poff, pm);
+        if (pc) pc_rows<B, double>(kb, act, pinfo, poff, bt, pm);
         if (act) {
 #pragma unroll
             for (int c = 0; c < B; c++) {
@@ -483,6 +532,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const 
         double vi[B];
 #pragma unroll
         for (int c = 0; c < B; c++) vi[c] = 0.0;
+        PcRound<B, T> pm;   // first round of the row's inverse entries
         if (act) {
             T ri[B];
             if constexpr (FIRST) {
@@ -501,6 +551,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const 
                 stv<B, T>(V.r, ro, ri);
             }
             if (!stop) {
+                if (pc) pc_first<B, T>(S.kb, pinfo, poff, pm);
                 double pi[B];
                 fx(own, pi);
 #pragma unroll
@@ -519,7 +570,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const 
             if (act && r + stride < nA) fetch(r + stride);
             continue;
         }
-        if (pc) pc_rows<B, T>(S.kb, act, pinfo, poff, vi);   // v = M^{-1} A~ p
+        if (pc) pc_rows<B, T>(S.kb, act, pinfo, poff, vi, pm);   // v = M^{-1} A~ p
         if (act) {
             T vT[B];
 #pragma unroll
@@ -635,7 +686,9 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const 
             ti[c] = 0.0;
             sT[c] = (T)0;
         }
+        PcRound<B, T> pm;   // first round of the row's inverse entries
         if (act) {
+            if (pc) pc_first<B, T>(S.kb, pinfo, poff, pm);
             double si[B];
             fx(own, si);
 #pragma unroll
@@ -648,7 +701,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const 
             }
             stv<B, T>(V.s, ro, sT);
         }
-        if (pc) pc_rows<B, T>(S.kb, act, pinfo, poff, ti);   // t = M^{-1} A~ s
+        if (pc) pc_rows<B, T>(S.kb, act, pinfo, poff, ti, pm);   // t = M^{-1} A~ s
         if (act) {
             T tT[B];
 #pragma unroll
