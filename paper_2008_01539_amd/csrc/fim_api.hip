@@ -439,7 +439,15 @@ static const SegStatus& status_of(SolveTable& t, Group* G, int g, int pos) {
 // FP32; a model whose pass fails to cut its FP64 residual norm by at least
 // 10 % (stagnation or breakdown on a badly conditioned fracture subsystem)
 // has the pass undone and continues with the FP64 Krylov.
-static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStream_t s) {
+// prepped: each model's block-Jacobi scaling (k_precond) and zero initial
+// guess were already queued on its own stream (batched steps)
+static void solve_prep(fim_model* m, hipStream_t s) {
+    launch_precond(m->B, m->o.precision == FIM_MIXED, m->nA, lsys(m), m->dinv, m->At, s);
+    launch_fill_f64(m->x64, (long)m->nA * m->B, 0.0, s);
+}
+
+static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStream_t s,
+                              bool prepped = false) {
     fim_model* lead = ms[0];
     fim_model* m = lead;
     const int K = (int)ms.size();
@@ -449,16 +457,18 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         fim_model* mq = ms[q];
         SolveItem& it = items[q];
         it = SolveItem{mq, mq->o.precision == FIM_MIXED, false, true, 0, 0, 0, 0, 0, 0, 0, 0};
-        const int pi = pbeg(lead, PK_PRECOND);
-        launch_precond(mq->B, it.fp32, mq->nA, lsys(mq), mq->dinv, mq->At, s);
-        pend(lead, pi, mq->nA);
+        if (!prepped) {
+            const int pi = pbeg(lead, PK_PRECOND);
+            launch_precond(mq->B, it.fp32, mq->nA, lsys(mq), mq->dinv, mq->At, s);
+            pend(lead, pi, mq->nA);
+        }
         if (mq->use_pc && K == 1) {
             const int pv = pbeg(lead, PK_PCINV);
             launch_pc_invert(mq->B, it.fp32, mq->pc_inv_grid, lsys(mq), mq->At, mq->pclist,
                              &mq->dint[6], mq->pcoff, mq->pcM, s);
             pend(lead, pv, mq->nA);
         }
-        launch_fill_f64(mq->x64, (long)mq->nA * mq->B, 0.0, s);
+        if (!prepped) launch_fill_f64(mq->x64, (long)mq->nA * mq->B, 0.0, s);
         G[it.fp32 ? 0 : 1].idx.push_back(q);
     }
     if (K > 1) {
@@ -1732,6 +1742,7 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
             }
         }
         newton_assemble(m);
+        solve_prep(m, m->s);
         live.push_back(m);
         pos.push_back(q);
     }
@@ -1742,7 +1753,7 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
             return FIM_E_HIP;
         }
         for (fim_model* m : live) m->s = b->s;
-        fim_status r = solve_batch(live, b->tab, b->s);
+        fim_status r = solve_batch(live, b->tab, b->s, true);
         if (r != FIM_OK) {
             b->err = live[0]->err;
             restore();
