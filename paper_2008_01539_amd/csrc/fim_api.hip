@@ -84,6 +84,7 @@ struct fim_model {
     int8_t *st = nullptr, *stn = nullptr;
     uint8_t *act = nullptr, *act2 = nullptr, *supp = nullptr, *bnd = nullptr, *vt = nullptr,
             *outer = nullptr;
+    uint8_t* lvl = nullptr;         // neighbourhood marking: distance to the nearest seed
     // local system
     int *l2g = nullptr, *g2l = nullptr, *swidth = nullptr, *blk = nullptr;
     int *col = nullptr;
@@ -823,7 +824,7 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
         HIPX(hipMemcpyAsync(m->act, m->supp, m->n, hipMemcpyDeviceToDevice, m->s));
     } else {
         launch_fill_u8(m->act, m->n, 0, m->s);
-        launch_mark_seeds(m->n, m->g, layers, m->act, m->s);
+        launch_mark_seeds(m->n, m->g, layers, m->act, m->lvl, m->s);
     }
     if (mode == FIM_DD) {
         launch_fill_f64(m->last_dp, m->n, 0.0, m->s);
@@ -956,7 +957,7 @@ static void free_all(fim_model* m) {
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
                     m->part_ir, m->classes, m->frac_id, m->ford, m->pcinfo, m->pcoff,
-                    m->pcM, m->pclist};
+                    m->pcM, m->pclist, m->lvl};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (m->hsc) (void)hipHostFree(m->hsc);
@@ -1159,6 +1160,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(dal(m, &m->stn, nn));
     CK(dal(m, &m->act, nn));
     CK(dal(m, &m->act2, nn));
+    CK(dal(m, &m->lvl, nn));
     CK(dal(m, &m->supp, nn));
     CK(dal(m, &m->bnd, nn));
     CK(dal(m, &m->vt, nn));
@@ -1303,7 +1305,7 @@ static fim_status newton_post_launch(fim_model* m) {
         const int pi = pbeg(m, PK_SETS);
         launch_fill_i32(m->dint, 1, 0, m->s);
         launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, m->o.eps_loc, m->o.m_layers, m->g,
-                           m->act, nullptr, m->dint, m->s);
+                           m->act, nullptr, m->dint, m->lvl, m->s);
         launch_shrink(m->nA, m->l2g, m->dp_abs, m->o.eps_loc, m->g, m->act, m->dint, m->s);
         compact(m);
         pend(m, pi, m->n);
@@ -1381,7 +1383,7 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
         launch_fill_u8(m->act2, m->n, 0, m->s);
         launch_fill_i32(m->dint, 1, 0, m->s);
         launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, m->o.eps_loc, m->o.m_layers_dd,
-                           m->g, m->vt, m->act2, m->dint, m->s);
+                           m->g, m->vt, m->act2, m->dint, m->lvl, m->s);
         HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
         TRY(read_int(m));
         m->nu++;
@@ -1530,7 +1532,7 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     b += (n + 1) * 4 + nc2 * 12;                  // adjacency
     b += n * (8 * 4 + 1);                         // pv, depth, wi, bhp, flags
     b += n * B * 8 * 3 + n * 8 * 2 + n * 2;       // u, un, Mn, dp_abs, last_dp, status
-    b += n * 6;                                   // byte flags
+    b += n * 7;                                   // byte flags, marking levels
     b += n * 4 * 4 + nsl * 4;                     // l2g, g2l (2n each), swidth
     b += slots * (4 + B * B * 8 + B * B * 8);     // col, J, A~ (sized for FP64)
     b += n * B * (8 + B * 8);                     // F, dinv
@@ -1933,7 +1935,7 @@ fim_status fim_inspect_sets(fim_model* m, const uint8_t* act_in, const double* d
     TRY(prepare_active(m, true));
     launch_fill_i32(m->dint, 1, 0, m->s);
     launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, eps, layers, m->g, m->act, nullptr,
-                       m->dint, m->s);
+                       m->dint, m->lvl, m->s);
     launch_shrink(m->nA, m->l2g, m->dp_abs, eps, m->g, m->act, m->dint, m->s);
     TRY(read_int(m));
     *is_expand = m->hint[0] != 0;

@@ -102,14 +102,15 @@ void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
                       int* swidth, int* nnzb, hipStream_t s);
 void launch_boundary(int nA, const int* l2g, const int* g2l, const Graph& g,
                      uint8_t* bnd, int* count, hipStream_t s);
+// lvl: n bytes of scratch (graph distance to the nearest seed)
 void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
                         const double* dp_abs, double eps, int m,
                         const Graph& g, uint8_t* act, uint8_t* act2,
-                        int* flag, hipStream_t s);
+                        int* flag, uint8_t* lvl, hipStream_t s);
 void launch_shrink(int nA, const int* l2g, const double* dp_abs, double eps,
                    const Graph& g, uint8_t* act, const int* flag,
                    hipStream_t s);
-void launch_mark_seeds(int n, const Graph& g, int m, uint8_t* act,
+void launch_mark_seeds(int n, const Graph& g, int m, uint8_t* act, uint8_t* lvl,
                        hipStream_t s);
 void launch_support(int n, const double* p, const double* pn, double eps,
                     const Graph& g, uint8_t* act, hipStream_t s);

@@ -162,46 +162,50 @@ void launch_boundary(int nA, const int* l2g, const int* g2l, const Graph& g,
 }
 
 // ------------------------------------------------- neighbourhood marking
-// Marks V_nbr^{i,m}: every cell reachable by a path of length <= m.
-__device__ inline void mark_ball(int i, int m, const Graph& g, uint8_t* act,
-                                 uint8_t* act2) {
-    int node[MAX_LAYERS + 1];
-    int pos[MAX_LAYERS + 1];
-    act[i] = 1;
-    if (act2) act2[i] = 1;
-    if (m <= 0) return;
-    int d = 0;
-    node[0] = i;
-    pos[0] = g.adj_ptr[i];
-    while (d >= 0) {
-        const int c = node[d];
-        if (pos[d] >= g.adj_ptr[c + 1]) { d--; continue; }
-        const int j = g.adj_nbr[pos[d]++];
-        act[j] = 1;
-        if (act2) act2[j] = 1;
-        if (d + 1 < m) {
-            d++;
-            node[d] = j;
-            pos[d] = g.adj_ptr[j];
+// V_nbr^{i,m} of a set of seed cells: every cell within graph distance m
+// of a seed.  Level-synchronous: lvl[n] holds the distance found so far
+// (0xff: none); pass k marks the unmarked neighbours of the cells at
+// distance k - 1.  A cell can be written by several threads in one pass,
+// always with the same value k, and a cell at distance k - 1 is never
+// rewritten in pass k, so the result is the same in any order.
+__global__ __launch_bounds__(NT) void k_ball_step(int n, Graph g, int k,
+                                                  uint8_t* __restrict__ lvl, uint8_t* act,
+                                                  uint8_t* act2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || lvl[i] != k - 1) return;
+    const int e = g.adj_ptr[i + 1];
+    for (int p = g.adj_ptr[i]; p < e; p++) {
+        const int j = g.adj_nbr[p];
+        if (lvl[j] > k) {
+            lvl[j] = (uint8_t)k;
+            act[j] = 1;
+            if (act2) act2[j] = 1;
         }
     }
 }
 
-// Algorithm 1/2 expansion: for i in V_B with |dp_i| >= eps, V_A (and the
-// optional second set) grows by V_nbr^{i,m}; *flag = 1 if any did.
-__global__ __launch_bounds__(NT) void k_mark_expand(int nA, const int* __restrict__ l2g,
-                                                    const uint8_t* __restrict__ bnd,
-                                                    const double* __restrict__ dp_abs,
-                                                    double eps, int m, Graph g,
-                                                    uint8_t* act, uint8_t* act2,
-                                                    int* flag) {
+static void ball_steps(int n, const Graph& g, int m, uint8_t* lvl, uint8_t* act, uint8_t* act2,
+                       hipStream_t s) {
+    for (int k = 1; k <= m; k++)
+        k_ball_step<<<nblocks(n), NT, 0, s>>>(n, g, k, lvl, act, act2);
+}
+
+// Algorithm 1/2 expansion seeds: i in V_B with |dp_i| >= eps (level 0,
+// marked in V_A and the optional second set); *flag = 1 if any
+__global__ __launch_bounds__(NT) void k_expand_seeds(int nA, const int* __restrict__ l2g,
+                                                     const uint8_t* __restrict__ bnd,
+                                                     const double* __restrict__ dp_abs,
+                                                     double eps, uint8_t* __restrict__ lvl,
+                                                     uint8_t* act, uint8_t* act2, int* flag) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     int hit = 0;
     if (r < nA) {
         const int i = l2g[r];
         if (bnd[i] && dp_abs[i] >= eps) {
             hit = 1;
-            mark_ball(i, m, g, act, act2);
+            lvl[i] = 0;
+            act[i] = 1;
+            if (act2) act2[i] = 1;
         }
     }
     hit = block_sum_i(hit);
@@ -211,11 +215,11 @@ __global__ __launch_bounds__(NT) void k_mark_expand(int nA, const int* __restric
 void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
                         const double* dp_abs, double eps, int m,
                         const Graph& g, uint8_t* act, uint8_t* act2,
-                        int* flag, hipStream_t s) {
-    if (nA > 0)
-        k_mark_expand<<<nblocks(nA), NT, 0, s>>>(nA, l2g, bnd, dp_abs, eps,
-                                                 m < MAX_LAYERS ? m : MAX_LAYERS,
-                                                 g, act, act2, flag);
+                        int* flag, uint8_t* lvl, hipStream_t s) {
+    if (nA <= 0) return;
+    launch_fill_u8(lvl, g.n, 0xff, s);
+    k_expand_seeds<<<nblocks(nA), NT, 0, s>>>(nA, l2g, bnd, dp_abs, eps, lvl, act, act2, flag);
+    ball_steps(g.n, g, m < MAX_LAYERS ? m : MAX_LAYERS, lvl, act, act2, s);
 }
 
 // Algorithm 1 shrink (only when no boundary update was non-negligible):
@@ -238,13 +242,20 @@ void launch_shrink(int nA, const int* l2g, const double* dp_abs, double eps,
 
 // First-step initial set: the always-active cells and their m-layer
 // neighbourhood (act must be cleared before).
-__global__ __launch_bounds__(NT) void k_mark_seeds(int n, Graph g, int m, uint8_t* act) {
+__global__ __launch_bounds__(NT) void k_mark_seeds(int n, Graph g, uint8_t* __restrict__ lvl,
+                                                   uint8_t* act) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && (g.flags[i] & CF_AA)) mark_ball(i, m, g, act, nullptr);
+    if (i >= n) return;
+    const bool seed = (g.flags[i] & CF_AA) != 0;
+    lvl[i] = seed ? 0 : 0xff;
+    if (seed) act[i] = 1;
 }
 
-void launch_mark_seeds(int n, const Graph& g, int m, uint8_t* act, hipStream_t s) {
-    if (n > 0) k_mark_seeds<<<nblocks(n), NT, 0, s>>>(n, g, m < MAX_LAYERS ? m : MAX_LAYERS, act);
+void launch_mark_seeds(int n, const Graph& g, int m, uint8_t* act, uint8_t* lvl,
+                       hipStream_t s) {
+    if (n <= 0) return;
+    k_mark_seeds<<<nblocks(n), NT, 0, s>>>(n, g, lvl, act);
+    ball_steps(n, g, m < MAX_LAYERS ? m : MAX_LAYERS, lvl, act, nullptr, s);
 }
 
 // Later steps: the support of the previous timestep plus the always-active
@@ -361,16 +372,27 @@ struct SubTab {
     int on[MAX_SUBS];
 };
 
+// SUB_WG workgroups per subdomain; the values are >= 0, so their IEEE bit
+// patterns order like the values and an integer atomic max combines the
+// workgroups' maxima (order-independent).
+constexpr int SUB_WG = 64;
+
+__global__ void k_zero_f64(double* out, int n) {
+    if ((int)threadIdx.x < n) out[threadIdx.x] = 0.0;
+}
+
 __global__ __launch_bounds__(NT) void k_sub_max(SubTab t, const int* __restrict__ cells,
                                                 const int* __restrict__ outer,
                                                 const double* __restrict__ last_dp,
                                                 double* __restrict__ out) {
-    const int k = blockIdx.x;
+    const int k = blockIdx.x / SUB_WG, w = blockIdx.x % SUB_WG;
+    const int step = SUB_WG * NT, q0 = w * NT + threadIdx.x;
     double m[1] = {0.0};
-    for (int q = threadIdx.x; q < t.cn[k]; q += NT) m[0] = fmax(m[0], last_dp[cells[t.co[k] + q]]);
-    for (int q = threadIdx.x; q < t.on[k]; q += NT) m[0] = fmax(m[0], last_dp[outer[t.oo[k] + q]]);
+    for (int q = q0; q < t.cn[k]; q += step) m[0] = fmax(m[0], last_dp[cells[t.co[k] + q]]);
+    for (int q = q0; q < t.on[k]; q += step) m[0] = fmax(m[0], last_dp[outer[t.oo[k] + q]]);
     block_max<1>(m);
-    if (threadIdx.x == 0) out[k] = m[0];
+    if (threadIdx.x == 0 && m[0] > 0.0)
+        atomicMax((unsigned long long*)&out[k], (unsigned long long)__double_as_longlong(m[0]));
 }
 
 void launch_sub_max(int N, const DDSub* subs, const int* cells, const int* outer,
@@ -383,7 +405,9 @@ void launch_sub_max(int N, const DDSub* subs, const int* cells, const int* outer
         t.oo[k] = subs[k].outer_off;
         t.on[k] = subs[k].outer_n;
     }
-    k_sub_max<<<N < MAX_SUBS ? N : MAX_SUBS, NT, 0, s>>>(t, cells, outer, last_dp, out);
+    const int nk = N < MAX_SUBS ? N : MAX_SUBS;
+    k_zero_f64<<<1, MAX_SUBS, 0, s>>>(out, nk);
+    k_sub_max<<<nk * SUB_WG, NT, 0, s>>>(t, cells, outer, last_dp, out);
 }
 
 } // namespace fimk

@@ -73,7 +73,9 @@ def test_linear_solve_matches_direct_solve(c1, fm_c1, oracle_c1):
     assert np.abs(x - ref).max() <= 1e-8 * np.abs(ref).max()
 
 
-def test_sets_match_reference_bitwise(c1, fm_c1):
+@pytest.mark.parametrize("layers", [1, 2, 4])
+def test_sets_match_reference_bitwise(c1, fm_c1, layers):
+    """m = 2 is Algorithm 1's neighbourhood, m = 4 Algorithm 2's."""
     rp, nb = adjacency(c1)
     rng = np.random.default_rng(5)
     aa = np.nonzero(c1.always_active)[0]
@@ -87,10 +89,10 @@ def test_sets_match_reference_bitwise(c1, fm_c1):
         idx = np.fromiter(act0, np.int64)
         dp[idx] = rng.exponential(1.0, idx.size) * (0.3 * PSI) * (0.5 if trial % 2 else 2.0)
         eps = 0.3 * PSI
-        ref_act, ref_bnd, ref_ex = S.alg1_update(rp, nb, act0, bnd0, dp, eps, 2, aa)
+        ref_act, ref_bnd, ref_ex = S.alg1_update(rp, nb, act0, bnd0, dp, eps, layers, aa)
         a = np.zeros(c1.n, np.uint8)
         a[idx] = 1
-        g = fm_c1.inspect_sets(a, dp, eps, 2)
+        g = fm_c1.inspect_sets(a, dp, eps, layers)
         assert g["is_expand"] == ref_ex
         assert set(np.nonzero(g["act"])[0].tolist()) == ref_act
         assert set(np.nonzero(g["bnd"])[0].tolist()) == ref_bnd
