@@ -351,18 +351,38 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
 #pragma unroll
             for (int c = 0; c < B; c++) res[c] = -ls.F[(long)r * B + c];
             if (!x_zero) {
+                // UR slots at a time: their column indices in one round of
+                // loads, then their FP64 blocks and x64 gathers in the next
+                // (slots past the width read the row itself, weight 0); the
+                // slots are summed in order, as one at a time would
+                constexpr int UR = B == 3 ? 4 : 8;
                 const long base = slot_of(ls, r, 0);
                 const int width = ls.swidth[r / SLICE];
-                for (int k = 0; k < width; k++) {
-                    const long pos = base + (long)k * SLICE;
-                    const int cl = ls.col[pos];
-                    const double* a = ls.J + pos * BB;
+                for (int k0 = 0; k0 < width; k0 += UR) {
+                    int cl[UR];
 #pragma unroll
-                    for (int c = 0; c < B; c++) {
-                        double acc = 0.0;
+                    for (int u = 0; u < UR; u++)
+                        cl[u] = k0 + u < width ? ls.col[base + (long)(k0 + u) * SLICE] : r;
+                    double a[UR][BB], xv[UR][B];
 #pragma unroll
-                        for (int v = 0; v < B; v++) acc += a[c * B + v] * kb.x64[(long)cl * B + v];
-                        res[c] -= acc;
+                    for (int u = 0; u < UR; u++) {
+                        const bool in = k0 + u < width;
+                        const long pos = base + (long)min(k0 + u, width - 1) * SLICE;
+#pragma unroll
+                        for (int q = 0; q < BB; q++) a[u][q] = in ? ls.J[pos * BB + q] : 0.0;
+#pragma unroll
+                        for (int v = 0; v < B; v++) xv[u][v] = kb.x64[(long)cl[u] * B + v];
+                    }
+#pragma unroll
+                    for (int u = 0; u < UR; u++) {
+                        if (k0 + u >= width) break;
+#pragma unroll
+                        for (int c = 0; c < B; c++) {
+                            double acc = 0.0;
+#pragma unroll
+                            for (int v = 0; v < B; v++) acc += a[u][c * B + v] * xv[u][v];
+                            res[c] -= acc;
+                        }
                     }
                 }
             }
