@@ -16,9 +16,12 @@ reservoirs", that it follows):
                  distance-2 colouring;
 * ``newton``   : the Newton method of Section 4.1 with a direct sparse LU
                  solve (SuperLU), timestep commit / rollback;
-* ``sets``     : the set logic of Algorithms 1 and 2 with Python sets;
-* ``localized``: Algorithm 1 (localized Newton) and Algorithm 2 (adaptive
-                 nonlinear domain decomposition) built from the pieces above.
+* ``sets``     : the set logic of Algorithms 1 and 2 and of the
+                 residual-based estimate with Python sets;
+* ``localized``: Algorithm 1 (localized Newton), Algorithm 2 (adaptive
+                 nonlinear domain decomposition) and the residual-based
+                 localization of Sections 1 and 4.2, built from the pieces
+                 above.
 
 Readings where the paper is silent are listed in each module header.
 """

@@ -1,5 +1,7 @@
-"""Algorithm 1 (localized Newton) and Algorithm 2 (adaptive nonlinear
-domain decomposition), oracle versions (test infrastructure only).
+"""Algorithm 1 (localized Newton), Algorithm 2 (adaptive nonlinear
+domain decomposition) and the residual-based localization the paper
+compares against (Sections 1 and 4.2), oracle versions (test
+infrastructure only).
 
 Each local solve is the restricted Newton step of Section 4.3,
 J_A du_A = -F_A with J_A = R_A J R_A^T: the full residual and Jacobian are
@@ -17,7 +19,17 @@ Readings where the paper is silent (shared with the HIP library):
 * Algorithm 2: each visit of a subdomain is one Newton iteration on it;
   last_dp[i] holds |dp_i| from the latest solve that touched cell i; a
   subdomain is skipped when last_dp < eps on V_A^k and on its outer layer;
-  the sweeps stop when no subdomain would be solved.
+  the sweeps stop when no subdomain would be solved;
+* residual-based localization (Lu and Beckner, as Sections 1 and 4.2
+  describe it: the first iteration of a timestep takes the whole domain,
+  later ones the unconverged cells plus one layer of neighbours): a cell is
+  unconverged when its error measure
+      e_i = dt max_c |R_{i,c}| / (V_i rho_c)
+  is at or above eps_res, with R the residual at the current iterate (kg/s),
+  V_i the reference pore volume and rho_c the reference density of
+  component c (the mass imbalance over the step as a fraction of the pore
+  volume filled with that component); the timestep ends when the update
+  meets the usual convergence test or when no cell is unconverged.
 """
 from __future__ import annotations
 
@@ -25,8 +37,26 @@ import numpy as np
 
 from .jacobian import adjacency
 from .newton import Options, Solver, State, converged
-from .physics import accumulation
+from .physics import accumulation, residual
 from . import sets
+
+
+def reference_densities(fluid):
+    """rho_c of the error measure, in component order (single phase;
+    water, oil; water, oil, gas)."""
+    k = fluid["kind"]
+    if k == 1:
+        return np.array([fluid["rho_ref"]])
+    if k == 2:
+        return np.array([fluid["rho_w"], fluid["rho_o"]])
+    return np.array([fluid["rho_wsc"], fluid["rho_osc"], fluid["rho_gsc"]])
+
+
+def resid_error(model, u, status, m_old, dt):
+    """e_i = dt max_c |R_{i,c}| / (V_i rho_c) at state u (n,)."""
+    R = residual(model, u, status, m_old, dt)
+    scale = model.pv_ref[None, :] * reference_densities(model.fluid)[:, None]
+    return dt * np.max(np.abs(R) / scale, axis=0)
 
 
 class LocalSolver(Solver):
@@ -116,10 +146,33 @@ class LocalSolver(Solver):
         support = set(np.nonzero(np.abs(work.u[0] - st.u[0]) >= o.eps_loc)[0].tolist())
         return work, inner, support
 
+    # ------------------------------------ residual-based (Lu and Beckner)
+    def resid_timestep(self, st: State, dt, prev_support=None, log=None):
+        o = self.opts
+        m_old = accumulation(self.model, st.u, st.status)
+        work = st.copy()
+        act = None                              # first iteration: all cells
+        for it in range(1, o.max_newton + 1):
+            n_a = self.model.n if act is None else len(act)
+            dp, ds, nsw = self.newton_iteration(work, m_old, dt, active=act)
+            if not np.all(np.isfinite(work.u)):
+                return None, it, None
+            if log is not None:
+                log.append(dict(n_a=n_a, dp=float(dp.max())))
+            if converged(o, float(dp.max()), ds, nsw):
+                return work, it, None
+            err = resid_error(self.model, work.u, work.status, m_old, dt)
+            act = sets.resid_active(self.rp, self.nb, err, o.eps_res, o.res_layers)
+            if not act:
+                return work, it, None
+        return None, o.max_newton, None
+
     # ------------------------------------------------------ schedules
     def run_local(self, st: State, schedule, alg=1, log=None):
-        """Run a schedule with Algorithm 1 or 2, halving dt on failure."""
-        step = self.alg1_timestep if alg == 1 else self.alg2_timestep
+        """Run a schedule with Algorithm 1 or 2 (alg=3: the residual-based
+        localization), halving dt on failure."""
+        step = {1: self.alg1_timestep, 2: self.alg2_timestep,
+                3: self.resid_timestep}[alg]
         prev = None
         recs = []
         for dt in schedule:

@@ -44,6 +44,8 @@ class Options:
     ds_max: float = 0.2
     max_cuts: int = 8
     max_sweeps: int = 40             # Alg. 2 outer iterations cap
+    eps_res: float = 1e-6            # residual-based localization cutoff
+    res_layers: int = 1              # its neighbour inflation
 
     @staticmethod
     def tight_mode(**kw):

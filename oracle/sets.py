@@ -12,7 +12,10 @@ Definitions (Section 4.3):
 * a cell's update is non-negligible when |dp_i| >= eps (the cutoff is a
   pressure quantity in Section 5);
 * the outer layer dB of a set (Section 4.4, Step 1): the cells outside the
-  set adjacent to it.
+  set adjacent to it;
+* the residual-based estimate that Sections 1 and 4.2 attribute to Lu and
+  Beckner: the unconverged cells (error measure at or above a tolerance)
+  inflated by a fixed number of neighbour layers, one by default.
 
 Everything here is the plain definition over Python sets; nothing is
 vectorized.
@@ -105,3 +108,14 @@ def alg2_expand(rp, nb, vt, bnd_k, dp_abs, eps, m):
         return set(), vt, set(), set(), False
     vb_t = boundary(rp, nb, vt)
     return nxt, vt, vb_t & nxt, outer_layer(rp, nb, nxt), True
+
+
+def resid_active(rp, nb, err, tol, layers):
+    """Residual-based active set (Sections 1 and 4.2, the estimator of Lu
+    and Beckner): every cell with err_i >= tol, inflated by its
+    ``layers``-layer neighbourhood."""
+    out = set()
+    for i in range(len(err)):
+        if err[i] >= tol:
+            out |= ball(rp, nb, i, layers)
+    return out
