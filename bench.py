@@ -410,6 +410,7 @@ def main():
         log(f"local (events): wall {prof_run['wall']:.3f}s")
     full = None
     dd = None
+    res = None
     if not args.no_full:
         log("full Newton on the same steps")
         full = run_gpu(model, opts, P.FULL, args.steps, args.warmup)
@@ -419,6 +420,10 @@ def main():
         dd = run_gpu(model, opts, P.DD, args.steps, args.warmup)
         log(f"dd: {dd['iters']} inner iterations, wall {dd['wall']:.3f}s, "
             f"krylov {dd['krylov']}")
+        log("residual-based localization (the prior method) on the same steps")
+        res = run_gpu(model, opts, P.RESID, args.steps, args.warmup)
+        log(f"resid: {res['iters']} iterations, wall {res['wall']:.3f}s, "
+            f"krylov {res['krylov']}")
     value = loc["active"] / loc["wall"]
     out = {
         "metric": "active-cell Newton updates/s, local vs full Newton (1 GPU); "
@@ -466,6 +471,16 @@ def main():
                      "newton_step_ms_p99": dd["p99"],
                      "speedup_vs_full": full["wall"] / dd["wall"],
                      "max_dp_vs_full_psi": float(np.abs(full["u"][0] - dd["u"][0]).max()) / PSI}
+    if res is not None:
+        out["resid"] = {"iterations": res["iters"], "sum_active": res["active"],
+                        "avg_ma": res["active"] / model.n / res["iters"],
+                        "updates_per_s": res["active"] / res["wall"],
+                        "krylov_iters": res["krylov"], "wall_s": res["wall"],
+                        "newton_step_ms_p50": res["p50"], "newton_step_ms_p99": res["p99"],
+                        "speedup_vs_full": full["wall"] / res["wall"],
+                        "local_speedup_vs_resid": res["wall"] / loc["wall"],
+                        "max_dp_vs_full_psi":
+                            float(np.abs(full["u"][0] - res["u"][0]).max()) / PSI}
     # roofline of the dominant matrix kernel (local run, events on its stream)
     prof = prof_run["prof"] if prof_run else None
     if prof:

@@ -45,7 +45,15 @@ typedef enum fim_status {
     FIM_E_NONFINITE = -5     /* non-finite input                          */
 } fim_status;
 
-enum { FIM_FULL = 0, FIM_LOCAL = 1, FIM_DD = 2 };          /* solver mode */
+/* Solver modes.  FIM_RESID is the residual-based localization that
+ * Sections 1 and 4.2 describe as the prior method (Lu and Beckner): the
+ * first iteration of a timestep takes every cell, each later one the cells
+ * whose residual error measure e_i = dt max_c |R_{i,c}| / (V_i rho_c)
+ * (V_i the reference pore volume, rho_c the reference density of component
+ * c: rho_ref; rho_w, rho_o; rho_wsc, rho_osc, rho_gsc) is at least eps_res,
+ * inflated by res_layers neighbour layers.  Its step ends when the update
+ * meets the convergence test or no cell is at or above eps_res. */
+enum { FIM_FULL = 0, FIM_LOCAL = 1, FIM_DD = 2, FIM_RESID = 3 };
 enum { FIM_FP64 = 0, FIM_MIXED = 1 };                     /* Krylov precision */
 enum { FIM_HOST = 0, FIM_DEVICE = 1 };                    /* pointer kind */
 enum { FIM_FLUID_SINGLE = 1, FIM_FLUID_DEADOIL = 2, FIM_FLUID_BLACKOIL = 3 };
@@ -127,6 +135,10 @@ typedef struct fim_options {
     int32_t check_every;     /* BiCGStab iterations between host checks        */
     int32_t precond;         /* FIM_PC_JACOBI or FIM_PC_FRACTURE (default;
                                 Jacobi when the model has no frac_id)          */
+    double  eps_res;         /* FIM_RESID: unconverged when e_i >= eps_res
+                                (default 1e-6)                                 */
+    int32_t res_layers;      /* FIM_RESID: neighbour layers added (default 1,
+                                at most 8)                                     */
 } fim_options;
 
 typedef struct fim_iter_stats {
@@ -181,7 +193,8 @@ fim_status fim_set_state(fim_model* m, const double* u, const int8_t* status, in
 fim_status fim_get_state(fim_model* m, double* u_out, int8_t* status_out, int mem);
 
 /* One Newton iteration (Algorithm 1 in FIM_LOCAL, the standard iteration
- * in FIM_FULL, one subdomain solve of Algorithm 2 in FIM_DD).  The first
+ * in FIM_FULL, one subdomain solve of Algorithm 2 in FIM_DD, one
+ * residual-localized iteration in FIM_RESID).  The first
  * call of a timestep stores u^n and the initial active set.  When the
  * stopping test of the algorithm holds the step is committed and
  * st->converged = 1.  Calling with a different dt or mode inside a step
@@ -305,6 +318,24 @@ fim_status fim_inspect_sets(fim_model* m, const uint8_t* act_in,
                             uint8_t* act_out, uint8_t* bnd_out,
                             int32_t* l2g_out, int32_t* n_active,
                             int32_t* is_expand);
+
+/* The error measure of FIM_RESID (see the solver modes) at state u_iter
+ * with old-time state u_old and step dt, on every cell: err_out (host,
+ * [n]).  status may be NULL (all 0).  Ends any timestep in progress and
+ * leaves u_iter as the current state. */
+fim_status fim_inspect_resid_error(fim_model* m, const double* u_old,
+                                   const double* u_iter, const int8_t* status,
+                                   double dt, double* err_out);
+
+/* The FIM_RESID active set from a given error array err (host, [n]): the
+ * cells with err_i >= tol and their layers-layer neighbourhood (layers in
+ * [0, 8], else FIM_E_ARG).  Writes act_out (host u8[n]), l2g_out (host
+ * i32[n]; first *n_active entries, ascending) and *n_unconverged (cells
+ * with err_i >= tol).  Ends any timestep in progress. */
+fim_status fim_inspect_resid_sets(fim_model* m, const double* err, double tol,
+                                  int32_t layers, uint8_t* act_out,
+                                  int32_t* l2g_out, int32_t* n_active,
+                                  int32_t* n_unconverged);
 
 /* Solves J_A x = -F_A for the system of the last fim_inspect_assemble with
  * the library's Krylov solver (precision as in the options); x (host,

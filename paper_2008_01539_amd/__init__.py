@@ -8,10 +8,10 @@ Also: ``FimBatch`` (several models per batched call), ``serve`` (the
 continuous-batching serving loop), ``trace`` (per-iteration JSONL log).
 """
 from .fim import (DD, DEVICE, FP64, FULL, HOST, LIB_PATH, LOCAL, MIXED, PC_FRACTURE, PC_JACOBI,
-                  FimBatch, FimError, FimModel, IterStats, NotConverged, Options, StepStats,
+                  RESID, FimBatch, FimError, FimModel, IterStats, NotConverged, Options, StepStats,
                   estimate_bytes, exported_symbols)
 
 __all__ = ["FimModel", "FimBatch", "Options", "FimError", "NotConverged", "IterStats",
-           "StepStats", "FULL", "LOCAL", "DD", "FP64", "MIXED", "HOST", "DEVICE", "PC_JACOBI",
-           "PC_FRACTURE",
+           "StepStats", "FULL", "LOCAL", "DD", "RESID", "FP64", "MIXED", "HOST", "DEVICE",
+           "PC_JACOBI", "PC_FRACTURE",
            "LIB_PATH", "estimate_bytes", "exported_symbols"]

@@ -760,7 +760,8 @@ static void newton_update(fim_model* m, fim_iter_stats* it) {
     pend(m, pi, m->nA);
     if (m->flags_on) {
         launch_fill_u8(m->classes, m->n, 0, m->s);
-        launch_cell_classes(m->nA, m->l2g, m->bnd, m->step_mode != FIM_FULL, m->dp_abs,
+        launch_cell_classes(m->nA, m->l2g, m->bnd,
+                            m->step_mode == FIM_LOCAL || m->step_mode == FIM_DD, m->dp_abs,
                             m->o.eps_loc, m->classes, m->s);
     }
     if (it) {
@@ -809,7 +810,8 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
     m->max_active = 0;
     m->step_kry = 0;
     m->inspect_ready = false;
-    if (mode == FIM_FULL) {
+    if (mode == FIM_FULL || mode == FIM_RESID) {
+        // the residual-based localization starts every step on all cells
         if (!m->full_ready) {
             launch_fill_u8(m->act, m->n, 1, m->s);
             TRY(prepare_active(m, false));
@@ -936,6 +938,8 @@ void fim_default_options(fim_options* o) {
     o->max_refine = 20;
     o->check_every = 8;
     o->precond = FIM_PC_FRACTURE;
+    o->eps_res = 1e-6;
+    o->res_layers = 1;
 }
 
 static thread_local std::string g_create_err;
@@ -1043,8 +1047,14 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
         }
     }
     if (m->o.m_layers < 0 || m->o.m_layers > MAX_LAYERS || m->o.m_layers_dd < 0 ||
-        m->o.m_layers_dd > MAX_LAYERS) {
+        m->o.m_layers_dd > MAX_LAYERS || m->o.res_layers < 0 ||
+        m->o.res_layers > MAX_LAYERS) {
         g_create_err = "neighbour layers must be in [0, 8]";
+        delete m;
+        return FIM_E_ARG;
+    }
+    if (!(m->o.eps_res >= 0.0) || !std::isfinite(m->o.eps_res)) {
+        g_create_err = "eps_res must be finite and >= 0";
         delete m;
         return FIM_E_ARG;
     }
@@ -1309,6 +1319,19 @@ static fim_status newton_post_launch(fim_model* m) {
         launch_shrink(m->nA, m->l2g, m->dp_abs, m->o.eps_loc, m->g, m->act, m->dint, m->s);
         compact(m);
         pend(m, pi, m->n);
+    } else if (m->step_mode == FIM_RESID) {
+        // error measure at the updated state on every cell (into last_dp,
+        // unused outside Algorithm 2), the unconverged cells and their
+        // neighbour layers; dint[0] = number of unconverged cells
+        const int pi = pbeg(m, PK_SETS);
+        launch_resid_err(m->fk, m->n, m->g, m->f, m->u, m->st, m->Mn, m->step_dt, m->last_dp,
+                         m->s);
+        launch_fill_i32(m->dint, 1, 0, m->s);
+        launch_mark_resid(m->n, m->last_dp, m->o.eps_res, m->o.res_layers, m->g, m->act,
+                          m->dint, m->lvl, m->s);
+        compact(m);
+        pend(m, pi, m->n);
+        m->full_ready = false;   // l2g / g2l now hold the new set
     }
     HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
     HIPX(hipMemcpyAsync(m->hint, m->dint, 4 * sizeof(int), hipMemcpyDeviceToHost, m->s));
@@ -1335,11 +1358,14 @@ static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it) {
         m->err = "non-finite update";
         return FIM_NOT_CONVERGED;
     }
+    const bool resid = m->step_mode == FIM_RESID;
     bool done;
     if (local) {
         m->is_expand = m->hint[0] != 0;
         done = conv && !m->is_expand;
         if (it) it->is_expand = m->is_expand;
+    } else if (resid) {
+        done = conv || m->hint[0] == 0;   // or no cell left unconverged
     } else {
         done = conv;
     }
@@ -1359,6 +1385,11 @@ static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it) {
         TRY(structure(m));
         launch_fill_i32(&m->dint[2], 1, 0, m->s);
         launch_boundary(m->nA, m->l2g, m->g2l, m->g, m->bnd, &m->dint[2], m->s);
+        pend(m, pi, m->nA);
+    } else if (resid) {
+        m->nA = m->hint[1];
+        const int pi = pbeg(m, PK_SETS);
+        TRY(structure(m));
         pend(m, pi, m->nA);
     }
     return FIM_OK;
@@ -1452,8 +1483,8 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
 
 fim_status fim_newton_step(fim_model* m, double dt, int mode, fim_iter_stats* it) {
     if (!m) return FIM_E_ARG;
-    if (!(dt > 0.0) || !std::isfinite(dt) || mode < FIM_FULL || mode > FIM_DD) {
-        m->err = "dt must be positive and mode FULL, LOCAL or DD";
+    if (!(dt > 0.0) || !std::isfinite(dt) || mode < FIM_FULL || mode > FIM_RESID) {
+        m->err = "dt must be positive and mode FULL, LOCAL, DD or RESID";
         return FIM_E_ARG;
     }
     if (it) std::memset(it, 0, sizeof(*it));
@@ -1948,6 +1979,55 @@ fim_status fim_inspect_sets(fim_model* m, const uint8_t* act_in, const double* d
     HIPX(hipStreamSynchronize(m->s));
     for (int i = 0; i < m->n; i++) bnd_out[i] = act_out[i] ? hb[i] : 0;
     *n_active = m->nA;
+    return FIM_OK;
+}
+
+fim_status fim_inspect_resid_error(fim_model* m, const double* u_old, const double* u_iter,
+                                   const int8_t* status, double dt, double* err_out) {
+    if (!m || !u_old || !u_iter || !err_out || !(dt > 0.0) || !std::isfinite(dt))
+        return FIM_E_ARG;
+    const size_t nb = (size_t)m->n * m->B;
+    m->in_step = false;
+    m->full_ready = false;
+    m->inspect_ready = false;
+    HIPX(hipMemcpyAsync(m->un, u_old, nb * sizeof(double), hipMemcpyHostToDevice, m->s));
+    HIPX(hipMemcpyAsync(m->u, u_iter, nb * sizeof(double), hipMemcpyHostToDevice, m->s));
+    if (status) {
+        HIPX(hipMemcpyAsync(m->st, status, m->n, hipMemcpyHostToDevice, m->s));
+        HIPX(hipMemcpyAsync(m->stn, status, m->n, hipMemcpyHostToDevice, m->s));
+    } else {
+        launch_fill_u8((uint8_t*)m->st, m->n, 0, m->s);
+        launch_fill_u8((uint8_t*)m->stn, m->n, 0, m->s);
+    }
+    launch_accumulation(m->fk, m->n, m->un, m->stn, m->g, m->f, m->Mn, m->s);
+    launch_resid_err(m->fk, m->n, m->g, m->f, m->u, m->st, m->Mn, dt, m->last_dp, m->s);
+    HIPX(hipMemcpyAsync(err_out, m->last_dp, m->n * sizeof(double), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    return FIM_OK;
+}
+
+fim_status fim_inspect_resid_sets(fim_model* m, const double* err, double tol, int32_t layers,
+                                  uint8_t* act_out, int32_t* l2g_out, int32_t* n_active,
+                                  int32_t* n_unconverged) {
+    if (!m || !err || !act_out || !l2g_out || !n_active || !n_unconverged) return FIM_E_ARG;
+    if (layers < 0 || layers > MAX_LAYERS) {
+        m->err = "layers must be in [0, 8]";
+        return FIM_E_ARG;
+    }
+    m->in_step = false;
+    m->full_ready = false;
+    m->inspect_ready = false;
+    HIPX(hipMemcpyAsync(m->last_dp, err, m->n * sizeof(double), hipMemcpyHostToDevice, m->s));
+    launch_fill_i32(m->dint, 1, 0, m->s);
+    launch_mark_resid(m->n, m->last_dp, tol, layers, m->g, m->act, m->dint, m->lvl, m->s);
+    compact(m);
+    TRY(read_int(m));
+    m->nA = m->hint[1];
+    *n_unconverged = m->hint[0];
+    *n_active = m->nA;
+    HIPX(hipMemcpyAsync(act_out, m->act, m->n, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(l2g_out, m->l2g, m->nA * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
     return FIM_OK;
 }
 

@@ -1,6 +1,7 @@
 // Residual and Jacobian assembly on the active rows (Appendix A residual;
-// J_A = R_A J R_A^T built directly, Section 4.3) and the block-Jacobi
-// scaling of the local system.
+// J_A = R_A J R_A^T built directly, Section 4.3), the block-Jacobi
+// scaling of the local system and the per-cell residual error measure of
+// the residual-based localization.
 //
 // One thread per active row.  The row gathers every connection of its
 // cell (an inactive neighbour contributes its frozen state: the Dirichlet
@@ -167,6 +168,89 @@ __global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, D
 }
 
 // ---------------------------------------------------------------------
+// Error measure of the residual-based localization (the estimator of Lu
+// and Beckner that Sections 1 and 4.2 describe), on every cell:
+//     e_i = dt max_c |R_{i,c}| / (V_i rho_c)
+// with R the residual of the Appendix A equations at the current state,
+// V_i the reference pore volume and rho_c the reference density of
+// component c: the step's mass imbalance of the cell as a fraction of its
+// pore volume filled with that component.  The flux arithmetic (canonical
+// orientation, phase-potential upwinding, well term) is that of k_assemble
+// without the derivatives.
+template <int FK>
+__device__ inline double ref_density(const DevFluid& f, int c) {
+    if constexpr (FK == 1) return f.rho_ref;
+    else if constexpr (FK == 2) return c == 0 ? f.rho_w : f.rho_o;
+    else return c == 0 ? f.rho_wsc : (c == 1 ? f.rho_osc : f.rho_gsc);
+}
+
+template <int FK>
+__global__ __launch_bounds__(NT) void k_resid_err(int n, Graph g, DevFluid f,
+                                                  const double* __restrict__ u,
+                                                  const int8_t* __restrict__ st,
+                                                  const double* __restrict__ Mn, double dt,
+                                                  double* __restrict__ err) {
+    constexpr int B = FluidTraits<FK>::B;
+    constexpr int NPH = FluidTraits<FK>::NPH;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double inv_dt = 1.0 / dt;
+    double ui[B];
+#pragma unroll
+    for (int v = 0; v < B; v++) ui[v] = u[(long)v * n + i];
+    Props<FK> Pi;
+    cell_props<FK>(ui, st[i], g.pv[i], f, Pi);
+    double R[B];
+#pragma unroll
+    for (int c = 0; c < B; c++) R[c] = (Pi.M[c].v - Mn[(long)c * n + i]) * inv_dt;
+    const double zi = g.depth[i];
+    const double gg = f.gravity;
+    for (int e = g.adj_ptr[i]; e < g.adj_ptr[i + 1]; e++) {
+        const int j = g.adj_nbr[e];
+        const double T = g.adj_T[e];
+        double uj[B];
+#pragma unroll
+        for (int v = 0; v < B; v++) uj[v] = u[(long)v * n + j];
+        Props<FK> Pj;
+        cell_props<FK>(uj, st[j], g.pv[j], f, Pj);
+        const double zj = g.depth[j];
+        const bool i_lo = i < j;
+        const double sgn = i_lo ? -1.0 : 1.0;
+        const double p_lo = i_lo ? ui[0] : uj[0];
+        const double p_hi = i_lo ? uj[0] : ui[0];
+        const double dz = i_lo ? (zj - zi) : (zi - zj);
+#pragma unroll
+        for (int l = 0; l < NPH; l++) {
+            const double rlo = i_lo ? Pi.rho[l].v : Pj.rho[l].v;
+            const double rhi = i_lo ? Pj.rho[l].v : Pi.rho[l].v;
+            const double dphi = (p_hi - p_lo) - 0.5 * (rlo + rhi) * gg * dz;
+            const bool up_i = ((dphi > 0.0) != i_lo);
+#pragma unroll
+            for (int c = 0; c < B; c++) {
+                if (!carries<FK>(c, l)) continue;
+                const double mob = up_i ? Pi.mob[c][l].v : Pj.mob[c][l].v;
+                R[c] += sgn * (T * mob * dphi);
+            }
+        }
+    }
+    if (g.flags[i] & CF_PERF) {
+        const double dpw = g.bhp[i] - ui[0];
+#pragma unroll
+        for (int c = 0; c < B; c++) {
+            double ms = 0.0;
+#pragma unroll
+            for (int l = 0; l < NPH; l++)
+                if (carries<FK>(c, l)) ms += Pi.mob[c][l].v;
+            R[c] -= g.wi[i] * ms * dpw;
+        }
+    }
+    double e = 0.0;
+#pragma unroll
+    for (int c = 0; c < B; c++) e = fmax(e, fabs(R[c]) / (g.pv[i] * ref_density<FK>(f, c)));
+    err[i] = dt * e;
+}
+
+// ---------------------------------------------------------------------
 // Block-Jacobi scaling: dinv = (J_ii)^{-1} (FP64) and the scaled blocks
 // A~_ik = dinv J_ik stored in the Krylov precision (the scaled diagonal is
 // the identity and is not stored).
@@ -281,6 +365,18 @@ void launch_assemble(int fk, int nA, const LocalSys& ls, const Graph& g,
     case 1: k_assemble<1><<<nb, NT, 0, s>>>(nA, ls, g, f, u, st, Mn, inv_dt); break;
     case 2: k_assemble<2><<<nb, NT, 0, s>>>(nA, ls, g, f, u, st, Mn, inv_dt); break;
     default: k_assemble<3><<<nb, NT, 0, s>>>(nA, ls, g, f, u, st, Mn, inv_dt); break;
+    }
+}
+
+void launch_resid_err(int fk, int n, const Graph& g, const DevFluid& f, const double* u,
+                      const int8_t* st, const double* Mn, double dt, double* err,
+                      hipStream_t s) {
+    if (n <= 0) return;
+    const int nb = nblocks(n);
+    switch (fk) {
+    case 1: k_resid_err<1><<<nb, NT, 0, s>>>(n, g, f, u, st, Mn, dt, err); break;
+    case 2: k_resid_err<2><<<nb, NT, 0, s>>>(n, g, f, u, st, Mn, dt, err); break;
+    default: k_resid_err<3><<<nb, NT, 0, s>>>(n, g, f, u, st, Mn, dt, err); break;
     }
 }
 

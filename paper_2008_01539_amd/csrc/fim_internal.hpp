@@ -112,6 +112,10 @@ void launch_shrink(int nA, const int* l2g, const double* dp_abs, double eps,
                    hipStream_t s);
 void launch_mark_seeds(int n, const Graph& g, int m, uint8_t* act, uint8_t* lvl,
                        hipStream_t s);
+// residual-based set: act = {err_i >= tol} and its m-layer neighbourhood on
+// all n cells; *count += number of cells with err_i >= tol
+void launch_mark_resid(int n, const double* err, double tol, int m, const Graph& g,
+                       uint8_t* act, int* count, uint8_t* lvl, hipStream_t s);
 void launch_support(int n, const double* p, const double* pn, double eps,
                     const Graph& g, uint8_t* act, hipStream_t s);
 void launch_dd_boundary(int nA, const int* l2g, const uint8_t* vt,
@@ -145,6 +149,10 @@ void launch_accumulation(int fk, int n, const double* u, const int8_t* st,
 void launch_assemble(int fk, int nA, const LocalSys& ls, const Graph& g,
                      const DevFluid& f, const double* u, const int8_t* st,
                      const double* Mn, double inv_dt, hipStream_t s);
+// e_i = dt max_c |R_{i,c}| / (V_i rho_c) on all n cells
+void launch_resid_err(int fk, int n, const Graph& g, const DevFluid& f, const double* u,
+                      const int8_t* st, const double* Mn, double dt, double* err,
+                      hipStream_t s);
 void launch_precond(int b, bool fp32, int nA, const LocalSys& ls,
                     double* dinv, void* At, hipStream_t s);
 

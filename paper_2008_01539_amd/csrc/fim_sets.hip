@@ -7,12 +7,15 @@
 //   l2g comes out ascending and g2l is the inverse map (-1 = inactive);
 //   tile offsets are prefix sums of the per-tile counts (two launches, no
 //   spin waits, deterministic);
-// * neighbourhood marking: each boundary cell with a non-negligible update
-//   walks every path of length <= m from itself and sets the byte flag of
-//   each cell reached; the writes are idempotent, so the set is the same in
-//   any schedule;
+// * neighbourhood marking: level by level from the seed cells (the
+//   boundary cells with a non-negligible update), one launch per layer over
+//   a byte array of graph distances; a cell reached in pass k gets the
+//   value k whichever thread writes it, so the set is the same in any
+//   schedule;
 // * the slice width of the sliced-ELL matrix is the wave maximum of the
-//   active-neighbour counts of its 64 rows.
+//   active-neighbour counts of its 64 rows;
+// * the residual-based set: the cells whose residual error measure reaches
+//   the tolerance, inflated by the same level-by-level marking.
 #include "fim_device.hpp"
 
 namespace fimk {
@@ -220,6 +223,30 @@ void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
     launch_fill_u8(lvl, g.n, 0xff, s);
     k_expand_seeds<<<nblocks(nA), NT, 0, s>>>(nA, l2g, bnd, dp_abs, eps, lvl, act, act2, flag);
     ball_steps(g.n, g, m < MAX_LAYERS ? m : MAX_LAYERS, lvl, act, act2, s);
+}
+
+// Residual-based set (the estimator of Lu and Beckner, Sections 1 and 4.2):
+// the cells with err_i >= tol (level 0, *count = their number) and every
+// cell within m layers of them; act is rewritten on all n cells.
+__global__ __launch_bounds__(NT) void k_resid_seeds(int n, const double* __restrict__ err,
+                                                    double tol, uint8_t* __restrict__ lvl,
+                                                    uint8_t* __restrict__ act, int* count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int hit = 0;
+    if (i < n) {
+        hit = err[i] >= tol ? 1 : 0;
+        lvl[i] = hit ? 0 : 0xff;
+        act[i] = (uint8_t)hit;
+    }
+    hit = block_sum_i(hit);
+    if (threadIdx.x == 0 && hit) atomicAdd(count, hit);
+}
+
+void launch_mark_resid(int n, const double* err, double tol, int m, const Graph& g,
+                       uint8_t* act, int* count, uint8_t* lvl, hipStream_t s) {
+    if (n <= 0) return;
+    k_resid_seeds<<<nblocks(n), NT, 0, s>>>(n, err, tol, lvl, act, count);
+    ball_steps(n, g, m < MAX_LAYERS ? m : MAX_LAYERS, lvl, act, nullptr, s);
 }
 
 // Algorithm 1 shrink (only when no boundary update was non-negligible):

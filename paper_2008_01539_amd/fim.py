@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfim.so")
 
 FIM_OK, FIM_NOT_CONVERGED = 0, 1
 FIM_E_ARG, FIM_E_NOMEM, FIM_E_HIP, FIM_E_STATE, FIM_E_NONFINITE = -1, -2, -3, -4, -5
-FULL, LOCAL, DD = 0, 1, 2
+FULL, LOCAL, DD, RESID = 0, 1, 2, 3
 FP64, MIXED = 0, 1
 HOST, DEVICE = 0, 1
 PC_JACOBI, PC_FRACTURE = 0, 1
@@ -64,7 +64,8 @@ class _Opts(C.Structure):
                 ("precision", C.c_int32), ("lin_rtol", C.c_double),
                 ("inner_rtol", C.c_double), ("krylov_maxit", C.c_int32),
                 ("max_refine", C.c_int32), ("check_every", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("eps_res", C.c_double),
+                ("res_layers", C.c_int32)]
 
 
 class IterStats(C.Structure):
@@ -121,6 +122,8 @@ def _load():
                                        C.c_int64]),
         "fim_inspect_sets": (i32, [vp, vp, vp, f64, i32, vp, vp, vp, vp, vp]),
         "fim_inspect_solve": (i32, [vp, vp, vp, vp]),
+        "fim_inspect_resid_error": (i32, [vp, vp, vp, vp, f64, vp]),
+        "fim_inspect_resid_sets": (i32, [vp, vp, f64, i32, vp, vp, vp, vp]),
         "fim_profile_enable": (i32, [vp, i32]),
         "fim_batch_create": (i32, [vp, i32, vp, vp]),
         "fim_model_bytes": (C.c_int64, [vp]),
@@ -164,6 +167,8 @@ class Options:
     max_refine: int = 20
     check_every: int = 8
     precond: int = PC_FRACTURE
+    eps_res: float = 1e-6
+    res_layers: int = 1
 
     @staticmethod
     def tight_mode(**kw):
@@ -382,6 +387,27 @@ class FimModel:
                self._h)
         return dict(act=ao, bnd=bo, l2g=l2g[:na.value].copy(), n_active=na.value,
                     is_expand=bool(ex.value))
+
+    def inspect_resid_error(self, u_old, u_iter, status, dt):
+        n, b = self.n, self.b
+        uo, ui = _f64(u_old).reshape(b, n), _f64(u_iter).reshape(b, n)
+        st = np.ascontiguousarray(status, np.int8) if status is not None else None
+        err = np.empty(n)
+        _check(_lib.fim_inspect_resid_error(self._h, _ptr(uo), _ptr(ui), _ptr(st), float(dt),
+                                            _ptr(err)), self._h)
+        return err
+
+    def inspect_resid_sets(self, err, tol, layers):
+        n = self.n
+        e = _f64(err)
+        ao = np.empty(n, np.uint8)
+        l2g = np.empty(n, np.int32)
+        na = C.c_int32()
+        nu = C.c_int32()
+        _check(_lib.fim_inspect_resid_sets(self._h, _ptr(e), float(tol), int(layers), _ptr(ao),
+                                           _ptr(l2g), C.byref(na), C.byref(nu)), self._h)
+        return dict(act=ao, l2g=l2g[:na.value].copy(), n_active=na.value,
+                    n_unconverged=nu.value)
 
 
 class FimBatch:
