@@ -326,6 +326,7 @@ def run_c3(steps, warmup):
     opts = P.Options(precision=P.MIXED)
     loc = run_gpu(model, opts, P.LOCAL, steps, warmup)
     full = run_gpu(model, opts, P.FULL, steps, warmup)
+    res = run_gpu(model, opts, P.RESID, steps, warmup)
     return {
         "metric": "active-cell Newton updates/s, local vs full Newton (1 GPU); p50/p99 step latency",
         "value": loc["active"] / loc["wall"], "unit": "active-cell Newton updates/s",
@@ -339,6 +340,10 @@ def run_c3(steps, warmup):
         "full": {"updates_per_s": full["active"] / full["wall"], "wall": full["wall"]},
         "speedup_local_vs_full": full["wall"] / loc["wall"],
         "max_dp_local_vs_full_psi": float(np.abs(full["u"][0] - loc["u"][0]).max() / 6894.757293168),
+        "resid": {"iters": res["iters"], "krylov": res["krylov"], "wall": res["wall"],
+                  "sum_active": res["active"],
+                  "max_dp_vs_full_psi":
+                      float(np.abs(full["u"][0] - res["u"][0]).max() / 6894.757293168)},
     }
 
 
