@@ -85,6 +85,41 @@ def measured_traffic_per_row():
     return out if ok else {}
 
 
+def roofline_of(prof, b, kbytes=4, names=("assemble", "bicg_spmv_p", "bicg_spmv_s")):
+    """Achieved algorithmic bandwidth of the kernel with the most time in an
+    event-profiled run: bytes per launch / average launch duration."""
+    cands = {k: v for k, v in prof.items() if k in names and v["launches"]}
+    dom = max(cands, key=lambda k: cands[k]["total_ms"])
+    rec = cands[dom]
+    avg_s = rec["total_ms"] / rec["launches"] * 1e-3
+    byt = algorithmic_bytes(dom, rec, b, kbytes) / rec["launches"]
+    ach = byt / avg_s / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "avg_launch_us": avg_s * 1e6,
+            "bytes_per_launch": byt, "rows_per_launch": rec["rows"] / rec["launches"]}
+
+
+def copy_bandwidth(mib=1024, reps=10):
+    """Read + write bytes per second of a plain device-to-device copy of
+    `mib` MiB (larger than the 256 MiB Infinity Cache), timed with events."""
+    import torch
+    n_el = mib * 2**20 // 4
+    src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n_el * 4 / sec / 1e9
+
+
 def run_gpu(model, opts, mode, steps, warmup, profile=False):
     import numpy as np
     import torch
@@ -327,6 +362,11 @@ def run_c3(steps, warmup):
     loc = run_gpu(model, opts, P.LOCAL, steps, warmup)
     full = run_gpu(model, opts, P.FULL, steps, warmup)
     res = run_gpu(model, opts, P.RESID, steps, warmup)
+    # the whole 784k-cell system: full Newton again with launch events
+    full_prof = run_gpu(model, opts, P.FULL, steps, warmup, profile=True)
+    roof = roofline_of(full_prof["prof"], model.b)
+    copy = copy_bandwidth()
+    roof.update(copy_gbps=copy, frac_of_copy=roof["achieved"] / copy)
     return {
         "metric": "active-cell Newton updates/s, local vs full Newton (1 GPU); p50/p99 step latency",
         "value": loc["active"] / loc["wall"], "unit": "active-cell Newton updates/s",
@@ -344,6 +384,7 @@ def run_c3(steps, warmup):
                   "sum_active": res["active"],
                   "max_dp_vs_full_psi":
                       float(np.abs(full["u"][0] - res["u"][0]).max() / 6894.757293168)},
+        "roofline_full_system": roof,
     }
 
 
@@ -414,6 +455,7 @@ def main():
         prof_run = run_gpu(model, opts, P.LOCAL, args.steps, args.warmup, profile=True)
         log(f"local (events): wall {prof_run['wall']:.3f}s")
     full = None
+    full_prof = None
     dd = None
     res = None
     if not args.no_full:
@@ -421,6 +463,8 @@ def main():
         full = run_gpu(model, opts, P.FULL, args.steps, args.warmup)
         log(f"full: {full['iters']} iterations, wall {full['wall']:.3f}s, "
             f"krylov {full['krylov']}")
+        if args.profile:
+            full_prof = run_gpu(model, opts, P.FULL, args.steps, args.warmup, profile=True)
         log("Algorithm 2 (adaptive localized DD) on the same steps")
         dd = run_gpu(model, opts, P.DD, args.steps, args.warmup)
         log(f"dd: {dd['iters']} inner iterations, wall {dd['wall']:.3f}s, "
@@ -489,25 +533,21 @@ def main():
     # roofline of the dominant matrix kernel (local run, events on its stream)
     prof = prof_run["prof"] if prof_run else None
     if prof:
-        cands = {k: v for k, v in prof.items()
-                 if k in ("assemble", "bicg_spmv_p", "bicg_spmv_s") and v["launches"]}
-        dom = max(cands, key=lambda k: cands[k]["total_ms"])
-        rec = cands[dom]
-        avg_s = rec["total_ms"] / rec["launches"] * 1e-3
-        byt = algorithmic_bytes(dom, rec, model.b, 4) / rec["launches"]
-        ach = byt / avg_s / 1e9
-        per_row = measured_traffic_per_row().get(dom)
-        rows_pl = rec["rows"] / rec["launches"]
-        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": ach,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                           # counter-measured bytes per launch (FETCH_SIZE + WRITE_SIZE
-                           # scaled by a plain copy, per row, times this run's rows per
-                           # launch); None once the kernels changed since the counters
-                           "traffic": per_row * rows_pl if per_row else None,
-                           "avg_launch_us": avg_s * 1e6,
-                           "bytes_per_launch": byt, "rows_per_launch": rows_pl}
+        copy = copy_bandwidth()
+        roof = roofline_of(prof, model.b)
+        per_row = measured_traffic_per_row().get(roof["kernel"])
+        out["roofline"] = {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
+        # counter-measured bytes per launch (FETCH_SIZE + WRITE_SIZE scaled by a
+        # plain copy, per row, times this run's rows per launch); None once the
+        # kernels changed since the counters were taken
+        out["roofline"]["traffic"] = per_row * roof["rows_per_launch"] if per_row else None
+        out["roofline"].update({k: roof[k] for k in ("kernel", "avg_launch_us",
+                                                     "bytes_per_launch", "rows_per_launch")})
+        out["roofline"].update(copy_gbps=copy, frac_of_copy=roof["achieved"] / copy,
+                               profiled_wall_s=prof_run["wall"])
         out["kernel_profile_local"] = prof
-        out["roofline"]["profiled_wall_s"] = prof_run["wall"]
+    if full_prof is not None:
+        out["roofline_full_newton"] = roofline_of(full_prof["prof"], model.b)
     if args.calibrate_copy:
         # one plain device-to-device copy of known size (memory-counter scale)
         n_el = args.calibrate_copy * 2**20 // 4

@@ -95,16 +95,19 @@ constexpr int kbp_waves() { return (B == 3 && sizeof(T) == 8) ? 2 : 3; }
 template <int B, typename T, bool PC>
 constexpr int kb_waves() { return PC ? 2 : kbp_waves<B, T>(); }
 
-// Slot geometry of row r: slot k at base + 64 k; width slots are in use,
-// cap (the slice stride) bounds the slots that may be read at all.
+// Slot geometry of row r: slot k at base + 64 k; width slots are in use
+// (the slice's widest row; narrower rows are padded with column r and a
+// zero block), cap (the slice stride) bounds the slots that may be read at
+// all.
 struct RowGeo {
-    unsigned base, width, cap;
+    unsigned base, width, cap, row;
 };
 __device__ inline RowGeo row_geo(const LocalSys& ls, int r) {
     RowGeo g;
     g.base = (unsigned)slot_of(ls, r, 0);
     g.width = (unsigned)ldg<int>(ls.swidth, 4u * (unsigned)(r / SLICE));
     g.cap = (unsigned)ls.wcap;
+    g.row = (unsigned)r;
     return g;
 }
 
@@ -123,7 +126,8 @@ __device__ inline const KSeg& seg_of(const KSeg* segs, const int* blk_seg) {
 // together with the slice width (their addresses follow from the row index
 // alone); the blocks and gathers of the slots below the width follow, so a
 // chunk costs about two memory round trips.  Column words at or past the
-// width (stale memory) are never used.
+// width (stale memory) are never used, and in FP32 padding slots (column =
+// the row itself past the diagonal) load nothing: their block is zero.
 template <int B, typename T, int NV, int U>
 struct Chunk {
     T a[U][B * B];
@@ -144,7 +148,9 @@ __device__ inline void fetch_chunk(const LocalSys& ls, const T* At, const RowGeo
 #pragma unroll
     for (int u = 0; u < U; u++) {
         const unsigned k = k0 + u;
-        if (k < g.width) {
+        // (FP32 kernels only: the FP64 ones have no register left for it)
+        const bool pad = sizeof(T) == 4 && cl[u] == g.row;
+        if (k < g.width && !pad) {
             const unsigned ab = (g.base + k * SLICE) * (BB * (unsigned)sizeof(T));
 #pragma unroll
             for (unsigned q = 0; q < BB; q++) ch.a[u][q] = ldg<T>(At, ab + q * (unsigned)sizeof(T));
@@ -353,8 +359,9 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
             if (!x_zero) {
                 // UR slots at a time: their column indices in one round of
                 // loads, then their FP64 blocks and x64 gathers in the next
-                // (slots past the width read the row itself, weight 0); the
-                // slots are summed in order, as one at a time would
+                // (slots past the width, and padding slots, read no block:
+                // weight 0); the slots are summed in order, as one at a time
+                // would
                 constexpr int UR = B == 3 ? 4 : 8;
                 const long base = slot_of(ls, r, 0);
                 const int width = ls.swidth[r / SLICE];
@@ -366,7 +373,8 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
                     double a[UR][BB], xv[UR][B];
 #pragma unroll
                     for (int u = 0; u < UR; u++) {
-                        const bool in = k0 + u < width;
+                        // padding past the diagonal (column r) holds a zero block
+                        const bool in = k0 + u < width && (k0 + u == 0 || cl[u] != r);
                         const long pos = base + (long)min(k0 + u, width - 1) * SLICE;
 #pragma unroll
                         for (int q = 0; q < BB; q++) a[u][q] = in ? ls.J[pos * BB + q] : 0.0;
@@ -492,7 +500,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const 
         src[2] = V.p_old;
         src[3] = V.v_old;
     }
-    RowGeo g{0, 0, 0};
+    RowGeo g{0, 0, 0, 0};
     T own[NV][B] = {}, ox[B] = {}, orh[B] = {};
     Chunk<B, T, NV, U> ch{};
     int pinfo = 1, poff = 0;   // fracture-block layout of the row
@@ -654,7 +662,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const 
     const T* const src[NV] = {V.r, V.v_new};
     const int r0 = lb * blockDim.x + threadIdx.x;
     const int stride = nbk * blockDim.x;
-    RowGeo g{0, 0, 0};
+    RowGeo g{0, 0, 0, 0};
     T own[NV][B] = {}, orh[B] = {};
     Chunk<B, T, NV, U> ch{};
     int pinfo = 1, poff = 0;   // fracture-block layout of the row
