@@ -245,7 +245,7 @@ fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_strea
                             fim_batch** out);
 fim_status fim_batch_set(fim_batch* b, fim_model* const* models, int32_t k);
 
-/* dts[k], modes[k] (FIM_FULL or FIM_LOCAL) per member; stats (nullable)
+/* dts[k], modes[k] (FIM_FULL, FIM_LOCAL or FIM_RESID) per member; stats (nullable)
  * and codes receive each member's statistics and status (FIM_OK,
  * FIM_NOT_CONVERGED after a rollback, or a negative error).  The call
  * itself returns FIM_OK unless the batch as a whole failed. */

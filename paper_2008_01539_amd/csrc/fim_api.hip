@@ -1719,8 +1719,8 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
     if (!b || !dts || !modes || !codes) return FIM_E_ARG;
     const int K = (int)b->ms.size();
     for (int q = 0; q < K; q++) {
-        if (modes[q] != FIM_FULL && modes[q] != FIM_LOCAL) {
-            b->err = "batched steps run FIM_FULL or FIM_LOCAL";
+        if (modes[q] != FIM_FULL && modes[q] != FIM_LOCAL && modes[q] != FIM_RESID) {
+            b->err = "batched steps run FIM_FULL, FIM_LOCAL or FIM_RESID";
             return FIM_E_ARG;
         }
         if (!(dts[q] > 0.0) || !std::isfinite(dts[q])) {

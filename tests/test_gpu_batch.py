@@ -75,7 +75,7 @@ def test_batch_equals_solo_two_phase_mixed():
               make_small_c2(seed=24, nx=16, ny=10, nz=3, nfrac=6, nstage=2)]
     opts = P.Options(precision=P.MIXED)
     n = 5
-    for mode in (P.LOCAL, P.FULL):
+    for mode in (P.LOCAL, P.FULL, P.RESID):
         got, _ = _batched(models, opts, mode, n)
         for m, (u, st) in zip(models, got):
             ref, _ = _solo(m, opts, mode, m.schedule[:n])
