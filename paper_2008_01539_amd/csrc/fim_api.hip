@@ -1,8 +1,9 @@
 // Host driver and C ABI of libfim: model residency in HBM, the Newton
 // iteration (Section 4.1), the localized Newton state machine
 // (Algorithm 1), the adaptive nonlinear domain decomposition
-// (Algorithm 2), the iterative-refinement Krylov driver and the inspection
-// entry points.  All arithmetic of the path runs in the kernels; the host
+// (Algorithm 2), the residual-based localization the paper compares
+// against (Sections 1 and 4.2), the iterative-refinement Krylov driver and
+// the inspection entry points.  All arithmetic of the path runs in the kernels; the host
 // only sequences launches and reads one small status record per Newton
 // iteration (plus one per block of Krylov iterations).
 #include <algorithm>
