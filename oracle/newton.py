@@ -18,7 +18,10 @@ Readings where the paper is silent (shared with the HIP library):
 * "tight" convergence additionally requires ||dS||_inf < eps_s and no
   switch in the iteration;
 * failure (iteration cap or non-finite values) rolls the state back to u^n
-  and the driver halves dt, at most ``max_cuts`` times.
+  and the driver halves dt, at most ``max_cuts`` times;
+* an iteration restricted to an empty active set (a model with no
+  always-active cells and nothing in the previous step's support) updates
+  nothing: du = 0, which meets the convergence test at once.
 """
 from __future__ import annotations
 
@@ -136,10 +139,11 @@ class Solver:
             du = x.reshape(self.model.n, b).T
         else:
             act = np.asarray(sorted(active), np.int64)
-            rows = (act[:, None] * b + np.arange(b)[None, :]).reshape(-1)
-            x = self.linear_solve(J, R, rows)
             du = np.zeros((b, self.model.n))
-            du[:, act] = x.reshape(act.size, b).T
+            if act.size:   # an empty restriction leaves nothing to solve
+                rows = (act[:, None] * b + np.arange(b)[None, :]).reshape(-1)
+                x = self.linear_solve(J, R, rows)
+                du[:, act] = x.reshape(act.size, b).T
         return apply_update(self.model, st, du, self.opts)
 
     def solve_timestep(self, st: State, dt):

@@ -1396,7 +1396,23 @@ static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it) {
     return FIM_OK;
 }
 
+// An iteration on an empty active set (Algorithm 1 or 2 on a model with
+// no always-active cells and an empty previous support) has nothing to
+// solve: du = 0, which meets the convergence test, so the step ends with
+// u^n unchanged after this one iteration.
+static fim_status empty_iteration(fim_model* m, fim_iter_stats* it) {
+    m->nu++;
+    if (m->flags_on) launch_fill_u8(m->classes, m->n, 0, m->s);
+    commit(m);
+    if (it) {
+        it->n_active = 0;
+        it->converged = 1;
+    }
+    return FIM_OK;
+}
+
 static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
+    if (m->nA == 0) return empty_iteration(m, it);
     TRY(local_newton(m, it));
     TRY(newton_post_launch(m));
     HIPX(spin_sync(m, m->s));
@@ -1407,6 +1423,7 @@ static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
 // one inner iteration of Algorithm 2
 static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
     if (it) it->phase = m->dd_phase;
+    if (m->dd_phase == 1 && m->nA == 0) return empty_iteration(m, it);
     if (m->dd_phase == 1) {
         if (it) it->subdomain = (int)m->subs.size();
         TRY(local_newton(m, it));
@@ -1774,6 +1791,10 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
                 codes[q] = r;
                 continue;
             }
+        }
+        if (m->nA == 0) {
+            codes[q] = empty_iteration(m, stats ? &stats[q] : nullptr);
+            continue;
         }
         newton_assemble(m);
         solve_prep(m, m->s);

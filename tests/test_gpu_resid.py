@@ -166,3 +166,35 @@ def test_rejects_bad_options(models):
                dict(eps_res=float("nan"))):
         with pytest.raises(P.FimError):
             P.FimModel(models["c1"], P.Options(**kw))
+
+
+def test_empty_active_set_leaves_the_state_unchanged(models):
+    """No always-active cells and no history: Algorithms 1 and 2 start from
+    an empty set; the step ends after one iteration with u^n unchanged, as
+    in the oracle (alone and inside a batch next to a model with work)."""
+    import paper_2008_01539_amd as P
+    from fimgen import make_tiny
+    m = make_tiny("grid3")
+    m.always_active[:] = 0
+    for mode in (P.LOCAL, P.DD):
+        fm = _fm(m)
+        try:
+            it = fm.newton_step(m.schedule[0], mode)
+            assert it.converged == 1 and it.n_active == 0
+            u, _ = fm.get_state()
+            assert np.array_equal(u, m.u0)
+        finally:
+            fm.close()
+    c1 = models["c1"]
+    fms = [_fm(m), _fm(c1)]
+    try:
+        bat = P.FimBatch(fms)
+        stats, codes = bat.newton_step([m.schedule[0], c1.schedule[0]], [P.LOCAL, P.LOCAL])
+        bat.close()
+        assert np.all(codes == 0)
+        assert stats[0]["converged"] == 1 and stats[0]["n_active"] == 0
+        assert stats[1]["n_active"] > 0
+        assert np.array_equal(fms[0].get_state()[0], m.u0)
+    finally:
+        for f in fms:
+            f.close()

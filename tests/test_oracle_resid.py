@@ -3,7 +3,7 @@ and Beckner that Sections 1 and 4.2 describe) against facts that do not
 come from the oracle: closed forms of the error measure on one and two
 cells, brute-force neighbourhoods on a chain and a grid, the residual
 vanishing at the standard Newton solution, and the method reaching that
-solution.  CPU only."""
+solution; and the empty active set of Algorithms 1 and 2.  CPU only."""
 import numpy as np
 
 from fimgen import DAY, FLUID_DEADOIL, PSI, make_c1, make_chain, make_tiny
@@ -142,3 +142,18 @@ def test_resid_localization_costs_more_than_algorithm_1():
     w3 = sum(e["n_a"] for e in l3)
     assert w3 > 5 * w1
     assert np.abs(s3.u[0] - full.u[0]).max() < 1.0 * PSI
+
+
+def test_empty_active_set_leaves_the_state_unchanged():
+    """A model with no always-active cells and no history: Algorithms 1 and
+    2 start from an empty set, whose restricted Newton step is empty, so
+    the step ends after one iteration with u^n unchanged."""
+    m = make_tiny("grid3")
+    m.always_active[:] = 0
+    ls = LocalSolver(m, Options())
+    st = _state(m)
+    for alg in (ls.alg1_timestep, ls.alg2_timestep):
+        log = []
+        new, its, sup = alg(st, m.schedule[0], None, log)
+        assert its == 1 and log[0]["n_a"] == 0
+        assert np.array_equal(new.u, st.u) and not sup
