@@ -104,13 +104,14 @@ def test_sets_full_size_bitwise(c2):
     assert np.array_equal(np.nonzero(out["bnd"])[0], np.array(sorted(ref_bnd)))
 
 
-@pytest.mark.parametrize("mode_name", ["FULL", "LOCAL"])
+@pytest.mark.parametrize("mode_name", ["FULL", "LOCAL", "RESID"])
 def test_converged_steps_satisfy_oracle_equations(c2, c2_jb, mode_name):
     """Tight mode, mixed precision, the first three steps at full size: the
     oracle's residual at the GPU state is at the level of a sub-1e-3 Pa
-    pressure error per row, and the step mass balance closes."""
+    pressure error per row, and the step mass balance closes (the
+    residual-based mode with a vanishing residual cutoff)."""
     import paper_2008_01539_amd as P
-    fm = P.FimModel(c2, P.Options.tight_mode(precision=P.MIXED))
+    fm = P.FimModel(c2, P.Options.tight_mode(precision=P.MIXED, eps_res=1e-14))
     fm.set_state(c2.u0, c2.status0)
     prev, prev_st = c2.u0.copy(), c2.status0.copy()
     for k, dt in enumerate(c2.schedule[:3]):
@@ -128,3 +129,32 @@ def test_converged_steps_satisfy_oracle_equations(c2, c2_jb, mode_name):
             assert np.all(np.abs(R) <= 1e-3 * scale + 1e-30)
         prev, prev_st = u, st
     fm.close()
+
+
+def test_residual_error_measure_full_size(c2):
+    """The residual-based mode's error measure on every one of the 258,096
+    cells against the oracle's (vectorised over the whole model) at an
+    iterate away from convergence: FP64 on both sides, ≤ 1e-11 of the
+    largest value; and the unconverged set at the default cutoff with its
+    neighbour layer, bit for bit."""
+    import paper_2008_01539_amd as P
+    from oracle.localized import resid_error
+    rng = np.random.default_rng(31)
+    u_old = c2.u0.copy()
+    u = u_old.copy()
+    u[0] += rng.uniform(-5, 5, c2.n) * PSI
+    u[1] = np.clip(u[1] + rng.uniform(-0.01, 0.01, c2.n), 0.0, 1.0)
+    dt = c2.schedule[4]
+    eo = resid_error(c2, u, c2.status0, accumulation(c2, u_old, c2.status0), dt)
+    fm = P.FimModel(c2, P.Options(precision=P.MIXED))
+    try:
+        eg = fm.inspect_resid_error(u_old, u, c2.status0, dt)
+        assert np.abs(eg - eo).max() <= 1e-11 * eo.max()
+        tol = float(np.quantile(eo, 0.97))
+        g = fm.inspect_resid_sets(eo, tol, 1)
+    finally:
+        fm.close()
+    rp, nb = adjacency(c2)
+    ref = S.resid_active(rp, nb, eo, tol, 1)
+    assert g["n_unconverged"] == int((eo >= tol).sum())
+    assert np.array_equal(g["l2g"], np.array(sorted(ref)))
