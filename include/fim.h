@@ -7,9 +7,10 @@
  * state u^n and a timestep dt, find u^{n+1} with F(u^{n+1}) = 0 by Newton
  * iterates J(u^nu) du^nu = -F(u^nu); Section 4.3 (Algorithm 1, localized
  * Newton) and Section 4.4 (Algorithm 2, adaptive nonlinear domain
- * decomposition) restrict each iteration to an a-priori active set.  F is
- * the finite-volume two-point-flux residual with phase-potential upwinding
- * of Appendix A.
+ * decomposition) restrict each iteration to an a-priori active set; the
+ * residual-based localization that Sections 1 and 4.2 describe as the
+ * prior method is a fourth mode.  F is the finite-volume two-point-flux
+ * residual with phase-potential upwinding of Appendix A.
  *
  * Conventions
  *  - SI units everywhere (Pa, m, m^2, m^3, s, kg, Pa s).
