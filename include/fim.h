@@ -208,6 +208,24 @@ fim_status fim_newton_step(fim_model* m, double dt, int mode, fim_iter_stats* st
  * with halved dt (at most max_cuts halvings). */
 fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats* st);
 
+/* For callers that cannot allocate memory (code that must not call
+ * hipMalloc: HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): fim_newton_step with the same arguments, results (bit for
+ * bit) and return codes, but no device or pinned memory is allocated or
+ * freed by the call.  The kernels' partial sums, Krylov scalars,
+ * compaction tile counts and launch descriptors come from one static
+ * device array per GPU (about 0.65 MB, held until the process ends)
+ * instead of the model's own buffers; everything else is the model's
+ * memory, allocated by fim_create_model.  Limits: models of at most
+ * 4,194,304 cells (FIM_E_ARG beyond), modes FIM_FULL, FIM_LOCAL and
+ * FIM_RESID (FIM_DD returns FIM_E_ARG: its subdomain lists grow), the
+ * event profiler off (FIM_E_STATE).  All models on one GPU share that
+ * GPU's array and it keeps the last call's contents: calls that overlap
+ * in time on one GPU (different streams or threads) race and must be
+ * serialised by the caller.  It may be mixed with fim_newton_step on the
+ * same model and timestep. */
+fim_status fim_newton_step_noalloc(fim_model* m, double dt, int mode, fim_iter_stats* st);
+
 /* Frees all device memory after synchronising the stream. */
 fim_status fim_destroy_model(fim_model* m);
 

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,59 @@ struct SolveTable {
     int* hblk = nullptr;
     int cap = 0;
 };
+
+// Scratch of the allocation-free Newton iteration (fim_newton_step_noalloc):
+// one static device array per GPU that the library runs on, held until
+// the process ends.  Host code never passes the array's name to a kernel
+// (in host code it is a host-side stand-in, not a device address): the
+// address comes from hipGetSymbolAddress, taken once per device with that
+// device current and kept per device.  Layout (bytes, 256-aligned parts):
+// the Krylov partial sums (14 KB_MAXB doubles), the Krylov scalars, the two
+// launch descriptors of a one-model solve and its (unread) block map, the
+// compaction tile counts and the update's per-block partials, sized for
+// models of at most NA_MAX_CELLS cells.
+constexpr int NA_MAX_CELLS = 1 << 22;
+constexpr size_t na_align(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t NA_OFF_PART = 0;
+constexpr size_t NA_OFF_SC = NA_OFF_PART + na_align(14 * KB_MAXB * sizeof(double));
+constexpr size_t NA_OFF_SEGS = NA_OFF_SC + na_align(sizeof(KScal));
+constexpr size_t NA_OFF_BMAP = NA_OFF_SEGS + na_align(2 * sizeof(KSeg));
+constexpr size_t NA_OFF_TILES = NA_OFF_BMAP + na_align(2 * KB_MAXB * sizeof(int));
+constexpr size_t NA_OFF_UPART =
+    NA_OFF_TILES + na_align(((size_t)NA_MAX_CELLS / TILE + 2) * sizeof(int));
+constexpr size_t NA_SCRATCH_BYTES =
+    NA_OFF_UPART + na_align(4 * ((size_t)NA_MAX_CELLS / NT + 2) * sizeof(double));
+static __device__ __align__(256) char scratch[NA_SCRATCH_BYTES];
+static_assert(sizeof(KScal) % sizeof(int) == 0, "KScal is cleared as ints");
+
+constexpr int NA_MAX_DEV = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[NA_MAX_DEV] = {};
+static bool g_scratch_done[NA_MAX_DEV] = {};
+static std::string g_scratch_err[NA_MAX_DEV];
+
+// The scratch address on the current device (looked up once per device);
+// null with *why set when it is not available.
+static char* scratch_address(int dev, std::string* why) {
+    if (dev < 0 || dev >= NA_MAX_DEV) {
+        *why = "device ordinal out of range for the scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && p) {
+            g_scratch_ptr[dev] = (char*)p;
+        } else {
+            g_scratch_err[dev] = std::string("hipGetSymbolAddress(scratch): ") +
+                                 hipGetErrorString(e);
+        }
+        g_scratch_done[dev] = true;
+    }
+    if (!g_scratch_ptr[dev]) *why = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
 
 struct fim_model {
     int n = 0, nconn = 0, B = 1, fk = 1;
@@ -134,6 +188,15 @@ struct fim_model {
     double cur_pcn2 = 0.0;   // sum of N^2 over its fracture blocks (profiling)
     bool flags_on = false;
     SolveTable solo;
+    // allocation-free Newton iterations (fim_newton_step_noalloc): the
+    // kernels' partial sums, Krylov scalars, compaction tile counts and
+    // launch descriptors live in the per-device static scratch array;
+    // nat is the solve table of those calls (device parts in the scratch
+    // array, pinned host parts allocated with the model)
+    int dev = 0;
+    char* scratch = nullptr;        // this device's scratch address (null: unavailable)
+    SolveTable nat;
+    bool noalloc = false;           // inside fim_newton_step_noalloc
     size_t bytes = 0;   // device bytes held
     uint8_t* classes = nullptr;   // per-cell classes of the last iteration
     Prof prof;
@@ -332,12 +395,9 @@ static void table_free(SolveTable& t) {
     t = SolveTable();
 }
 
-static fim_status table_alloc(fim_model* m, SolveTable& t, int cap) {
+// the pinned host parts and events of a solve table
+static fim_status table_alloc_host(fim_model* m, SolveTable& t, int cap) {
     t.cap = cap;
-    TRY(dal(m, &t.dpc, (size_t)2 * cap));
-    TRY(dal(m, &t.dpref, (size_t)2 * (cap + 1)));
-    TRY(dal(m, &t.dsegs, (size_t)2 * cap));
-    TRY(dal(m, &t.dblk, (size_t)2 * cap * KB_MAXB));
     if (hipHostMalloc((void**)&t.hsegs, 2 * cap * sizeof(KSeg)) != hipSuccess ||
         hipHostMalloc((void**)&t.hblk, (size_t)2 * cap * KB_MAXB * sizeof(int)) != hipSuccess) {
         m->err = "hipHostMalloc failed";
@@ -350,6 +410,15 @@ static fim_status table_alloc(fim_model* m, SolveTable& t, int cap) {
         return FIM_E_NOMEM;
     }
     for (hipEvent_t& e : t.ev) HIPX(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return FIM_OK;
+}
+
+static fim_status table_alloc(fim_model* m, SolveTable& t, int cap) {
+    TRY(table_alloc_host(m, t, cap));
+    TRY(dal(m, &t.dpc, (size_t)2 * cap));
+    TRY(dal(m, &t.dpref, (size_t)2 * (cap + 1)));
+    TRY(dal(m, &t.dsegs, (size_t)2 * cap));
+    TRY(dal(m, &t.dblk, (size_t)2 * cap * KB_MAXB));
     return FIM_OK;
 }
 
@@ -734,8 +803,9 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
 }
 
 static fim_status linear_solve(fim_model* m) {
-    if (!m->solo.cap) TRY(table_alloc(m, m->solo, 1));
     std::vector<fim_model*> one{m};
+    if (m->noalloc) return solve_batch(one, m->nat, m->s);
+    if (!m->solo.cap) TRY(table_alloc(m, m->solo, 1));
     return solve_batch(one, m->solo, m->s);
 }
 
@@ -951,6 +1021,10 @@ int32_t fim_block_size(const fim_model* m) { return m ? m->B : 0; }
 
 static void free_all(fim_model* m) {
     table_free(m->solo);
+    // the device parts of the allocation-free table are the scratch array
+    m->nat.dsegs = nullptr;
+    m->nat.dblk = nullptr;
+    table_free(m->nat);
     for (const ProfRec& r : m->prof.pend) {
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -1046,6 +1120,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             m->pc_grid = std::min(KB_MAXB, 2 * cus);
             m->cus = cus;
         }
+        m->dev = dev;
     }
     if (m->o.m_layers < 0 || m->o.m_layers > MAX_LAYERS || m->o.m_layers_dd < 0 ||
         m->o.m_layers_dd > MAX_LAYERS || m->o.res_layers < 0 ||
@@ -1230,6 +1305,17 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
         hipHostMalloc((void**)&m->hpart, 2 * KB_MAXB * sizeof(double)) != hipSuccess) {
         m->err = "hipHostMalloc failed";
         CK(FIM_E_NOMEM);
+    }
+    // the allocation-free iteration: this device's scratch address (looked
+    // up once per device) and the pinned parts of its solve table
+    CK(table_alloc_host(m, m->nat, 1));
+    {
+        std::string why;
+        m->scratch = n <= NA_MAX_CELLS ? scratch_address(m->dev, &why) : nullptr;
+        if (m->scratch) {
+            m->nat.dsegs = (KSeg*)(m->scratch + NA_OFF_SEGS);
+            m->nat.dblk = (int*)(m->scratch + NA_OFF_BMAP);
+        }
     }
     auto up = [&](void* dst, const void* src, size_t bytes) -> fim_status {
         if (!bytes) return FIM_OK;
@@ -1512,6 +1598,64 @@ fim_status fim_newton_step(fim_model* m, double dt, int mode, fim_iter_stats* it
     }
     if (!m->in_step) TRY(begin_step(m, dt, mode));
     return mode == FIM_DD ? newton_dd(m, it) : newton_full_or_local(m, it);
+}
+
+// For the duration of one allocation-free call: the kernels' partial
+// sums, Krylov scalars, compaction tile counts and the solve table come
+// from this device's scratch array instead of the model's own buffers.
+struct NoallocScope {
+    fim_model* m;
+    double* part_ir;
+    KScal* sc;
+    int* blk;
+    double* part;
+    explicit NoallocScope(fim_model* mm)
+        : m(mm), part_ir(mm->part_ir), sc(mm->sc), blk(mm->blk), part(mm->part) {
+        m->part_ir = (double*)(m->scratch + NA_OFF_PART);
+        m->sc = (KScal*)(m->scratch + NA_OFF_SC);
+        m->blk = (int*)(m->scratch + NA_OFF_TILES);
+        m->part = (double*)(m->scratch + NA_OFF_UPART);
+        m->noalloc = true;
+    }
+    ~NoallocScope() {
+        m->part_ir = part_ir;
+        m->sc = sc;
+        m->blk = blk;
+        m->part = part;
+        m->noalloc = false;
+    }
+    NoallocScope(const NoallocScope&) = delete;
+    NoallocScope& operator=(const NoallocScope&) = delete;
+};
+
+fim_status fim_newton_step_noalloc(fim_model* m, double dt, int mode, fim_iter_stats* it) {
+    if (!m) return FIM_E_ARG;
+    if (m->n > NA_MAX_CELLS) {
+        m->err = "fim_newton_step_noalloc: the model has " + std::to_string(m->n) +
+                 " cells, more than the " + std::to_string(NA_MAX_CELLS) +
+                 " its scratch array is sized for";
+        return FIM_E_ARG;
+    }
+    if (mode == FIM_DD) {
+        m->err = "fim_newton_step_noalloc runs FIM_FULL, FIM_LOCAL or FIM_RESID "
+                 "(Algorithm 2 grows its subdomain lists)";
+        return FIM_E_ARG;
+    }
+    if (m->prof.on) {
+        m->err = "fim_newton_step_noalloc: the event profiler creates events; disable it";
+        return FIM_E_STATE;
+    }
+    if (!m->scratch) {
+        std::string why;
+        (void)scratch_address(m->dev, &why);
+        m->err = "fim_newton_step_noalloc: no scratch address on this device: " + why;
+        return FIM_E_HIP;
+    }
+    NoallocScope scope(m);
+    // the scratch array keeps the previous call's contents: the Krylov
+    // scalars start from zero (every other part is written before it is read)
+    launch_fill_i32((int*)m->sc, (int)(sizeof(KScal) / sizeof(int)), 0, m->s);
+    return fim_newton_step(m, dt, mode, it);
 }
 
 static fim_status solve_once(fim_model* m, double dt, int mode, fim_step_stats* st) {

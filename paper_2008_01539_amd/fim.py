@@ -113,6 +113,7 @@ def _load():
         "fim_set_state": (i32, [vp, vp, vp, i32]),
         "fim_get_state": (i32, [vp, vp, vp, i32]),
         "fim_newton_step": (i32, [vp, f64, i32, vp]),
+        "fim_newton_step_noalloc": (i32, [vp, f64, i32, vp]),
         "fim_solve_timestep": (i32, [vp, f64, i32, vp]),
         "fim_destroy_model": (i32, [vp]),
         "fim_last_error": (C.c_char_p, [vp]),
@@ -304,6 +305,16 @@ class FimModel:
     def newton_step(self, dt, mode=LOCAL):
         it = IterStats()
         code = _check(_lib.fim_newton_step(self._h, float(dt), int(mode), C.byref(it)), self._h)
+        if code == FIM_NOT_CONVERGED:
+            raise NotConverged(_lib.fim_last_error(self._h).decode())
+        return it
+
+    def newton_step_noalloc(self, dt, mode=LOCAL):
+        """fim_newton_step without allocating (kernel scratch in the
+        library's per-device static array)."""
+        it = IterStats()
+        code = _check(_lib.fim_newton_step_noalloc(self._h, float(dt), int(mode), C.byref(it)),
+                      self._h)
         if code == FIM_NOT_CONVERGED:
             raise NotConverged(_lib.fim_last_error(self._h).decode())
         return it
