@@ -19,7 +19,10 @@ Readings where the paper is silent (shared with the HIP library):
 * Algorithm 2: each visit of a subdomain is one Newton iteration on it;
   last_dp[i] holds |dp_i| from the latest solve that touched cell i; a
   subdomain is skipped when last_dp < eps on V_A^k and on its outer layer;
-  the sweeps stop when no subdomain would be solved;
+  the sweeps stop when no subdomain would be solved; the step fails when
+  phase 1 would need more than max_newton solves, when a sweep beyond
+  max_sweeps starts, or when the inner iterations would pass
+  8 max_newton (the paper states no caps);
 * residual-based localization (Lu and Beckner, as Sections 1 and 4.2
   describe it: the first iteration of a timestep takes the whole domain,
   later ones the unconverged cells plus one layer of neighbours): a cell is
@@ -110,20 +113,20 @@ class LocalSolver(Solver):
             if inner > o.max_newton:
                 return None, inner, None
             dp, _, _ = self.newton_iteration(work, m_old, dt, active=va)
-            idx = np.fromiter(va, np.int64)
+            if not np.all(np.isfinite(work.u)):
+                return None, inner, None
+            idx = np.fromiter(sorted(va), np.int64)
             last_dp[idx] = dp[idx]
-            subs.append((idx, np.fromiter(db, np.int64)))
+            subs.append((idx, np.fromiter(sorted(db), np.int64)))
             if log is not None:
-                log.append(dict(n_a=len(va), phase=1, dp=float(dp.max())))
+                log.append(dict(n_a=len(va), phase=1, sub=len(subs) - 1,
+                                dp=float(dp.max())))
             va, vt, vb, db, is_expand = sets.alg2_expand(
                 self.rp, self.nb, vt, vb, dp, o.eps_loc, m)
 
         def pending(k):
             a, d = subs[k]
-            mx = last_dp[a].max() if a.size else 0.0
-            if d.size:
-                mx = max(mx, last_dp[d].max())
-            return mx >= o.eps_loc
+            return sets.alg2_sub_max(a, d, last_dp) >= o.eps_loc
 
         sweeps = 0
         while any(pending(k) for k in range(len(subs))):   # phase 2
@@ -135,6 +138,8 @@ class LocalSolver(Solver):
                     continue
                 a = subs[k][0]
                 inner += 1
+                if inner > 8 * o.max_newton:
+                    return None, inner, None
                 dp, _, _ = self.newton_iteration(work, m_old, dt,
                                                  active=set(a.tolist()))
                 if not np.all(np.isfinite(work.u)):
@@ -143,6 +148,8 @@ class LocalSolver(Solver):
                 if log is not None:
                     log.append(dict(n_a=int(a.size), phase=2, sweep=sweeps,
                                     sub=k, dp=float(dp.max())))
+        if log is not None:
+            log.append(dict(phase=0, n_sub=len(subs), sweeps=sweeps, vt=set(vt)))
         support = set(np.nonzero(np.abs(work.u[0] - st.u[0]) >= o.eps_loc)[0].tolist())
         return work, inner, support
 

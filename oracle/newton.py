@@ -17,8 +17,9 @@ Readings where the paper is silent (shared with the HIP library):
   S_g = 0;
 * "tight" convergence additionally requires ||dS||_inf < eps_s and no
   switch in the iteration;
-* failure (iteration cap or non-finite values) rolls the state back to u^n
-  and the driver halves dt, at most ``max_cuts`` times;
+* failure (iteration cap, non-finite values or a singular Jacobian) rolls
+  the state back to u^n and the driver halves dt, at most ``max_cuts``
+  times;
 * an iteration restricted to an empty active set (a model with no
   always-active cells and nothing in the previous step's support) updates
   nothing: du = 0, which meets the convergence test at once.
@@ -125,7 +126,12 @@ class Solver:
         if rows is not None:
             J = J[rows][:, rows]
             rhs = rhs[rows]
-        lu = spla.splu(J.tocsc(), permc_spec="MMD_AT_PLUS_A")
+        try:
+            lu = spla.splu(J.tocsc(), permc_spec="MMD_AT_PLUS_A")
+        except RuntimeError:
+            # a singular (or non-finite) Jacobian: the iteration fails like
+            # one that produced non-finite values
+            return np.full(rhs.shape, np.nan)
         return lu.solve(rhs)
 
     def newton_iteration(self, st: State, m_old, dt, active=None):

@@ -110,6 +110,14 @@ def alg2_expand(rp, nb, vt, bnd_k, dp_abs, eps, m):
     return nxt, vt, vb_t & nxt, outer_layer(rp, nb, nxt), True
 
 
+def alg2_sub_max(cells, outer, last_dp):
+    """Phase-2 skip test of Algorithm 2 (Section 4.4, Step 2): the largest
+    latest update over subdomain V_A^k and its outer layer dB^k (0 for two
+    empty lists).  The subdomain is solved when this is at least eps."""
+    vals = [float(last_dp[int(i)]) for i in cells] + [float(last_dp[int(i)]) for i in outer]
+    return max(vals) if vals else 0.0
+
+
 def resid_active(rp, nb, err, tol, layers):
     """Residual-based active set (Sections 1 and 4.2, the estimator of Lu
     and Beckner): every cell with err_i >= tol, inflated by its

@@ -336,3 +336,11 @@ def test_dd_leaves_cells_outside_total_set_unchanged():
     changed = np.nonzero(new.u[0] != st.u[0])[0]
     assert changed.size > 0
     assert changed.size < m.n // 2
+    vt = log[-1]["vt"]
+    assert set(changed.tolist()) <= vt
+    outside = np.setdiff1d(np.arange(m.n), np.fromiter(vt, np.int64))
+    assert outside.size > m.n // 2
+    assert np.array_equal(new.u[:, outside], st.u[:, outside])
+    # the subdomains are the phase-1 solves, numbered in build order
+    p1 = [r for r in log if r.get("phase") == 1]
+    assert [r["sub"] for r in p1] == list(range(log[-1]["n_sub"]))

@@ -122,6 +122,36 @@ def test_alg2_boundary_only_where_total_set_ends():
     assert db == {4, 8}
 
 
+def test_alg2_sub_max_and_skip_test():
+    """Skip test of Algorithm 2, Step 2: the largest latest update over the
+    subdomain and its outer layer, by hand."""
+    last = np.array([0.0, 0.1, 0.5, 2.0, 0.2, 0.0, 3.0])
+    assert S.alg2_sub_max([0, 1, 2], [3], last) == 2.0    # outer layer counts
+    assert S.alg2_sub_max([4, 5], [], last) == 0.2
+    assert S.alg2_sub_max([], [], last) == 0.0
+    assert S.alg2_sub_max([6], [0], last) == 3.0
+
+
+def test_alg2_sweep_cap():
+    """A step that needs a second sweep fails with max_sweeps = 1 and
+    succeeds with the default cap; the sweep count of the log is the
+    number of outer passes."""
+    from fimgen import make_c1
+    from oracle.localized import LocalSolver
+    from oracle.newton import Options, State
+    m = make_c1()
+    st = State(m.u0.copy(), m.status0.copy())
+    log = []
+    new, _, _ = LocalSolver(m, Options()).alg2_timestep(st, m.schedule[5], None, log)
+    assert new is not None
+    sweeps = log[-1]["sweeps"]
+    assert sweeps == max(r.get("sweep", 0) for r in log)
+    assert sweeps >= 2
+    bad, _, _ = LocalSolver(m, Options(max_sweeps=sweeps - 1)).alg2_timestep(
+        st, m.schedule[5], None)
+    assert bad is None
+
+
 def test_work_ratio_definition_matches_paper_tables():
     """M_A per iteration is n_A / n; the tables' average column equals the
     total divided by the iteration count (to the printed rounding)."""
