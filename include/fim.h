@@ -204,8 +204,12 @@ fim_status fim_get_state(fim_model* m, double* u_out, int8_t* status_out, int me
 fim_status fim_newton_step(fim_model* m, double dt, int mode, fim_iter_stats* st);
 
 /* Loops fim_newton_step to convergence (Section 4.1).  On failure rolls
- * back to u^n and returns FIM_NOT_CONVERGED, or with auto_cut substeps
- * with halved dt (at most max_cuts halvings). */
+ * back to u^n and returns FIM_NOT_CONVERGED.  With auto_cut a failed step
+ * is replaced by two substeps of half the size, each cut again on failure
+ * (at most max_cuts halvings); substeps that converge are committed as
+ * they go, and when a substep fails at the halving limit the model is
+ * restored to the state, phase status and previous-step support it had
+ * on entry before FIM_NOT_CONVERGED returns. */
 fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats* st);
 
 /* For callers that cannot allocate memory (code that must not call
@@ -362,6 +366,50 @@ fim_status fim_inspect_resid_sets(fim_model* m, const double* err, double tol,
  * ||J x + F|| / ||F||. */
 fim_status fim_inspect_solve(fim_model* m, double* x, int32_t* iters,
                              double* relres);
+
+/* Algorithm 2 (Section 4.4, Step 1), the set logic that follows the local
+ * solve on subdomain V_A^k, on given inputs (host u8[n] flags and
+ * dp_abs[n] = |dp_i|): vt_in = V_T so far, act_in = V_A^k, bnd_in = V_B^k
+ * (read on the cells of act_in only).  The layers-layer neighbourhoods of
+ * the cells of V_B^k with dp_abs >= eps join V_T and form V_A^{k+1}; then
+ * V_B^{k+1} = boundary(V_T) ^ V_A^{k+1} (boundary: cells of the set with a
+ * neighbour outside it) and dB^{k+1} = the cells outside V_A^{k+1}
+ * adjacent to it.  Outputs (host u8[n]): vt_out = updated V_T, act_out =
+ * V_A^{k+1}, bnd_out = V_B^{k+1}, outer_out = dB^{k+1}; *n_active =
+ * |V_A^{k+1}|; *is_expand = whether any cell of V_B^k qualified (when 0,
+ * the three next-set outputs are all zero).  layers in [0, 8], else
+ * FIM_E_ARG.  Ends any timestep in progress. */
+fim_status fim_inspect_dd_expand(fim_model* m, const uint8_t* vt_in,
+                                 const uint8_t* act_in, const uint8_t* bnd_in,
+                                 const double* dp_abs, double eps, int32_t layers,
+                                 uint8_t* vt_out, uint8_t* act_out,
+                                 uint8_t* bnd_out, uint8_t* outer_out,
+                                 int32_t* n_active, int32_t* is_expand);
+
+/* Algorithm 2 (Section 4.4, Step 2), the choice of the next subdomain to
+ * solve.  n_sub subdomains (1..64) given as host lists: subdomain k has
+ * the cells cells[cells_ptr[k] .. cells_ptr[k+1]) and the outer-layer
+ * cells outer[outer_ptr[k] .. outer_ptr[k+1]) (offsets start at 0 and do
+ * not decrease; indices in [0, n)).  last_dp (host, [n]) holds each cell's
+ * |dp| from the latest solve that touched it.  sub_max[k] (host, [n_sub])
+ * receives the largest last_dp over subdomain k and its outer layer;
+ * *pick the first k, searching cyclically from position next (0..n_sub:
+ * one past the subdomain solved last), with sub_max[k] >= eps, or -1;
+ * *new_sweep = 1 when that search passed the end of the list (the pick
+ * opens the next sweep).  Ends any timestep in progress. */
+fim_status fim_inspect_dd_pick(fim_model* m, int32_t n_sub,
+                               const int32_t* cells_ptr, const int32_t* cells,
+                               const int32_t* outer_ptr, const int32_t* outer,
+                               const double* last_dp, double eps, int32_t next,
+                               double* sub_max, int32_t* pick,
+                               int32_t* new_sweep);
+
+/* V_T (Section 4.4: the union of the subdomains) of the most recent
+ * Algorithm 2 timestep (in progress or committed): vt_out host u8[n];
+ * *n_sub = the number of subdomains built.  FIM_E_STATE when no Algorithm
+ * 2 step has run since the model was created or an Algorithm 2
+ * inspection call ran. */
+fim_status fim_get_dd_total(fim_model* m, uint8_t* vt_out, int32_t* n_sub);
 
 #ifdef __cplusplus
 }

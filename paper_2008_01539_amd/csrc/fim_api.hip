@@ -174,6 +174,7 @@ struct fim_model {
     long sd_cap = 0, sd_used = 0, ob_cap = 0, ob_used = 0;
     std::vector<DDSub> subs;
     int dd_phase = 0, dd_next = 0, dd_sweeps = 0, dd_k = 0;
+    bool dd_valid = false;          // vt holds V_T of an Algorithm 2 timestep
     // step state machine
     bool in_step = false, have_history = false, full_ready = false;
     double step_dt = 0.0;
@@ -187,6 +188,11 @@ struct fim_model {
     int cur_nnzb = 0;   // blocks of the current local matrix (profiling)
     double cur_pcn2 = 0.0;   // sum of N^2 over its fracture blocks (profiling)
     bool flags_on = false;
+    // auto_cut: the state, phase status and support set on entry to
+    // fim_solve_timestep, restored when the last substep fails
+    double* usave = nullptr;
+    int8_t* stsave = nullptr;
+    uint8_t* suppsave = nullptr;
     SolveTable solo;
     // allocation-free Newton iterations (fim_newton_step_noalloc): the
     // kernels' partial sums, Krylov scalars, compaction tile counts and
@@ -905,6 +911,7 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
         m->subs.clear();
         m->sd_used = m->ob_used = 0;
         m->dd_phase = 1;
+        m->dd_valid = true;
         m->dd_sweeps = 0;
         m->dd_next = 0;
         m->dd_k = 0;
@@ -985,6 +992,50 @@ static fim_status dd_activate(fim_model* m, int k) {
     return FIM_OK;
 }
 
+// Phase-1 set logic of Algorithm 2 (Section 4.4, Step 1) after the solve
+// on V_A^k (l2g, n_A), with the boundary flags of V_B^k in bnd and the
+// update in dp_abs: the layers-layer neighbourhoods of the cells of V_B^k
+// with |dp| >= eps join V_T and form V_A^{k+1}.  When there are any,
+// V_A^{k+1} becomes the active set (compacted), V_B^{k+1} =
+// boundary(V_T) ^ V_A^{k+1} goes into bnd and the outer layer dB^{k+1}
+// into outer.  *expand receives whether any cell qualified (host read).
+static fim_status dd_expand_sets(fim_model* m, double eps, int layers, bool* expand) {
+    launch_fill_u8(m->act2, m->n, 0, m->s);
+    launch_fill_i32(m->dint, 1, 0, m->s);
+    launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, eps, layers, m->g, m->vt, m->act2,
+                       m->dint, m->lvl, m->s);
+    TRY(read_int(m));
+    *expand = m->hint[0] != 0;
+    if (*expand) {
+        HIPX(hipMemcpyAsync(m->act, m->act2, m->n, hipMemcpyDeviceToDevice, m->s));
+        TRY(prepare_active(m, false));
+        launch_dd_boundary(m->nA, m->l2g, m->vt, m->g, m->bnd, m->s);
+        launch_fill_u8(m->outer, m->n, 0, m->s);
+        launch_outer_layer(m->nA, m->l2g, m->act, m->g, m->outer, m->s);
+    }
+    return FIM_OK;
+}
+
+// Phase 2 of Algorithm 2 (Section 4.4, Step 2): the next subdomain in
+// sweep order whose largest latest update over V_A^k and its outer layer
+// dB^k (smax[k]) is at least eps.  The search starts at position next in
+// [0, N] (one past the subdomain solved last; N when that was the last of
+// the list) and runs cyclically; -1 when no subdomain qualifies.
+// *new_sweep: the search passed the end of the list, so the pick opens
+// the next sweep.
+static int dd_pick(const double* smax, int N, double eps, int next, bool* new_sweep) {
+    *new_sweep = false;
+    for (int q = 0; q < N; q++) {
+        const int pos = next + q;
+        const int k = pos % N;
+        if (smax[k] >= eps) {
+            *new_sweep = pos >= N;
+            return k;
+        }
+    }
+    return -1;
+}
+
 // ----------------------------------------------------------- C ABI
 extern "C" {
 
@@ -1036,7 +1087,7 @@ static void free_all(fim_model* m) {
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
                     m->part_ir, m->classes, m->frac_id, m->ford, m->pcinfo, m->pcoff,
-                    m->pcM, m->pclist, m->lvl};
+                    m->pcM, m->pclist, m->lvl, m->usave, m->stsave, m->suppsave};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (m->hsc) (void)hipHostFree(m->hsc);
@@ -1266,6 +1317,11 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(dal(m, &m->part, 4 * ((nn * B + NT - 1) / NT + 1)));
     CK(dalloc(m, &m->kvec, 9 * nn * B * sizeof(double)));
     CK(dal(m, &m->xprev, nn * B));
+    if (m->o.auto_cut) {
+        CK(dal(m, &m->usave, nn * B));
+        CK(dal(m, &m->stsave, nn));
+        CK(dal(m, &m->suppsave, nn));
+    }
     std::vector<int> ford;   // fracture-cell ordinal per cell, -1 elsewhere
     if (d->frac_id && m->o.precond == FIM_PC_FRACTURE) {
         ford.assign(n, -1);
@@ -1511,16 +1567,19 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
     if (it) it->phase = m->dd_phase;
     if (m->dd_phase == 1 && m->nA == 0) return empty_iteration(m, it);
     if (m->dd_phase == 1) {
+        // at most max_newton subdomain-building solves
+        if (m->nu >= m->o.max_newton) {
+            TRY(rollback(m));
+            m->err = "Algorithm 2 built subdomains for max_newton iterations";
+            return FIM_NOT_CONVERGED;
+        }
         if (it) it->subdomain = (int)m->subs.size();
         TRY(local_newton(m, it));
         launch_copy_masked(m->nA, m->l2g, m->dp_abs, m->last_dp, m->s);
         TRY(dd_store(m));
-        launch_fill_u8(m->act2, m->n, 0, m->s);
-        launch_fill_i32(m->dint, 1, 0, m->s);
-        launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, m->o.eps_loc, m->o.m_layers_dd,
-                           m->g, m->vt, m->act2, m->dint, m->lvl, m->s);
         HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
-        TRY(read_int(m));
+        bool expand = false;
+        TRY(dd_expand_sets(m, m->o.eps_loc, m->o.m_layers_dd, &expand));
         m->nu++;
         const NStat ns = *m->hns;
         if (it) { it->dp_max = ns.dp_max; it->ds_max = ns.ds_max; it->nonfinite = ns.nonfinite; }
@@ -1529,13 +1588,7 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
             m->err = "non-finite update";
             return FIM_NOT_CONVERGED;
         }
-        if (m->hint[0]) {
-            // V_A^{k+1} = new balls; V_B^{k+1} = boundary(V_T) ^ V_A^{k+1}
-            HIPX(hipMemcpyAsync(m->act, m->act2, m->n, hipMemcpyDeviceToDevice, m->s));
-            TRY(prepare_active(m, false));
-            launch_dd_boundary(m->nA, m->l2g, m->vt, m->g, m->bnd, m->s);
-            launch_fill_u8(m->outer, m->n, 0, m->s);
-            launch_outer_layer(m->nA, m->l2g, m->act, m->g, m->outer, m->s);
+        if (expand) {
             if (it) it->is_expand = 1;
         } else {
             m->dd_phase = 2;
@@ -1548,17 +1601,14 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
         // outer-layer boundary values are not negligible
         launch_sub_max(N, m->subs.data(), m->sd_cells, m->sd_outer, m->last_dp, m->dsub, m->s);
         TRY(sync_read(m, m->hsub, m->dsub, N * sizeof(double)));
-        int pick = -1;
-        for (int q = 0; q < N; q++) {
-            const int k = (m->dd_next + q) % N;
-            if (m->hsub[k] >= m->o.eps_loc) { pick = k; break; }
-        }
+        bool new_sweep = false;
+        const int pick = dd_pick(m->hsub, N, m->o.eps_loc, m->dd_next, &new_sweep);
         if (pick < 0) {
             commit(m);
             if (it) it->converged = 1;
             return FIM_OK;
         }
-        if (pick < m->dd_next) m->dd_sweeps++;
+        if (new_sweep) m->dd_sweeps++;
         if (m->dd_sweeps > m->o.max_sweeps || m->nu >= m->o.max_newton * 8) {
             TRY(rollback(m));
             m->err = "Algorithm 2 sweep cap reached";
@@ -1578,8 +1628,7 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
             m->err = "non-finite update";
             return FIM_NOT_CONVERGED;
         }
-        m->dd_next = pick + 1;
-        if (m->dd_next >= N) { m->dd_next = 0; }
+        m->dd_next = pick + 1;    // N after the last subdomain: the next pick wraps
         m->dd_k = pick;
     }
     return FIM_OK;
@@ -1662,8 +1711,10 @@ static fim_status solve_once(fim_model* m, double dt, int mode, fim_step_stats* 
     fim_iter_stats it;
     for (;;) {
         fim_status r = fim_newton_step(m, dt, mode, &it);
+        // Algorithm 2's last call finds no subdomain to solve: no iteration
+        const bool solved = !(mode == FIM_DD && it.phase == 2 && it.n_active == 0);
         if (st) {
-            st->iterations += 1;
+            st->iterations += solved ? 1 : 0;
             st->krylov_iters += it.krylov_iters;
             st->sum_active += it.n_active;
             st->max_active = std::max(st->max_active, it.n_active);
@@ -1686,6 +1737,15 @@ fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats*
         m->err = "a timestep is already in progress";
         return FIM_E_STATE;
     }
+    const size_t nb = (size_t)m->n * m->B;
+    const bool had_history = m->have_history;
+    if (m->o.auto_cut) {
+        // substeps that succeed are committed one by one; a later failure
+        // must still leave the model at u^n of this call
+        HIPX(hipMemcpyAsync(m->usave, m->u, nb * sizeof(double), hipMemcpyDeviceToDevice, m->s));
+        HIPX(hipMemcpyAsync(m->stsave, m->st, m->n, hipMemcpyDeviceToDevice, m->s));
+        HIPX(hipMemcpyAsync(m->suppsave, m->supp, m->n, hipMemcpyDeviceToDevice, m->s));
+    }
     fim_status r = solve_once(m, dt, mode, st);
     if (r != FIM_NOT_CONVERGED || !m->o.auto_cut) return r;
     // halve dt and substep; each substep may be cut further
@@ -1696,8 +1756,22 @@ fim_status fim_solve_timestep(fim_model* m, double dt, int mode, fim_step_stats*
         if (st) st->cuts = std::max(st->cuts, depth);
         r = solve_once(m, h, mode, st);
         if (r == FIM_OK) continue;
-        if (r != FIM_NOT_CONVERGED || depth >= m->o.max_cuts) return r;
-        todo.insert(todo.begin(), {{h * 0.5, depth + 1}, {h * 0.5, depth + 1}});
+        if (r == FIM_NOT_CONVERGED && depth < m->o.max_cuts) {
+            todo.insert(todo.begin(), {{h * 0.5, depth + 1}, {h * 0.5, depth + 1}});
+            continue;
+        }
+        if (r == FIM_NOT_CONVERGED) {
+            const std::string why = m->err;
+            HIPX(hipMemcpyAsync(m->u, m->usave, nb * sizeof(double), hipMemcpyDeviceToDevice, m->s));
+            HIPX(hipMemcpyAsync(m->st, m->stsave, m->n, hipMemcpyDeviceToDevice, m->s));
+            HIPX(hipMemcpyAsync(m->supp, m->suppsave, m->n, hipMemcpyDeviceToDevice, m->s));
+            HIPX(hipStreamSynchronize(m->s));
+            m->have_history = had_history;
+            m->in_step = false;
+            if (st) st->converged = 0;
+            m->err = "timestep cut limit reached (" + why + "); state restored to u^n";
+        }
+        return r;
     }
     if (st) st->converged = 1;
     return FIM_OK;
@@ -1731,6 +1805,7 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     b += n * B * (8 + B * 8);                     // F, dinv
     b += n * B * 8 * 3 + n * B * 8 * 9;           // x64, xprev, rir, Krylov vectors
     b += 4 * (n * B / NT + 2) * 8 + 8 * KB_MAXB * 8;
+    if (o && o->auto_cut) b += n * B * 8 + 2 * n;   // entry snapshot of auto_cut
     const int pc = o ? o->precond : FIM_PC_FRACTURE;
     if (d->frac_id && pc == FIM_PC_FRACTURE) {
         size_t nfc = 0;
@@ -2194,6 +2269,134 @@ fim_status fim_inspect_resid_sets(fim_model* m, const double* err, double tol, i
     HIPX(hipMemcpyAsync(act_out, m->act, m->n, hipMemcpyDeviceToHost, m->s));
     HIPX(hipMemcpyAsync(l2g_out, m->l2g, m->nA * sizeof(int), hipMemcpyDeviceToHost, m->s));
     HIPX(hipStreamSynchronize(m->s));
+    return FIM_OK;
+}
+
+// Algorithm 2 phase-1 set logic (Section 4.4, Step 1) on given inputs.
+fim_status fim_inspect_dd_expand(fim_model* m, const uint8_t* vt_in, const uint8_t* act_in,
+                                 const uint8_t* bnd_in, const double* dp_abs, double eps,
+                                 int32_t layers, uint8_t* vt_out, uint8_t* act_out,
+                                 uint8_t* bnd_out, uint8_t* outer_out, int32_t* n_active,
+                                 int32_t* is_expand) {
+    if (!m || !vt_in || !act_in || !bnd_in || !dp_abs || !vt_out || !act_out || !bnd_out ||
+        !outer_out || !n_active || !is_expand)
+        return FIM_E_ARG;
+    if (layers < 0 || layers > MAX_LAYERS) {
+        m->err = "layers must be in [0, 8]";
+        return FIM_E_ARG;
+    }
+    const int n = m->n;
+    m->in_step = false;
+    m->full_ready = false;
+    m->inspect_ready = false;
+    m->dd_valid = false;
+    HIPX(hipMemcpyAsync(m->act, act_in, n, hipMemcpyHostToDevice, m->s));
+    HIPX(hipMemcpyAsync(m->vt, vt_in, n, hipMemcpyHostToDevice, m->s));
+    HIPX(hipMemcpyAsync(m->bnd, bnd_in, n, hipMemcpyHostToDevice, m->s));
+    HIPX(hipMemcpyAsync(m->dp_abs, dp_abs, (size_t)n * sizeof(double), hipMemcpyHostToDevice,
+                        m->s));
+    TRY(prepare_active(m, false));
+    bool expand = false;
+    TRY(dd_expand_sets(m, eps, layers, &expand));
+    std::vector<uint8_t> hb(n), ho(n);
+    HIPX(hipMemcpyAsync(vt_out, m->vt, n, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(act_out, m->act, n, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(hb.data(), m->bnd, n, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(ho.data(), m->outer, n, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    *is_expand = expand ? 1 : 0;
+    if (!expand) {
+        // no subdomain follows: the next sets are empty
+        std::memset(act_out, 0, n);
+        std::memset(bnd_out, 0, n);
+        std::memset(outer_out, 0, n);
+        *n_active = 0;
+        return FIM_OK;
+    }
+    for (int i = 0; i < n; i++) {
+        bnd_out[i] = act_out[i] ? hb[i] : 0;
+        outer_out[i] = ho[i];
+    }
+    *n_active = m->nA;
+    return FIM_OK;
+}
+
+// Algorithm 2 phase-2 subdomain choice (Section 4.4, Step 2) on given
+// subdomain lists and latest updates.
+fim_status fim_inspect_dd_pick(fim_model* m, int32_t n_sub, const int32_t* cells_ptr,
+                               const int32_t* cells, const int32_t* outer_ptr,
+                               const int32_t* outer, const double* last_dp, double eps,
+                               int32_t next, double* sub_max, int32_t* pick,
+                               int32_t* new_sweep) {
+    if (!m || !cells_ptr || !outer_ptr || !last_dp || !sub_max || !pick || !new_sweep)
+        return FIM_E_ARG;
+    if (n_sub < 1 || n_sub > MAX_SUBS || next < 0 || next > n_sub) {
+        m->err = "n_sub must be in [1, 64] and next in [0, n_sub]";
+        return FIM_E_ARG;
+    }
+    const int n = m->n;
+    for (const int32_t* ptr : {cells_ptr, outer_ptr}) {
+        if (ptr[0] != 0) {
+            m->err = "list offsets must start at 0";
+            return FIM_E_ARG;
+        }
+        for (int k = 0; k < n_sub; k++)
+            if (ptr[k + 1] < ptr[k]) {
+                m->err = "list offsets must not decrease";
+                return FIM_E_ARG;
+            }
+    }
+    const long nc = cells_ptr[n_sub], no = outer_ptr[n_sub];
+    if ((nc > 0 && !cells) || (no > 0 && !outer)) return FIM_E_ARG;
+    for (long q = 0; q < nc; q++)
+        if (cells[q] < 0 || cells[q] >= n) {
+            m->err = "cell index out of range";
+            return FIM_E_ARG;
+        }
+    for (long q = 0; q < no; q++)
+        if (outer[q] < 0 || outer[q] >= n) {
+            m->err = "cell index out of range";
+            return FIM_E_ARG;
+        }
+    m->in_step = false;
+    m->full_ready = false;
+    m->inspect_ready = false;
+    m->dd_valid = false;
+    m->subs.clear();
+    m->sd_used = m->ob_used = 0;
+    TRY(dd_grow(m, &m->sd_cells, &m->sd_cap, nc + 1));
+    TRY(dd_grow(m, &m->sd_outer, &m->ob_cap, no + 1));
+    if (nc > 0)
+        HIPX(hipMemcpyAsync(m->sd_cells, cells, nc * sizeof(int), hipMemcpyHostToDevice, m->s));
+    if (no > 0)
+        HIPX(hipMemcpyAsync(m->sd_outer, outer, no * sizeof(int), hipMemcpyHostToDevice, m->s));
+    HIPX(hipMemcpyAsync(m->last_dp, last_dp, (size_t)n * sizeof(double), hipMemcpyHostToDevice,
+                        m->s));
+    std::vector<DDSub> subs(n_sub);
+    for (int k = 0; k < n_sub; k++) {
+        subs[k].cells_off = cells_ptr[k];
+        subs[k].cells_n = cells_ptr[k + 1] - cells_ptr[k];
+        subs[k].outer_off = outer_ptr[k];
+        subs[k].outer_n = outer_ptr[k + 1] - outer_ptr[k];
+    }
+    launch_sub_max(n_sub, subs.data(), m->sd_cells, m->sd_outer, m->last_dp, m->dsub, m->s);
+    TRY(sync_read(m, m->hsub, m->dsub, n_sub * sizeof(double)));
+    std::memcpy(sub_max, m->hsub, n_sub * sizeof(double));
+    bool ns = false;
+    *pick = dd_pick(m->hsub, n_sub, eps, next, &ns);
+    *new_sweep = ns ? 1 : 0;
+    return FIM_OK;
+}
+
+fim_status fim_get_dd_total(fim_model* m, uint8_t* vt_out, int32_t* n_sub) {
+    if (!m || !vt_out || !n_sub) return FIM_E_ARG;
+    if (!m->dd_valid) {
+        m->err = "no Algorithm 2 timestep has run since the last inspection call";
+        return FIM_E_STATE;
+    }
+    HIPX(hipMemcpyAsync(vt_out, m->vt, m->n, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    *n_sub = (int32_t)m->subs.size();
     return FIM_OK;
 }
 

@@ -125,6 +125,10 @@ def _load():
         "fim_inspect_solve": (i32, [vp, vp, vp, vp]),
         "fim_inspect_resid_error": (i32, [vp, vp, vp, vp, f64, vp]),
         "fim_inspect_resid_sets": (i32, [vp, vp, f64, i32, vp, vp, vp, vp]),
+        "fim_inspect_dd_expand": (i32, [vp, vp, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp,
+                                        vp]),
+        "fim_inspect_dd_pick": (i32, [vp, i32, vp, vp, vp, vp, vp, f64, i32, vp, vp, vp]),
+        "fim_get_dd_total": (i32, [vp, vp, vp]),
         "fim_profile_enable": (i32, [vp, i32]),
         "fim_batch_create": (i32, [vp, i32, vp, vp]),
         "fim_model_bytes": (C.c_int64, [vp]),
@@ -419,6 +423,48 @@ class FimModel:
                                            _ptr(l2g), C.byref(na), C.byref(nu)), self._h)
         return dict(act=ao, l2g=l2g[:na.value].copy(), n_active=na.value,
                     n_unconverged=nu.value)
+
+    def inspect_dd_expand(self, vt, act, bnd, dp_abs, eps, layers):
+        n = self.n
+        vi, ai, bi = (np.ascontiguousarray(x, np.uint8).reshape(n) for x in (vt, act, bnd))
+        dp = _f64(dp_abs)
+        vo, ao, bo, oo = (np.empty(n, np.uint8) for _ in range(4))
+        na = C.c_int32()
+        ex = C.c_int32()
+        _check(_lib.fim_inspect_dd_expand(self._h, _ptr(vi), _ptr(ai), _ptr(bi), _ptr(dp),
+                                          float(eps), int(layers), _ptr(vo), _ptr(ao),
+                                          _ptr(bo), _ptr(oo), C.byref(na), C.byref(ex)),
+               self._h)
+        return dict(vt=vo, act=ao, bnd=bo, outer=oo, n_active=na.value,
+                    is_expand=bool(ex.value))
+
+    def inspect_dd_pick(self, cells, outers, last_dp, eps, nxt):
+        """cells, outers: lists of index arrays, one per subdomain."""
+        k = len(cells)
+        cp = np.zeros(k + 1, np.int32)
+        op = np.zeros(k + 1, np.int32)
+        cp[1:] = np.cumsum([len(c) for c in cells])
+        op[1:] = np.cumsum([len(c) for c in outers])
+        cc = np.ascontiguousarray(np.concatenate([np.asarray(c, np.int32) for c in cells])
+                                  if cp[-1] else np.zeros(1, np.int32), np.int32)
+        oc = np.ascontiguousarray(np.concatenate([np.asarray(c, np.int32) for c in outers])
+                                  if op[-1] else np.zeros(1, np.int32), np.int32)
+        ld = _f64(last_dp)
+        smax = np.empty(k)
+        pick = C.c_int32()
+        nsw = C.c_int32()
+        _check(_lib.fim_inspect_dd_pick(self._h, k, _ptr(cp), _ptr(cc), _ptr(op), _ptr(oc),
+                                        _ptr(ld), float(eps), int(nxt), _ptr(smax),
+                                        C.byref(pick), C.byref(nsw)), self._h)
+        return smax, pick.value, bool(nsw.value)
+
+    def dd_total(self):
+        """V_T of the most recent Algorithm 2 timestep and its subdomain
+        count."""
+        vt = np.empty(self.n, np.uint8)
+        ns = C.c_int32()
+        _check(_lib.fim_get_dd_total(self._h, _ptr(vt), C.byref(ns)), self._h)
+        return vt, ns.value
 
 
 class FimBatch:

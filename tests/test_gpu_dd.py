@@ -1,0 +1,238 @@
+"""GPU parity of Algorithm 2, the adaptive localized nonlinear domain
+decomposition of Section 4.4: the phase-1 partitions (V_A^{k+1}, V_T,
+V_B^{k+1}, dB^{k+1}) and the phase-2 choice of the next subdomain bit for
+bit against the oracle's set logic on identical inputs; the sequence of
+inner iterations (phase, subdomain, n_A) and the subdomain count against
+the oracle's Algorithm 2 in paper mode; cells outside V_T unchanged over a
+step (Section 5.3.1); sweep-cap enforcement; tight-mode timesteps of the
+two-phase and black-oil models against the oracle's full Newton."""
+import numpy as np
+import pytest
+
+from fimgen import PSI, make_c1, make_small_c2, make_small_c3
+from oracle import sets as S
+from oracle.localized import LocalSolver
+from oracle.newton import Options as OOptions
+from oracle.newton import Solver, State
+
+from gpu_util import check_dd_expand, flags_of, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return make_c1()
+
+
+@pytest.fixture(scope="module")
+def c2s():
+    return make_small_c2(frac_sw=0.6)
+
+
+@pytest.fixture(scope="module")
+def c3s():
+    return make_small_c3()
+
+
+@pytest.mark.parametrize("layers", [4, 2])
+def test_dd_expand_matches_oracle_bitwise_c1(c1, layers):
+    import paper_2008_01539_amd as P
+    fm = P.FimModel(c1, P.Options())
+    check_dd_expand(fm, c1, np.random.default_rng(40 + layers), layers, 0.3 * PSI)
+    fm.close()
+
+
+def test_dd_pick_matches_oracle_skip_test(c1):
+    """Subdomain maxima exact, and the pick is the first subdomain with a
+    non-negligible latest update in the oracle's sweep order (the rest of
+    the current sweep, then the next sweep from subdomain 0)."""
+    import paper_2008_01539_amd as P
+    fm = P.FimModel(c1, P.Options())
+    rng = np.random.default_rng(77)
+    n = c1.n
+    seen = set()
+    for trial in range(40):
+        N = int(rng.integers(1, 13))
+        cells = [rng.choice(n, int(rng.integers(1, 400)), replace=False) for _ in range(N)]
+        outers = [rng.choice(n, int(rng.integers(0, 90)), replace=False) for _ in range(N)]
+        last = np.where(rng.random(n) < 0.02, rng.exponential(0.3 * PSI, n), 0.0)
+        if trial % 7 == 6:
+            last[:] = 0.0
+        ref = [S.alg2_sub_max(cells[k], outers[k], last) for k in range(N)]
+        eps = 0.3 * PSI if trial % 3 else float(rng.choice(ref))   # ties at eps
+        nxt = int(rng.integers(0, N + 1))
+        smax, pick, new_sweep = fm.inspect_dd_pick(cells, outers, last, eps, nxt)
+        assert np.array_equal(smax, np.array(ref))
+        order = list(range(nxt, N)) + list(range(0, nxt))
+        want = next((k for k in order if ref[k] >= eps), -1)
+        assert pick == want, (trial, nxt, ref, eps)
+        assert new_sweep == (want >= 0 and want < nxt)
+        seen.add((want >= 0, new_sweep))
+    fm.close()
+    assert seen >= {(True, True), (True, False), (False, False)}
+
+
+def _gpu_dd_steps(model, opts, schedule):
+    """Algorithm 2 timesteps on the GPU, one fim_newton_step per inner
+    iteration; per step the (phase, subdomain, n_A) sequence, the
+    subdomain count, V_T and the states before and after."""
+    import paper_2008_01539_amd as P
+    fm = P.FimModel(model, opts)
+    fm.set_state(model.u0, model.status0)
+    steps = []
+    for dt in schedule:
+        u0, _ = fm.get_state()
+        seq = []
+        while True:
+            it = fm.newton_step(dt, P.DD)
+            if it.converged and it.phase == 2 and it.n_active == 0:
+                break                      # the sweep found nothing to solve
+            seq.append((it.phase, it.subdomain, it.n_active))
+            if it.converged:
+                break
+        vt, nsub = fm.dd_total()
+        u1, st1 = fm.get_state()
+        steps.append(dict(seq=seq, n_sub=nsub, vt=vt, u0=u0, u1=u1, st1=st1))
+    fm.close()
+    return steps
+
+
+def _oracle_dd_steps(model, opts, schedule):
+    ls = LocalSolver(model, opts)
+    st = State(model.u0.copy(), model.status0.copy())
+    prev = None
+    out = []
+    for dt in schedule:
+        log = []
+        new, _, sup = ls.alg2_timestep(st, dt, prev, log)
+        assert new is not None
+        seq = [(r["phase"], r["sub"], r["n_a"]) for r in log if r.get("phase") in (1, 2)]
+        out.append(dict(seq=seq, n_sub=log[-1]["n_sub"], vt=log[-1]["vt"], u=new.u))
+        st, prev = new, sup
+    return out
+
+
+@pytest.mark.parametrize("which,nsteps", [("c1", 8), ("c2s", 6), ("c3s", 6)])
+def test_dd_paper_mode_sequence_matches_oracle(which, nsteps, c1, c2s, c3s):
+    """Paper settings (eps = 0.3 psi, m = 4) with exact linear solves on
+    both sides: the same subdomains are built and visited in the same
+    order with the same sizes, V_T is the same set, and cells outside V_T
+    keep their old state bit for bit."""
+    import paper_2008_01539_amd as P
+    model = {"c1": c1, "c2s": c2s, "c3s": c3s}[which]
+    sched = model.schedule[:nsteps]
+    g = _gpu_dd_steps(model, P.Options(lin_rtol=1e-12), sched)
+    o = _oracle_dd_steps(model, OOptions(), sched)
+    saw_phase2 = False
+    for k, (gs, os_) in enumerate(zip(g, o)):
+        assert gs["seq"] == os_["seq"], (which, k)
+        assert gs["n_sub"] == os_["n_sub"]
+        assert np.array_equal(gs["vt"], flags_of(os_["vt"], model.n))
+        out = gs["vt"] == 0
+        assert np.array_equal(gs["u1"][:, out], gs["u0"][:, out])
+        saw_phase2 |= any(p == 2 for p, _, _ in gs["seq"])
+        pmin = os_["u"][0].min()
+        assert np.abs(gs["u1"][0] - os_["u"][0]).max() <= 1e-8 * pmin
+    assert saw_phase2
+
+
+def test_dd_sweep_cap_matches_oracle(c1):
+    """A step that needs two sweeps fails on both sides with
+    max_sweeps = 1 (the model is left at u^n) and succeeds with 2."""
+    import paper_2008_01539_amd as P
+    dt = c1.schedule[5]
+    ls = LocalSolver(c1, OOptions())
+    st = State(c1.u0.copy(), c1.status0.copy())
+    log = []
+    assert ls.alg2_timestep(st, dt, None, log)[0] is not None
+    sweeps = log[-1]["sweeps"]
+    assert sweeps >= 2
+    for cap, ok in ((sweeps - 1, False), (sweeps, True)):
+        fm = P.FimModel(c1, P.Options(lin_rtol=1e-12, max_sweeps=cap))
+        fm.set_state(c1.u0, c1.status0)
+        stats = fm.solve_timestep(dt, P.DD, raise_on_fail=False)
+        u, _ = fm.get_state()
+        fm.close()
+        assert bool(stats.converged) == ok
+        oracle_ok = LocalSolver(c1, OOptions(max_sweeps=cap)).alg2_timestep(
+            st, dt, None)[0] is not None
+        assert oracle_ok == ok
+        if not ok:
+            assert np.array_equal(u, c1.u0)
+
+
+@pytest.mark.parametrize("which,prec", [("c2s", "FP64"), ("c2s", "MIXED"),
+                                        ("c3s", "FP64"), ("c3s", "MIXED")])
+def test_dd_tight_timesteps_match_oracle(which, prec, c2s, c3s):
+    """Tight mode: Algorithm 2 on the two-phase and black-oil models
+    reaches the oracle's full-Newton solution (1e-8 relative p, 1e-8 S,
+    phase status identical)."""
+    import paper_2008_01539_amd as P
+    model = c2s if which == "c2s" else c3s
+    ref = run_oracle(Solver(model, OOptions.tight_mode()), model, model.schedule)[-1]
+    fm = P.FimModel(model, P.Options.tight_mode(precision=getattr(P, prec)))
+    fm.set_state(model.u0, model.status0)
+    for dt in model.schedule:
+        fm.solve_timestep(dt, P.DD)
+    u, st = fm.get_state()
+    fm.close()
+    assert np.array_equal(st, ref.status)
+    assert np.abs(u[0] - ref.u[0]).max() <= 1e-8 * ref.u[0].min()
+    assert np.abs(u[1] - ref.u[1]).max() <= 1e-8
+    if model.b == 3:
+        sat = ref.status == 1
+        if sat.any():
+            assert np.abs(u[2][sat] - ref.u[2][sat]).max() <= 1e-8
+        assert np.abs(u[2][~sat] - ref.u[2][~sat]).max() <= 1e-8 * ref.u[2][~sat].max()
+
+
+def _oracle_auto_cut(model, opts, st, dt):
+    """The cut rule of fim_solve_timestep on the oracle: a failed step is
+    replaced by two halves, each cut again on failure, at most max_cuts
+    halvings deep.  Returns the final state or None."""
+    s = Solver(model, opts)
+    new, _ = s.solve_timestep(st, dt)
+    if new is not None:
+        return new
+    todo = [(dt / 2, 1), (dt / 2, 1)]
+    while todo:
+        h, d = todo.pop(0)
+        new, _ = s.solve_timestep(st, h)
+        if new is not None:
+            st = new
+            continue
+        if d >= opts.max_cuts:
+            return None
+        todo = [(h / 2, d + 1), (h / 2, d + 1)] + todo
+    return st
+
+
+@pytest.mark.parametrize("max_newton", [8, 12])
+def test_auto_cut_matches_oracle_and_restores_on_failure(c3s, max_newton):
+    """Black oil from its initial state, one 1-day step in tight mode with
+    at most two halvings: with max_newton = 12 the halves converge (as in
+    the oracle) and give the oracle's state; with 8 every level fails and
+    the model is left exactly at its entry state, phase status included,
+    and still advances normally afterwards."""
+    import paper_2008_01539_amd as P
+    from fimgen import DAY
+    dt = 1.0 * DAY
+    oo = OOptions.tight_mode(max_newton=max_newton, max_cuts=2)
+    ref = _oracle_auto_cut(c3s, oo, State(c3s.u0.copy(), c3s.status0.copy()), dt)
+    fm = P.FimModel(c3s, P.Options.tight_mode(auto_cut=1, max_cuts=2,
+                                              max_newton=max_newton))
+    fm.set_state(c3s.u0, c3s.status0)
+    stats = fm.solve_timestep(dt, P.FULL, raise_on_fail=False)
+    u, st = fm.get_state()
+    assert stats.cuts > 0
+    assert bool(stats.converged) == (ref is not None)
+    if ref is None:
+        assert np.array_equal(u, c3s.u0)
+        assert np.array_equal(st, c3s.status0)
+        assert fm.solve_timestep(c3s.schedule[0], P.FULL, raise_on_fail=False).converged
+    else:
+        assert np.array_equal(st, ref.status)
+        assert np.abs(u[0] - ref.u[0]).max() <= 1e-8 * ref.u[0].min()
+        assert np.abs(u[1] - ref.u[1]).max() <= 1e-8
+    fm.close()

@@ -104,6 +104,17 @@ def test_sets_full_size_bitwise(c2):
     assert np.array_equal(np.nonzero(out["bnd"])[0], np.array(sorted(ref_bnd)))
 
 
+@pytest.mark.parametrize("layers", [4, 2])
+def test_dd_expand_full_size_bitwise(c2, layers):
+    """Algorithm 2's phase-1 partitions at full size against the oracle's
+    set logic, bit for bit (two chained expansions, then a stop)."""
+    import paper_2008_01539_amd as P
+    from gpu_util import check_dd_expand
+    fm = P.FimModel(c2, P.Options(precision=P.MIXED))
+    check_dd_expand(fm, c2, np.random.default_rng(90 + layers), layers, 0.3 * PSI, rounds=2)
+    fm.close()
+
+
 @pytest.mark.parametrize("mode_name", ["FULL", "LOCAL", "RESID"])
 def test_converged_steps_satisfy_oracle_equations(c2, c2_jb, mode_name):
     """Tight mode, mixed precision, the first three steps at full size: the
