@@ -4,11 +4,13 @@ MI355X, with p50/p99 Newton-step latency, the roofline of the dominant kernel
 and the FP64 oracle timed on the host cores.
 
 Workload (one "step" = one fully implicit timestep solved to convergence):
-the water/dead-oil model of 200x100x10 matrix cells plus a seeded
-2000-fracture DFN and a 10-stage horizontal well (258,096 cells), its 20-step
-schedule to 71.6 days, localized Newton (Algorithm 1, eps_p = 0.3 psi,
-m = 2) with FP64 assembly and an FP32 BiCGStab inside FP64 refinement.
-Steps past the end of the schedule restart it from the initial state.
+the black-oil model of 400x200x8 matrix cells plus a seeded 5000-fracture
+DFN and a 10-stage horizontal well (784,166 cells, 3x3 blocks), its
+40-step schedule to 365 days; the first `warmup` steps run untimed, the
+next `steps` are timed (warmup + steps must fit the schedule); localized
+Newton (Algorithm 1, eps_p = 0.3 psi, m = 2) with FP64 assembly, flash and
+switching and an FP32 BiCGStab inside FP64 refinement.  `--workload c2`
+runs the water/dead-oil config-2 model (258,096 cells) the same way.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -32,22 +34,55 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(kernel, rec, b, kbytes, pc=True):
-    """Bytes a kernel must move per the work it did (one active row = one
-    unit): every array entry it reads or writes once, neighbour gathers
-    counted once (cache reuse), padding of the sliced-ELL matrix excluded.
-    rec: profile record with rows, nnzb (blocks incl. diagonal) and aux
-    (FP32 fracture-block inverse entries applied by the product kernels)."""
+def plan_bytes(kernel, rec, b, kbytes):
+    """Algorithmic bytes of the method's work in the launches of one profile
+    record, by the per-row figures of the measurement plan (one unit = one
+    active row, i.e. one row of the local block system; nnzb = blocks of the
+    active rows, diagonal included, so nnzb = rows (1 + f') with f' the
+    active-active connections per row):
+
+    * matrix product (BSR SpMV): s b^2 + 4 bytes per block (values,
+      column index), 4 per row (row pointer), 2 s b per row (source and
+      result vectors);
+    * block-Jacobi apply: s b^2 + 2 s b per row;
+    * one BiCGStab iteration = 2 products + 2 applies + about 20 vector
+      passes of s b bytes per row; each of the library's two kernels per
+      iteration carries one product, one apply and 10 passes;
+    * assembly: reads 8 (2b + 1) per row plus 20 per connection (neighbour
+      index, T, neighbour state counted once; f taken as f'), writes 8b +
+      8b^2 (1 + f') + 4 (1 + f') + 4 per row, plus the s b^2 (1 + f')
+      Krylov-precision copy.
+
+    s = bytes of the Krylov precision.  These figures count what the
+    method must move on the active rows; the library's own kernels fuse
+    the apply into the product (the matrix is stored block-Jacobi scaled
+    with an implicit identity diagonal) and move less, and its
+    fracture-block preconditioner adds the bytes that fracture_bytes
+    reports."""
+    rows, nnzb = rec["rows"], rec["nnzb"]
+    if kernel in ("bicg_spmv_p", "bicg_spmv_s"):
+        spmv = nnzb * (kbytes * b * b + 4) + rows * (4 + 2 * kbytes * b)
+        apply = rows * (kbytes * b * b + 2 * kbytes * b)
+        return spmv + apply + rows * 10 * kbytes * b
+    if kernel == "assemble":
+        f = max(nnzb - rows, 0.0)
+        return (rows * (8 * (2 * b + 1) + 8 * b + 4) + f * 20
+                + nnzb * (8 * b * b + 4 + kbytes * b * b))
+    raise KeyError(kernel)
+
+
+def kernel_bytes(kernel, rec, b, kbytes):
+    """Bytes the library's fused kernel itself must move for the same work
+    (every entry it reads or writes once, neighbour gathers counted once,
+    sliced-ELL padding excluded), without its fracture-block preconditioner
+    (fracture_bytes)."""
     rows, nnzb = rec["rows"], rec["nnzb"]
     off = max(nnzb - rows, 0.0)
-    aux = rec.get("aux", 0.0)
-    blk = 8 if (pc and aux > 0) else 0   # block layout words per row
     if kernel == "bicg_spmv_p":
-        # col + block per off-diagonal; s, t, p, v, x, rh read; x, r, p, v
-        # written; the inverse entries of the fracture blocks
-        return off * (4 + kbytes * b * b) + rows * (10 * b * kbytes + blk) + 4 * aux
+        # col + block per off-diagonal; s, t, p, v, x, rh read; x, r, p, v written
+        return off * (4 + kbytes * b * b) + rows * 10 * b * kbytes
     if kernel == "bicg_spmv_s":   # col + block; r, v, rh read; s, t written
-        return off * (4 + kbytes * b * b) + rows * (5 * b * kbytes + blk) + 4 * aux
+        return off * (4 + kbytes * b * b) + rows * 5 * b * kbytes
     if kernel == "assemble":
         # per row: l2g 4, state 8b, status 1, pv 8, depth 8, flags 1, old
         # masses 8b, adjacency pointers 8, residual 8b written; per
@@ -57,18 +92,29 @@ def algorithmic_bytes(kernel, rec, b, kbytes, pc=True):
     raise KeyError(kernel)
 
 
-PROFILE_SUMMARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                               "c2_local_kernels.md")
+def fracture_bytes(kernel, rec):
+    """Bytes of the fracture-block preconditioner inside a product kernel:
+    the FP32 inverse entries it applied (aux) and 8 bytes of block layout
+    per row."""
+    if kernel not in ("bicg_spmv_p", "bicg_spmv_s") or not rec.get("aux"):
+        return 0.0
+    return 4.0 * rec["aux"] + 8.0 * rec["rows"]
+
+
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+PROFILE_SUMMARY = {"c3": os.path.join(PROFILES, "c3_local_kernels.md"),
+                   "c2": os.path.join(PROFILES, "c2_local_kernels.md")}
 KERNEL_SOURCES = ["fim_krylov.hip", "fim_fracpc.hip", "fim_internal.hpp", "fim_device.hpp"]
 
 
-def measured_traffic_per_row():
+def measured_traffic_per_row(workload):
     """HBM bytes per row of each kernel from the committed rocprofv3 counter
-    summary, or {} when the kernel sources changed since it was taken."""
+    summary of the workload, or {} when the kernel sources changed since it
+    was taken."""
     import hashlib
     try:
-        text = open(PROFILE_SUMMARY).read()
-    except OSError:
+        text = open(PROFILE_SUMMARY[workload]).read()
+    except (OSError, KeyError):
         return {}
     h = hashlib.sha256()
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2008_01539_amd", "csrc")
@@ -86,17 +132,27 @@ def measured_traffic_per_row():
 
 
 def roofline_of(prof, b, kbytes=4, names=("assemble", "bicg_spmv_p", "bicg_spmv_s")):
-    """Achieved algorithmic bandwidth of the kernel with the most time in an
-    event-profiled run: bytes per launch / average launch duration."""
+    """The kernel with the most time in an event-profiled run: algorithmic
+    bytes per launch (plan_bytes) over its average launch duration; beside
+    it the bytes of the fused kernel itself and of the fracture-block
+    preconditioner it applies (not part of frac)."""
     cands = {k: v for k, v in prof.items() if k in names and v["launches"]}
     dom = max(cands, key=lambda k: cands[k]["total_ms"])
     rec = cands[dom]
-    avg_s = rec["total_ms"] / rec["launches"] * 1e-3
-    byt = algorithmic_bytes(dom, rec, b, kbytes) / rec["launches"]
+    L = rec["launches"]
+    avg_s = rec["total_ms"] / L * 1e-3
+    byt = plan_bytes(dom, rec, b, kbytes) / L
+    own = kernel_bytes(dom, rec, b, kbytes) / L
+    frc = fracture_bytes(dom, rec) / L
     ach = byt / avg_s / 1e9
     return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "avg_launch_us": avg_s * 1e6,
-            "bytes_per_launch": byt, "rows_per_launch": rec["rows"] / rec["launches"]}
+            "bytes_per_launch": byt, "rows_per_launch": rec["rows"] / L,
+            "blocks_per_launch": rec["nnzb"] / L,
+            "kernel_own_bytes_per_launch": own,
+            "kernel_own_gbs": own / avg_s / 1e9,
+            "fracture_block_bytes_per_launch": frc,
+            "fracture_block_gbs": frc / avg_s / 1e9}
 
 
 def copy_bandwidth(mib=1024, reps=10):
@@ -121,21 +177,19 @@ def copy_bandwidth(mib=1024, reps=10):
 
 
 def run_gpu(model, opts, mode, steps, warmup, profile=False):
+    """Timesteps warmup .. warmup+steps-1 of the model's schedule with
+    `mode`; the first `warmup` steps run untimed from the initial state.
+    Returns totals over the timed steps, Newton-step and timestep
+    latencies and the final state."""
     import numpy as np
     import torch
     import paper_2008_01539_amd as P
+    sched = model.schedule
+    assert warmup + steps <= len(sched)
     fm = P.FimModel(model, opts)
     fm.set_state(model.u0, model.status0)
-    sched = model.schedule
-    L = len(sched)
-    k = 0
 
-    def one_step(lat):
-        nonlocal k
-        if k > 0 and k % L == 0:
-            fm.set_state(model.u0, model.status0)
-        dt = sched[k % L]
-        k += 1
+    def one_step(dt, lat):
         act = its = kry = 0
         t0 = time.perf_counter()
         while True:
@@ -143,6 +197,8 @@ def run_gpu(model, opts, mode, steps, warmup, profile=False):
             it = fm.newton_step(dt, mode)
             if lat is not None:
                 lat.append(time.perf_counter() - t1)
+            if it.converged and mode == P.DD and it.phase == 2 and it.n_active == 0:
+                break                 # Algorithm 2 found nothing left to solve
             act += it.n_active
             its += 1
             kry += it.krylov_iters
@@ -150,8 +206,8 @@ def run_gpu(model, opts, mode, steps, warmup, profile=False):
                 break
         return act, its, kry, time.perf_counter() - t0
 
-    for _ in range(warmup):
-        one_step(None)
+    for dt in sched[:warmup]:
+        one_step(dt, None)
     torch.cuda.synchronize()
     if profile:
         fm.profile(True)
@@ -159,8 +215,8 @@ def run_gpu(model, opts, mode, steps, warmup, profile=False):
     tot_act = tot_its = tot_kry = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        a, i, kr, st = one_step(lat)
+    for dt in sched[warmup:warmup + steps]:
+        a, i, kr, st = one_step(dt, lat)
         tot_act += a
         tot_its += i
         tot_kry += kr
@@ -175,31 +231,59 @@ def run_gpu(model, opts, mode, steps, warmup, profile=False):
                 p50=float(np.percentile(lat_ms, 50)), p99=float(np.percentile(lat_ms, 99)),
                 step_p50=float(np.percentile(np.array(step_lat) * 1e3, 50)),
                 step_p99=float(np.percentile(np.array(step_lat) * 1e3, 99)),
-                u=u, prof=prof, k_end=k)
+                u=u, prof=prof)
 
 
-def cpu_baseline(log_fn):
-    """The FP64 oracle (full Newton, SuperLU) on a bounded sample of the
-    same workload: the config-2 recipe (same physics, DFN density and well
-    layout) on a 30x15x10 grid, its first 8 timesteps, single thread."""
-    os.environ["OMP_NUM_THREADS"] = "1"
-    from fimgen.configs import _two_phase_model, c1_schedule
-    from fimgen.model import FLUID_DEADOIL
+def _oracle_schedule(model, schedule, runs):
+    """The oracle's full Newton over a schedule from the initial state, the
+    median wall of `runs` runs; returns (wall, iterations, steps)."""
+    import numpy as np
     from oracle.newton import Options, Solver, State
-    m = _two_phase_model("c2_sample", 2, 30, 15, 10, 45, FLUID_DEADOIL, c1_schedule())
-    s = Solver(m, Options())
-    st = State(m.u0.copy(), m.status0.copy())
-    t0 = time.perf_counter()
+    walls = []
     its = 0
-    for dt in m.schedule[:8]:
-        st, i = s.solve_timestep(st, dt)
-        its += i
-    wall = time.perf_counter() - t0
-    log_fn(f"oracle sample: n={m.n} iterations={its} wall={wall:.1f}s")
+    for _ in range(runs):
+        s = Solver(model, Options())
+        st = State(model.u0.copy(), model.status0.copy())
+        its = 0
+        t0 = time.perf_counter()
+        for dt in schedule:
+            st, i = s.solve_timestep(st, dt)
+            assert st is not None
+            its += i
+        walls.append(time.perf_counter() - t0)
+    return float(np.median(walls)), its, len(schedule)
+
+
+def cpu_baseline(log_fn, workload, warmup, steps):
+    """The FP64 oracle (full Newton, complex-step Jacobian, SuperLU) on one
+    host thread: a bounded sample of the benchmark workload (its recipe on
+    a reduced grid over the same timestep window) and config 1 over its
+    whole 20-step schedule (median of three runs)."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from fimgen import make_c1
+    from fimgen.configs import _two_phase_model, c1_schedule, geometric_schedule
+    from fimgen.model import FLUID_BLACKOIL, FLUID_DEADOIL
+    if workload == "c3":
+        m = _two_phase_model("c3_sample", 3, 24, 12, 8, 18, FLUID_BLACKOIL,
+                             geometric_schedule(40, 1e-3, 365.0), nstage=2)
+        desc = "config-3 recipe (black oil) on a 24x12x8 grid + 18 fractures + 2 stages"
+    else:
+        m = _two_phase_model("c2_sample", 2, 30, 15, 10, 45, FLUID_DEADOIL, c1_schedule())
+        desc = "config-2 recipe (water/dead oil) on a 30x15x10 grid + 45 fractures"
+    sched = m.schedule[:min(len(m.schedule), warmup + steps)]
+    wall, its, nst = _oracle_schedule(m, sched, 1)
+    log_fn(f"oracle sample: n={m.n} steps={nst} iterations={its} wall={wall:.1f}s")
+    c1 = make_c1()
+    w1, i1, n1 = _oracle_schedule(c1, c1.schedule, 3)
+    log_fn(f"oracle config 1: {n1} steps, {i1} iterations, median wall {w1:.1f}s")
     return dict(value=m.n * its / wall, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"config-2 recipe on a 30x15x10 grid + 45 fractures (n={m.n} cells), "
-                       f"first 8 timesteps, full Newton + SuperLU, FP64, 1 thread: "
-                       f"{its} iterations in {wall:.1f} s",
+                sample=f"{desc} (n={m.n} cells), timesteps 0..{nst - 1} of its schedule "
+                       f"(the benchmark's window from the initial state), full Newton + "
+                       f"SuperLU, FP64, 1 thread: {its} iterations in {wall:.1f} s",
+                s_per_iteration=wall / its, s_per_timestep=wall / nst,
+                config1={"n_cells": c1.n, "timesteps": n1, "iterations": i1,
+                         "wall_s_median_of_3": w1, "s_per_iteration": w1 / i1,
+                         "s_per_timestep": w1 / n1, "cell_updates_per_s": c1.n * i1 / w1},
                 host_cpu=_cpu_name(), host_cores=os.cpu_count())
 
 
@@ -221,20 +305,22 @@ def _member(k):
 
 
 def _pool_models(fn, ids, procs=16):
+    """Builds models in worker processes; called before this process
+    initialises the GPU (the workers are forked from it)."""
     import multiprocessing as mp
+    log(f"generating {len(ids)} models")
     with mp.get_context("fork").Pool(min(procs, len(ids))) as pool:
         return pool.map(fn, ids)
 
 
-def run_c4(members, steps):
-    """Batched ensemble: `members` config-4 models advanced together, one
-    Newton iteration of every live member per batched call, each member
-    through its own schedule; then the same members one after another."""
+def run_c4(models, steps):
+    """Batched ensemble: the config-4 models advanced together, one Newton
+    iteration of every live member per batched call, each member through
+    its own schedule; then the same members one after another."""
     import numpy as np
     import torch
     import paper_2008_01539_amd as P
-    log(f"generating {members} ensemble members")
-    models = _pool_models(_member, list(range(members)))
+    members = len(models)
     ncell = sum(m.n for m in models)
     log(f"total cells {ncell}")
     opts = P.Options(precision=P.MIXED)
@@ -310,7 +396,7 @@ def _c5_session(args):
     return make_c3(seed=7000 + k)
 
 
-def run_c5(seconds, pool, budget_gib, rate=50.0):
+def run_c5(models, ids, seconds, pool, budget_gib, rate=50.0):
     """Serving: Poisson timestep requests at `rate`/s over a pool of
     config-1, -2 and -3 sessions (50/40/10 % of requests); sessions are
     admitted up to the HBM budget before the clock starts, the rest on
@@ -319,9 +405,6 @@ def run_c5(seconds, pool, budget_gib, rate=50.0):
     import paper_2008_01539_amd as P
     from paper_2008_01539_amd.serve import GpuExecutor, Server, SessionSpec
     n1, n2, n3 = pool
-    log(f"generating sessions {n1}/{n2}/{n3}")
-    ids = [(1, k) for k in range(n1)] + [(2, k) for k in range(n2)] + [(3, k) for k in range(n3)]
-    models = _pool_models(_c5_session, ids)
     specs = [SessionSpec(name=f"{kind}-{k}", model=m, options=P.Options(precision=P.MIXED),
                          schedule=m.schedule) for (kind, k), m in zip(ids, models)]
     mix = np.array([0.5 / n1] * n1 + [0.4 / n2] * n2 + [0.1 / n3] * n3)
@@ -351,88 +434,59 @@ def run_c5(seconds, pool, budget_gib, rate=50.0):
     }
 
 
-def run_c3(steps, warmup):
+WORKLOADS = {
+    "c3": "config 3: black oil (bubble point 3500 psi, S_g/R_s switching), 400x200x8 grid "
+          "+ seeded 5000-fracture DFN + 10-stage horizontal well ({n} cells, {nc} "
+          "connections, 3x3 blocks), 40-step schedule to 365 d",
+    "c2": "config 2: water/dead-oil, 200x100x10 grid + seeded 2000-fracture DFN + 10-stage "
+          "horizontal well ({n} cells, {nc} connections, 2x2 blocks), 20-step schedule to "
+          "71.6 d",
+}
+
+
+def _rel_dp(u, ref):
     import numpy as np
-    import paper_2008_01539_amd as P
-    from fimgen import make_c3
-    log("building config 3")
-    model = make_c3()
-    log(f"n={model.n}")
-    opts = P.Options(precision=P.MIXED)
-    loc = run_gpu(model, opts, P.LOCAL, steps, warmup)
-    full = run_gpu(model, opts, P.FULL, steps, warmup)
-    res = run_gpu(model, opts, P.RESID, steps, warmup)
-    # the whole 784k-cell system: full Newton again with launch events
-    full_prof = run_gpu(model, opts, P.FULL, steps, warmup, profile=True)
-    roof = roofline_of(full_prof["prof"], model.b)
-    copy = copy_bandwidth()
-    roof.update(copy_gbps=copy, frac_of_copy=roof["achieved"] / copy)
-    return {
-        "metric": "active-cell Newton updates/s, local vs full Newton (1 GPU); p50/p99 step latency",
-        "value": loc["active"] / loc["wall"], "unit": "active-cell Newton updates/s",
-        "n_gpus": 1, "steps": steps, "warmup": warmup, "higher_is_better": True,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"config 3: black oil (bubble point 3500 psi, Sg/Rs switching), "
-                               f"400x200x8 + 5000-fracture DFN ({model.n} cells), 3x3 blocks, "
-                               f"timesteps {warmup}..{warmup + steps - 1} of 40, localized Newton, "
-                               "FP32 Krylov in FP64 refinement"},
-        "local": {k: loc[k] for k in ("iters", "krylov", "wall", "p50", "p99")},
-        "full": {"updates_per_s": full["active"] / full["wall"], "wall": full["wall"]},
-        "speedup_local_vs_full": full["wall"] / loc["wall"],
-        "max_dp_local_vs_full_psi": float(np.abs(full["u"][0] - loc["u"][0]).max() / 6894.757293168),
-        "resid": {"iters": res["iters"], "krylov": res["krylov"], "wall": res["wall"],
-                  "sum_active": res["active"],
-                  "max_dp_vs_full_psi":
-                      float(np.abs(full["u"][0] - res["u"][0]).max() / 6894.757293168)},
-        "roofline_full_system": roof,
-    }
+    return float(np.abs(u[0] - ref[0]).max() / ref[0].min())
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
-    ap.add_argument("--localize-fractures", action="store_true",
-                    help="fracture cells not always active (only perforated cells are); "
-                         "the default keeps them active as in the paper's runs")
-    ap.add_argument("--members", type=int, default=256)
-    ap.add_argument("--serve-seconds", type=float, default=30.0)
-    ap.add_argument("--budget-gib", type=float, default=64.0)
-    ap.add_argument("--pool", default="256,64,16",
-                    help="serving: config-1,2,3 session counts")
-    ap.add_argument("--steps", type=int, default=18)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-full", action="store_true")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="after the run, copy MIB MiB device to device once (a plain copy "
-                         "kernel of known size for scaling memory counters)")
-    ap.add_argument("--profile", type=int, default=1,
-                    help="record per-kernel hipEvents during the timed local run")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU design is documented, not built)", file=sys.stderr)
-        sys.exit(2)
+def _max_dp_psi(u, ref):
+    import numpy as np
+    return float(np.abs(u[0] - ref[0]).max() / 6894.757293168)
+
+
+def _leg(r, model, full_wall=None, ref=None):
+    out = {"iterations": r["iters"], "sum_active": r["active"],
+           "avg_ma": r["active"] / model.n / max(r["iters"], 1),
+           "updates_per_s": r["active"] / r["wall"], "krylov_iters": r["krylov"],
+           "wall_s": r["wall"], "newton_step_ms_p50": r["p50"],
+           "newton_step_ms_p99": r["p99"], "timestep_ms_p50": r["step_p50"],
+           "timestep_ms_p99": r["step_p99"]}
+    if full_wall is not None:
+        out["speedup_vs_full"] = full_wall / r["wall"]
+    if ref is not None:
+        out["max_rel_dp_vs_tight_ref"] = _rel_dp(r["u"], ref)
+        out["max_dp_vs_tight_ref_psi"] = _max_dp_psi(r["u"], ref)
+    return out
+
+
+def run_single(workload, args):
+    """One model at full size: localized Newton (Algorithm 1, the headline),
+    full Newton, Algorithm 2 and the residual-based localization on the same
+    timesteps, each from the initial state with the same untimed warm-up
+    steps; a tight FP64 full-Newton reference over the same steps for the
+    accuracy of every leg; the roofline of the dominant kernel from an
+    event-profiled replay of the localized leg."""
     import numpy as np
     import torch
-    assert torch.cuda.is_available(), "no GPU"
-    torch.cuda.set_device(0)
-    from fimgen import PSI, make_c2
     import paper_2008_01539_amd as P
-    if args.workload == "c4":
-        print(json.dumps(run_c4(args.members, max(1, args.steps))), flush=True)
-        return
-    if args.workload == "c5":
-        pool = tuple(int(v) for v in args.pool.split(","))
-        print(json.dumps(run_c5(args.serve_seconds, pool, args.budget_gib)), flush=True)
-        return
-    if args.workload == "c3":
-        print(json.dumps(run_c3(args.steps, args.warmup)), flush=True)
-        return
-
-    log("building the config-2 model")
-    model = make_c2()
+    from fimgen import make_c2, make_c3
+    log(f"building the {workload} model")
+    model = make_c3() if workload == "c3" else make_c2()
+    L = len(model.schedule)
+    if args.warmup + args.steps > L:
+        print(f"bench.py: warmup + steps = {args.warmup + args.steps} exceeds the "
+              f"{L}-step schedule of {workload}", file=sys.stderr)
+        sys.exit(2)
     if args.localize_fractures:
         aa = np.zeros_like(model.always_active)
         aa[np.asarray(model.perf_cell, dtype=np.int64)] = 1
@@ -440,39 +494,27 @@ def main():
     log(f"n={model.n} connections={model.nc}")
     opts = P.Options(precision=P.MIXED)
     if args.localize_fractures:
-        # the active set has to grow along whole fractures, m layers per
-        # expanding iteration
         opts.max_newton = 400
-    log(f"localized Newton: warmup {args.warmup}, timed {args.steps} steps")
-    loc = run_gpu(model, opts, P.LOCAL, args.steps, args.warmup)
-    log(f"local: {loc['iters']} iterations, wall {loc['wall']:.3f}s, "
-        f"krylov {loc['krylov']}")
+    W, K = args.warmup, args.steps
+    log(f"localized Newton: warm-up steps 0..{W - 1}, timed steps {W}..{W + K - 1}")
+    loc = run_gpu(model, opts, P.LOCAL, K, W)
+    log(f"local: {loc['iters']} iterations, wall {loc['wall']:.3f}s, krylov {loc['krylov']}")
     prof_run = None
     if args.profile:
-        # the same timed region again with hipEvents around every launch
-        # (the events add host work, so the headline value comes from the
-        # run above)
-        prof_run = run_gpu(model, opts, P.LOCAL, args.steps, args.warmup, profile=True)
+        # the same steps again with launch events (they add host work, so the
+        # headline comes from the run above)
+        prof_run = run_gpu(model, opts, P.LOCAL, K, W, profile=True)
         log(f"local (events): wall {prof_run['wall']:.3f}s")
-    full = None
-    full_prof = None
-    dd = None
-    res = None
+    legs = {}
     if not args.no_full:
-        log("full Newton on the same steps")
-        full = run_gpu(model, opts, P.FULL, args.steps, args.warmup)
-        log(f"full: {full['iters']} iterations, wall {full['wall']:.3f}s, "
-            f"krylov {full['krylov']}")
-        if args.profile:
-            full_prof = run_gpu(model, opts, P.FULL, args.steps, args.warmup, profile=True)
-        log("Algorithm 2 (adaptive localized DD) on the same steps")
-        dd = run_gpu(model, opts, P.DD, args.steps, args.warmup)
-        log(f"dd: {dd['iters']} inner iterations, wall {dd['wall']:.3f}s, "
-            f"krylov {dd['krylov']}")
-        log("residual-based localization (the prior method) on the same steps")
-        res = run_gpu(model, opts, P.RESID, args.steps, args.warmup)
-        log(f"resid: {res['iters']} iterations, wall {res['wall']:.3f}s, "
-            f"krylov {res['krylov']}")
+        for name, mode in (("full", P.FULL), ("dd", P.DD), ("resid", P.RESID)):
+            legs[name] = run_gpu(model, opts, mode, K, W)
+            log(f"{name}: {legs[name]['iters']} iterations, wall {legs[name]['wall']:.3f}s, "
+                f"krylov {legs[name]['krylov']}")
+        legs["local_fp64"] = run_gpu(model, P.Options(precision=P.FP64), P.LOCAL, K, W)
+        log(f"local FP64: wall {legs['local_fp64']['wall']:.3f}s")
+        ref = run_gpu(model, P.Options.tight_mode(precision=P.FP64), P.FULL, K, W)["u"]
+        log("tight FP64 full-Newton reference done")
     value = loc["active"] / loc["wall"]
     out = {
         "metric": "active-cell Newton updates/s, local vs full Newton (1 GPU); "
@@ -480,74 +522,55 @@ def main():
         "value": value,
         "unit": "active-cell Newton updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": loc["wall"] / args.steps * 1e3,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": loc["wall"] / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "config 2: water/dead-oil, 200x100x10 grid + seeded 2000-fracture "
-                        "DFN + 10-stage horizontal well (258096 cells, 722225 connections), "
-                        "20-step schedule to 71.6 d; localized Newton (Algorithm 1, "
-                        "eps_p 0.3 psi, m 2); FP64 assembly/update, FP32 BiCGStab "
-                        "(block-Jacobi scaling + fracture-block inverses) inside FP64 "
-                        "refinement",
+            "workload": WORKLOADS[workload].format(n=model.n, nc=model.nc)
+                        + f"; timed steps {W}..{W + K - 1} after {W} untimed; localized "
+                          "Newton (Algorithm 1, eps_p 0.3 psi, m 2), FP64 assembly/update/"
+                          "switching, FP32 BiCGStab (block-Jacobi scaling + fracture-block "
+                          "inverses) inside FP64 refinement",
             "n_cells": model.n,
             "fractures_always_active": not args.localize_fractures,
             "krylov_dtype": "f32",
             "parallelism": "1 GPU",
         },
-        "local": {"iterations": loc["iters"], "sum_active": loc["active"],
-                  "avg_ma": loc["active"] / model.n / loc["iters"],
-                  "krylov_iters": loc["krylov"], "wall_s": loc["wall"],
-                  "newton_step_ms_p50": loc["p50"], "newton_step_ms_p99": loc["p99"],
-                  "timestep_ms_p50": loc["step_p50"], "timestep_ms_p99": loc["step_p99"]},
+        "local": _leg(loc, model),
     }
-    if full is not None:
-        dp = float(np.abs(full["u"][0] - loc["u"][0]).max())
-        out["full"] = {"iterations": full["iters"], "updates_per_s": full["active"] / full["wall"],
-                       "krylov_iters": full["krylov"], "wall_s": full["wall"],
-                       "newton_step_ms_p50": full["p50"], "newton_step_ms_p99": full["p99"]}
-        out["speedup_local_vs_full"] = full["wall"] / loc["wall"]
-        out["max_dp_local_vs_full_psi"] = dp / PSI
-    if dd is not None:
-        out["dd"] = {"inner_iterations": dd["iters"], "sum_active": dd["active"],
-                     "updates_per_s": dd["active"] / dd["wall"], "krylov_iters": dd["krylov"],
-                     "wall_s": dd["wall"], "newton_step_ms_p50": dd["p50"],
-                     "newton_step_ms_p99": dd["p99"],
-                     "speedup_vs_full": full["wall"] / dd["wall"],
-                     "max_dp_vs_full_psi": float(np.abs(full["u"][0] - dd["u"][0]).max()) / PSI}
-    if res is not None:
-        out["resid"] = {"iterations": res["iters"], "sum_active": res["active"],
-                        "avg_ma": res["active"] / model.n / res["iters"],
-                        "updates_per_s": res["active"] / res["wall"],
-                        "krylov_iters": res["krylov"], "wall_s": res["wall"],
-                        "newton_step_ms_p50": res["p50"], "newton_step_ms_p99": res["p99"],
-                        "speedup_vs_full": full["wall"] / res["wall"],
-                        "local_speedup_vs_resid": res["wall"] / loc["wall"],
-                        "max_dp_vs_full_psi":
-                            float(np.abs(full["u"][0] - res["u"][0]).max()) / PSI}
-    # roofline of the dominant matrix kernel (local run, events on its stream)
+    if legs:
+        fw = legs["full"]["wall"]
+        out["local"].update(speedup_vs_full=fw / loc["wall"],
+                            max_rel_dp_vs_tight_ref=_rel_dp(loc["u"], ref),
+                            max_dp_vs_tight_ref_psi=_max_dp_psi(loc["u"], ref),
+                            max_rel_dp_mixed_vs_fp64=_rel_dp(loc["u"], legs["local_fp64"]["u"]))
+        out["full"] = _leg(legs["full"], model, ref=ref)
+        out["dd"] = _leg(legs["dd"], model, fw, ref)
+        out["resid"] = _leg(legs["resid"], model, fw, ref)
+        out["resid"]["local_speedup_vs_resid"] = legs["resid"]["wall"] / loc["wall"]
+        out["local_fp64"] = _leg(legs["local_fp64"], model, fw, ref)
+        out["speedup_local_vs_full"] = fw / loc["wall"]
+        out["accuracy_reference"] = ("tight-mode FP64 full Newton (eps 1e-7 psi, linear rtol "
+                                     "1e-12) over the same steps from the same initial state")
     prof = prof_run["prof"] if prof_run else None
     if prof:
         copy = copy_bandwidth()
         roof = roofline_of(prof, model.b)
-        per_row = measured_traffic_per_row().get(roof["kernel"])
+        per_row = measured_traffic_per_row(workload).get(roof["kernel"])
         out["roofline"] = {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac")}
-        # counter-measured bytes per launch (FETCH_SIZE + WRITE_SIZE scaled by a
-        # plain copy, per row, times this run's rows per launch); None once the
-        # kernels changed since the counters were taken
+        # counter-measured HBM bytes per launch (FETCH_SIZE + WRITE_SIZE scaled
+        # by a plain copy, per row, times this run's rows per launch); None
+        # once the kernels changed since the counters were taken
         out["roofline"]["traffic"] = per_row * roof["rows_per_launch"] if per_row else None
-        out["roofline"].update({k: roof[k] for k in ("kernel", "avg_launch_us",
-                                                     "bytes_per_launch", "rows_per_launch")})
+        out["roofline"].update({k: v for k, v in roof.items() if k not in out["roofline"]})
         out["roofline"].update(copy_gbps=copy, frac_of_copy=roof["achieved"] / copy,
                                profiled_wall_s=prof_run["wall"])
         out["kernel_profile_local"] = prof
-    if full_prof is not None:
-        out["roofline_full_newton"] = roofline_of(full_prof["prof"], model.b)
     if args.calibrate_copy:
         # one plain device-to-device copy of known size (memory-counter scale)
         n_el = args.calibrate_copy * 2**20 // 4
@@ -560,8 +583,57 @@ def main():
         del src, dst
     if not args.no_cpu:
         log("oracle CPU baseline")
-        out["cpu_baseline"] = cpu_baseline(log)
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = cpu_baseline(log, workload, W, K)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--localize-fractures", action="store_true",
+                    help="fracture cells not always active (only perforated cells are); "
+                         "the default keeps them active as in the paper's runs")
+    ap.add_argument("--members", type=int, default=256)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
+    ap.add_argument("--budget-gib", type=float, default=64.0)
+    ap.add_argument("--pool", default="256,64,16",
+                    help="serving: config-1,2,3 session counts")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-full", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device to device once (a plain copy "
+                         "kernel of known size for scaling memory counters)")
+    ap.add_argument("--profile", type=int, default=1,
+                    help="replay the timed localized steps with per-kernel hipEvents")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU design is documented, not built)", file=sys.stderr)
+        sys.exit(2)
+    if args.workload in ("c4", "c5"):
+        # the ensemble and serving pools are generated in worker processes
+        # before this process touches the GPU
+        if args.workload == "c4":
+            models = _pool_models(_member, list(range(args.members)))
+        else:
+            pool = tuple(int(v) for v in args.pool.split(","))
+            ids = ([(1, k) for k in range(pool[0])] + [(2, k) for k in range(pool[1])]
+                   + [(3, k) for k in range(pool[2])])
+            models = _pool_models(_c5_session, ids)
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    torch.cuda.set_device(0)
+    if args.workload == "c4":
+        print(json.dumps(run_c4(models, max(1, args.steps))), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(run_c5(models, ids, args.serve_seconds, pool, args.budget_gib)),
+              flush=True)
+        return
+    print(json.dumps(run_single(args.workload, args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -71,8 +71,10 @@ class JacobianBuilder:
         self.by_colour = [np.nonzero(self.colour[self.pair_j] == c)[0]
                           for c in range(self.ncol)]
 
-    def build(self, u, status, m_old, dt, h=1e-30):
-        """Return (R, J): R (b, n) real, J scipy CSR (b n x b n)."""
+    def build(self, u, status, m_old, dt, h=1e-30, variables=None):
+        """Return (R, J): R (b, n) real, J scipy CSR (b n x b n).
+        ``variables``: the unknowns (0 = pressure, ...) whose columns are
+        formed; the other columns are left empty (default: all)."""
         b, n = self.b, self.n
         R = residual(self.model, u, status, m_old, dt)
         rr, cc, vv = [], [], []
@@ -80,7 +82,7 @@ class JacobianBuilder:
             sel = self.by_colour[c]
             pi, pj = self.pair_i[sel], self.pair_j[sel]
             cells = np.nonzero(self.colour == c)[0]
-            for v in range(b):
+            for v in (range(b) if variables is None else variables):
                 scale = np.maximum(1.0, np.abs(u[v][cells]))
                 uc = u.astype(np.complex128)
                 uc[v, cells] += 1j * h * scale

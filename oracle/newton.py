@@ -2,7 +2,8 @@
 
 Section 4.1: at each timestep, given u^n and dt, solve F(u^{n+1}) = 0 by
 Newton iterates J(u^nu) du^nu = -F(u^nu), u^{nu+1} = u^nu + du^nu.  The
-linear systems are solved by SuperLU (scipy.sparse.linalg.splu) in FP64.
+linear systems are solved by SuperLU (scipy.sparse.linalg.splu, COLAMD column
+ordering, partial pivoting) in FP64.
 Section 5 states the convergence test ||dp||_inf < eps_p.
 
 Readings where the paper is silent (shared with the HIP library):
@@ -127,7 +128,7 @@ class Solver:
             J = J[rows][:, rows]
             rhs = rhs[rows]
         try:
-            lu = spla.splu(J.tocsc(), permc_spec="MMD_AT_PLUS_A")
+            lu = spla.splu(J.tocsc(), permc_spec="COLAMD")
         except RuntimeError:
             # a singular (or non-finite) Jacobian: the iteration fails like
             # one that produced non-finite values
