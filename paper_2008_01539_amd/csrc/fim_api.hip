@@ -150,6 +150,7 @@ struct fim_model {
     bool use_pc = false;
     int pc_cap = 0;                 // rows per block
     int pc_grid = KB_MAXB;          // Krylov workgroups with fracture blocks (2 per CU)
+    int pc_grid_wide = KB_MAXB;     // the same in the three-per-CU FP32 variant
     int *frac_id = nullptr, *ford = nullptr, *pcinfo = nullptr, *pcoff = nullptr;
     int* pclist = nullptr;          // multi-row blocks: (first row, rows) pairs
     int pc_inv_grid = 0;            // workgroups of the inversion launch
@@ -444,6 +445,7 @@ struct Group {
     std::vector<int> idx;   // items in this group
     int nblk = 0;
     bool pc = false;        // some model uses fracture blocks
+    bool wide = false;      // FP32 with fracture blocks, more tiles than 2 per CU
 };
 
 static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
@@ -451,6 +453,16 @@ static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
     std::vector<KSeg> segs;
     std::vector<int> blk;
     int off = 0;
+    // FP32 launches with fracture blocks and more 256-row tiles than two
+    // resident workgroups per CU cover use the three-per-CU variant (its
+    // grid cap is larger)
+    G.pc = false;
+    long tiles = 0;
+    for (int q : G.idx) {
+        G.pc = G.pc || items[q].m->use_pc;
+        tiles += krylov_grid(items[q].m->nA, KB_MAXB);
+    }
+    G.wide = G.pc && g == 0 && tiles > lead->pc_grid;
     for (int q : G.idx) {
         SolveItem& it = items[q];
         fim_model* m = it.m;
@@ -459,7 +471,8 @@ static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
         k.kb = kbufs(m, g == 0);
         k.nA = m->nA;
         k.blk0 = off;
-        k.nblk = krylov_grid(m->nA, m->use_pc ? m->pc_grid : KB_MAXB);
+        k.nblk = krylov_grid(m->nA, m->use_pc ? (G.wide ? m->pc_grid_wide : m->pc_grid)
+                                              : KB_MAXB);
         k.active = it.active ? 1 : 0;
         k.tol2 = it.tol2;
         k.bnorm2 = it.bnorm2;
@@ -470,8 +483,6 @@ static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
         segs.push_back(k);
     }
     G.nblk = off;
-    G.pc = false;
-    for (int q : G.idx) G.pc = G.pc || items[q].m->use_pc;
     if (segs.empty()) return fim_status(FIM_OK);
     fim_model* m = lead;
     KSeg* hs = t.hsegs + (size_t)g * t.cap;
@@ -636,7 +647,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                                          t.dsegs + (size_t)g * t.cap,
                                          t.dblk + (size_t)g * t.cap * KB_MAXB, G[g].nblk,
                                          first_it + c, s, q >= 0 ? lead->prof.pend[q].a : nullptr,
-                                         q >= 0 ? lead->prof.pend[q].b : nullptr, rec);
+                                         q >= 0 ? lead->prof.pend[q].b : nullptr, rec, G[g].wide);
                         if (q >= 0) lead->prof.pend[q].rows = lead->nA;
                     }
         };
@@ -1169,6 +1180,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             cus > 0) {
             m->pc_grid = std::min(KB_MAXB, 2 * cus);
+            m->pc_grid_wide = std::min(KB_MAXB, 3 * cus);
             m->cus = cus;
         }
         m->dev = dev;

@@ -204,10 +204,12 @@ void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int
 // refinement sums zero); may be the device address of coherent pinned host
 // memory
 struct SegStatus;
+// wide (FP32 with fracture blocks only): the launch has more workgroups
+// than two per CU; a variant with three resident per CU runs it
 void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSeg* segs,
                       const int* blk_seg, int nblk_total, int it, hipStream_t s,
                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
-                      SegStatus* rec = nullptr);
+                      SegStatus* rec = nullptr, bool wide = false);
 void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,
                           int nblk_total, hipStream_t s);
 

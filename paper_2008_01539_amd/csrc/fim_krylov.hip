@@ -64,25 +64,49 @@ template <typename V>
 __device__ inline void stg(void* base, unsigned off, V v) {
     *(FIM_GLOBAL V*)((FIM_GLOBAL char*)base + off) = v;
 }
+// N consecutive values of T at a byte offset, moved as vectors of up to 16
+// bytes that are only T-aligned (dwordx2/x3/x4 memory instructions): one
+// instruction per row vector instead of one per component.  Element-wise
+// accesses through a 32-bit offset are not merged by the compiler (the
+// offset arithmetic may wrap as far as it can tell).
+template <typename T, int K>
+using vec_of = T __attribute__((ext_vector_type(K), aligned(sizeof(T))));
+
+template <int N, typename T>
+__device__ inline void ldn(T* d, const void* base, unsigned off) {
+    constexpr int K = (int)(16 / sizeof(T)) < N ? (int)(16 / sizeof(T)) : N;
+    const vec_of<T, K> v = ldg<vec_of<T, K>>(base, off);
+#pragma unroll
+    for (int c = 0; c < K; c++) d[c] = v[c];
+    if constexpr (N > K) ldn<N - K, T>(d + K, base, off + K * (unsigned)sizeof(T));
+}
+template <int N, typename T>
+__device__ inline void stn(void* base, unsigned off, const T* d) {
+    constexpr int K = (int)(16 / sizeof(T)) < N ? (int)(16 / sizeof(T)) : N;
+    vec_of<T, K> v;
+#pragma unroll
+    for (int c = 0; c < K; c++) v[c] = d[c];
+    stg<vec_of<T, K>>(base, off, v);
+    if constexpr (N > K) stn<N - K, T>(base, off + K * (unsigned)sizeof(T), d + K);
+}
 template <int B, typename T>
 __device__ inline void ldv(T (&d)[B], const void* base, unsigned off) {
-#pragma unroll
-    for (int c = 0; c < B; c++) d[c] = ldg<T>(base, off + c * (unsigned)sizeof(T));
+    ldn<B, T>(d, base, off);
 }
 template <int B, typename T>
 __device__ inline void stv(void* base, unsigned off, const T (&v)[B]) {
-#pragma unroll
-    for (int c = 0; c < B; c++) stg<T>(base, off + c * (unsigned)sizeof(T), v[c]);
+    stn<B, T>(base, off, v);
 }
 
 // Neighbour slots fetched together: enough to keep the raw operands of a
 // chunk within about 104 VGPRs (column offsets, blocks and NV gathered
 // vectors per slot), at most 8.
-template <int B, typename T, int NV>
+constexpr int CHUNK_BUDGET = 104;
+template <int B, typename T, int NV, int BUDGET = CHUNK_BUDGET>
 constexpr int chunk_slots() {
     constexpr int w = (int)sizeof(T) / 4;
     constexpr int per = 1 + (B * B + NV * B) * w;
-    constexpr int u = 104 / per;
+    constexpr int u = BUDGET / per;
     return u < 2 ? 2 : (u > 8 ? 8 : u);
 }
 
@@ -91,9 +115,16 @@ constexpr int chunk_slots() {
 // more registers than that leaves.
 template <int B, typename T>
 constexpr int kbp_waves() { return (B == 3 && sizeof(T) == 8) ? 2 : 3; }
-// with the fracture-block step fused in (PC), two waves per SIMD
-template <int B, typename T, bool PC>
-constexpr int kb_waves() { return PC ? 2 : kbp_waves<B, T>(); }
+// With the fracture-block step fused in (PC), two waves per SIMD; the WIDE
+// FP32 variant runs three (smaller neighbour chunks, chunk_budget) so that
+// systems of up to 3 x 64 x 4 x CUs rows take one pass of resident
+// workgroups instead of a second, mostly idle one.
+template <int B, typename T, bool PC, bool WIDE>
+constexpr int kb_waves() {
+    return PC ? ((WIDE && sizeof(T) == 4) ? 3 : 2) : kbp_waves<B, T>();
+}
+template <typename T, bool PC, bool WIDE>
+constexpr int chunk_budget() { return (PC && WIDE && sizeof(T) == 4) ? 48 : CHUNK_BUDGET; }
 
 // Slot geometry of row r: slot k at base + 64 k; width slots are in use
 // (the slice's widest row; narrower rows are padded with column r and a
@@ -152,8 +183,7 @@ __device__ inline void fetch_chunk(const LocalSys& ls, const T* At, const RowGeo
         const bool pad = sizeof(T) == 4 && cl[u] == g.row;
         if (k < g.width && !pad) {
             const unsigned ab = (g.base + k * SLICE) * (BB * (unsigned)sizeof(T));
-#pragma unroll
-            for (unsigned q = 0; q < BB; q++) ch.a[u][q] = ldg<T>(At, ab + q * (unsigned)sizeof(T));
+            ldn<(int)BB, T>(ch.a[u], At, ab);
 #pragma unroll
             for (int v = 0; v < NV; v++) ldv<B, T>(ch.xn[v][u], src[v], cl[u] * RB);
         } else {
@@ -462,8 +492,8 @@ __device__ inline void put_status(SegStatus* o, double rr, int done, int iters, 
 // update) at the iteration cap or when omega = 0.  The own-row operands
 // and the first chunk of neighbour slots are fetched before the previous
 // kernel's partial sums are reduced, so those loads overlap the reduction.
-template <int B, typename T, bool FIRST, bool SOLO, bool PC>
-__global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const KSeg* __restrict__ segs,
+template <int B, typename T, bool FIRST, bool SOLO, bool PC, bool WIDE>
+__global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_p(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
                                                                       int it) {
     const KSeg& S = seg_of<SOLO>(segs, blk_seg);
@@ -489,7 +519,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const 
     const int r0 = lb * blockDim.x + threadIdx.x;
     const int stride = nbk * blockDim.x;
     constexpr int NV = FIRST ? 1 : 4;
-    constexpr int U = chunk_slots<B, T, NV>();
+    constexpr int U = chunk_slots<B, T, NV, chunk_budget<T, PC, WIDE>()>();
     constexpr unsigned RB = B * sizeof(T);
     const T* src[NV];
     if constexpr (FIRST) {
@@ -625,8 +655,8 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_p(const 
 // |r_i|^2 <= tol2 (x_i is the answer) or on a breakdown of sigma; else
 // alpha = rho_i / sigma, s = r_i - alpha v_i, t = A~ s (s rebuilt at the
 // neighbours).  Partial sums: (t,s), (t,t), (rh,s), (rh,t).
-template <int B, typename T, bool SOLO, bool PC>
-__global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const KSeg* __restrict__ segs,
+template <int B, typename T, bool SOLO, bool PC, bool WIDE>
+__global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_s(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
                                                                       int it,
                                                                       SegStatus* __restrict__ rec) {
@@ -657,7 +687,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC>())) void k_bicg_s(const 
         return;
     }
     constexpr int NV = 2;
-    constexpr int U = chunk_slots<B, T, NV>();
+    constexpr int U = chunk_slots<B, T, NV, chunk_budget<T, PC, WIDE>()>();
     constexpr unsigned RB = B * sizeof(T);
     const T* const src[NV] = {V.r, V.v_new};
     const int r0 = lb * blockDim.x + threadIdx.x;
@@ -777,21 +807,32 @@ void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s) {
 
 // ev0/ev1 (optional): events stamped by the dispatch itself
 // (hipExtLaunchKernelGGL), i.e. the kernel's own start and end
-template <int B, typename T, bool SOLO, bool PC>
-static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
-                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, SegStatus* rec) {
+template <int B, typename T, bool SOLO, bool PC, bool WIDE>
+static void part_impl_w(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
+                        hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, SegStatus* rec) {
     const dim3 nb(nblk_total), nt(KB_NT);
     if (which == 0) {
         if (it == 0)
-            hipExtLaunchKernelGGL(k_bicg_p<B, T, true, SOLO, PC>, nb, nt, 0, s, ev0, ev1, 0, segs,
-                                  blk_seg, it);
-        else
-            hipExtLaunchKernelGGL(k_bicg_p<B, T, false, SOLO, PC>, nb, nt, 0, s, ev0, ev1, 0,
+            hipExtLaunchKernelGGL(k_bicg_p<B, T, true, SOLO, PC, WIDE>, nb, nt, 0, s, ev0, ev1, 0,
                                   segs, blk_seg, it);
+        else
+            hipExtLaunchKernelGGL(k_bicg_p<B, T, false, SOLO, PC, WIDE>, nb, nt, 0, s, ev0, ev1,
+                                  0, segs, blk_seg, it);
     } else {
-        hipExtLaunchKernelGGL(k_bicg_s<B, T, SOLO, PC>, nb, nt, 0, s, ev0, ev1, 0, segs, blk_seg,
-                              it, rec);
+        hipExtLaunchKernelGGL(k_bicg_s<B, T, SOLO, PC, WIDE>, nb, nt, 0, s, ev0, ev1, 0, segs,
+                              blk_seg, it, rec);
     }
+}
+
+// wide: the launch has more tiles than two resident workgroups per CU
+// cover (FP32 with fracture blocks: the three-wave variant)
+template <int B, typename T, bool SOLO, bool PC>
+static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
+                      hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, SegStatus* rec, bool wide) {
+    if (PC && wide && sizeof(T) == 4)
+        part_impl_w<B, T, SOLO, PC, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1, rec);
+    else
+        part_impl_w<B, T, SOLO, PC, false>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1, rec);
 }
 
 int krylov_grid(int nA, int cap) { return std::min(kgrid(nA), std::max(1, cap)); }
@@ -852,23 +893,23 @@ void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int
 
 void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSeg* segs,
                       const int* blk_seg, int nblk_total, int it, hipStream_t s, hipEvent_t ev0,
-                      hipEvent_t ev1, SegStatus* rec) {
+                      hipEvent_t ev1, SegStatus* rec, bool wide) {
     if (nblk_total <= 0) return;
 #define PI(BV, TT)                                                                             \
     do {                                                                                       \
         if (solo) {                                                                            \
             if (pc)                                                                            \
-                part_impl<BV, TT, true, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1, rec); \
+                part_impl<BV, TT, true, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1, rec, wide); \
             else                                                                               \
                 part_impl<BV, TT, true, false>(which, segs, blk_seg, nblk_total, it, s, ev0,   \
-                                               ev1, rec);                                           \
+                                               ev1, rec, wide);                                     \
         } else {                                                                               \
             if (pc)                                                                            \
                 part_impl<BV, TT, false, true>(which, segs, blk_seg, nblk_total, it, s, ev0,   \
-                                               ev1, rec);                                           \
+                                               ev1, rec, wide);                                     \
             else                                                                               \
                 part_impl<BV, TT, false, false>(which, segs, blk_seg, nblk_total, it, s, ev0,  \
-                                                ev1, rec);                                          \
+                                                ev1, rec, wide);                                    \
         }                                                                                      \
     } while (0)
     KDISPATCH(PI)
