@@ -16,6 +16,10 @@ Readings where the paper is silent (shared with the HIP library):
 * the initial active set is the fracture/perforated cells and their m-layer
   neighbourhood on the first step, then the previous step's support
   {|p^n - p^{n-1}| >= eps_loc} plus the always-active cells;
+* with localized fracture cells (not all fracture cells always active),
+  every active set of Algorithm 1 is closed under fracture components
+  (sets.frac_closure); Algorithm 2 and the residual-based mode leave the
+  fracture cells as the model marks them;
 * Algorithm 2: each visit of a subdomain is one Newton iteration on it;
   last_dp[i] holds |dp_i| from the latest solve that touched cell i; a
   subdomain is skipped when last_dp < eps on V_A^k and on its outer layer;
@@ -67,6 +71,12 @@ class LocalSolver(Solver):
         super().__init__(model, opts)
         self.rp, self.nb = adjacency(model)
         self.aa = np.nonzero(model.always_active)[0]
+        # localized fracture cells (some fracture cell not always active):
+        # Algorithm 1's sets are closed under fracture components
+        frac = model.kind == 1
+        self.fcomp = None
+        if np.any(frac & (model.always_active == 0)):
+            self.fcomp = sets.fracture_components(self.rp, self.nb, frac)
 
     # ------------------------------------------------------ Algorithm 1
     def alg1_timestep(self, st: State, dt, prev_support, log=None):
@@ -74,7 +84,7 @@ class LocalSolver(Solver):
         m_old = accumulation(self.model, st.u, st.status)
         work = st.copy()
         act = sets.initial_active(self.rp, self.nb, self.aa, o.m_layers,
-                                  prev_support)
+                                  prev_support, self.fcomp)
         bnd = sets.boundary(self.rp, self.nb, act)
         is_expand, conv = True, False
         it = 0
@@ -90,7 +100,7 @@ class LocalSolver(Solver):
             if log is not None:
                 log.append(dict(n_a=n_a, n_b=len(bnd), dp=float(dp.max())))
             act, bnd, is_expand = sets.alg1_update(
-                self.rp, self.nb, act, bnd, dp, o.eps_loc, o.m_layers, self.aa)
+                self.rp, self.nb, act, bnd, dp, o.eps_loc, o.m_layers, self.aa, self.fcomp)
         support = set(np.nonzero(np.abs(work.u[0] - st.u[0]) >= o.eps_loc)[0].tolist())
         return work, it, support
 

@@ -15,7 +15,16 @@ Definitions (Section 4.3):
   set adjacent to it;
 * the residual-based estimate that Sections 1 and 4.2 attribute to Lu and
   Beckner: the unconverged cells (error measure at or above a tolerance)
-  inflated by a fixed number of neighbour layers, one by default.
+  inflated by a fixed number of neighbour layers, one by default;
+* localized fracture cells (Section 5.2.3 keeps fracture cells active and
+  notes that localizing them would save more work): fracture cells that
+  are not always active join the active set a whole fracture component at
+  a time -- a component being the fracture cells connected through
+  fracture-fracture connections (intersections included) -- because a
+  pressure change crosses such a component within one step while the
+  m-layer growth advances m cells per iteration.  Every active set of
+  Algorithm 1 is closed under components (frac_closure); with all fracture
+  cells always active the closure changes nothing.
 
 Everything here is the plain definition over Python sets; nothing is
 vectorized.
@@ -59,27 +68,64 @@ def outer_layer(rp, nb, act):
     return out
 
 
-def initial_active(rp, nb, always_active, m, prev_support=None):
+def fracture_components(rp, nb, is_frac):
+    """Connected components of the fracture cells over fracture-fracture
+    connections: (comp, members) with comp[i] the component of cell i (-1
+    for matrix cells) and members[c] the set of cells of component c."""
+    n = len(is_frac)
+    comp = [-1] * n
+    members = []
+    for i in range(n):
+        if not is_frac[i] or comp[i] >= 0:
+            continue
+        c = len(members)
+        comp[i] = c
+        todo, cells = [i], {i}
+        while todo:
+            a = todo.pop()
+            for j in neighbours(rp, nb, a):
+                j = int(j)
+                if is_frac[j] and comp[j] < 0:
+                    comp[j] = c
+                    cells.add(j)
+                    todo.append(j)
+        members.append(cells)
+    return comp, members
+
+
+def frac_closure(act, comp, members):
+    """The set plus every fracture component it touches."""
+    out = set(act)
+    for c in {comp[i] for i in act if comp[i] >= 0}:
+        out |= members[c]
+    return out
+
+
+def initial_active(rp, nb, always_active, m, prev_support=None, fcomp=None):
     """Initial V_A.  First step: the wells / fractures and their m-layer
     neighbourhood (Section 4.3 remark on the initial set); later steps:
     the support of the previous timestep plus the always-active cells
-    (Section 5.2.1 takes the last timestep's support)."""
+    (Section 5.2.1 takes the last timestep's support).  fcomp: the
+    (comp, members) pair of localized fracture cells, or None."""
     aa = {int(i) for i in always_active}
     if prev_support is None:
         out = set()
         for i in aa:
             out |= ball(rp, nb, i, m)
-        return out
-    return {int(i) for i in prev_support} | aa
+    else:
+        out = {int(i) for i in prev_support} | aa
+    return frac_closure(out, *fcomp) if fcomp else out
 
 
-def alg1_update(rp, nb, act, bnd, dp_abs, eps, m, always_active):
+def alg1_update(rp, nb, act, bnd, dp_abs, eps, m, always_active, fcomp=None):
     """One pass of the set logic of Algorithm 1 after a local solve.
 
     For each boundary cell with a non-negligible update, V_A grows by its
     m-layer neighbourhood ('expand').  If no boundary update is
     non-negligible, V_A becomes the support of the update plus the
-    always-active cells ('shrink').  Returns (act, bnd, is_expand)."""
+    always-active cells ('shrink').  With localized fracture cells (fcomp)
+    the new set is closed under fracture components.  Returns (act, bnd,
+    is_expand)."""
     new = set(act)
     is_expand = False
     for i in bnd:
@@ -88,6 +134,8 @@ def alg1_update(rp, nb, act, bnd, dp_abs, eps, m, always_active):
             new |= ball(rp, nb, i, m)
     if not is_expand:
         new = {i for i in act if dp_abs[i] >= eps} | {int(i) for i in always_active}
+    if fcomp:
+        new = frac_closure(new, *fcomp)
     return new, boundary(rp, nb, new), is_expand
 
 

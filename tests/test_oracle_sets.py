@@ -152,6 +152,55 @@ def test_alg2_sweep_cap():
     assert bad is None
 
 
+def _fractured_chain():
+    """Matrix chain 0..7; fracture A = cells 8-9-10 (8-9, 9-10), hosted by
+    matrix cells 2, 3, 4; fracture B = cells 11-12, intersecting A at 10
+    (10-11) and hosted by 5, 6; fracture C = cell 13 alone, hosted by 7."""
+    edges = [(i, i + 1) for i in range(7)]
+    edges += [(8, 9), (9, 10), (10, 11), (11, 12)]
+    edges += [(2, 8), (3, 9), (4, 10), (5, 11), (6, 12), (7, 13)]
+    rp, nb = _csr(14, edges)
+    is_frac = np.array([0] * 8 + [1] * 6, bool)
+    return rp, nb, is_frac
+
+
+def test_fracture_components_and_closure_by_hand():
+    """Localized fracture cells: components through fracture-fracture
+    connections (the intersection 10-11 joins A and B), and the closure of
+    a set under them."""
+    rp, nb, is_frac = _fractured_chain()
+    comp, members = S.fracture_components(rp, nb, is_frac)
+    assert comp[:8] == [-1] * 8
+    assert members == [{8, 9, 10, 11, 12}, {13}]
+    assert comp[12] == 0 and comp[13] == 1
+    assert S.frac_closure({1, 9}, comp, members) == {1, 8, 9, 10, 11, 12}
+    assert S.frac_closure({1, 2, 3}, comp, members) == {1, 2, 3}
+    assert S.frac_closure({13, 0}, comp, members) == {0, 13}
+
+
+def test_alg1_update_with_localized_fractures():
+    """An expansion whose ball reaches one fracture cell takes the whole
+    component; a shrink keeps whole components; the initial set is closed
+    too."""
+    rp, nb, is_frac = _fractured_chain()
+    fc = S.fracture_components(rp, nb, is_frac)
+    act = {0, 1}
+    bnd = S.boundary(rp, nb, act)
+    dp = np.zeros(14)
+    dp[1] = 5.0
+    new, vb, ex = S.alg1_update(rp, nb, act, bnd, dp, 1.0, 1, [0], fc)
+    assert ex and new == {0, 1, 2}                  # 2 hosts fracture cell 8 ...
+    new, vb, ex = S.alg1_update(rp, nb, act, bnd, dp, 1.0, 2, [0], fc)
+    assert ex and new == {0, 1, 2, 3} | {8, 9, 10, 11, 12}   # ... reached at m = 2
+    assert vb == {3, 10, 11, 12}   # 10, 11, 12 border their inactive hosts 4..6
+    dp[:] = 0.0
+    dp[9] = 2.0
+    new, vb, ex = S.alg1_update(rp, nb, {0, 1, 8, 9}, set(), dp, 1.0, 1, [0], fc)
+    assert not ex and new == {0, 8, 9, 10, 11, 12}  # shrink, then closure
+    assert S.initial_active(rp, nb, [13], 1, None, fc) == {7, 13}
+    assert S.initial_active(rp, nb, [0], 1, {10}, fc) == {0, 8, 9, 10, 11, 12}
+
+
 def test_work_ratio_definition_matches_paper_tables():
     """M_A per iteration is n_A / n; the tables' average column equals the
     total divided by the iteration count (to the printed rounding)."""
