@@ -487,14 +487,14 @@ def run_single(workload, args):
         print(f"bench.py: warmup + steps = {args.warmup + args.steps} exceeds the "
               f"{L}-step schedule of {workload}", file=sys.stderr)
         sys.exit(2)
+    # fracture cells localized too: only perforated cells always active
+    aa = np.zeros_like(model.always_active)
+    aa[np.asarray(model.perf_cell, dtype=np.int64)] = 1
+    model_lf = model.copy_with(always_active=aa)
     if args.localize_fractures:
-        aa = np.zeros_like(model.always_active)
-        aa[np.asarray(model.perf_cell, dtype=np.int64)] = 1
-        model.always_active = aa
+        model = model_lf
     log(f"n={model.n} connections={model.nc}")
     opts = P.Options(precision=P.MIXED)
-    if args.localize_fractures:
-        opts.max_newton = 400
     W, K = args.warmup, args.steps
     log(f"localized Newton: warm-up steps 0..{W - 1}, timed steps {W}..{W + K - 1}")
     loc = run_gpu(model, opts, P.LOCAL, K, W)
@@ -511,6 +511,9 @@ def run_single(workload, args):
             legs[name] = run_gpu(model, opts, mode, K, W)
             log(f"{name}: {legs[name]['iters']} iterations, wall {legs[name]['wall']:.3f}s, "
                 f"krylov {legs[name]['krylov']}")
+        if not args.localize_fractures:
+            legs["local_frac"] = run_gpu(model_lf, opts, P.LOCAL, K, W)
+            log(f"local, fracture cells localized: wall {legs['local_frac']['wall']:.3f}s")
         legs["local_fp64"] = run_gpu(model, P.Options(precision=P.FP64), P.LOCAL, K, W)
         log(f"local FP64: wall {legs['local_fp64']['wall']:.3f}s")
         ref = run_gpu(model, P.Options.tight_mode(precision=P.FP64), P.FULL, K, W)["u"]
@@ -554,6 +557,10 @@ def run_single(workload, args):
         out["resid"] = _leg(legs["resid"], model, fw, ref)
         out["resid"]["local_speedup_vs_resid"] = legs["resid"]["wall"] / loc["wall"]
         out["local_fp64"] = _leg(legs["local_fp64"], model, fw, ref)
+        if "local_frac" in legs:
+            # NEXT-1 of the scope: fracture cells localized as well, the
+            # active sets closed under fracture components
+            out["local_localized_fractures"] = _leg(legs["local_frac"], model, fw, ref)
         out["speedup_local_vs_full"] = fw / loc["wall"]
         out["accuracy_reference"] = ("tight-mode FP64 full Newton (eps 1e-7 psi, linear rtol "
                                      "1e-12) over the same steps from the same initial state")

@@ -189,6 +189,14 @@ struct fim_model {
     int cur_nnzb = 0;   // blocks of the current local matrix (profiling)
     double cur_pcn2 = 0.0;   // sum of N^2 over its fracture blocks (profiling)
     bool flags_on = false;
+    // localized fracture cells (some fracture cell not always active):
+    // Algorithm 1's sets are closed under fracture components; fcells
+    // lists the fracture cells, fcomp their components, ftouch one flag
+    // per component
+    bool fclose = false;
+    int nfcell = 0, ncomp = 0;
+    int *fcells = nullptr, *fcomp = nullptr;
+    uint8_t* ftouch = nullptr;
     // auto_cut: the state, phase status and support set on entry to
     // fim_solve_timestep, restored when the last substep fails
     double* usave = nullptr;
@@ -884,6 +892,13 @@ static fim_status prepare_active(fim_model* m, bool need_bnd) {
     return FIM_OK;
 }
 
+// Localized fracture cells: close the active flags under fracture
+// components (Algorithm 1 only; a no-op without localized fracture cells).
+static void frac_closure(fim_model* m) {
+    if (m->fclose)
+        launch_frac_closure(m->nfcell, m->fcells, m->fcomp, m->ncomp, m->ftouch, m->act, m->s);
+}
+
 static fim_status begin_step(fim_model* m, double dt, int mode) {
     const int pi = pbeg(m, PK_SETUP);
     launch_copy_state(m->B, m->n, m->u, m->st, m->un, m->stn, m->s);
@@ -916,6 +931,7 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
         launch_fill_u8(m->act, m->n, 0, m->s);
         launch_mark_seeds(m->n, m->g, layers, m->act, m->lvl, m->s);
     }
+    if (mode == FIM_LOCAL) frac_closure(m);
     if (mode == FIM_DD) {
         launch_fill_f64(m->last_dp, m->n, 0.0, m->s);
         HIPX(hipMemcpyAsync(m->vt, m->act, m->n, hipMemcpyDeviceToDevice, m->s));
@@ -1098,7 +1114,8 @@ static void free_all(fim_model* m) {
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
                     m->part_ir, m->classes, m->frac_id, m->ford, m->pcinfo, m->pcoff,
-                    m->pcM, m->pclist, m->lvl, m->usave, m->stsave, m->suppsave};
+                    m->pcM, m->pclist, m->lvl, m->usave, m->stsave, m->suppsave,
+                    m->fcells, m->fcomp, m->ftouch};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (m->hsc) (void)hipHostFree(m->hsc);
@@ -1334,6 +1351,50 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
         CK(dal(m, &m->stsave, nn));
         CK(dal(m, &m->suppsave, nn));
     }
+    if (d->frac_id) {
+        // fracture components (connected over fracture-fracture
+        // connections), needed when some fracture cell is not always active
+        std::vector<int> comp(n, -1), fc, fcc;
+        bool any_loc = false;
+        for (int i = 0; i < n; i++) any_loc = any_loc || (d->frac_id[i] >= 0 && !(fl[i] & CF_AA));
+        if (any_loc) {
+            int nc = 0;
+            std::vector<int> todo;
+            for (int i = 0; i < n; i++) {
+                if (d->frac_id[i] < 0 || comp[i] >= 0) continue;
+                comp[i] = nc;
+                todo.assign(1, i);
+                while (!todo.empty()) {
+                    const int a = todo.back();
+                    todo.pop_back();
+                    for (int q = deg[a]; q < deg[a + 1]; q++) {
+                        const int j = nbr[q];
+                        if (d->frac_id[j] >= 0 && comp[j] < 0) {
+                            comp[j] = nc;
+                            todo.push_back(j);
+                        }
+                    }
+                }
+                nc++;
+            }
+            for (int i = 0; i < n; i++)
+                if (comp[i] >= 0) {
+                    fc.push_back(i);
+                    fcc.push_back(comp[i]);
+                }
+            m->fclose = true;
+            m->nfcell = (int)fc.size();
+            m->ncomp = nc;
+            CK(dal(m, &m->fcells, fc.size()));
+            CK(dal(m, &m->fcomp, fc.size()));
+            CK(dal(m, &m->ftouch, (size_t)nc));
+            HIPX(hipMemcpyAsync(m->fcells, fc.data(), fc.size() * sizeof(int),
+                                hipMemcpyHostToDevice, m->s));
+            HIPX(hipMemcpyAsync(m->fcomp, fcc.data(), fcc.size() * sizeof(int),
+                                hipMemcpyHostToDevice, m->s));
+            HIPX(hipStreamSynchronize(m->s));
+        }
+    }
     std::vector<int> ford;   // fracture-cell ordinal per cell, -1 elsewhere
     if (d->frac_id && m->o.precond == FIM_PC_FRACTURE) {
         ford.assign(n, -1);
@@ -1472,6 +1533,7 @@ static fim_status newton_post_launch(fim_model* m) {
         launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, m->o.eps_loc, m->o.m_layers, m->g,
                            m->act, nullptr, m->dint, m->lvl, m->s);
         launch_shrink(m->nA, m->l2g, m->dp_abs, m->o.eps_loc, m->g, m->act, m->dint, m->s);
+        frac_closure(m);
         compact(m);
         pend(m, pi, m->n);
     } else if (m->step_mode == FIM_RESID) {
@@ -1818,6 +1880,17 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     b += n * B * 8 * 3 + n * B * 8 * 9;           // x64, xprev, rir, Krylov vectors
     b += 4 * (n * B / NT + 2) * 8 + 8 * KB_MAXB * 8;
     if (o && o->auto_cut) b += n * B * 8 + 2 * n;   // entry snapshot of auto_cut
+    if (d->frac_id) {
+        // fracture-component lists of localized fracture cells (at most)
+        size_t nfc = 0;
+        bool loc = false;
+        for (size_t i = 0; i < n; i++)
+            if (d->frac_id[i] >= 0) {
+                nfc++;
+                loc = loc || !(d->always_active && d->always_active[i]);
+            }
+        if (loc) b += nfc * 9;
+    }
     const int pc = o ? o->precond : FIM_PC_FRACTURE;
     if (d->frac_id && pc == FIM_PC_FRACTURE) {
         size_t nfc = 0;
@@ -2221,6 +2294,7 @@ fim_status fim_inspect_sets(fim_model* m, const uint8_t* act_in, const double* d
     launch_mark_expand(m->nA, m->l2g, m->bnd, m->dp_abs, eps, layers, m->g, m->act, nullptr,
                        m->dint, m->lvl, m->s);
     launch_shrink(m->nA, m->l2g, m->dp_abs, eps, m->g, m->act, m->dint, m->s);
+    frac_closure(m);
     TRY(read_int(m));
     *is_expand = m->hint[0] != 0;
     TRY(prepare_active(m, true));

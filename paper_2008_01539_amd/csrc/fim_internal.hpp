@@ -118,6 +118,11 @@ void launch_mark_resid(int n, const double* err, double tol, int m, const Graph&
                        uint8_t* act, int* count, uint8_t* lvl, hipStream_t s);
 void launch_support(int n, const double* p, const double* pn, double eps,
                     const Graph& g, uint8_t* act, hipStream_t s);
+// localized fracture cells: activate every fracture component that holds
+// an active cell (fcells: the nf fracture cells, fcomp their components
+// 0..ncomp-1, touch: ncomp bytes of scratch)
+void launch_frac_closure(int nf, const int* fcells, const int* fcomp, int ncomp,
+                         uint8_t* touch, uint8_t* act, hipStream_t s);
 void launch_dd_boundary(int nA, const int* l2g, const uint8_t* vt,
                         const Graph& g, uint8_t* bnd, hipStream_t s);
 void launch_outer_layer(int nA, const int* l2g, const uint8_t* in_set,

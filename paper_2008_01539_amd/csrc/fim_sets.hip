@@ -300,6 +300,35 @@ void launch_support(int n, const double* p, const double* pn, double eps,
     if (n > 0) k_support<<<nblocks(n), NT, 0, s>>>(n, p, pn, eps, g, act);
 }
 
+// Localized fracture cells: every fracture component (fracture cells
+// connected through fracture-fracture connections) with an active cell
+// becomes active as a whole.  Pass 1 flags the components that hold an
+// active cell, pass 2 activates every cell of a flagged component; both
+// run over the list of fracture cells only.
+__global__ __launch_bounds__(NT) void k_frac_touch(int nf, const int* __restrict__ fcells,
+                                                   const int* __restrict__ fcomp,
+                                                   const uint8_t* __restrict__ act,
+                                                   uint8_t* __restrict__ touch) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nf && act[fcells[q]]) touch[fcomp[q]] = 1;
+}
+
+__global__ __launch_bounds__(NT) void k_frac_close(int nf, const int* __restrict__ fcells,
+                                                   const int* __restrict__ fcomp,
+                                                   const uint8_t* __restrict__ touch,
+                                                   uint8_t* __restrict__ act) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nf && touch[fcomp[q]]) act[fcells[q]] = 1;
+}
+
+void launch_frac_closure(int nf, const int* fcells, const int* fcomp, int ncomp,
+                         uint8_t* touch, uint8_t* act, hipStream_t s) {
+    if (nf <= 0) return;
+    launch_fill_u8(touch, ncomp, 0, s);
+    k_frac_touch<<<nblocks(nf), NT, 0, s>>>(nf, fcells, fcomp, act, touch);
+    k_frac_close<<<nblocks(nf), NT, 0, s>>>(nf, fcells, fcomp, touch, act);
+}
+
 // Algorithm 2: V_B^{k+1} = boundary(V_T) intersected with V_A^{k+1}.
 __global__ __launch_bounds__(NT) void k_dd_boundary(int nA, const int* __restrict__ l2g,
                                                     const uint8_t* __restrict__ vt, Graph g,
