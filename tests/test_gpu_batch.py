@@ -136,3 +136,40 @@ def test_batch_rejects_mixed_precisions():
         P.FimBatch([a, b])
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("mode_name", ["LOCAL", "FULL"])
+def test_batch_members_match_oracle_tight(mode_name):
+    """Tight mode, mixed precision: every member of an uneven batch (two
+    config-4-recipe members of different sizes, the small config-2 model
+    and a config-1 variant with another seed) advanced by batched Newton
+    iterations reaches the oracle's full-Newton solution of its own model
+    (1e-8 relative p, 1e-8 S)."""
+    import paper_2008_01539_amd as P
+    from fimgen.configs import _two_phase_model, c1_schedule
+    from fimgen.model import FLUID_DEADOIL
+    from oracle.newton import Options as OOptions
+    from oracle.newton import Solver, State
+    nsteps = 4
+    two = [_two_phase_model(f"c4s_{k}", 4000 + k, nx, ny, 4, nf, FLUID_DEADOIL,
+                            c1_schedule(8, 1e-3, 10.0), nstage=2)
+           for k, (nx, ny, nf) in enumerate(((20, 10, 8), (30, 14, 14)))]
+    two.append(make_small_c2())
+    outs, sizes = _batched(two, P.Options.tight_mode(precision=P.MIXED),
+                           getattr(P, mode_name), nsteps)
+    assert max(sizes) == len(two)
+    for m, (u, _) in zip(two, outs):
+        st = State(m.u0.copy(), m.status0.copy())
+        s = Solver(m, OOptions.tight_mode())
+        for dt in m.schedule[:nsteps]:
+            st, _ = s.solve_timestep(st, dt)
+        assert np.abs(u[0] - st.u[0]).max() <= 1e-8 * st.u[0].min()
+        assert np.abs(u[1] - st.u[1]).max() <= 1e-8
+    one = [make_c1_variant(seed=11, uniform_perm=False), make_c1_variant(seed=12, nx=15, ny=14)]
+    outs, _ = _batched(one, P.Options.tight_mode(precision=P.MIXED), getattr(P, mode_name), 3)
+    for m, (u, _) in zip(one, outs):
+        st = State(m.u0.copy(), m.status0.copy())
+        s = Solver(m, OOptions.tight_mode())
+        for dt in m.schedule[:3]:
+            st, _ = s.solve_timestep(st, dt)
+        assert np.abs(u[0] - st.u[0]).max() <= 1e-8 * st.u[0].min()
