@@ -20,7 +20,10 @@ Readings where the paper is silent (shared with the HIP library):
   every active set of Algorithm 1 is closed under fracture components
   (sets.frac_closure); Algorithm 2 and the residual-based mode leave the
   fracture cells as the model marks them;
-* Algorithm 2: each visit of a subdomain is one Newton iteration on it;
+* Algorithm 2: each visit of a subdomain is one Newton iteration on it
+  (its additive form: every pending subdomain of a sweep from the same
+  state, each cell taking the update of the first subdomain containing it,
+  sets.alg2_owner);
   last_dp[i] holds |dp_i| from the latest solve that touched cell i; a
   subdomain is skipped when last_dp < eps on V_A^k and on its outer layer;
   the sweeps stop when no subdomain would be solved; the step fails when
@@ -105,7 +108,13 @@ class LocalSolver(Solver):
         return work, it, support
 
     # ------------------------------------------------------ Algorithm 2
-    def alg2_timestep(self, st: State, dt, prev_support, log=None):
+    def alg2_timestep(self, st: State, dt, prev_support, log=None, additive=False):
+        """Algorithm 2.  additive=True: the additive form of phase 2 (the
+        additive Schwarz form Section 4.4 starts from, with the paper's
+        adaptive subdomains): each sweep solves every pending subdomain
+        from the same state, and each cell takes the update of the first
+        subdomain (in build order) that contains it, so the overlapping
+        updates combine as in restricted additive Schwarz."""
         o = self.opts
         m = o.m_layers_dd
         m_old = accumulation(self.model, st.u, st.status)
@@ -139,7 +148,33 @@ class LocalSolver(Solver):
             return sets.alg2_sub_max(a, d, last_dp) >= o.eps_loc
 
         sweeps = 0
-        while any(pending(k) for k in range(len(subs))):   # phase 2
+        owner = np.array(sets.alg2_owner([a for a, _ in subs], self.model.n))
+        while additive and any(pending(k) for k in range(len(subs))):
+            sweeps += 1
+            if sweeps > o.max_sweeps:
+                return None, inner, None
+            todo = [k for k in range(len(subs)) if pending(k)]
+            if inner + len(todo) > 8 * o.max_newton:
+                return None, inner, None
+            base = work.copy()
+            trials = []
+            for k in todo:                      # all from the same state
+                trial = base.copy()
+                dp, _, _ = self.newton_iteration(trial, m_old, dt,
+                                                 active=set(subs[k][0].tolist()))
+                trials.append((k, trial, dp))
+            for k, trial, dp in trials:          # restricted combination
+                own = np.nonzero(owner == k)[0]
+                work.u[:, own] = trial.u[:, own]
+                work.status[own] = trial.status[own]
+                last_dp[own] = dp[own]
+                inner += 1
+                if log is not None:
+                    log.append(dict(n_a=int(subs[k][0].size), phase=2, sweep=sweeps,
+                                    sub=k, dp=float(dp.max())))
+            if not np.all(np.isfinite(work.u)):
+                return None, inner, None
+        while not additive and any(pending(k) for k in range(len(subs))):   # phase 2
             sweeps += 1
             if sweeps > o.max_sweeps:
                 return None, inner, None
@@ -187,9 +222,11 @@ class LocalSolver(Solver):
     # ------------------------------------------------------ schedules
     def run_local(self, st: State, schedule, alg=1, log=None):
         """Run a schedule with Algorithm 1 or 2 (alg=3: the residual-based
-        localization), halving dt on failure."""
+        localization; alg=4: Algorithm 2 with the additive phase 2),
+        halving dt on failure."""
         step = {1: self.alg1_timestep, 2: self.alg2_timestep,
-                3: self.resid_timestep}[alg]
+                3: self.resid_timestep,
+                4: lambda *a: self.alg2_timestep(*a, additive=True)}[alg]
         prev = None
         recs = []
         for dt in schedule:

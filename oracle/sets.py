@@ -166,6 +166,18 @@ def alg2_sub_max(cells, outer, last_dp):
     return max(vals) if vals else 0.0
 
 
+def alg2_owner(subdomains, n):
+    """The additive form of Algorithm 2's phase 2 combines overlapping
+    updates by ownership: cell i takes the update of the first subdomain
+    (in build order) that contains it; -1 for cells in none."""
+    owner = [-1] * n
+    for k, cells in enumerate(subdomains):
+        for i in cells:
+            if owner[int(i)] < 0:
+                owner[int(i)] = k
+    return owner
+
+
 def resid_active(rp, nb, err, tol, layers):
     """Residual-based active set (Sections 1 and 4.2, the estimator of Lu
     and Beckner): every cell with err_i >= tol, inflated by its

@@ -324,6 +324,41 @@ def test_p9_localized_and_dd_match_full_newton():
     assert ma / len(log) < 0.5
 
 
+@pytest.mark.parametrize("maker", [make_c1, make_small_c2, make_small_c3])
+def test_additive_dd_reaches_full_newton(maker):
+    """Algorithm 2 with the additive phase 2 (every pending subdomain from
+    the same state, restricted combination) reaches the full-Newton
+    solution in tight mode, like the multiplicative form (Section 4.4 and
+    the claim of Section 5.3)."""
+    m = maker()
+    sched = m.schedule[:6]
+    o = Options.tight_mode()
+    full, _ = Solver(m, o).run(_state(m), sched)
+    log = []
+    add, _ = LocalSolver(m, o).run_local(_state(m), sched, alg=4, log=log)
+    pmin = full.u[0].min()
+    assert np.abs(add.u[0] - full.u[0]).max() <= 1e-8 * pmin
+    if m.b > 1:
+        assert np.abs(add.u[1] - full.u[1]).max() <= 1e-8
+    if m.b == 3:
+        assert np.array_equal(add.status, full.status)
+    assert any(r.get("phase") == 2 for r in log)
+
+
+def test_additive_dd_leaves_cells_outside_total_set_unchanged():
+    """The additive form keeps Section 5.3.1's property: cells outside the
+    union of the subdomains keep their old state bitwise over the step."""
+    m = make_c1()
+    st = _state(m)
+    log = []
+    new, _, _ = LocalSolver(m, Options()).alg2_timestep(st, m.schedule[5], None, log,
+                                                        additive=True)
+    vt = log[-1]["vt"]
+    outside = np.setdiff1d(np.arange(m.n), np.fromiter(vt, np.int64))
+    assert outside.size > m.n // 2
+    assert np.array_equal(new.u[:, outside], st.u[:, outside])
+
+
 def _localized_fracture_model():
     """Config-2 recipe (small, hydrostatic initial state) with only the
     perforated cells always active: fracture cells are localized too.  (An

@@ -201,6 +201,14 @@ def test_alg1_update_with_localized_fractures():
     assert S.initial_active(rp, nb, [0], 1, {10}, fc) == {0, 8, 9, 10, 11, 12}
 
 
+def test_alg2_owner_by_hand():
+    """Additive phase 2: each cell's update comes from the first subdomain
+    containing it."""
+    subs = [[2, 3, 4], [4, 5, 6, 7], [1, 2, 7, 8]]
+    assert S.alg2_owner(subs, 10) == [-1, 2, 0, 0, 0, 1, 1, 1, 2, -1]
+    assert S.alg2_owner([], 3) == [-1, -1, -1]
+
+
 def test_work_ratio_definition_matches_paper_tables():
     """M_A per iteration is n_A / n; the tables' average column equals the
     total divided by the iteration count (to the printed rounding)."""
