@@ -507,7 +507,8 @@ def run_single(workload, args):
         log(f"local (events): wall {prof_run['wall']:.3f}s")
     legs = {}
     if not args.no_full:
-        for name, mode in (("full", P.FULL), ("dd", P.DD), ("resid", P.RESID)):
+        for name, mode in (("full", P.FULL), ("dd", P.DD), ("dd_add", P.DD_ADD),
+                           ("resid", P.RESID)):
             legs[name] = run_gpu(model, opts, mode, K, W)
             log(f"{name}: {legs[name]['iters']} iterations, wall {legs[name]['wall']:.3f}s, "
                 f"krylov {legs[name]['krylov']}")
@@ -554,6 +555,9 @@ def run_single(workload, args):
                             max_rel_dp_mixed_vs_fp64=_rel_dp(loc["u"], legs["local_fp64"]["u"]))
         out["full"] = _leg(legs["full"], model, ref=ref)
         out["dd"] = _leg(legs["dd"], model, fw, ref)
+        # NEXT-3 of the scope: Algorithm 2 with the additive phase 2 (an
+        # iteration here is one sweep over the pending subdomains)
+        out["dd_additive"] = _leg(legs["dd_add"], model, fw, ref)
         out["resid"] = _leg(legs["resid"], model, fw, ref)
         out["resid"]["local_speedup_vs_resid"] = legs["resid"]["wall"] / loc["wall"]
         out["local_fp64"] = _leg(legs["local_fp64"], model, fw, ref)

@@ -46,7 +46,18 @@ typedef enum fim_status {
     FIM_E_NONFINITE = -5     /* non-finite input                          */
 } fim_status;
 
-/* Solver modes.  FIM_RESID is the residual-based localization that
+/* Solver modes.  FIM_DD_ADD is Algorithm 2 with the additive form of its
+ * phase 2 (Section 4.4 names the additive Schwarz form; the combination rule
+ * for the adaptive, overlapping subdomains is this library's): phase 1 is
+ * as in FIM_DD; each later fim_newton_step is one sweep that solves every
+ * subdomain whose latest update on V_A^k or its outer layer is at least
+ * eps_loc, all from the same state and in one batched linear solve, and
+ * each cell takes the update of the first subdomain (in build order) that
+ * contains it.  Its iteration statistics report the sweep: n_active = the
+ * sum of the solved subdomains' sizes, subdomain = how many were solved.
+ * The first sweep of a model allocates one subdomain workspace (about the
+ * model's local-system memory) per subdomain solved at once, kept until the
+ * model is destroyed.  FIM_RESID is the residual-based localization that
  * Sections 1 and 4.2 describe as the prior method (Lu and Beckner): the
  * first iteration of a timestep takes every cell, each later one the cells
  * whose residual error measure e_i = dt max_c |R_{i,c}| / (V_i rho_c)
@@ -54,7 +65,7 @@ typedef enum fim_status {
  * c: rho_ref; rho_w, rho_o; rho_wsc, rho_osc, rho_gsc) is at least eps_res,
  * inflated by res_layers neighbour layers.  Its step ends when the update
  * meets the convergence test or no cell is at or above eps_res. */
-enum { FIM_FULL = 0, FIM_LOCAL = 1, FIM_DD = 2, FIM_RESID = 3 };
+enum { FIM_FULL = 0, FIM_LOCAL = 1, FIM_DD = 2, FIM_RESID = 3, FIM_DD_ADD = 4 };
 enum { FIM_FP64 = 0, FIM_MIXED = 1 };                     /* Krylov precision */
 enum { FIM_HOST = 0, FIM_DEVICE = 1 };                    /* pointer kind */
 enum { FIM_FLUID_SINGLE = 1, FIM_FLUID_DEADOIL = 2, FIM_FLUID_BLACKOIL = 3 };

@@ -154,6 +154,7 @@ struct fim_model {
     int *frac_id = nullptr, *ford = nullptr, *pcinfo = nullptr, *pcoff = nullptr;
     int* pclist = nullptr;          // multi-row blocks: (first row, rows) pairs
     int pc_inv_grid = 0;            // workgroups of the inversion launch
+    int pc_nfc = 0;                 // fracture cells (inverse store size)
     int cus = 256;                  // compute units of the device
     float* pcM = nullptr;           // FP32 inverses
     // Krylov
@@ -176,6 +177,14 @@ struct fim_model {
     std::vector<DDSub> subs;
     int dd_phase = 0, dd_next = 0, dd_sweeps = 0, dd_k = 0;
     bool dd_valid = false;          // vt holds V_T of an Algorithm 2 timestep
+    // additive Algorithm 2 (FIM_DD_ADD): the first subdomain of each cell,
+    // one workspace per subdomain solved at once (a clone that shares the
+    // model's static data and state and owns its local-system buffers), the
+    // solve table of the batched subdomain solves
+    int* dd_owner = nullptr;
+    std::vector<fim_model*> dd_clones;
+    SolveTable dd_tab;
+    bool is_clone = false;
     // step state machine
     bool in_step = false, have_history = false, full_ready = false;
     double step_dt = 0.0;
@@ -857,7 +866,9 @@ static void newton_update(fim_model* m, fim_iter_stats* it) {
     if (m->flags_on) {
         launch_fill_u8(m->classes, m->n, 0, m->s);
         launch_cell_classes(m->nA, m->l2g, m->bnd,
-                            m->step_mode == FIM_LOCAL || m->step_mode == FIM_DD, m->dp_abs,
+                            m->step_mode == FIM_LOCAL || m->step_mode == FIM_DD ||
+                                m->step_mode == FIM_DD_ADD,
+                            m->dp_abs,
                             m->o.eps_loc, m->classes, m->s);
     }
     if (it) {
@@ -924,7 +935,8 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
         return FIM_OK;
     }
     m->full_ready = false;
-    const int layers = mode == FIM_DD ? m->o.m_layers_dd : m->o.m_layers;
+    const bool dd = mode == FIM_DD || mode == FIM_DD_ADD;
+    const int layers = dd ? m->o.m_layers_dd : m->o.m_layers;
     if (m->have_history) {
         HIPX(hipMemcpyAsync(m->act, m->supp, m->n, hipMemcpyDeviceToDevice, m->s));
     } else {
@@ -932,7 +944,11 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
         launch_mark_seeds(m->n, m->g, layers, m->act, m->lvl, m->s);
     }
     if (mode == FIM_LOCAL) frac_closure(m);
-    if (mode == FIM_DD) {
+    if (mode == FIM_DD_ADD) {
+        if (!m->dd_owner) TRY(dal(m, &m->dd_owner, (size_t)m->n));
+        launch_fill_i32(m->dd_owner, m->n, -1, m->s);
+    }
+    if (dd) {
         launch_fill_f64(m->last_dp, m->n, 0.0, m->s);
         HIPX(hipMemcpyAsync(m->vt, m->act, m->n, hipMemcpyDeviceToDevice, m->s));
         m->subs.clear();
@@ -944,7 +960,7 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
         m->dd_k = 0;
     }
     TRY(prepare_active(m, true));
-    if (mode == FIM_DD) {
+    if (dd) {
         launch_fill_u8(m->outer, m->n, 0, m->s);
         launch_outer_layer(m->nA, m->l2g, m->act, m->g, m->outer, m->s);
     }
@@ -1016,6 +1032,87 @@ static fim_status dd_activate(fim_model* m, int k) {
     compact(m);
     m->nA = sd.cells_n;
     TRY(structure(m));
+    return FIM_OK;
+}
+
+// ------------------------------------------- additive Algorithm 2 workspaces
+// A subdomain workspace: shares the parent's static data, state and options
+// (pointers copied), owns the buffers of one local system (active flags,
+// compaction, matrix, right-hand side, Krylov vectors and scalars,
+// fracture-block layout and inverses, the update's |dp| and partials).
+static void free_clone(fim_model* c) {
+    void* own[] = {c->act, c->l2g, c->g2l, c->swidth, c->blk, c->col, c->J, c->F, c->dinv,
+                   c->At, c->x64, c->rir, c->part, c->kvec, c->xprev, c->sc, c->part_ir,
+                   c->ns, c->dint, c->dp_abs, c->pcinfo, c->pcoff, c->pcM, c->pclist};
+    for (void* p : own)
+        if (p) (void)hipFree(p);
+    if (c->hsc) (void)hipHostFree(c->hsc);
+    if (c->hns) (void)hipHostFree(c->hns);
+    if (c->hint) (void)hipHostFree(c->hint);
+    if (c->hpart) (void)hipHostFree(c->hpart);
+    if (c->sync_ev) (void)hipEventDestroy(c->sync_ev);
+    delete c;
+}
+
+static fim_status make_clone(fim_model* m, fim_model** out) {
+    fim_model* c = new fim_model();
+    c->is_clone = true;
+    c->n = m->n; c->nconn = m->nconn; c->B = m->B; c->fk = m->fk;
+    c->o = m->o; c->f = m->f; c->s = m->s; c->g = m->g;
+    c->adj_ptr = m->adj_ptr; c->adj_nbr = m->adj_nbr; c->adj_T = m->adj_T;
+    c->pv = m->pv; c->depth = m->depth; c->wi = m->wi; c->bhp = m->bhp; c->flags = m->flags;
+    c->max_deg = m->max_deg; c->slot_cap = m->slot_cap;
+    c->u = m->u; c->un = m->un; c->Mn = m->Mn; c->st = m->st; c->stn = m->stn;
+    c->use_pc = m->use_pc; c->pc_cap = m->pc_cap; c->pc_grid = m->pc_grid;
+    c->pc_grid_wide = m->pc_grid_wide; c->pc_inv_grid = m->pc_inv_grid; c->pc_nfc = m->pc_nfc;
+    c->frac_id = m->frac_id; c->ford = m->ford; c->cus = m->cus; c->dev = m->dev;
+    const size_t nn = (size_t)m->n, B = (size_t)m->B;
+    const size_t nsl = (nn + SLICE - 1) / SLICE;
+    const size_t ntile = std::max((nn + TILE - 1) / TILE, (nsl + TILE - 1) / TILE) + 1;
+    fim_status r = FIM_OK;
+    auto al = [&](auto** p, size_t cnt) {
+        if (r == FIM_OK) r = dal(c, p, cnt);
+    };
+    al(&c->act, nn);
+    al(&c->l2g, 2 * nn);
+    al(&c->g2l, 2 * nn);
+    al(&c->swidth, nsl + 1);
+    al(&c->blk, ntile);
+    al(&c->col, (size_t)c->slot_cap);
+    al(&c->J, (size_t)c->slot_cap * B * B);
+    al(&c->F, nn * B);
+    al(&c->dinv, nn * B * B);
+    if (r == FIM_OK) r = dalloc(c, &c->At, (size_t)c->slot_cap * B * B * sizeof(double));
+    al(&c->x64, nn * B);
+    al(&c->rir, nn * B);
+    al(&c->part, 4 * ((nn * B + NT - 1) / NT + 1));
+    if (r == FIM_OK) r = dalloc(c, &c->kvec, 9 * nn * B * sizeof(double));
+    al(&c->xprev, nn * B);
+    al(&c->sc, 1);
+    al(&c->part_ir, 14 * KB_MAXB);
+    al(&c->ns, 1);
+    al(&c->dint, 8);
+    al(&c->dp_abs, nn);
+    if (c->use_pc) {
+        al(&c->pcinfo, nn);
+        al(&c->pcoff, nn);
+        al(&c->pcM, (size_t)c->pc_nfc * pc_cell_stride(m->B));
+        al(&c->pclist, 2 * ((size_t)c->pc_nfc / 2 + 1));
+    }
+    if (r == FIM_OK &&
+        (hipHostMalloc((void**)&c->hsc, sizeof(KScal)) != hipSuccess ||
+         hipHostMalloc((void**)&c->hns, sizeof(NStat)) != hipSuccess ||
+         hipHostMalloc((void**)&c->hint, 8 * sizeof(int)) != hipSuccess ||
+         hipHostMalloc((void**)&c->hpart, 2 * KB_MAXB * sizeof(double)) != hipSuccess ||
+         hipEventCreateWithFlags(&c->sync_ev, hipEventDisableTiming) != hipSuccess))
+        r = FIM_E_NOMEM;
+    if (r != FIM_OK) {
+        m->err = "subdomain workspace: " + (c->err.empty() ? std::string("allocation failed") : c->err);
+        free_clone(c);
+        return r;
+    }
+    m->bytes += c->bytes;
+    *out = c;
     return FIM_OK;
 }
 
@@ -1115,7 +1212,7 @@ static void free_all(fim_model* m) {
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
                     m->part_ir, m->classes, m->frac_id, m->ford, m->pcinfo, m->pcoff,
                     m->pcM, m->pclist, m->lvl, m->usave, m->stsave, m->suppsave,
-                    m->fcells, m->fcomp, m->ftouch};
+                    m->fcells, m->fcomp, m->ftouch, m->dd_owner};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (m->hsc) (void)hipHostFree(m->hsc);
@@ -1419,6 +1516,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             CK(dal(m, &m->pclist, 2 * (nfc / 2 + 1)));
             // about as many single-wave workgroups as fit at once (LDS)
             m->pc_inv_grid = std::min(nfc / 2 + 1, 8 * m->cus);
+            m->pc_nfc = nfc;
             m->use_pc = true;
         }
     }
@@ -1483,6 +1581,9 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
 fim_status fim_destroy_model(fim_model* m) {
     if (!m) return FIM_E_ARG;
     if (m->s) (void)hipStreamSynchronize(m->s);
+    for (fim_model* c : m->dd_clones) free_clone(c);
+    m->dd_clones.clear();
+    table_free(m->dd_tab);
     free_all(m);
     delete m;
     return FIM_OK;
@@ -1636,6 +1737,91 @@ static fim_status newton_full_or_local(fim_model* m, fim_iter_stats* it) {
     return newton_post_finish(m, it);
 }
 
+// One sweep of the additive phase 2 (FIM_DD_ADD): the pending subdomains
+// (subdomain maxima already in hsub) are activated in workspaces, assembled
+// from the same state, solved together in one batched linear solve, and
+// each cell takes the update of the first subdomain that contains it.
+static fim_status dd_additive_sweep(fim_model* m, int N, fim_iter_stats* it) {
+    std::vector<int> todo;
+    for (int k = 0; k < N; k++)
+        if (m->hsub[k] >= m->o.eps_loc) todo.push_back(k);
+    if (todo.empty()) {
+        commit(m);
+        if (it) it->converged = 1;
+        return FIM_OK;
+    }
+    const int P = (int)todo.size();
+    m->dd_sweeps++;
+    if (m->dd_sweeps > m->o.max_sweeps || m->nu + P > m->o.max_newton * 8) {
+        TRY(rollback(m));
+        m->err = "Algorithm 2 sweep cap reached";
+        return FIM_NOT_CONVERGED;
+    }
+    while ((int)m->dd_clones.size() < P) {
+        fim_model* c = nullptr;
+        TRY(make_clone(m, &c));
+        m->dd_clones.push_back(c);
+    }
+    if (m->dd_tab.cap < P) {
+        table_free(m->dd_tab);
+        TRY(table_alloc(m, m->dd_tab, std::max(P, 4)));
+    }
+    std::vector<fim_model*> ws(m->dd_clones.begin(), m->dd_clones.begin() + P);
+    long sum_n = 0;
+    for (int j = 0; j < P; j++) {
+        fim_model* c = ws[j];
+        const DDSub& sd = m->subs[todo[j]];
+        c->s = m->s;
+        c->step_dt = m->step_dt;
+        c->step_mode = m->step_mode;
+        launch_fill_u8(c->act, c->n, 0, c->s);
+        launch_scatter_flags(sd.cells_n, m->sd_cells + sd.cells_off, c->act, c->s);
+        compact(c);
+        c->nA = sd.cells_n;
+        TRY(structure(c));
+        newton_assemble(c);
+        solve_prep(c, c->s);
+        sum_n += sd.cells_n;
+    }
+    TRY(solve_batch(ws, m->dd_tab, m->s, true));
+    int kry = 0;
+    for (int j = 0; j < P; j++) {
+        fim_model* c = ws[j];
+        launch_update(c->fk, c->nA, c->l2g, c->x64, c->u, c->st, c->n, c->f, c->o.ds_max,
+                      c->dp_abs, c->part, c->ns, c->s, m->dd_owner, todo[j]);
+        launch_copy_owned(c->nA, c->l2g, m->dd_owner, todo[j], c->dp_abs, m->last_dp, c->s);
+        HIPX(hipMemcpyAsync(c->hns, c->ns, sizeof(NStat), hipMemcpyDeviceToHost, c->s));
+        kry += c->last_kry;
+    }
+    HIPX(spin_sync(m, m->s));
+    m->nu += P;
+    double dpm = 0.0, dsm = 0.0;
+    bool bad = false;
+    for (int j = 0; j < P; j++) {
+        const NStat& ns = *ws[j]->hns;
+        dpm = std::max(dpm, ns.dp_max);
+        dsm = std::max(dsm, ns.ds_max);
+        bad = bad || ns.nonfinite;
+    }
+    m->sum_active += (double)sum_n;
+    m->max_active = std::max(m->max_active, (int)std::min<long>(sum_n, INT_MAX));
+    m->step_kry += kry;
+    if (it) {
+        it->n_active = (int)std::min<long>(sum_n, INT_MAX);
+        it->subdomain = P;
+        it->krylov_iters = kry;
+        it->dp_max = dpm;
+        it->ds_max = dsm;
+        it->nonfinite = bad ? 1 : 0;
+    }
+    if (bad) {
+        TRY(rollback(m));
+        m->err = "non-finite update";
+        return FIM_NOT_CONVERGED;
+    }
+    return FIM_OK;
+}
+
 // one inner iteration of Algorithm 2
 static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
     if (it) it->phase = m->dd_phase;
@@ -1651,6 +1837,11 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
         TRY(local_newton(m, it));
         launch_copy_masked(m->nA, m->l2g, m->dp_abs, m->last_dp, m->s);
         TRY(dd_store(m));
+        if (m->step_mode == FIM_DD_ADD) {
+            const DDSub& sd = m->subs.back();
+            launch_set_owner(sd.cells_n, m->sd_cells + sd.cells_off, m->dd_owner,
+                             (int)m->subs.size() - 1, m->s);
+        }
         HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
         bool expand = false;
         TRY(dd_expand_sets(m, m->o.eps_loc, m->o.m_layers_dd, &expand));
@@ -1667,7 +1858,9 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
         } else {
             m->dd_phase = 2;
             m->dd_next = 0;
-            m->dd_sweeps = 1;
+            // the multiplicative search counts its first sweep here, each
+            // additive call counts its own
+            m->dd_sweeps = m->step_mode == FIM_DD_ADD ? 0 : 1;
         }
     } else {
         const int N = (int)m->subs.size();
@@ -1675,6 +1868,7 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
         // outer-layer boundary values are not negligible
         launch_sub_max(N, m->subs.data(), m->sd_cells, m->sd_outer, m->last_dp, m->dsub, m->s);
         TRY(sync_read(m, m->hsub, m->dsub, N * sizeof(double)));
+        if (m->step_mode == FIM_DD_ADD) return dd_additive_sweep(m, N, it);
         bool new_sweep = false;
         const int pick = dd_pick(m->hsub, N, m->o.eps_loc, m->dd_next, &new_sweep);
         if (pick < 0) {
@@ -1710,8 +1904,8 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
 
 fim_status fim_newton_step(fim_model* m, double dt, int mode, fim_iter_stats* it) {
     if (!m) return FIM_E_ARG;
-    if (!(dt > 0.0) || !std::isfinite(dt) || mode < FIM_FULL || mode > FIM_RESID) {
-        m->err = "dt must be positive and mode FULL, LOCAL, DD or RESID";
+    if (!(dt > 0.0) || !std::isfinite(dt) || mode < FIM_FULL || mode > FIM_DD_ADD) {
+        m->err = "dt must be positive and mode FULL, LOCAL, DD, RESID or DD_ADD";
         return FIM_E_ARG;
     }
     if (it) std::memset(it, 0, sizeof(*it));
@@ -1720,7 +1914,8 @@ fim_status fim_newton_step(fim_model* m, double dt, int mode, fim_iter_stats* it
         return FIM_E_STATE;
     }
     if (!m->in_step) TRY(begin_step(m, dt, mode));
-    return mode == FIM_DD ? newton_dd(m, it) : newton_full_or_local(m, it);
+    return (mode == FIM_DD || mode == FIM_DD_ADD) ? newton_dd(m, it)
+                                                   : newton_full_or_local(m, it);
 }
 
 // For the duration of one allocation-free call: the kernels' partial
@@ -1759,7 +1954,7 @@ fim_status fim_newton_step_noalloc(fim_model* m, double dt, int mode, fim_iter_s
                  " its scratch array is sized for";
         return FIM_E_ARG;
     }
-    if (mode == FIM_DD) {
+    if (mode == FIM_DD || mode == FIM_DD_ADD) {
         m->err = "fim_newton_step_noalloc runs FIM_FULL, FIM_LOCAL or FIM_RESID "
                  "(Algorithm 2 grows its subdomain lists)";
         return FIM_E_ARG;
@@ -1786,7 +1981,8 @@ static fim_status solve_once(fim_model* m, double dt, int mode, fim_step_stats* 
     for (;;) {
         fim_status r = fim_newton_step(m, dt, mode, &it);
         // Algorithm 2's last call finds no subdomain to solve: no iteration
-        const bool solved = !(mode == FIM_DD && it.phase == 2 && it.n_active == 0);
+        const bool solved =
+            !((mode == FIM_DD || mode == FIM_DD_ADD) && it.phase == 2 && it.n_active == 0);
         if (st) {
             st->iterations += solved ? 1 : 0;
             st->krylov_iters += it.krylov_iters;

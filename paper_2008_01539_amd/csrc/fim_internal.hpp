@@ -123,6 +123,12 @@ void launch_support(int n, const double* p, const double* pn, double eps,
 // 0..ncomp-1, touch: ncomp bytes of scratch)
 void launch_frac_closure(int nf, const int* fcells, const int* fcomp, int ncomp,
                          uint8_t* touch, uint8_t* act, hipStream_t s);
+// additive Algorithm 2: owner[c] = k for the cells of a subdomain list
+// that have no owner yet; dst[i] = src[i] for the rows of a local system
+// whose cell is owned by k
+void launch_set_owner(int cnt, const int* cells, int* owner, int k, hipStream_t s);
+void launch_copy_owned(int nA, const int* l2g, const int* owner, int k, const double* src,
+                       double* dst, hipStream_t s);
 void launch_dd_boundary(int nA, const int* l2g, const uint8_t* vt,
                         const Graph& g, uint8_t* bnd, hipStream_t s);
 void launch_outer_layer(int nA, const int* l2g, const uint8_t* in_set,
@@ -256,7 +262,8 @@ void launch_pc_invert_batch(int b, bool fp32, int grid, const PcSeg* segs, int n
 void launch_update(int fk, int nA, const int* l2g, const double* x64,
                    double* u, int8_t* st, int n, const DevFluid& f,
                    double ds_max, double* dp_abs, double* part, NStat* ns,
-                   hipStream_t s);
+                   hipStream_t s,
+                   const int* owner = nullptr, int own_k = 0);
 void launch_copy_state(int b, int n, const double* src, const int8_t* ssrc,
                        double* dst, int8_t* sdst, hipStream_t s);
 

@@ -329,6 +329,34 @@ void launch_frac_closure(int nf, const int* fcells, const int* fcomp, int ncomp,
     k_frac_close<<<nblocks(nf), NT, 0, s>>>(nf, fcells, fcomp, touch, act);
 }
 
+// Additive Algorithm 2: each cell takes the update of the first subdomain
+// (in build order) that contains it.  Subdomain k's cells get owner k
+// unless an earlier subdomain owns them; the lists are launched in build
+// order, so no two threads of one launch race for a cell.
+__global__ void k_set_owner(int cnt, const int* __restrict__ cells, int* __restrict__ owner,
+                            int k) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < cnt && owner[cells[q]] < 0) owner[cells[q]] = k;
+}
+
+void launch_set_owner(int cnt, const int* cells, int* owner, int k, hipStream_t s) {
+    if (cnt > 0) k_set_owner<<<nblocks(cnt), NT, 0, s>>>(cnt, cells, owner, k);
+}
+
+__global__ void k_copy_owned(int nA, const int* __restrict__ l2g, const int* __restrict__ owner,
+                             int k, const double* __restrict__ src, double* __restrict__ dst) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nA) {
+        const int i = l2g[r];
+        if (owner[i] == k) dst[i] = src[i];
+    }
+}
+
+void launch_copy_owned(int nA, const int* l2g, const int* owner, int k, const double* src,
+                       double* dst, hipStream_t s) {
+    if (nA > 0) k_copy_owned<<<nblocks(nA), NT, 0, s>>>(nA, l2g, owner, k, src, dst);
+}
+
 // Algorithm 2: V_B^{k+1} = boundary(V_T) intersected with V_A^{k+1}.
 __global__ __launch_bounds__(NT) void k_dd_boundary(int nA, const int* __restrict__ l2g,
                                                     const uint8_t* __restrict__ vt, Graph g,

@@ -7,18 +7,22 @@
 
 namespace fimk {
 
+// owner (optional): only rows whose cell has owner[i] == own_k are
+// updated (the additive form of Algorithm 2 combines overlapping subdomain
+// updates by ownership); the others are left alone and do not count
 template <int FK>
 __global__ __launch_bounds__(NT) void k_update(int nA, const int* __restrict__ l2g,
                                                const double* __restrict__ x64,
                                                double* __restrict__ u, int8_t* __restrict__ st,
                                                int n, DevFluid f, double ds_max,
                                                double* __restrict__ dp_abs,
-                                               double* __restrict__ part, NStat* ns) {
+                                               double* __restrict__ part, NStat* ns,
+                                               const int* __restrict__ owner, int own_k) {
     constexpr int B = FluidTraits<FK>::B;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     double red[4] = {0.0, 0.0, 0.0, 0.0};   // |dp| max, |dS| max, switches, nonfinite
-    if (r < nA) {
-        const int i = l2g[r];
+    const int i = r < nA ? l2g[r] : 0;
+    if (r < nA && (!owner || owner[i] == own_k)) {
         double du[B];
 #pragma unroll
         for (int v = 0; v < B; v++) du[v] = x64[(long)r * B + v];
@@ -107,12 +111,12 @@ __global__ __launch_bounds__(1024) void k_update_finish(const double* __restrict
 void launch_update(int fk, int nA, const int* l2g, const double* x64,
                    double* u, int8_t* st, int n, const DevFluid& f,
                    double ds_max, double* dp_abs, double* part, NStat* ns,
-                   hipStream_t s) {
+                   hipStream_t s, const int* owner, int own_k) {
     const int nb = nblocks(nA > 0 ? nA : 1);
     switch (fk) {
-    case 1: k_update<1><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns); break;
-    case 2: k_update<2><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns); break;
-    default: k_update<3><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns); break;
+    case 1: k_update<1><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns, owner, own_k); break;
+    case 2: k_update<2><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns, owner, own_k); break;
+    default: k_update<3><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns, owner, own_k); break;
     }
     k_update_finish<<<1, 1024, 0, s>>>(part, nb, ns);
 }

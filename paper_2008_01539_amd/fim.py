@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libfim.so")
 
 FIM_OK, FIM_NOT_CONVERGED = 0, 1
 FIM_E_ARG, FIM_E_NOMEM, FIM_E_HIP, FIM_E_STATE, FIM_E_NONFINITE = -1, -2, -3, -4, -5
-FULL, LOCAL, DD, RESID = 0, 1, 2, 3
+FULL, LOCAL, DD, RESID, DD_ADD = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 HOST, DEVICE = 0, 1
 PC_JACOBI, PC_FRACTURE = 0, 1

@@ -236,3 +236,95 @@ def test_auto_cut_matches_oracle_and_restores_on_failure(c3s, max_newton):
         assert np.abs(u[0] - ref.u[0]).max() <= 1e-8 * ref.u[0].min()
         assert np.abs(u[1] - ref.u[1]).max() <= 1e-8
     fm.close()
+
+
+# ------------------------------------------------ additive form (FIM_DD_ADD)
+def _gpu_dda_steps(model, opts, schedule):
+    """FIM_DD_ADD timesteps: phase-1 calls as in FIM_DD, then one call per
+    additive sweep (subdomain = how many were solved, n_active their total
+    size)."""
+    import paper_2008_01539_amd as P
+    fm = P.FimModel(model, opts)
+    fm.set_state(model.u0, model.status0)
+    steps = []
+    for dt in schedule:
+        u0, _ = fm.get_state()
+        seq = []
+        while True:
+            it = fm.newton_step(dt, P.DD_ADD)
+            if it.converged and it.phase == 2 and it.n_active == 0:
+                break
+            seq.append((it.phase, it.subdomain, it.n_active))
+            if it.converged:
+                break
+        vt, nsub = fm.dd_total()
+        u1, st1 = fm.get_state()
+        steps.append(dict(seq=seq, n_sub=nsub, vt=vt, u0=u0, u1=u1, st1=st1))
+    fm.close()
+    return steps
+
+
+def _oracle_dda_steps(model, opts, schedule):
+    ls = LocalSolver(model, opts)
+    st = State(model.u0.copy(), model.status0.copy())
+    prev = None
+    out = []
+    for dt in schedule:
+        log = []
+        new, _, sup = ls.alg2_timestep(st, dt, prev, log, additive=True)
+        assert new is not None
+        seq = [(1, r["sub"], r["n_a"]) for r in log if r.get("phase") == 1]
+        sweeps = {}
+        for r in log:
+            if r.get("phase") == 2:
+                c, s = sweeps.get(r["sweep"], (0, 0))
+                sweeps[r["sweep"]] = (c + 1, s + r["n_a"])
+        seq += [(2, c, s) for _, (c, s) in sorted(sweeps.items())]
+        out.append(dict(seq=seq, n_sub=log[-1]["n_sub"], vt=log[-1]["vt"], u=new.u,
+                        status=new.status))
+        st, prev = new, sup
+    return out
+
+
+@pytest.mark.parametrize("which,nsteps", [("c1", 8), ("c2s", 6), ("c3s", 6)])
+def test_dd_additive_paper_mode_sequence_matches_oracle(which, nsteps, c1, c2s, c3s):
+    """Paper settings with exact linear solves: the same subdomains, the
+    same number and total size of subdomains solved in every additive
+    sweep, the same V_T; cells outside V_T unchanged; the state within
+    1e-8 of the oracle's additive Algorithm 2."""
+    import paper_2008_01539_amd as P
+    model = {"c1": c1, "c2s": c2s, "c3s": c3s}[which]
+    sched = model.schedule[:nsteps]
+    g = _gpu_dda_steps(model, P.Options(lin_rtol=1e-12), sched)
+    o = _oracle_dda_steps(model, OOptions(), sched)
+    multi = False
+    for k, (gs, os_) in enumerate(zip(g, o)):
+        assert gs["seq"] == os_["seq"], (which, k)
+        assert gs["n_sub"] == os_["n_sub"]
+        assert np.array_equal(gs["vt"], flags_of(os_["vt"], model.n))
+        out = gs["vt"] == 0
+        assert np.array_equal(gs["u1"][:, out], gs["u0"][:, out])
+        multi |= any(p == 2 and c > 1 for p, c, _ in gs["seq"])
+        assert np.abs(gs["u1"][0] - os_["u"][0]).max() <= 1e-8 * os_["u"][0].min()
+    assert multi          # some sweep solved several subdomains at once
+
+
+@pytest.mark.parametrize("which,prec", [("c1", "FP64"), ("c2s", "FP64"), ("c2s", "MIXED"),
+                                        ("c3s", "MIXED")])
+def test_dd_additive_tight_timesteps_match_oracle(which, prec, c1, c2s, c3s):
+    """Tight mode: the additive form reaches the oracle's full-Newton
+    solution (1e-8 relative p, 1e-8 S, phase status identical)."""
+    import paper_2008_01539_amd as P
+    model = {"c1": c1, "c2s": c2s, "c3s": c3s}[which]
+    sched = model.schedule[:6]
+    ref = run_oracle(Solver(model, OOptions.tight_mode()), model, sched)[-1]
+    fm = P.FimModel(model, P.Options.tight_mode(precision=getattr(P, prec)))
+    fm.set_state(model.u0, model.status0)
+    for dt in sched:
+        fm.solve_timestep(dt, P.DD_ADD)
+    u, st = fm.get_state()
+    fm.close()
+    assert np.array_equal(st, ref.status)
+    assert np.abs(u[0] - ref.u[0]).max() <= 1e-8 * ref.u[0].min()
+    if model.b > 1:
+        assert np.abs(u[1] - ref.u[1]).max() <= 1e-8
