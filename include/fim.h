@@ -371,6 +371,21 @@ fim_status fim_inspect_resid_sets(fim_model* m, const double* err, double tol,
                                   int32_t* l2g_out, int32_t* n_active,
                                   int32_t* n_unconverged);
 
+/* The fracture-block layout of the preconditioner (FIM_PC_FRACTURE) for
+ * the active set act (host u8[n], NULL = all cells): *n_active, l2g (host
+ * i32[n], first *n_active entries, ascending) and, per active row r,
+ * blk_start[r] = the first row of r's block and blk_rows[r] = its rows
+ * (1 for matrix rows and one-row blocks).  Each run of consecutive rows of
+ * one fracture inside a 256-row tile is cut into blocks of whole units of
+ * the fracture (its cells in index order, u at a time, u = the largest
+ * index-order distance of a connection inside the fracture when that is at
+ * most 64 / b cells, else 1), at most 64 / b cells each, in about equal
+ * parts.  FIM_E_STATE without fracture blocks.  Ends any timestep in
+ * progress. */
+fim_status fim_inspect_pc_blocks(fim_model* m, const uint8_t* act,
+                                 int32_t* n_active, int32_t* l2g,
+                                 int32_t* blk_start, int32_t* blk_rows);
+
 /* Solves J_A x = -F_A for the system of the last fim_inspect_assemble with
  * the library's Krylov solver (precision as in the options); x (host,
  * [n_active b]).  *iters receives BiCGStab iterations, *relres the final

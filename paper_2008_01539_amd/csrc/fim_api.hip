@@ -10,6 +10,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -149,6 +150,7 @@ struct fim_model {
     // fracture-block preconditioner (use_pc false: block Jacobi only)
     bool use_pc = false;
     int pc_cap = 0;                 // rows per block
+    int* funit = nullptr;           // fracture cells: unit << 8 | units per block
     int pc_grid = KB_MAXB;          // Krylov workgroups with fracture blocks (2 per CU)
     int pc_grid_wide = KB_MAXB;     // the same in the three-per-CU FP32 variant
     int *frac_id = nullptr, *ford = nullptr, *pcinfo = nullptr, *pcoff = nullptr;
@@ -400,9 +402,8 @@ static fim_status read_int(fim_model* m) {
 static fim_status structure(fim_model* m) {
     launch_structure(m->nA, m->l2g, m->g2l, m->g, m->swidth, &m->dint[4], m->s);
     if (m->use_pc)
-        launch_pc_blocks(m->nA, m->l2g, m->frac_id, m->ford, m->pc_cap,
-                         pc_cell_stride(m->B), m->pcinfo, m->pcoff, m->pclist, &m->dint[5],
-                         m->s);
+        launch_pc_blocks(m->nA, m->l2g, m->frac_id, m->ford, m->funit, pc_cell_stride(m->B),
+                         m->pcinfo, m->pcoff, m->pclist, &m->dint[5], m->s);
     return FIM_OK;
 }
 
@@ -1064,6 +1065,7 @@ static fim_status make_clone(fim_model* m, fim_model** out) {
     c->max_deg = m->max_deg; c->slot_cap = m->slot_cap;
     c->u = m->u; c->un = m->un; c->Mn = m->Mn; c->st = m->st; c->stn = m->stn;
     c->use_pc = m->use_pc; c->pc_cap = m->pc_cap; c->pc_grid = m->pc_grid;
+    c->funit = m->funit;
     c->pc_grid_wide = m->pc_grid_wide; c->pc_inv_grid = m->pc_inv_grid; c->pc_nfc = m->pc_nfc;
     c->frac_id = m->frac_id; c->ford = m->ford; c->cus = m->cus; c->dev = m->dev;
     const size_t nn = (size_t)m->n, B = (size_t)m->B;
@@ -1210,7 +1212,7 @@ static void free_all(fim_model* m) {
                     m->supp, m->bnd, m->vt, m->outer, m->l2g, m->g2l, m->swidth,
                     m->blk, m->col, m->J, m->F, m->dinv, m->At, m->x64, m->xprev, m->rir, m->part,
                     m->kvec, m->sc, m->ns, m->dint, m->dsub, m->sd_cells, m->sd_outer,
-                    m->part_ir, m->classes, m->frac_id, m->ford, m->pcinfo, m->pcoff,
+                    m->part_ir, m->classes, m->frac_id, m->ford, m->funit, m->pcinfo, m->pcoff,
                     m->pcM, m->pclist, m->lvl, m->usave, m->stsave, m->suppsave,
                     m->fcells, m->fcomp, m->ftouch, m->dd_owner};
     for (void* p : ptrs)
@@ -1269,6 +1271,45 @@ static fim_status validate(const fim_model_desc* d, std::string& e) {
         }
     }
     return FIM_OK;
+}
+
+// Units of the fracture blocks.  Per fracture, its cells in index order
+// (position p); u = the largest position distance of a connection between
+// two of its cells when that is at most cap (a layered fracture numbered
+// segment by segment: u = its layers, one unit = one segment's cells over
+// the layers), else 1.  funit[i] = (p / u) << 8 | cap / u for a fracture
+// cell (a block holds at most cap / u whole units, so at most cap cells).
+// False if a fracture has more units than the 23 bits of the unit field.
+static bool fracture_units(int n, const int* frac_id, const std::vector<int>& deg,
+                           const std::vector<int>& nbr, int cap, std::vector<int>& funit) {
+    std::vector<std::pair<int, int>> fc;   // (fracture, cell), cells ascending
+    for (int i = 0; i < n; i++)
+        if (frac_id[i] >= 0) fc.emplace_back(frac_id[i], i);
+    std::stable_sort(fc.begin(), fc.end(),
+                     [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+                         return a.first < b.first;
+                     });
+    std::vector<int> pos(n, 0);
+    funit.assign(n, 0);
+    for (size_t a = 0; a < fc.size();) {
+        size_t e = a;
+        while (e < fc.size() && fc[e].first == fc[a].first) e++;
+        for (size_t q = a; q < e; q++) pos[fc[q].second] = (int)(q - a);
+        int bw = 0;
+        for (size_t q = a; q < e; q++) {
+            const int i = fc[q].second;
+            for (int k = deg[i]; k < deg[i + 1]; k++) {
+                const int j = nbr[k];
+                if (frac_id[j] == fc[a].first) bw = std::max(bw, std::abs(pos[j] - pos[i]));
+            }
+        }
+        const int u = (bw >= 1 && bw <= cap) ? bw : 1;
+        if ((e - a - 1) / u >= ((size_t)1 << 23)) return false;
+        for (size_t q = a; q < e; q++)
+            funit[fc[q].second] = ((int)(q - a) / u) << 8 | std::min(255, cap / u);
+        a = e;
+    }
+    return true;
 }
 
 fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
@@ -1493,6 +1534,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
         }
     }
     std::vector<int> ford;   // fracture-cell ordinal per cell, -1 elsewhere
+    std::vector<int> funit;  // fracture cells: unit << 8 | units per block
     if (d->frac_id && m->o.precond == FIM_PC_FRACTURE) {
         ford.assign(n, -1);
         int nfc = 0;
@@ -1500,6 +1542,12 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             if (d->frac_id[i] >= 0) ford[i] = nfc++;
         if (nfc > 0) {
             m->pc_cap = PC_DOF / B;
+            if (!fracture_units(n, d->frac_id, deg, nbr, m->pc_cap, funit)) {
+                g_create_err = "model too large: a fracture has more than 2^23 cells";
+                free_all(m);
+                delete m;
+                return FIM_E_ARG;
+            }
             const double store = (double)nfc * pc_cell_stride(B) * sizeof(float);
             if (store >= 4294967296.0) {
                 g_create_err = "model too large: fracture-block inverses would exceed 4 GiB";
@@ -1509,6 +1557,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             }
             CK(dal(m, &m->frac_id, nn));
             CK(dal(m, &m->ford, nn));
+            CK(dal(m, &m->funit, nn));
             CK(dal(m, &m->pcinfo, nn));
             CK(dal(m, &m->pcoff, nn));
             CK(dal(m, &m->pcM, (size_t)nfc * pc_cell_stride(B)));
@@ -1560,6 +1609,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     if (m->use_pc) {
         CK(up(m->frac_id, d->frac_id, nn * sizeof(int)));
         CK(up(m->ford, ford.data(), nn * sizeof(int)));
+        CK(up(m->funit, funit.data(), nn * sizeof(int)));
     }
     // zero the counters and state
     std::vector<char> z(std::max(sizeof(KScal), sizeof(NStat)), 0);
@@ -2091,7 +2141,7 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
     if (d->frac_id && pc == FIM_PC_FRACTURE) {
         size_t nfc = 0;
         for (size_t i = 0; i < n; i++) nfc += d->frac_id[i] >= 0 ? 1 : 0;
-        if (nfc) b += n * 16 + nfc * (size_t)pc_cell_stride(B) * 4 + (nfc / 2 + 1) * 8;
+        if (nfc) b += n * 20 + nfc * (size_t)pc_cell_stride(B) * 4 + (nfc / 2 + 1) * 8;
     }
     return (int64_t)b;
 }
@@ -2551,6 +2601,32 @@ fim_status fim_inspect_resid_sets(fim_model* m, const double* err, double tol, i
     HIPX(hipMemcpyAsync(act_out, m->act, m->n, hipMemcpyDeviceToHost, m->s));
     HIPX(hipMemcpyAsync(l2g_out, m->l2g, m->nA * sizeof(int), hipMemcpyDeviceToHost, m->s));
     HIPX(hipStreamSynchronize(m->s));
+    return FIM_OK;
+}
+
+fim_status fim_inspect_pc_blocks(fim_model* m, const uint8_t* act, int32_t* n_active,
+                                 int32_t* l2g, int32_t* blk_start, int32_t* blk_rows) {
+    if (!m || !n_active || !l2g || !blk_start || !blk_rows) return FIM_E_ARG;
+    if (!m->use_pc) {
+        m->err = "the model has no fracture blocks";
+        return FIM_E_STATE;
+    }
+    m->in_step = false;
+    m->full_ready = false;
+    m->inspect_ready = false;
+    if (act) HIPX(hipMemcpyAsync(m->act, act, m->n, hipMemcpyHostToDevice, m->s));
+    else launch_fill_u8(m->act, m->n, 1, m->s);
+    TRY(prepare_active(m, false));
+    const int nA = m->nA;
+    std::vector<int> info(nA);
+    HIPX(hipMemcpyAsync(l2g, m->l2g, nA * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(info.data(), m->pcinfo, nA * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    HIPX(hipStreamSynchronize(m->s));
+    *n_active = nA;
+    for (int r = 0; r < nA; r++) {
+        blk_start[r] = (r / KB_NT) * KB_NT + (info[r] >> 16);
+        blk_rows[r] = info[r] & 0xffff;
+    }
     return FIM_OK;
 }
 

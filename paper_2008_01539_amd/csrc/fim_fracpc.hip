@@ -4,8 +4,8 @@
 // transmissibilities orders of magnitude above the matrix ones, while
 // matrix rows are strongly diagonally dominant.  On top of the b x b
 // block-Jacobi scaling (A~ = D^{-1} J), each run of consecutive local rows
-// that belong to one fracture is grouped into a block of at most
-// PC_DOF / b rows that never crosses a 256-row Krylov tile; the exact
+// that belong to one fracture is split into blocks of at most PC_DOF / b
+// rows that never cross a 256-row Krylov tile; the exact
 // inverse of A~ restricted to the block is formed once per Newton
 // iteration and applied on the left inside each Krylov product kernel
 // (fim_krylov.hip).  Matrix rows and rows of one-row blocks keep the plain
@@ -22,50 +22,77 @@ namespace fimk {
 //               blocks of one system never overlap.
 // and the list of multi-row blocks, (first row, rows) pairs in no
 // particular order: cnt[1] entries; cnt[0] = sum of rows^2.
+// A fracture's run of rows inside the tile covers units i0 .. iL of it
+// (funit); it is cut into nb = ceil((iL - i0 + 1) / cap_units) blocks, block
+// k taking the units from floor(k (iL - i0 + 1) / nb) on.  Whole units keep
+// a layered fracture's pieces (the cells of one segment over its layers,
+// coupled the most strongly) inside one block, and equal parts avoid a
+// short leftover block.
 __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restrict__ l2g,
                                                      const int* __restrict__ frac_id,
-                                                     const int* __restrict__ ford, int cap,
+                                                     const int* __restrict__ ford,
+                                                     const int* __restrict__ funit,
                                                      int cell_stride, int* __restrict__ pcinfo,
                                                      int* __restrict__ pcoff,
                                                      int* __restrict__ list,
                                                      int* __restrict__ cnt) {
     constexpr int NW = KB_NT / WAVE;
     __shared__ int sf[KB_NT];              // fracture id of each row (-1 matrix, -2 past nA)
-    __shared__ int wfirst[NW], wlast[NW];  // first / last run start in each wave
+    __shared__ int su[KB_NT];              // funit of each fracture row, then its block
+    __shared__ int wfirst[NW], wlast[NW];  // first / last start in each wave
     __shared__ int nlead[NW], sq[NW + 1], base_q;
     const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
     const int base = blockIdx.x * KB_NT, r = base + t;
     const bool valid = r < nA;
-    const int f = valid ? frac_id[l2g[r]] : -2;
+    const int cell = valid ? l2g[r] : 0;
+    const int f = valid ? frac_id[cell] : -2;
+    const int fu = f >= 0 ? funit[cell] : 0;
     sf[t] = f;
-    __syncthreads();
-    // runs of equal fracture id: the run around row t starts at the last
-    // run start at or before t and ends before the first one after t
-    const bool start = t == 0 || sf[t - 1] != f;
-    const unsigned long long m = __ballot(start);
-    if (lane == 0) {
-        wfirst[w] = m ? w * WAVE + __ffsll((long long)m) - 1 : KB_NT;
-        wlast[w] = m ? w * WAVE + 63 - __clzll((long long)m) : -1;
-    }
-    __syncthreads();
+    su[t] = fu;
     const unsigned long long upto = (2ull << lane) - 1ull;   // lanes 0 .. lane
-    int run = 0, rend = KB_NT;
-    if (m & upto) {
-        run = w * WAVE + 63 - __clzll((long long)(m & upto));
-    } else {
-        for (int v = w - 1; v >= 0; v--)
-            if (wlast[v] >= 0) { run = wlast[v]; break; }
+    // the segment around row t of the rows flagged by st: from the last
+    // flagged row at or before t to before the first one after it
+    auto segment = [&](bool st, int& lo, int& hi) {
+        const unsigned long long m = __ballot(st);
+        if (lane == 0) {
+            wfirst[w] = m ? w * WAVE + __ffsll((long long)m) - 1 : KB_NT;
+            wlast[w] = m ? w * WAVE + 63 - __clzll((long long)m) : -1;
+        }
+        __syncthreads();
+        lo = 0;
+        hi = KB_NT;
+        if (m & upto) {
+            lo = w * WAVE + 63 - __clzll((long long)(m & upto));
+        } else {
+            for (int v = w - 1; v >= 0; v--)
+                if (wlast[v] >= 0) { lo = wlast[v]; break; }
+        }
+        if (m & ~upto) {
+            hi = w * WAVE + __ffsll((long long)(m & ~upto)) - 1;
+        } else {
+            for (int v = w + 1; v < NW; v++)
+                if (wfirst[v] < KB_NT) { hi = wfirst[v]; break; }
+        }
+        __syncthreads();   // wfirst / wlast reused by the next call
+    };
+    __syncthreads();
+    // runs of equal fracture id
+    int run, rend;
+    segment(t == 0 || sf[t - 1] != f, run, rend);
+    // block k of the run's units (matrix rows and rows past nA: -1, one
+    // row each)
+    int k = -1;
+    if (f >= 0) {
+        const int i0 = su[run] >> 8, ru = (su[rend - 1] >> 8) - i0 + 1, cu = fu & 255;
+        const int nb = (ru + cu - 1) / cu, iu = (fu >> 8) - i0;
+        k = (int)(((long long)(iu + 1) * nb + ru - 1) / ru) - 1;
     }
-    if (m & ~upto) {
-        rend = w * WAVE + __ffsll((long long)(m & ~upto)) - 1;
-    } else {
-        for (int v = w + 1; v < NW; v++)
-            if (wfirst[v] < KB_NT) { rend = wfirst[v]; break; }
-    }
-    // fracture runs split into blocks of at most cap rows; matrix rows
-    // (and rows past nA) are blocks of one row
-    const int bs = f >= 0 ? run + ((t - run) / cap) * cap : t;
-    const int size = f >= 0 ? min(bs + cap, rend) - bs : 1;
+    __syncthreads();   // su read above
+    su[t] = k;
+    __syncthreads();
+    int bs, be;
+    segment(t == 0 || f < 0 || sf[t - 1] != f || su[t - 1] != k, bs, be);
+    const int size = be - bs;
     const bool lead = valid && size > 1 && bs == t;
     // list slots: one atomic per workgroup
     const unsigned long long lm = __ballot(lead);
@@ -96,12 +123,12 @@ __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restri
     if (lane == 0 && s2) atomicAdd(&cnt[0], s2);
 }
 
-void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
-                      int cell_stride, int* pcinfo, int* pcoff, int* list, int* cnt,
-                      hipStream_t s) {
+void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford,
+                      const int* funit, int cell_stride, int* pcinfo, int* pcoff, int* list,
+                      int* cnt, hipStream_t s) {
     launch_fill_i32(cnt, 2, 0, s);
     if (nA <= 0) return;
-    k_pc_blocks<<<(nA + KB_NT - 1) / KB_NT, KB_NT, 0, s>>>(nA, l2g, frac_id, ford, cap,
+    k_pc_blocks<<<(nA + KB_NT - 1) / KB_NT, KB_NT, 0, s>>>(nA, l2g, frac_id, ford, funit,
                                                             cell_stride, pcinfo, pcoff, list, cnt);
 }
 

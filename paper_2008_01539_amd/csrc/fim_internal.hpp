@@ -234,11 +234,15 @@ void launch_seg_status(const KSeg* segs, int nseg, SegStatus* out, hipStream_t s
 void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s);
 
 // fracture-block preconditioner (fim_fracpc.hip)
+// funit[cell] (fracture cells) = unit << 8 | cap_units: the cell's unit (its
+// position inside its fracture, in cell index order, divided by the unit
+// length of the fracture) and the most units one block may hold; blocks
+// split a fracture's run of rows at unit boundaries into about equal parts.
 // list: (first row, rows) of each multi-row block (room for nA / 2
 // blocks); cnt[0] = sum over them of rows^2, cnt[1] = their number
-void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford, int cap,
-                      int cell_stride, int* pcinfo, int* pcoff, int* list, int* cnt,
-                      hipStream_t s);
+void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford,
+                      const int* funit, int cell_stride, int* pcinfo, int* pcoff, int* list,
+                      int* cnt, hipStream_t s);
 // At: the scaled blocks in the Krylov precision (fp32: float, else double);
 // grid single-wave workgroups share the listed blocks
 void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void* At,

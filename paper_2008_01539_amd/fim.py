@@ -123,6 +123,7 @@ def _load():
                                        C.c_int64]),
         "fim_inspect_sets": (i32, [vp, vp, vp, f64, i32, vp, vp, vp, vp, vp]),
         "fim_inspect_solve": (i32, [vp, vp, vp, vp]),
+        "fim_inspect_pc_blocks": (i32, [vp, vp, vp, vp, vp, vp]),
         "fim_inspect_resid_error": (i32, [vp, vp, vp, vp, f64, vp]),
         "fim_inspect_resid_sets": (i32, [vp, vp, f64, i32, vp, vp, vp, vp]),
         "fim_inspect_dd_expand": (i32, [vp, vp, vp, vp, vp, f64, i32, vp, vp, vp, vp, vp,
@@ -411,6 +412,22 @@ class FimModel:
         _check(_lib.fim_inspect_resid_error(self._h, _ptr(uo), _ptr(ui), _ptr(st), float(dt),
                                             _ptr(err)), self._h)
         return err
+
+    def inspect_pc_blocks(self, act=None):
+        """Fracture-block layout for the active set act (None: all cells):
+        n_active, l2g and per active row the first row of its block and its
+        rows."""
+        n = self.n
+        a = None if act is None else np.ascontiguousarray(act, np.uint8).reshape(n)
+        l2g = np.empty(n, np.int32)
+        bs = np.empty(n, np.int32)
+        br = np.empty(n, np.int32)
+        na = C.c_int32()
+        _check(_lib.fim_inspect_pc_blocks(self._h, _ptr(a), C.byref(na), _ptr(l2g), _ptr(bs),
+                                          _ptr(br)), self._h)
+        k = na.value
+        return dict(n_active=k, l2g=l2g[:k].copy(), blk_start=bs[:k].copy(),
+                    blk_rows=br[:k].copy())
 
     def inspect_resid_sets(self, err, tol, layers):
         n = self.n
