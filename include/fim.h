@@ -379,8 +379,8 @@ fim_status fim_inspect_resid_sets(fim_model* m, const double* err, double tol,
  * one fracture inside a 256-row tile is cut into blocks of whole units of
  * the fracture (its cells in index order, u at a time, u = the largest
  * index-order distance of a connection inside the fracture when that is at
- * most 64 / b cells, else 1), at most 64 / b cells each, in about equal
- * parts.  FIM_E_STATE without fracture blocks.  Ends any timestep in
+ * most c cells, else 1), at most c cells each (c = 64, 20, 21 for b = 1, 2,
+ * 3), in about equal parts.  FIM_E_STATE without fracture blocks.  Ends any timestep in
  * progress. */
 fim_status fim_inspect_pc_blocks(fim_model* m, const uint8_t* act,
                                  int32_t* n_active, int32_t* l2g,

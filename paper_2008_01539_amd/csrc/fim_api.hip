@@ -1541,7 +1541,7 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
         for (int i = 0; i < n; i++)
             if (d->frac_id[i] >= 0) ford[i] = nfc++;
         if (nfc > 0) {
-            m->pc_cap = PC_DOF / B;
+            m->pc_cap = pc_cells(B);
             if (!fracture_units(n, d->frac_id, deg, nbr, m->pc_cap, funit)) {
                 g_create_err = "model too large: a fracture has more than 2^23 cells";
                 free_all(m);

@@ -4,7 +4,7 @@
 // transmissibilities orders of magnitude above the matrix ones, while
 // matrix rows are strongly diagonally dominant.  On top of the b x b
 // block-Jacobi scaling (A~ = D^{-1} J), each run of consecutive local rows
-// that belong to one fracture is split into blocks of at most PC_DOF / b
+// that belong to one fracture is split into blocks of at most pc_cells(b)
 // rows that never cross a 256-row Krylov tile; the exact
 // inverse of A~ restricted to the block is formed once per Newton
 // iteration and applied on the left inside each Krylov product kernel

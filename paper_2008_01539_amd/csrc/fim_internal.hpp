@@ -16,7 +16,12 @@ constexpr int MAX_LAYERS = 8;   // deepest neighbourhood the marker walks
 constexpr int MAX_SUBS = 64;    // Algorithm 2 subdomains per timestep
 constexpr int KB_NT = 256;      // threads per block of the Krylov kernels
 constexpr int KB_MAXB = 1024;   // blocks per Krylov launch (grid-stride above)
-constexpr int PC_DOF = 64;      // unknowns per fracture preconditioner block
+constexpr int PC_DOF = 64;      // unknowns per fracture preconditioner block (at most)
+// cells per fracture block: PC_DOF / b, but 20 for b = 2 (measured: on the
+// two-phase DFN workloads 20-cell blocks need about as many BiCGStab
+// iterations as 32-cell ones, and the product kernels read 5/8 of the
+// inverse bytes)
+constexpr int pc_cells(int b) { return b == 2 ? 20 : PC_DOF / b; }
 
 // Fracture-block inverse store.  A block of R rows (N = R b unknowns) at
 // element offset off keeps entry (unknown u = rr b + c, column j) at

@@ -12,6 +12,7 @@ from fimgen import make_c1, make_small_c2, make_small_c3
 pytestmark = pytest.mark.gpu
 
 TILE = 256
+CAP = {1: 64, 2: 20, 3: 21}   # cells per block at most, by block size b
 
 
 def _frac_id(model):
@@ -41,7 +42,7 @@ def _units(model, cap):
 
 
 def _expected(model, l2g, b):
-    cap = 64 // b
+    cap = CAP[b]
     frac, unit, cu, _, _ = _units(model, cap)
     n_a = l2g.size
     start = np.arange(n_a)
@@ -125,7 +126,7 @@ def test_layered_units_keep_segments_whole():
     tile starts at an even position of its fracture (a whole segment)."""
     from paper_2008_01539_amd import FimModel, Options
     model = make_small_c3(seed=43, nx=24, ny=12, nz=4, nfrac=16, nstage=2)
-    frac, _, _, ulen, pos = _units(model, 64 // model.b)
+    frac, _, _, ulen, pos = _units(model, CAP[model.b])
     fm = FimModel(model, Options())
     try:
         out = fm.inspect_pc_blocks((frac >= 0).astype(np.uint8))
