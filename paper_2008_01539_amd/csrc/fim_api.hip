@@ -858,20 +858,8 @@ static void newton_assemble(fim_model* m) {
     pend(m, pi, m->nA);
 }
 
-// Update after the solve (launch only) and the bookkeeping of the solve.
-static void newton_update(fim_model* m, fim_iter_stats* it) {
-    const int pi = pbeg(m, PK_UPDATE);
-    launch_update(m->fk, m->nA, m->l2g, m->x64, m->u, m->st, m->n, m->f, m->o.ds_max,
-                  m->dp_abs, m->part, m->ns, m->s);
-    pend(m, pi, m->nA);
-    if (m->flags_on) {
-        launch_fill_u8(m->classes, m->n, 0, m->s);
-        launch_cell_classes(m->nA, m->l2g, m->bnd,
-                            m->step_mode == FIM_LOCAL || m->step_mode == FIM_DD ||
-                                m->step_mode == FIM_DD_ADD,
-                            m->dp_abs,
-                            m->o.eps_loc, m->classes, m->s);
-    }
+// the bookkeeping of the solve (no launch)
+static void newton_update_stats(fim_model* m, fim_iter_stats* it) {
     if (it) {
         it->n_active = m->nA;
         it->krylov_iters = m->last_kry;
@@ -882,6 +870,28 @@ static void newton_update(fim_model* m, fim_iter_stats* it) {
     m->sum_active += m->nA;
     m->max_active = std::max(m->max_active, m->nA);
     m->step_kry += m->last_kry;
+}
+
+// the cell classes of the iteration (fim_flags_enable)
+static void newton_classes(fim_model* m) {
+    if (m->flags_on) {
+        launch_fill_u8(m->classes, m->n, 0, m->s);
+        launch_cell_classes(m->nA, m->l2g, m->bnd,
+                            m->step_mode == FIM_LOCAL || m->step_mode == FIM_DD ||
+                                m->step_mode == FIM_DD_ADD,
+                            m->dp_abs,
+                            m->o.eps_loc, m->classes, m->s);
+    }
+}
+
+// Update after the solve (launch only) and the bookkeeping of the solve.
+static void newton_update(fim_model* m, fim_iter_stats* it) {
+    const int pi = pbeg(m, PK_UPDATE);
+    launch_update(m->fk, m->nA, m->l2g, m->x64, m->u, m->st, m->n, m->f, m->o.ds_max,
+                  m->dp_abs, m->part, m->ns, m->s);
+    pend(m, pi, m->nA);
+    newton_classes(m);
+    newton_update_stats(m, it);
 }
 
 // Assembly + solve + update on the current active rows.
@@ -911,7 +921,11 @@ static void frac_closure(fim_model* m) {
         launch_frac_closure(m->nfcell, m->fcells, m->fcomp, m->ncomp, m->ftouch, m->act, m->s);
 }
 
-static fim_status begin_step(fim_model* m, double dt, int mode) {
+// The launches that start a timestep.  *pending: the step's first active
+// set is compacted and its n_A (dint[1], copied to hint[1]) must be read
+// before the structure pass (begin_finish); else n_A = n already.
+static fim_status begin_launch(fim_model* m, double dt, int mode, bool* pending) {
+    *pending = false;
     const int pi = pbeg(m, PK_SETUP);
     launch_copy_state(m->B, m->n, m->u, m->st, m->un, m->stn, m->s);
     launch_accumulation(m->fk, m->n, m->un, m->stn, m->g, m->f, m->Mn, m->s);
@@ -929,8 +943,9 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
         // the residual-based localization starts every step on all cells
         if (!m->full_ready) {
             launch_fill_u8(m->act, m->n, 1, m->s);
-            TRY(prepare_active(m, false));
-            m->full_ready = true;
+            compact(m);
+            HIPX(hipMemcpyAsync(m->hint, m->dint, 4 * sizeof(int), hipMemcpyDeviceToHost, m->s));
+            *pending = true;
         }
         m->nA = m->n;
         return FIM_OK;
@@ -960,12 +975,41 @@ static fim_status begin_step(fim_model* m, double dt, int mode) {
         m->dd_next = 0;
         m->dd_k = 0;
     }
-    TRY(prepare_active(m, true));
-    if (dd) {
+    compact(m);
+    HIPX(hipMemcpyAsync(m->hint, m->dint, 4 * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    *pending = true;
+    return FIM_OK;
+}
+
+// After the compaction of begin_launch has been read (hint[1]): the
+// structure of the first local system, V_B and Algorithm 2's outer layer.
+static fim_status begin_finish(fim_model* m) {
+    const int mode = m->step_mode;
+    if (mode == FIM_FULL || mode == FIM_RESID) {
+        m->nA = m->hint[1];
+        TRY(structure(m));
+        m->full_ready = true;
+        m->nA = m->n;
+        return FIM_OK;
+    }
+    m->nA = m->hint[1];
+    TRY(structure(m));
+    launch_fill_i32(&m->dint[2], 1, 0, m->s);
+    launch_boundary(m->nA, m->l2g, m->g2l, m->g, m->bnd, &m->dint[2], m->s);
+    if (mode == FIM_DD || mode == FIM_DD_ADD) {
         launch_fill_u8(m->outer, m->n, 0, m->s);
         launch_outer_layer(m->nA, m->l2g, m->act, m->g, m->outer, m->s);
     }
     return FIM_OK;
+}
+
+static fim_status begin_step(fim_model* m, double dt, int mode) {
+    bool pending = false;
+    TRY(begin_launch(m, dt, mode, &pending));
+    if (!pending) return FIM_OK;
+    HIPX(spin_sync(m, m->s));
+    pflush(m);
+    return begin_finish(m);
 }
 
 static void commit(fim_model* m) {
@@ -1707,7 +1751,11 @@ static fim_status newton_post_launch(fim_model* m) {
 }
 
 // The decisions of the iteration, once the status copies have landed.
-static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it) {
+// need_struct (batched iterations): instead of launching the next
+// iteration's structure pass, report that it is due (the new n_A is set).
+static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it,
+                                     bool* need_struct = nullptr) {
+    if (need_struct) *need_struct = false;
     const bool local = m->step_mode == FIM_LOCAL;
     const NStat ns = *m->hns;
     m->nu++;
@@ -1747,7 +1795,10 @@ static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it) {
         m->err = "Newton iteration cap reached";
         return FIM_NOT_CONVERGED;
     }
-    if (local) {
+    if ((local || resid) && need_struct) {
+        m->nA = m->hint[1];
+        *need_struct = true;
+    } else if (local) {
         m->nA = m->hint[1];
         const int pi = pbeg(m, PK_SETS);
         TRY(structure(m));
@@ -2164,7 +2215,191 @@ struct fim_batch {
     SolveTable tab;
     int B = 0, precision = 0;
     std::string err;
+    // member tables of the segmented launches, uploaded alternately into
+    // two slots (ev: the upload that last read a slot's host half)
+    struct Slot {
+        char* h = nullptr;
+        char* d = nullptr;
+        size_t host_bytes = 0, dev_bytes = 0;
+        hipEvent_t ev = nullptr;
+    } slot[2];
+    int cur = 0;
+    BStatus* hstat = nullptr;   // per member status words (pinned, mapped)
+    BStatus* dstat = nullptr;
+    int stat_cap = 0;
 };
+
+// Layout of a slot for K members whose cells need at most W cell
+// workgroups in all: host part = the BMember table and the three prefix
+// arrays; device part = the same plus the four workgroup maps.
+static int bt_blocks(long n) { return (int)((n + NT - 1) / NT); }
+static size_t bt_pref_off(int K) { return ((size_t)K * sizeof(BMember) + 255) / 256 * 256; }
+static size_t bt_host_bytes(int K) { return bt_pref_off(K) + 3 * (size_t)(K + 1) * sizeof(int); }
+static size_t bt_map_off(int K) { return (bt_host_bytes(K) + 255) / 256 * 256; }
+static size_t bt_dev_bytes(int K, long W) {
+    return bt_map_off(K) + (size_t)(3 * W + K) * sizeof(BMap);
+}
+
+static void batch_tables_free(fim_batch* b) {
+    for (auto& sl : b->slot) {
+        if (sl.ev) (void)hipEventSynchronize(sl.ev);
+        if (sl.h) (void)hipHostFree(sl.h);
+        if (sl.d) (void)hipFree(sl.d);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+        sl = fim_batch::Slot();
+    }
+    if (b->hstat) (void)hipHostFree(b->hstat);
+    b->hstat = b->dstat = nullptr;
+    b->stat_cap = 0;
+}
+
+// sized for the members of the batch (all of them live at most)
+static fim_status batch_tables_alloc(fim_batch* b) {
+    const int K = (int)b->ms.size();
+    long W = 0;
+    for (fim_model* m : b->ms) W += bt_blocks(m->n);
+    const size_t hb = bt_host_bytes(K), db = bt_dev_bytes(K, W);
+    for (auto& sl : b->slot) {
+        if (sl.host_bytes >= hb && sl.dev_bytes >= db) continue;
+        if (sl.ev) (void)hipEventSynchronize(sl.ev);
+        if (sl.h) (void)hipHostFree(sl.h);
+        if (sl.d) (void)hipFree(sl.d);
+        sl.h = sl.d = nullptr;
+        sl.host_bytes = sl.dev_bytes = 0;
+        if (hipHostMalloc((void**)&sl.h, hb) != hipSuccess ||
+            hipMalloc((void**)&sl.d, db) != hipSuccess) {
+            b->err = "batch table allocation failed";
+            return FIM_E_NOMEM;
+        }
+        sl.host_bytes = hb;
+        sl.dev_bytes = db;
+        if (!sl.ev && hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+            b->err = "hipEventCreate failed";
+            return FIM_E_HIP;
+        }
+    }
+    if (b->stat_cap < K) {
+        if (b->hstat) (void)hipHostFree(b->hstat);
+        b->hstat = b->dstat = nullptr;
+        b->stat_cap = 0;
+        if (hipHostMalloc((void**)&b->hstat, (size_t)K * sizeof(BStatus),
+                          hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&b->dstat, b->hstat, 0) != hipSuccess) {
+            b->err = "pinned status buffer not available";
+            return FIM_E_NOMEM;
+        }
+        b->stat_cap = K;
+    }
+    return FIM_OK;
+}
+
+// One member as the segmented kernels see it (its current n_A and step).
+static BMember bmember(fim_model* m) {
+    BMember x;
+    std::memset(&x, 0, sizeof(x));
+    x.ls = lsys(m);
+    x.g = m->g;
+    x.f = m->f;
+    x.u = m->u;
+    x.st = m->st;
+    x.Mn = m->Mn;
+    x.dt = m->step_dt;
+    x.inv_dt = 1.0 / m->step_dt;
+    x.ds_max = m->o.ds_max;
+    x.dinv = m->dinv;
+    x.At = m->At;
+    x.x64 = m->x64;
+    x.dp_abs = m->dp_abs;
+    x.part = m->part;
+    x.ns = m->ns;
+    x.act = m->act;
+    x.bnd = m->bnd;
+    x.lvl = m->lvl;
+    x.dint = m->dint;
+    x.blk = m->blk;
+    x.last_dp = m->last_dp;
+    x.eps_loc = m->o.eps_loc;
+    x.eps_res = m->o.eps_res;
+    if (m->use_pc) {
+        x.frac_id = m->frac_id;
+        x.ford = m->ford;
+        x.funit = m->funit;
+        x.pcinfo = m->pcinfo;
+        x.pcoff = m->pcoff;
+        x.pclist = m->pclist;
+    }
+    x.n = m->n;
+    x.nA = m->nA;
+    x.mode = m->step_mode;
+    x.layers = m->step_mode == FIM_LOCAL ? std::min(m->o.m_layers, MAX_LAYERS)
+             : m->step_mode == FIM_RESID ? std::min(m->o.res_layers, MAX_LAYERS) : 0;
+    return x;
+}
+
+// The device table and workgroup maps of one phase of a batched call.
+struct BPhase {
+    const BMember* t = nullptr;
+    const BMap *rows = nullptr, *cells = nullptr, *tiles = nullptr, *mem = nullptr;
+    int K = 0, nrows = 0, ncells = 0, ntiles = 0, layers = 0;
+    bool any_resid = false;
+};
+
+static fim_status batch_upload(fim_batch* b, const std::vector<fim_model*>& ms, BPhase& ph) {
+    const int K = (int)ms.size();
+    fim_batch::Slot& sl = b->slot[b->cur];
+    b->cur ^= 1;
+    if (hipEventSynchronize(sl.ev) != hipSuccess) {
+        b->err = "hipEventSynchronize failed";
+        return FIM_E_HIP;
+    }
+    BMember* t = (BMember*)sl.h;
+    int* pref = (int*)(sl.h + bt_pref_off(K));
+    int acc[3] = {0, 0, 0};
+    ph = BPhase();
+    ph.K = K;
+    for (int q = 0; q < K; q++) {
+        fim_model* m = ms[q];
+        t[q] = bmember(m);
+        const int c[3] = {bt_blocks(std::max(m->nA, 0)), bt_blocks(m->n),
+                          (m->n + TILE - 1) / TILE};
+        for (int k = 0; k < 3; k++) {
+            pref[k * (K + 1) + q] = acc[k];
+            acc[k] += c[k];
+        }
+        ph.layers = std::max(ph.layers, t[q].layers);
+        ph.any_resid = ph.any_resid || m->step_mode == FIM_RESID;
+    }
+    for (int k = 0; k < 3; k++) pref[k * (K + 1) + K] = acc[k];
+    if (hipMemcpyAsync(sl.d, sl.h, bt_host_bytes(K), hipMemcpyHostToDevice, b->s) != hipSuccess ||
+        hipEventRecord(sl.ev, b->s) != hipSuccess) {
+        b->err = "batch table upload failed";
+        return FIM_E_HIP;
+    }
+    const long W = acc[1];
+    BMap* maps = (BMap*)(sl.d + bt_map_off(K));
+    ph.t = (const BMember*)sl.d;
+    ph.rows = maps;
+    ph.cells = maps + W;
+    ph.tiles = maps + 2 * W;
+    ph.mem = maps + 3 * W;
+    ph.nrows = acc[0];
+    ph.ncells = acc[1];
+    ph.ntiles = acc[2];
+    launch_build_maps((const int*)(sl.d + bt_pref_off(K)), K,
+                      std::max(acc[0], std::max(acc[1], acc[2])), (BMap*)ph.rows,
+                      (BMap*)ph.cells, (BMap*)ph.tiles, (BMap*)ph.mem, b->s);
+    return FIM_OK;
+}
+
+// the structure pass of the members' new local systems (one launch per
+// kernel for all of them)
+static fim_status batch_structure(fim_batch* b, const std::vector<fim_model*>& ms) {
+    if (ms.empty()) return FIM_OK;
+    BPhase ph;
+    TRY(batch_upload(b, ms, ph));
+    launch_structure_seg(ph.t, ph.rows, ph.nrows, ph.mem, ph.K, pc_cell_stride(b->B), b->s);
+    return FIM_OK;
+}
 
 static thread_local std::string g_batch_err;
 
@@ -2199,7 +2434,7 @@ fim_status fim_batch_set(fim_batch* b, fim_model* const* models, int32_t k) {
     b->ms.assign(models, models + k);
     b->B = models[0]->B;
     b->precision = models[0]->o.precision;
-    return FIM_OK;
+    return batch_tables_alloc(b);
 }
 
 fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_stream, fim_batch** out) {
@@ -2249,6 +2484,7 @@ fim_status fim_batch_destroy(fim_batch* b) {
         if (b->join_ev[i]) (void)hipEventDestroy(b->join_ev[i]);
     }
     table_free(b->tab);
+    batch_tables_free(b);
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     if (b->done_ev) (void)hipEventDestroy(b->done_ev);
     if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
@@ -2325,8 +2561,9 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
         restore();
         return FIM_E_HIP;
     }
-    std::vector<fim_model*> live;
-    std::vector<int> pos;
+    // members that start a timestep: their first active set on the aux
+    // streams, one synchronisation for all of them, then one structure pass
+    std::vector<fim_model*> starters;
     for (int q = 0; q < K; q++) {
         fim_model* m = b->ms[q];
         m->s = b->aux[q % BATCH_AUX];
@@ -2336,54 +2573,111 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
             continue;
         }
         if (!m->in_step) {
-            fim_status r = begin_step(m, dts[q], modes[q]);
+            bool pending = false;
+            fim_status r = begin_launch(m, dts[q], modes[q], &pending);
             if (r != FIM_OK) {
                 codes[q] = r;
                 continue;
             }
+            if (pending) starters.push_back(m);
         }
+    }
+    if (batch_join(b) != FIM_OK) {
+        b->err = "stream join failed";
+        restore();
+        return FIM_E_HIP;
+    }
+    for (fim_model* m : b->ms) m->s = b->s;
+    if (!starters.empty()) {
+        if (hipStreamSynchronize(b->s) != hipSuccess) {
+            b->err = "hipStreamSynchronize failed";
+            restore();
+            return FIM_E_HIP;
+        }
+        for (fim_model* m : starters) {
+            pflush(m);
+            m->nA = m->hint[1];
+        }
+        fim_status r = batch_structure(b, starters);
+        if (r != FIM_OK) {
+            restore();
+            return r;
+        }
+        for (fim_model* m : starters)
+            if (m->step_mode == FIM_FULL || m->step_mode == FIM_RESID) {
+                m->full_ready = true;
+                m->nA = m->n;
+            }
+    }
+    // the live members: one launch per kernel for all of them
+    std::vector<fim_model*> live;
+    std::vector<int> pos;
+    for (int q = 0; q < K; q++) {
+        if (codes[q] != FIM_OK) continue;
+        fim_model* m = b->ms[q];
         if (m->nA == 0) {
             codes[q] = empty_iteration(m, stats ? &stats[q] : nullptr);
             continue;
         }
-        newton_assemble(m);
-        solve_prep(m, m->s);
         live.push_back(m);
         pos.push_back(q);
     }
     if (!live.empty()) {
-        if (batch_join(b) != FIM_OK) {
-            b->err = "stream join failed";
+        fim_model* lead = live[0];
+        BPhase ph;
+        fim_status r = batch_upload(b, live, ph);
+        if (r != FIM_OK) {
             restore();
-            return FIM_E_HIP;
+            return r;
         }
-        for (fim_model* m : live) m->s = b->s;
-        fim_status r = solve_batch(live, b->tab, b->s, true);
+        int pi = pbeg(lead, PK_ASSEMBLE);
+        launch_assemble_seg(b->B, ph.t, ph.rows, ph.nrows, b->s);
+        pend(lead, pi, ph.nrows * NT);
+        pi = pbeg(lead, PK_PRECOND);
+        launch_precond_seg(b->B, b->precision == FIM_MIXED, ph.t, ph.rows, ph.nrows, b->s);
+        pend(lead, pi, ph.nrows * NT);
+        r = solve_batch(live, b->tab, b->s, true);
         if (r != FIM_OK) {
             b->err = live[0]->err;
             restore();
             return r;
         }
-        if (batch_fork(b) != FIM_OK) {
-            b->err = "stream fork failed";
-            restore();
-            return FIM_E_HIP;
-        }
+        pi = pbeg(lead, PK_UPDATE);
+        launch_update_seg(b->B, ph.t, ph.rows, ph.nrows, ph.mem, ph.K, b->s);
+        pend(lead, pi, ph.nrows * NT);
         for (size_t t = 0; t < live.size(); t++) {
-            live[t]->s = b->aux[pos[t] % BATCH_AUX];
-            newton_update(live[t], stats ? &stats[pos[t]] : nullptr);
-            fim_status r2 = newton_post_launch(live[t]);
-            if (r2 != FIM_OK) codes[pos[t]] = r2;
+            newton_classes(live[t]);
+            newton_update_stats(live[t], stats ? &stats[pos[t]] : nullptr);
         }
-        if (batch_join(b) != FIM_OK || hipStreamSynchronize(b->s) != hipSuccess) {
+        pi = pbeg(lead, PK_SETS);
+        launch_sets_seg(b->B, ph.t, ph.rows, ph.nrows, ph.cells, ph.ncells, ph.mem, ph.K,
+                        ph.layers, ph.any_resid, b->s);
+        for (fim_model* m : live)
+            if (m->step_mode == FIM_LOCAL) frac_closure(m);
+        launch_compact_seg(ph.t, ph.tiles, ph.ntiles, b->s);
+        pend(lead, pi, ph.ncells * NT);
+        launch_status_seg(ph.t, ph.mem, ph.K, b->dstat, b->s);
+        for (fim_model* m : live)
+            if (m->step_mode == FIM_RESID) m->full_ready = false;   // l2g / g2l: the new set
+        if (hipStreamSynchronize(b->s) != hipSuccess) {
             b->err = "hipStreamSynchronize failed";
             restore();
             return FIM_E_HIP;
         }
+        std::vector<fim_model*> next;
         for (size_t t = 0; t < live.size(); t++) {
-            pflush(live[t]);
-            if (codes[pos[t]] == FIM_OK)
-                codes[pos[t]] = newton_post_finish(live[t], stats ? &stats[pos[t]] : nullptr);
+            fim_model* m = live[t];
+            pflush(m);
+            *m->hns = b->hstat[t].ns;
+            for (int k = 0; k < 4; k++) m->hint[k] = b->hstat[t].dint[k];
+            bool need = false;
+            codes[pos[t]] = newton_post_finish(m, stats ? &stats[pos[t]] : nullptr, &need);
+            if (need) next.push_back(m);
+        }
+        r = batch_structure(b, next);
+        if (r != FIM_OK) {
+            restore();
+            return r;
         }
     }
     restore();

@@ -32,16 +32,16 @@ __global__ __launch_bounds__(NT) void k_accumulation(int n, const double* __rest
     for (int c = 0; c < B; c++) M[(long)c * n + i] = P.M[c].v;
 }
 
+// (vb: the workgroup's index among the NT-row workgroups of this system)
 template <int FK>
-__global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, DevFluid f,
-                                                 const double* __restrict__ u,
-                                                 const int8_t* __restrict__ st,
-                                                 const double* __restrict__ Mn,
-                                                 double inv_dt) {
+__device__ inline void assemble_rows(int nA, const LocalSys& ls, const Graph& g,
+                                     const DevFluid& f, const double* __restrict__ u,
+                                     const int8_t* __restrict__ st,
+                                     const double* __restrict__ Mn, double inv_dt, int vb) {
     constexpr int B = FluidTraits<FK>::B;
     constexpr int NPH = FluidTraits<FK>::NPH;
     constexpr int BB = B * B;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = vb * NT + threadIdx.x;
     if (r >= nA) return;
     const int n = g.n;
     const int i = ls.l2g[r];
@@ -178,6 +178,23 @@ __global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, D
 // orientation, phase-potential upwinding, well term) is that of k_assemble
 // without the derivatives.
 template <int FK>
+__global__ __launch_bounds__(NT) void k_assemble(int nA, LocalSys ls, Graph g, DevFluid f,
+                                                 const double* __restrict__ u,
+                                                 const int8_t* __restrict__ st,
+                                                 const double* __restrict__ Mn,
+                                                 double inv_dt) {
+    assemble_rows<FK>(nA, ls, g, f, u, st, Mn, inv_dt, blockIdx.x);
+}
+
+template <int FK>
+__global__ __launch_bounds__(NT) void k_assemble_seg(const BMember* __restrict__ t,
+                                                     const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    assemble_rows<FK>(M.nA, M.ls, M.g, M.f, M.u, M.st, M.Mn, M.inv_dt, e.vb);
+}
+
+template <int FK>
 __device__ inline double ref_density(const DevFluid& f, int c) {
     if constexpr (FK == 1) return f.rho_ref;
     else if constexpr (FK == 2) return c == 0 ? f.rho_w : f.rho_o;
@@ -185,14 +202,14 @@ __device__ inline double ref_density(const DevFluid& f, int c) {
 }
 
 template <int FK>
-__global__ __launch_bounds__(NT) void k_resid_err(int n, Graph g, DevFluid f,
-                                                  const double* __restrict__ u,
-                                                  const int8_t* __restrict__ st,
-                                                  const double* __restrict__ Mn, double dt,
-                                                  double* __restrict__ err) {
+__device__ inline void resid_err_cells(int n, const Graph& g, const DevFluid& f,
+                                       const double* __restrict__ u,
+                                       const int8_t* __restrict__ st,
+                                       const double* __restrict__ Mn, double dt,
+                                       double* __restrict__ err, int vb) {
     constexpr int B = FluidTraits<FK>::B;
     constexpr int NPH = FluidTraits<FK>::NPH;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = vb * NT + threadIdx.x;
     if (i >= n) return;
     const double inv_dt = 1.0 / dt;
     double ui[B];
@@ -248,6 +265,25 @@ __global__ __launch_bounds__(NT) void k_resid_err(int n, Graph g, DevFluid f,
 #pragma unroll
     for (int c = 0; c < B; c++) e = fmax(e, fabs(R[c]) / (g.pv[i] * ref_density<FK>(f, c)));
     err[i] = dt * e;
+}
+
+template <int FK>
+__global__ __launch_bounds__(NT) void k_resid_err(int n, Graph g, DevFluid f,
+                                                  const double* __restrict__ u,
+                                                  const int8_t* __restrict__ st,
+                                                  const double* __restrict__ Mn, double dt,
+                                                  double* __restrict__ err) {
+    resid_err_cells<FK>(n, g, f, u, st, Mn, dt, err, blockIdx.x);
+}
+
+// the error measure of the FIM_RESID members (cell launch)
+template <int FK>
+__global__ __launch_bounds__(NT) void k_resid_err_seg(const BMember* __restrict__ t,
+                                                      const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (M.mode != FIM_RESID) return;
+    resid_err_cells<FK>(M.n, M.g, M.f, M.u, M.st, M.Mn, M.dt, M.last_dp, e.vb);
 }
 
 // ---------------------------------------------------------------------
@@ -311,12 +347,17 @@ __device__ inline bool invert_block(const double* a, double* inv) {
     }
 }
 
+// (x64: when non-null, the row's initial guess is zeroed as well)
 template <int B, typename T>
-__global__ __launch_bounds__(NT) void k_precond(int nA, LocalSys ls, double* __restrict__ dinv,
-                                                T* __restrict__ At) {
+__device__ inline void precond_rows(int nA, const LocalSys& ls, double* __restrict__ dinv,
+                                    T* __restrict__ At, double* __restrict__ x64, int vb) {
     constexpr int BB = B * B;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = vb * NT + threadIdx.x;
     if (r >= nA) return;
+    if (x64) {
+#pragma unroll
+        for (int c = 0; c < B; c++) x64[(long)r * B + c] = 0.0;
+    }
     const long base = slot_of(ls, r, 0);
     const int width = ls.swidth[r / SLICE];
     double d[BB], di[BB];
@@ -341,6 +382,20 @@ __global__ __launch_bounds__(NT) void k_precond(int nA, LocalSys ls, double* __r
                 At[pos * BB + rr * B + cc] = (T)acc;
             }
     }
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(NT) void k_precond(int nA, LocalSys ls, double* __restrict__ dinv,
+                                                T* __restrict__ At) {
+    precond_rows<B, T>(nA, ls, dinv, At, nullptr, blockIdx.x);
+}
+
+template <int B, typename T>
+__global__ __launch_bounds__(NT) void k_precond_seg(const BMember* __restrict__ t,
+                                                    const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    precond_rows<B, T>(M.nA, M.ls, M.dinv, (T*)M.At, M.x64, e.vb);
 }
 
 // ------------------------------------------------------------- launches
@@ -378,6 +433,36 @@ void launch_resid_err(int fk, int n, const Graph& g, const DevFluid& f, const do
     case 2: k_resid_err<2><<<nb, NT, 0, s>>>(n, g, f, u, st, Mn, dt, err); break;
     default: k_resid_err<3><<<nb, NT, 0, s>>>(n, g, f, u, st, Mn, dt, err); break;
     }
+}
+
+void launch_assemble_seg(int fk, const BMember* t, const BMap* rows, int nblk, hipStream_t s) {
+    if (nblk <= 0) return;
+    switch (fk) {
+    case 1: k_assemble_seg<1><<<nblk, NT, 0, s>>>(t, rows); break;
+    case 2: k_assemble_seg<2><<<nblk, NT, 0, s>>>(t, rows); break;
+    default: k_assemble_seg<3><<<nblk, NT, 0, s>>>(t, rows); break;
+    }
+}
+
+void launch_resid_err_seg(int fk, const BMember* t, const BMap* cells, int nblk, hipStream_t s) {
+    if (nblk <= 0) return;
+    switch (fk) {
+    case 1: k_resid_err_seg<1><<<nblk, NT, 0, s>>>(t, cells); break;
+    case 2: k_resid_err_seg<2><<<nblk, NT, 0, s>>>(t, cells); break;
+    default: k_resid_err_seg<3><<<nblk, NT, 0, s>>>(t, cells); break;
+    }
+}
+
+void launch_precond_seg(int b, bool fp32, const BMember* t, const BMap* rows, int nblk,
+                        hipStream_t s) {
+    if (nblk <= 0) return;
+#define PC(BV, TT) k_precond_seg<BV, TT><<<nblk, NT, 0, s>>>(t, rows)
+    if (fp32) {
+        if (b == 1) PC(1, float); else if (b == 2) PC(2, float); else PC(3, float);
+    } else {
+        if (b == 1) PC(1, double); else if (b == 2) PC(2, double); else PC(3, double);
+    }
+#undef PC
 }
 
 void launch_precond(int b, bool fp32, int nA, const LocalSys& ls,

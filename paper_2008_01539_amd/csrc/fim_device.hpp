@@ -101,7 +101,7 @@ __device__ inline int block_sum_i(int v) {
     return r;
 }
 
-inline int nblocks(long n, int nt = NT) { return (int)((n + nt - 1) / nt); }
+__host__ __device__ inline int nblocks(long n, int nt = NT) { return (int)((n + nt - 1) / nt); }
 
 // The dispatcher hands workgroups to the XCDs round robin (workgroup g to
 // XCD g mod 8), and each XCD has its own L2.  For a segment of nbk

@@ -28,21 +28,20 @@ namespace fimk {
 // a layered fracture's pieces (the cells of one segment over its layers,
 // coupled the most strongly) inside one block, and equal parts avoid a
 // short leftover block.
-__global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restrict__ l2g,
-                                                     const int* __restrict__ frac_id,
-                                                     const int* __restrict__ ford,
-                                                     const int* __restrict__ funit,
-                                                     int cell_stride, int* __restrict__ pcinfo,
-                                                     int* __restrict__ pcoff,
-                                                     int* __restrict__ list,
-                                                     int* __restrict__ cnt) {
+// (vb: the tile)
+__device__ inline void pc_blocks_tile(int nA, const int* __restrict__ l2g,
+                                      const int* __restrict__ frac_id,
+                                      const int* __restrict__ ford,
+                                      const int* __restrict__ funit, int cell_stride,
+                                      int* __restrict__ pcinfo, int* __restrict__ pcoff,
+                                      int* __restrict__ list, int* __restrict__ cnt, int vb) {
     constexpr int NW = KB_NT / WAVE;
     __shared__ int sf[KB_NT];              // fracture id of each row (-1 matrix, -2 past nA)
     __shared__ int su[KB_NT];              // funit of each fracture row, then its block
     __shared__ int wfirst[NW], wlast[NW];  // first / last start in each wave
     __shared__ int nlead[NW], sq[NW + 1], base_q;
     const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
-    const int base = blockIdx.x * KB_NT, r = base + t;
+    const int base = vb * KB_NT, r = base + t;
     const bool valid = r < nA;
     const int cell = valid ? l2g[r] : 0;
     const int f = valid ? frac_id[cell] : -2;
@@ -121,6 +120,34 @@ __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restri
     int s2 = lead ? size * size : 0;
     for (int o = WAVE / 2; o > 0; o /= 2) s2 += __shfl_xor(s2, o);
     if (lane == 0 && s2) atomicAdd(&cnt[0], s2);
+}
+
+__global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restrict__ l2g,
+                                                     const int* __restrict__ frac_id,
+                                                     const int* __restrict__ ford,
+                                                     const int* __restrict__ funit,
+                                                     int cell_stride, int* __restrict__ pcinfo,
+                                                     int* __restrict__ pcoff,
+                                                     int* __restrict__ list,
+                                                     int* __restrict__ cnt) {
+    pc_blocks_tile(nA, l2g, frac_id, ford, funit, cell_stride, pcinfo, pcoff, list, cnt,
+                   blockIdx.x);
+}
+
+// batched: members with fracture blocks (their counters cleared before)
+__global__ __launch_bounds__(KB_NT) void k_pc_blocks_seg(const BMember* __restrict__ t,
+                                                         const BMap* __restrict__ map,
+                                                         int cell_stride) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (!M.frac_id) return;
+    pc_blocks_tile(M.nA, M.ls.l2g, M.frac_id, M.ford, M.funit, cell_stride, M.pcinfo, M.pcoff,
+                   M.pclist, &M.dint[5], e.vb);
+}
+
+void launch_pc_blocks_seg(const BMember* t, const BMap* rows, int nrows, int cell_stride,
+                          hipStream_t s) {
+    if (nrows > 0) k_pc_blocks_seg<<<nrows, KB_NT, 0, s>>>(t, rows, cell_stride);
 }
 
 void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* ford,

@@ -276,4 +276,83 @@ void launch_update(int fk, int nA, const int* l2g, const double* x64,
 void launch_copy_state(int b, int n, const double* src, const int8_t* ssrc,
                        double* dst, int8_t* sdst, hipStream_t s);
 
+// ------------------------------------------------ batched Newton iteration
+// One member of a batched Newton iteration as the segmented kernels see it
+// (a device table of these, rewritten by the host for each phase of a
+// batched call): its graph, fluid, state, local system and set buffers,
+// and its current n_A.  Members share the block size and Krylov precision.
+struct BMember {
+    LocalSys ls;
+    Graph g;
+    DevFluid f;
+    double* u;
+    int8_t* st;
+    const double* Mn;
+    double inv_dt, dt, ds_max;
+    double* dinv;
+    void* At;
+    double* x64;
+    double* dp_abs;
+    double* part;           // update partials (4 per row workgroup)
+    NStat* ns;
+    uint8_t* act;
+    uint8_t* bnd;
+    uint8_t* lvl;
+    int* dint;              // [0] expand flag / unconverged count, [1] n_next,
+                            // [2] boundary count, [4] matrix blocks, [5..6] fracture blocks
+    int* blk;               // compaction tile counts
+    double* last_dp;        // residual error measure (FIM_RESID)
+    double eps_loc, eps_res;
+    const int* frac_id;     // fracture blocks (null: none)
+    const int* ford;
+    const int* funit;
+    int* pcinfo;
+    int* pcoff;
+    int* pclist;
+    int n, nA, mode, layers;
+};
+// workgroup -> (member, the member's own workgroup index)
+struct BMap {
+    int q, vb;
+};
+// the workgroup maps of a batched phase from three exclusive prefix arrays
+// of K + 1 ints (row, cell, tile workgroups of each member); most: the
+// largest of the three totals
+void launch_build_maps(const int* pref, int K, int most, BMap* rows, BMap* cells, BMap* tiles,
+                       BMap* mem, hipStream_t s);
+// Segmented launches: nblk workgroups, map[blockIdx.x] names the member and
+// its workgroup.  Row launches cover each member's n_A rows (NT per
+// workgroup), cell launches its n cells, tile launches its n cells in
+// TILE-cell tiles, member launches one workgroup per member.
+void launch_assemble_seg(int fk, const BMember* t, const BMap* rows, int nblk, hipStream_t s);
+// (also zeroes each member's x64 rows)
+void launch_precond_seg(int b, bool fp32, const BMember* t, const BMap* rows, int nblk,
+                        hipStream_t s);
+// the FIM_RESID members' error measure into last_dp (cell launch)
+void launch_resid_err_seg(int fk, const BMember* t, const BMap* cells, int nblk, hipStream_t s);
+// update + per-member reduction (one workgroup per member in mem); each
+// member's update workgroup count is nblocks(n_A) (its own partials)
+void launch_update_seg(int fk, const BMember* t, const BMap* rows, int nblk, const BMap* mem,
+                       int nmem, hipStream_t s);
+// Algorithm 1 expand / shrink (FIM_LOCAL members) and the residual-based
+// marking (FIM_RESID members); layers: the largest member layer count
+void launch_sets_seg(int fk, const BMember* t, const BMap* rows, int nrows, const BMap* cells,
+                     int ncells, const BMap* mem, int nmem, int layers, bool any_resid,
+                     hipStream_t s);
+// compaction of each member's act (FIM_LOCAL / FIM_RESID members)
+void launch_compact_seg(const BMember* t, const BMap* tiles, int ntiles, hipStream_t s);
+// each member's NStat and dint[0..3] into out (pinned host, nmem records)
+struct BStatus {
+    NStat ns;
+    int dint[4];
+};
+void launch_status_seg(const BMember* t, const BMap* mem, int nmem, BStatus* out, hipStream_t s);
+// structure of the new local systems (slice widths, fracture blocks of the
+// members that have them) and, for FIM_LOCAL members, the boundary V_B
+void launch_structure_seg(const BMember* t, const BMap* rows, int nrows, const BMap* mem,
+                          int nmem, int cell_stride, hipStream_t s);
+// (fim_fracpc.hip) the fracture-block layout of the members with blocks
+void launch_pc_blocks_seg(const BMember* t, const BMap* rows, int nrows, int cell_stride,
+                          hipStream_t s);
+
 } // namespace fimk

@@ -46,9 +46,11 @@ void launch_fill_f64(double* a, long n, double v, hipStream_t s) {
 // ------------------------------------------------------------ compaction
 constexpr int PER = TILE / NT;   // 16 cells per thread
 
-__global__ __launch_bounds__(NT) void k_compact_count(const uint8_t* __restrict__ act, int n,
-                                                      int* __restrict__ blk_cnt) {
-    const int base = blockIdx.x * TILE + threadIdx.x * PER;
+// (vb: the tile; the bodies below take the workgroup's index within its
+// own system, so that the batched launches share them)
+__device__ inline void compact_count(const uint8_t* __restrict__ act, int n,
+                                     int* __restrict__ blk_cnt, int vb) {
+    const int base = vb * TILE + threadIdx.x * PER;
     int c = 0;
 #pragma unroll
     for (int q = 0; q < PER; q++) {
@@ -56,20 +58,25 @@ __global__ __launch_bounds__(NT) void k_compact_count(const uint8_t* __restrict_
         if (i < n && act[i]) c++;
     }
     c = block_sum_i(c);
-    if (threadIdx.x == 0) blk_cnt[blockIdx.x] = c;
+    if (threadIdx.x == 0) blk_cnt[vb] = c;
 }
 
-__global__ __launch_bounds__(NT) void k_compact_scatter(const uint8_t* __restrict__ act, int n,
-                                                        const int* __restrict__ blk_cnt,
-                                                        int* __restrict__ l2g,
-                                                        int* __restrict__ g2l,
-                                                        int* __restrict__ n_out) {
+__global__ __launch_bounds__(NT) void k_compact_count(const uint8_t* __restrict__ act, int n,
+                                                      int* __restrict__ blk_cnt) {
+    compact_count(act, n, blk_cnt, blockIdx.x);
+}
+
+// (vb of ntile tiles; the last one writes n_out)
+__device__ inline void compact_scatter(const uint8_t* __restrict__ act, int n,
+                                       const int* __restrict__ blk_cnt, int* __restrict__ l2g,
+                                       int* __restrict__ g2l, int* __restrict__ n_out, int vb,
+                                       int ntile) {
     __shared__ int wsum[NT / WAVE];
     // offset of this tile: sum of the preceding tile counts
     int off = 0;
-    for (int t = threadIdx.x; t < (int)blockIdx.x; t += NT) off += blk_cnt[t];
+    for (int t = threadIdx.x; t < vb; t += NT) off += blk_cnt[t];
     off = block_sum_i(off);
-    const int base = blockIdx.x * TILE + threadIdx.x * PER;
+    const int base = vb * TILE + threadIdx.x * PER;
     uint8_t f[PER];
     int c = 0;
 #pragma unroll
@@ -105,7 +112,39 @@ __global__ __launch_bounds__(NT) void k_compact_scatter(const uint8_t* __restric
             }
         }
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == NT - 1) *n_out = pos;
+    if (vb == ntile - 1 && threadIdx.x == NT - 1) *n_out = pos;
+}
+
+__global__ __launch_bounds__(NT) void k_compact_scatter(const uint8_t* __restrict__ act, int n,
+                                                        const int* __restrict__ blk_cnt,
+                                                        int* __restrict__ l2g,
+                                                        int* __restrict__ g2l,
+                                                        int* __restrict__ n_out) {
+    compact_scatter(act, n, blk_cnt, l2g, g2l, n_out, blockIdx.x, gridDim.x);
+}
+
+// batched: the FIM_LOCAL and FIM_RESID members (tile launches)
+__global__ __launch_bounds__(NT) void k_compact_count_seg(const BMember* __restrict__ t,
+                                                          const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (M.mode == FIM_FULL) return;
+    compact_count(M.act, M.n, M.blk, e.vb);
+}
+
+__global__ __launch_bounds__(NT) void k_compact_scatter_seg(const BMember* __restrict__ t,
+                                                            const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (M.mode == FIM_FULL) return;
+    compact_scatter(M.act, M.n, M.blk, (int*)M.ls.l2g, (int*)M.ls.g2l, &M.dint[1], e.vb,
+                    (M.n + TILE - 1) / TILE);
+}
+
+void launch_compact_seg(const BMember* t, const BMap* tiles, int ntiles, hipStream_t s) {
+    if (ntiles <= 0) return;
+    k_compact_count_seg<<<ntiles, NT, 0, s>>>(t, tiles);
+    k_compact_scatter_seg<<<ntiles, NT, 0, s>>>(t, tiles);
 }
 
 void launch_compact(const uint8_t* act, int n, int* blk_cnt, int* l2g,
@@ -116,11 +155,10 @@ void launch_compact(const uint8_t* act, int n, int* blk_cnt, int* l2g,
 }
 
 // ------------------------------------------------------------- structure
-__global__ __launch_bounds__(NT) void k_slice_width(int nA, const int* __restrict__ l2g,
-                                                    const int* __restrict__ g2l, Graph g,
-                                                    int* __restrict__ swidth,
-                                                    int* __restrict__ nnzb) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void slice_width(int nA, const int* __restrict__ l2g,
+                                   const int* __restrict__ g2l, const Graph& g,
+                                   int* __restrict__ swidth, int* __restrict__ nnzb, int vb) {
+    const int r = vb * NT + threadIdx.x;
     int cnt = 0;
     if (r < nA) {
         const int i = l2g[r];
@@ -134,6 +172,13 @@ __global__ __launch_bounds__(NT) void k_slice_width(int nA, const int* __restric
     if ((threadIdx.x % WAVE) == 0 && r < nA) swidth[r / SLICE] = cnt;
 }
 
+__global__ __launch_bounds__(NT) void k_slice_width(int nA, const int* __restrict__ l2g,
+                                                    const int* __restrict__ g2l, Graph g,
+                                                    int* __restrict__ swidth,
+                                                    int* __restrict__ nnzb) {
+    slice_width(nA, l2g, g2l, g, swidth, nnzb, blockIdx.x);
+}
+
 void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
                       int* swidth, int* nnzb, hipStream_t s) {
     launch_fill_i32(nnzb, 1, 0, s);
@@ -143,11 +188,11 @@ void launch_structure(int nA, const int* l2g, const int* g2l, const Graph& g,
 
 // -------------------------------------------------------------- boundary
 // V_B: active cells with at least one inactive neighbour.
-__global__ __launch_bounds__(NT) void k_boundary(int nA, const int* __restrict__ l2g,
-                                                 const int* __restrict__ g2l, Graph g,
-                                                 uint8_t* __restrict__ bnd,
-                                                 int* __restrict__ count) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void boundary_rows(int nA, const int* __restrict__ l2g,
+                                     const int* __restrict__ g2l, const Graph& g,
+                                     uint8_t* __restrict__ bnd, int* __restrict__ count,
+                                     int vb) {
+    const int r = vb * NT + threadIdx.x;
     int b = 0;
     if (r < nA) {
         const int i = l2g[r];
@@ -157,6 +202,13 @@ __global__ __launch_bounds__(NT) void k_boundary(int nA, const int* __restrict__
     }
     b = block_sum_i(b);
     if (threadIdx.x == 0 && b) atomicAdd(count, b);
+}
+
+__global__ __launch_bounds__(NT) void k_boundary(int nA, const int* __restrict__ l2g,
+                                                 const int* __restrict__ g2l, Graph g,
+                                                 uint8_t* __restrict__ bnd,
+                                                 int* __restrict__ count) {
+    boundary_rows(nA, l2g, g2l, g, bnd, count, blockIdx.x);
 }
 
 void launch_boundary(int nA, const int* l2g, const int* g2l, const Graph& g,
@@ -171,10 +223,9 @@ void launch_boundary(int nA, const int* l2g, const int* g2l, const Graph& g,
 // distance k - 1.  A cell can be written by several threads in one pass,
 // always with the same value k, and a cell at distance k - 1 is never
 // rewritten in pass k, so the result is the same in any order.
-__global__ __launch_bounds__(NT) void k_ball_step(int n, Graph g, int k,
-                                                  uint8_t* __restrict__ lvl, uint8_t* act,
-                                                  uint8_t* act2) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void ball_step(int n, const Graph& g, int k, uint8_t* __restrict__ lvl,
+                                 uint8_t* act, uint8_t* act2, int vb) {
+    const int i = vb * NT + threadIdx.x;
     if (i >= n || lvl[i] != k - 1) return;
     const int e = g.adj_ptr[i + 1];
     for (int p = g.adj_ptr[i]; p < e; p++) {
@@ -187,6 +238,12 @@ __global__ __launch_bounds__(NT) void k_ball_step(int n, Graph g, int k,
     }
 }
 
+__global__ __launch_bounds__(NT) void k_ball_step(int n, Graph g, int k,
+                                                  uint8_t* __restrict__ lvl, uint8_t* act,
+                                                  uint8_t* act2) {
+    ball_step(n, g, k, lvl, act, act2, blockIdx.x);
+}
+
 static void ball_steps(int n, const Graph& g, int m, uint8_t* lvl, uint8_t* act, uint8_t* act2,
                        hipStream_t s) {
     for (int k = 1; k <= m; k++)
@@ -195,12 +252,12 @@ static void ball_steps(int n, const Graph& g, int m, uint8_t* lvl, uint8_t* act,
 
 // Algorithm 1/2 expansion seeds: i in V_B with |dp_i| >= eps (level 0,
 // marked in V_A and the optional second set); *flag = 1 if any
-__global__ __launch_bounds__(NT) void k_expand_seeds(int nA, const int* __restrict__ l2g,
-                                                     const uint8_t* __restrict__ bnd,
-                                                     const double* __restrict__ dp_abs,
-                                                     double eps, uint8_t* __restrict__ lvl,
-                                                     uint8_t* act, uint8_t* act2, int* flag) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void expand_seeds(int nA, const int* __restrict__ l2g,
+                                    const uint8_t* __restrict__ bnd,
+                                    const double* __restrict__ dp_abs, double eps,
+                                    uint8_t* __restrict__ lvl, uint8_t* act, uint8_t* act2,
+                                    int* flag, int vb) {
+    const int r = vb * NT + threadIdx.x;
     int hit = 0;
     if (r < nA) {
         const int i = l2g[r];
@@ -213,6 +270,14 @@ __global__ __launch_bounds__(NT) void k_expand_seeds(int nA, const int* __restri
     }
     hit = block_sum_i(hit);
     if (threadIdx.x == 0 && hit) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(NT) void k_expand_seeds(int nA, const int* __restrict__ l2g,
+                                                     const uint8_t* __restrict__ bnd,
+                                                     const double* __restrict__ dp_abs,
+                                                     double eps, uint8_t* __restrict__ lvl,
+                                                     uint8_t* act, uint8_t* act2, int* flag) {
+    expand_seeds(nA, l2g, bnd, dp_abs, eps, lvl, act, act2, flag, blockIdx.x);
 }
 
 void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
@@ -228,10 +293,10 @@ void launch_mark_expand(int nA, const int* l2g, const uint8_t* bnd,
 // Residual-based set (the estimator of Lu and Beckner, Sections 1 and 4.2):
 // the cells with err_i >= tol (level 0, *count = their number) and every
 // cell within m layers of them; act is rewritten on all n cells.
-__global__ __launch_bounds__(NT) void k_resid_seeds(int n, const double* __restrict__ err,
-                                                    double tol, uint8_t* __restrict__ lvl,
-                                                    uint8_t* __restrict__ act, int* count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ inline void resid_seeds(int n, const double* __restrict__ err, double tol,
+                                   uint8_t* __restrict__ lvl, uint8_t* __restrict__ act,
+                                   int* count, int vb) {
+    const int i = vb * NT + threadIdx.x;
     int hit = 0;
     if (i < n) {
         hit = err[i] >= tol ? 1 : 0;
@@ -240,6 +305,12 @@ __global__ __launch_bounds__(NT) void k_resid_seeds(int n, const double* __restr
     }
     hit = block_sum_i(hit);
     if (threadIdx.x == 0 && hit) atomicAdd(count, hit);
+}
+
+__global__ __launch_bounds__(NT) void k_resid_seeds(int n, const double* __restrict__ err,
+                                                    double tol, uint8_t* __restrict__ lvl,
+                                                    uint8_t* __restrict__ act, int* count) {
+    resid_seeds(n, err, tol, lvl, act, count, blockIdx.x);
 }
 
 void launch_mark_resid(int n, const double* err, double tol, int m, const Graph& g,
@@ -251,14 +322,165 @@ void launch_mark_resid(int n, const double* err, double tol, int m, const Graph&
 
 // Algorithm 1 shrink (only when no boundary update was non-negligible):
 // V_A = supp du_A plus the always-active cells.
-__global__ __launch_bounds__(NT) void k_shrink(int nA, const int* __restrict__ l2g,
-                                               const double* __restrict__ dp_abs, double eps,
-                                               Graph g, uint8_t* act, const int* flag) {
+__device__ inline void shrink_rows(int nA, const int* __restrict__ l2g,
+                                   const double* __restrict__ dp_abs, double eps, const Graph& g,
+                                   uint8_t* act, const int* flag, int vb) {
     if (*flag) return;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = vb * NT + threadIdx.x;
     if (r >= nA) return;
     const int i = l2g[r];
     act[i] = (dp_abs[i] >= eps || (g.flags[i] & CF_AA)) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(NT) void k_shrink(int nA, const int* __restrict__ l2g,
+                                               const double* __restrict__ dp_abs, double eps,
+                                               Graph g, uint8_t* act, const int* flag) {
+    shrink_rows(nA, l2g, dp_abs, eps, g, act, flag, blockIdx.x);
+}
+
+// ---------------------------------------------- batched set launches
+// Algorithm 1 after the update (FIM_LOCAL members): the expansion seeds
+// (boundary cells with |dp| >= eps_loc) and their layers-layer
+// neighbourhood, else the shrink; the residual-based marking (FIM_RESID
+// members, error measure already in last_dp); FIM_FULL members: nothing.
+// Same kernels and order as a member alone.
+__global__ __launch_bounds__(NT) void k_sets_init_seg(const BMember* __restrict__ t,
+                                                      const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (M.mode == FIM_LOCAL) {
+        const int i = e.vb * NT + threadIdx.x;
+        if (i < M.n) M.lvl[i] = 0xff;
+    } else if (M.mode == FIM_RESID) {
+        resid_seeds(M.n, M.last_dp, M.eps_res, M.lvl, M.act, M.dint, e.vb);
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_expand_seeds_seg(const BMember* __restrict__ t,
+                                                         const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (M.mode != FIM_LOCAL) return;
+    expand_seeds(M.nA, M.ls.l2g, M.bnd, M.dp_abs, M.eps_loc, M.lvl, M.act, nullptr, M.dint,
+                 e.vb);
+}
+
+__global__ __launch_bounds__(NT) void k_ball_step_seg(const BMember* __restrict__ t,
+                                                      const BMap* __restrict__ map, int k) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (M.mode == FIM_FULL || k > M.layers) return;
+    ball_step(M.n, M.g, k, M.lvl, M.act, nullptr, e.vb);
+}
+
+__global__ __launch_bounds__(NT) void k_shrink_seg(const BMember* __restrict__ t,
+                                                   const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (M.mode != FIM_LOCAL) return;
+    shrink_rows(M.nA, M.ls.l2g, M.dp_abs, M.eps_loc, M.g, M.act, M.dint, e.vb);
+}
+
+void launch_sets_seg(int fk, const BMember* t, const BMap* rows, int nrows, const BMap* cells,
+                     int ncells, const BMap* mem, int nmem, int layers, bool any_resid,
+                     hipStream_t s) {
+    (void)mem;
+    (void)nmem;
+    if (ncells <= 0) return;
+    if (any_resid) launch_resid_err_seg(fk, t, cells, ncells, s);
+    k_sets_init_seg<<<ncells, NT, 0, s>>>(t, cells);
+    if (nrows > 0) k_expand_seeds_seg<<<nrows, NT, 0, s>>>(t, rows);
+    for (int k = 1; k <= (layers < MAX_LAYERS ? layers : MAX_LAYERS); k++)
+        k_ball_step_seg<<<ncells, NT, 0, s>>>(t, cells, k);
+    if (nrows > 0) k_shrink_seg<<<nrows, NT, 0, s>>>(t, rows);
+}
+
+// Workgroup maps of the batched launches from the members' workgroup
+// counts: pref holds three exclusive prefix arrays of K + 1 ints (row,
+// cell and tile workgroups); map k gets, for each workgroup b < pref_k[K],
+// the member q with pref_k[q] <= b < pref_k[q + 1] and b - pref_k[q]; mem
+// lists the members.
+__global__ __launch_bounds__(NT) void k_build_maps(const int* __restrict__ pref, int K,
+                                                   BMap* __restrict__ rows,
+                                                   BMap* __restrict__ cells,
+                                                   BMap* __restrict__ tiles,
+                                                   BMap* __restrict__ mem) {
+    const int b = blockIdx.x * NT + threadIdx.x;
+    BMap* const out[3] = {rows, cells, tiles};
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const int* p = pref + k * (K + 1);
+        if (b < p[K]) {
+            int lo = 0, hi = K - 1;   // last q with p[q] <= b
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (p[mid] <= b) lo = mid;
+                else hi = mid - 1;
+            }
+            out[k][b] = BMap{lo, b - p[lo]};
+        }
+    }
+    if (b < K) mem[b] = BMap{b, 0};
+}
+
+void launch_build_maps(const int* pref, int K, int most, BMap* rows, BMap* cells, BMap* tiles,
+                       BMap* mem, hipStream_t s) {
+    const int w = most > K ? most : K;
+    if (w > 0) k_build_maps<<<nblocks(w), NT, 0, s>>>(pref, K, rows, cells, tiles, mem);
+}
+
+// status words of every member (one workgroup of 64 per member)
+__global__ void k_status_seg(const BMember* __restrict__ t, const BMap* __restrict__ map,
+                             BStatus* out) {
+    const int q = map[blockIdx.x].q;
+    const BMember& M = t[q];
+    if (threadIdx.x == 0) {
+        out[q].ns = *M.ns;
+#pragma unroll
+        for (int k = 0; k < 4; k++) out[q].dint[k] = M.dint[k];
+    }
+}
+
+void launch_status_seg(const BMember* t, const BMap* mem, int nmem, BStatus* out,
+                       hipStream_t s) {
+    if (nmem > 0) k_status_seg<<<nmem, 64, 0, s>>>(t, mem, out);
+}
+
+// the counters of the structure pass: matrix blocks, fracture blocks,
+// boundary size
+__global__ void k_struct_reset_seg(const BMember* __restrict__ t, const BMap* __restrict__ map) {
+    const BMember& M = t[map[blockIdx.x].q];
+    if (threadIdx.x == 0) {
+        M.dint[2] = 0;
+        M.dint[4] = 0;
+        M.dint[5] = 0;
+        M.dint[6] = 0;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_slice_width_seg(const BMember* __restrict__ t,
+                                                        const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    slice_width(M.nA, M.ls.l2g, M.ls.g2l, M.g, (int*)M.ls.swidth, &M.dint[4], e.vb);
+}
+
+__global__ __launch_bounds__(NT) void k_boundary_seg(const BMember* __restrict__ t,
+                                                     const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (M.mode != FIM_LOCAL) return;
+    boundary_rows(M.nA, M.ls.l2g, M.ls.g2l, M.g, M.bnd, &M.dint[2], e.vb);
+}
+
+void launch_structure_seg(const BMember* t, const BMap* rows, int nrows, const BMap* mem,
+                          int nmem, int cell_stride, hipStream_t s) {
+    if (nmem <= 0) return;
+    k_struct_reset_seg<<<nmem, 64, 0, s>>>(t, mem);
+    if (nrows <= 0) return;
+    k_slice_width_seg<<<nrows, NT, 0, s>>>(t, rows);
+    launch_pc_blocks_seg(t, rows, nrows, cell_stride, s);
+    k_boundary_seg<<<nrows, NT, 0, s>>>(t, rows);
 }
 
 void launch_shrink(int nA, const int* l2g, const double* dp_abs, double eps,

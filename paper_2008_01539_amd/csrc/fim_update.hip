@@ -10,16 +10,17 @@ namespace fimk {
 // owner (optional): only rows whose cell has owner[i] == own_k are
 // updated (the additive form of Algorithm 2 combines overlapping subdomain
 // updates by ownership); the others are left alone and do not count
+// (vb: the workgroup's index among the system's NT-row workgroups; its
+// partials go to part[4 vb ..])
 template <int FK>
-__global__ __launch_bounds__(NT) void k_update(int nA, const int* __restrict__ l2g,
-                                               const double* __restrict__ x64,
-                                               double* __restrict__ u, int8_t* __restrict__ st,
-                                               int n, DevFluid f, double ds_max,
-                                               double* __restrict__ dp_abs,
-                                               double* __restrict__ part, NStat* ns,
-                                               const int* __restrict__ owner, int own_k) {
+__device__ inline void update_rows(int nA, const int* __restrict__ l2g,
+                                   const double* __restrict__ x64, double* __restrict__ u,
+                                   int8_t* __restrict__ st, int n, const DevFluid& f,
+                                   double ds_max, double* __restrict__ dp_abs,
+                                   double* __restrict__ part, const int* __restrict__ owner,
+                                   int own_k, int vb) {
     constexpr int B = FluidTraits<FK>::B;
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = vb * NT + threadIdx.x;
     double red[4] = {0.0, 0.0, 0.0, 0.0};   // |dp| max, |dS| max, switches, nonfinite
     const int i = r < nA ? l2g[r] : 0;
     if (r < nA && (!owner || owner[i] == own_k)) {
@@ -84,13 +85,32 @@ __global__ __launch_bounds__(NT) void k_update(int nA, const int* __restrict__ l
     block_sum<2>(*reinterpret_cast<double(*)[2]>(&red[2]));
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int q = 0; q < 4; q++) part[4 * blockIdx.x + q] = red[q];
+        for (int q = 0; q < 4; q++) part[4 * vb + q] = red[q];
     }
 }
 
+template <int FK>
+__global__ __launch_bounds__(NT) void k_update(int nA, const int* __restrict__ l2g,
+                                               const double* __restrict__ x64,
+                                               double* __restrict__ u, int8_t* __restrict__ st,
+                                               int n, DevFluid f, double ds_max,
+                                               double* __restrict__ dp_abs,
+                                               double* __restrict__ part,
+                                               const int* __restrict__ owner, int own_k) {
+    update_rows<FK>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, owner, own_k, blockIdx.x);
+}
+
+template <int FK>
+__global__ __launch_bounds__(NT) void k_update_seg(const BMember* __restrict__ t,
+                                                   const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    update_rows<FK>(M.nA, M.ls.l2g, M.x64, M.u, M.st, M.n, M.f, M.ds_max, M.dp_abs, M.part,
+                    nullptr, 0, e.vb);
+}
+
 // one block: combine the per-block maxima and counts of k_update
-__global__ __launch_bounds__(1024) void k_update_finish(const double* __restrict__ part, int np,
-                                                        NStat* ns) {
+__device__ inline void update_finish(const double* __restrict__ part, int np, NStat* ns) {
     double mx[2] = {0.0, 0.0}, sm[2] = {0.0, 0.0};
     for (int q = threadIdx.x; q < np; q += blockDim.x) {
         mx[0] = fmax(mx[0], part[4 * q]);
@@ -108,17 +128,41 @@ __global__ __launch_bounds__(1024) void k_update_finish(const double* __restrict
     }
 }
 
+__global__ __launch_bounds__(1024) void k_update_finish(const double* __restrict__ part, int np,
+                                                        NStat* ns) {
+    update_finish(part, np, ns);
+}
+
+// one block per member; also clears dint[0] for the set kernels that follow
+__global__ __launch_bounds__(1024) void k_update_finish_seg(const BMember* __restrict__ t,
+                                                            const BMap* __restrict__ map) {
+    const BMember& M = t[map[blockIdx.x].q];
+    update_finish(M.part, nblocks(M.nA > 0 ? M.nA : 1), M.ns);
+    if (threadIdx.x == 0) M.dint[0] = 0;
+}
+
 void launch_update(int fk, int nA, const int* l2g, const double* x64,
                    double* u, int8_t* st, int n, const DevFluid& f,
                    double ds_max, double* dp_abs, double* part, NStat* ns,
                    hipStream_t s, const int* owner, int own_k) {
     const int nb = nblocks(nA > 0 ? nA : 1);
     switch (fk) {
-    case 1: k_update<1><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns, owner, own_k); break;
-    case 2: k_update<2><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns, owner, own_k); break;
-    default: k_update<3><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, ns, owner, own_k); break;
+    case 1: k_update<1><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, owner, own_k); break;
+    case 2: k_update<2><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, owner, own_k); break;
+    default: k_update<3><<<nb, NT, 0, s>>>(nA, l2g, x64, u, st, n, f, ds_max, dp_abs, part, owner, own_k); break;
     }
     k_update_finish<<<1, 1024, 0, s>>>(part, nb, ns);
+}
+
+void launch_update_seg(int fk, const BMember* t, const BMap* rows, int nblk, const BMap* mem,
+                       int nmem, hipStream_t s) {
+    if (nblk <= 0 || nmem <= 0) return;
+    switch (fk) {
+    case 1: k_update_seg<1><<<nblk, NT, 0, s>>>(t, rows); break;
+    case 2: k_update_seg<2><<<nblk, NT, 0, s>>>(t, rows); break;
+    default: k_update_seg<3><<<nblk, NT, 0, s>>>(t, rows); break;
+    }
+    k_update_finish_seg<<<nmem, 1024, 0, s>>>(t, mem);
 }
 
 __global__ void k_copy_state(int b, int n, const double* __restrict__ src,

@@ -4,7 +4,7 @@ each member keeps its own block partition and reduction order)."""
 import numpy as np
 import pytest
 
-from fimgen import make_c1, make_c1_variant, make_small_c2
+from fimgen import make_c1, make_c1_variant, make_small_c2, make_small_c3
 
 pytestmark = pytest.mark.gpu
 
@@ -35,9 +35,10 @@ def _batched(models, opts, mode, nsteps):
     live = list(range(len(models)))
     bat = P.FimBatch([fms[i] for i in live])
     sizes = []
+    mq = mode if isinstance(mode, (list, tuple)) else [mode] * len(models)
     while live:
         dts = [models[i].schedule[step[i]] for i in live]
-        stats, codes = bat.newton_step(dts, [mode] * len(live))
+        stats, codes = bat.newton_step(dts, [mq[i] for i in live])
         assert np.all(codes == 0)
         sizes.append(len(live))
         nxt = []
@@ -108,6 +109,25 @@ def test_serving_results_same_alone_and_in_the_mix():
         ref, _ = _solo(s.spec.model, s.spec.options, s.spec.mode, dts)
         assert np.array_equal(u, ref), s.spec.name
     ex.close()
+
+
+def test_batch_black_oil_mixed_modes_equals_solo():
+    """Black-oil members (3x3 blocks, fracture blocks) in one batch, each in
+    its own mode (Algorithm 1, full Newton, residual-based): every member
+    keeps its solo bits, states and phase status."""
+    import paper_2008_01539_amd as P
+    models = [make_small_c3(), make_small_c3(seed=43, nx=24, ny=12, nz=4, nfrac=16, nstage=2),
+              make_small_c3(seed=44, nx=16, ny=12, nz=3, nfrac=8, nstage=2),
+              make_small_c3(seed=45, nx=22, ny=8, nz=4, nfrac=12, nstage=2)]
+    modes = [P.LOCAL, P.FULL, P.RESID, P.LOCAL]
+    opts = P.Options(precision=P.MIXED)
+    n = 4
+    got, sizes = _batched(models, opts, modes, n)
+    for m, md, (u, st) in zip(models, modes, got):
+        ref, ref_st = _solo(m, opts, md, m.schedule[:n])
+        assert np.array_equal(u, ref)
+        assert np.array_equal(st, ref_st)
+    assert max(sizes) == 4
 
 
 def test_batch_two_phase_fp64_equals_solo():
