@@ -924,12 +924,11 @@ static void frac_closure(fim_model* m) {
 // The launches that start a timestep.  *pending: the step's first active
 // set is compacted and its n_A (dint[1], copied to hint[1]) must be read
 // before the structure pass (begin_finish); else n_A = n already.
-static fim_status begin_launch(fim_model* m, double dt, int mode, bool* pending) {
-    *pending = false;
-    const int pi = pbeg(m, PK_SETUP);
-    launch_copy_state(m->B, m->n, m->u, m->st, m->un, m->stn, m->s);
-    launch_accumulation(m->fk, m->n, m->un, m->stn, m->g, m->f, m->Mn, m->s);
-    pend(m, pi, m->n);
+// Host side of a timestep start.  Returns how the step's first active set
+// is formed: 1 = the previous step's support, 2 = the always-active cells
+// and their neighbour layers, 3 = all cells, 4 = all cells, already
+// compacted (full Newton and the residual-based mode on a ready set).
+static int begin_state(fim_model* m, double dt, int mode) {
     m->in_step = true;
     m->step_dt = dt;
     m->step_mode = mode;
@@ -939,6 +938,20 @@ static fim_status begin_launch(fim_model* m, double dt, int mode, bool* pending)
     m->max_active = 0;
     m->step_kry = 0;
     m->inspect_ready = false;
+    if (mode == FIM_FULL || mode == FIM_RESID) {
+        m->nA = m->n;
+        return m->full_ready ? 4 : 3;
+    }
+    return m->have_history ? 1 : 2;
+}
+
+static fim_status begin_launch(fim_model* m, double dt, int mode, bool* pending) {
+    *pending = false;
+    const int pi = pbeg(m, PK_SETUP);
+    launch_copy_state(m->B, m->n, m->u, m->st, m->un, m->stn, m->s);
+    launch_accumulation(m->fk, m->n, m->un, m->stn, m->g, m->f, m->Mn, m->s);
+    pend(m, pi, m->n);
+    (void)begin_state(m, dt, mode);
     if (mode == FIM_FULL || mode == FIM_RESID) {
         // the residual-based localization starts every step on all cells
         if (!m->full_ready) {
@@ -1751,11 +1764,15 @@ static fim_status newton_post_launch(fim_model* m) {
 }
 
 // The decisions of the iteration, once the status copies have landed.
-// need_struct (batched iterations): instead of launching the next
-// iteration's structure pass, report that it is due (the new n_A is set).
+// defer (batched iterations): instead of launching the next iteration's
+// structure pass or the converged step's support, report that they are
+// due (the new n_A is set).
+struct BatchDefer {
+    bool structure = false, commit = false;
+};
 static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it,
-                                     bool* need_struct = nullptr) {
-    if (need_struct) *need_struct = false;
+                                     BatchDefer* defer = nullptr) {
+    if (defer) *defer = BatchDefer();
     const bool local = m->step_mode == FIM_LOCAL;
     const NStat ns = *m->hns;
     m->nu++;
@@ -1786,7 +1803,13 @@ static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it,
         done = conv;
     }
     if (done) {
-        commit(m);
+        if (defer) {
+            m->have_history = true;
+            m->in_step = false;
+            defer->commit = true;
+        } else {
+            commit(m);
+        }
         if (it) it->converged = 1;
         return FIM_OK;
     }
@@ -1795,9 +1818,9 @@ static fim_status newton_post_finish(fim_model* m, fim_iter_stats* it,
         m->err = "Newton iteration cap reached";
         return FIM_NOT_CONVERGED;
     }
-    if ((local || resid) && need_struct) {
+    if ((local || resid) && defer) {
         m->nA = m->hint[1];
-        *need_struct = true;
+        defer->structure = true;
     } else if (local) {
         m->nA = m->hint[1];
         const int pi = pbeg(m, PK_SETS);
@@ -2198,20 +2221,12 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
 }
 
 // ------------------------------------------------------------- batches
-constexpr int BATCH_AUX = 4;   // streams for the members' own small kernels
-
 struct fim_batch {
     std::vector<fim_model*> ms;
     std::vector<hipEvent_t> ev;   // one per member: stream hand-over
     hipEvent_t done_ev = nullptr;
     hipStream_t s = nullptr;
     bool own_stream = false;
-    // the members' set, compaction, assembly and update launches are a few
-    // small kernels each; member q issues them on aux[q % BATCH_AUX] so that
-    // those of different members overlap; fork / join order them against
-    // the batch stream, which runs the batched solve
-    hipStream_t aux[BATCH_AUX] = {};
-    hipEvent_t fork_ev = nullptr, join_ev[BATCH_AUX] = {};
     SolveTable tab;
     int B = 0, precision = 0;
     std::string err;
@@ -2303,6 +2318,9 @@ static BMember bmember(fim_model* m) {
     x.u = m->u;
     x.st = m->st;
     x.Mn = m->Mn;
+    x.un = m->un;
+    x.stn = m->stn;
+    x.supp = m->supp;
     x.dt = m->step_dt;
     x.inv_dt = 1.0 / m->step_dt;
     x.ds_max = m->o.ds_max;
@@ -2333,6 +2351,7 @@ static BMember bmember(fim_model* m) {
     x.mode = m->step_mode;
     x.layers = m->step_mode == FIM_LOCAL ? std::min(m->o.m_layers, MAX_LAYERS)
              : m->step_mode == FIM_RESID ? std::min(m->o.res_layers, MAX_LAYERS) : 0;
+    x.compact = m->step_mode != FIM_FULL ? 1 : 0;
     return x;
 }
 
@@ -2344,8 +2363,8 @@ struct BPhase {
     bool any_resid = false;
 };
 
-static fim_status batch_upload(fim_batch* b, const std::vector<fim_model*>& ms, BPhase& ph) {
-    const int K = (int)ms.size();
+static fim_status batch_upload(fim_batch* b, const std::vector<BMember>& ent, BPhase& ph) {
+    const int K = (int)ent.size();
     fim_batch::Slot& sl = b->slot[b->cur];
     b->cur ^= 1;
     if (hipEventSynchronize(sl.ev) != hipSuccess) {
@@ -2358,16 +2377,15 @@ static fim_status batch_upload(fim_batch* b, const std::vector<fim_model*>& ms, 
     ph = BPhase();
     ph.K = K;
     for (int q = 0; q < K; q++) {
-        fim_model* m = ms[q];
-        t[q] = bmember(m);
-        const int c[3] = {bt_blocks(std::max(m->nA, 0)), bt_blocks(m->n),
-                          (m->n + TILE - 1) / TILE};
+        t[q] = ent[q];
+        const int n = t[q].n;
+        const int c[3] = {bt_blocks(std::max(t[q].nA, 0)), bt_blocks(n), (n + TILE - 1) / TILE};
         for (int k = 0; k < 3; k++) {
             pref[k * (K + 1) + q] = acc[k];
             acc[k] += c[k];
         }
         ph.layers = std::max(ph.layers, t[q].layers);
-        ph.any_resid = ph.any_resid || m->step_mode == FIM_RESID;
+        ph.any_resid = ph.any_resid || t[q].mode == FIM_RESID;
     }
     for (int k = 0; k < 3; k++) pref[k * (K + 1) + K] = acc[k];
     if (hipMemcpyAsync(sl.d, sl.h, bt_host_bytes(K), hipMemcpyHostToDevice, b->s) != hipSuccess ||
@@ -2393,11 +2411,29 @@ static fim_status batch_upload(fim_batch* b, const std::vector<fim_model*>& ms, 
 
 // the structure pass of the members' new local systems (one launch per
 // kernel for all of them)
+static std::vector<BMember> bmembers(const std::vector<fim_model*>& ms) {
+    std::vector<BMember> v;
+    v.reserve(ms.size());
+    for (fim_model* m : ms) v.push_back(bmember(m));
+    return v;
+}
+
 static fim_status batch_structure(fim_batch* b, const std::vector<fim_model*>& ms) {
     if (ms.empty()) return FIM_OK;
     BPhase ph;
-    TRY(batch_upload(b, ms, ph));
+    TRY(batch_upload(b, bmembers(ms), ph));
     launch_structure_seg(ph.t, ph.rows, ph.nrows, ph.mem, ph.K, pc_cell_stride(b->B), b->s);
+    return FIM_OK;
+}
+
+// the support of the members' converged steps
+static fim_status batch_commit(fim_batch* b, const std::vector<fim_model*>& ms) {
+    if (ms.empty()) return FIM_OK;
+    std::vector<BMember> v = bmembers(ms);
+    for (BMember& x : v) x.commit = 1;
+    BPhase ph;
+    TRY(batch_upload(b, v, ph));
+    launch_support_seg(ph.t, ph.cells, ph.ncells, b->s);
     return FIM_OK;
 }
 
@@ -2453,13 +2489,8 @@ fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_strea
     } else {
         b->own_stream = true;
     }
-    bool ok = hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming) == hipSuccess &&
-              hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess;
-    for (int i = 0; i < BATCH_AUX && ok; i++)
-        ok = hipStreamCreate(&b->aux[i]) == hipSuccess &&
-             hipEventCreateWithFlags(&b->join_ev[i], hipEventDisableTiming) == hipSuccess;
-    if (!ok) {
-        g_batch_err = "hipStreamCreate / hipEventCreate failed";
+    if (hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming) != hipSuccess) {
+        g_batch_err = "hipEventCreate failed";
         (void)fim_batch_destroy(b);
         return FIM_E_HIP;
     }
@@ -2476,37 +2507,12 @@ fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_strea
 fim_status fim_batch_destroy(fim_batch* b) {
     if (!b) return FIM_E_ARG;
     if (b->s) (void)hipStreamSynchronize(b->s);
-    for (int i = 0; i < BATCH_AUX; i++) {
-        if (b->aux[i]) {
-            (void)hipStreamSynchronize(b->aux[i]);
-            (void)hipStreamDestroy(b->aux[i]);
-        }
-        if (b->join_ev[i]) (void)hipEventDestroy(b->join_ev[i]);
-    }
     table_free(b->tab);
     batch_tables_free(b);
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     if (b->done_ev) (void)hipEventDestroy(b->done_ev);
-    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     if (b->own_stream && b->s) (void)hipStreamDestroy(b->s);
     delete b;
-    return FIM_OK;
-}
-
-// aux streams after everything queued on the batch stream so far
-static fim_status batch_fork(fim_batch* b) {
-    if (hipEventRecord(b->fork_ev, b->s) != hipSuccess) return FIM_E_HIP;
-    for (int i = 0; i < BATCH_AUX; i++)
-        if (hipStreamWaitEvent(b->aux[i], b->fork_ev, 0) != hipSuccess) return FIM_E_HIP;
-    return FIM_OK;
-}
-
-// the batch stream after everything queued on the aux streams so far
-static fim_status batch_join(fim_batch* b) {
-    for (int i = 0; i < BATCH_AUX; i++)
-        if (hipEventRecord(b->join_ev[i], b->aux[i]) != hipSuccess ||
-            hipStreamWaitEvent(b->s, b->join_ev[i], 0) != hipSuccess)
-            return FIM_E_HIP;
     return FIM_OK;
 }
 
@@ -2514,10 +2520,12 @@ const char* fim_batch_last_error(const fim_batch* b) {
     return b ? b->err.c_str() : g_batch_err.c_str();
 }
 
-// One Newton iteration of every member (Algorithm 1 or full Newton): the
-// per-member set, compaction and assembly launches, then one batched
-// Krylov solve over all members, then the per-member updates, and a single
-// synchronisation for the whole batch.
+// One Newton iteration of every member (Algorithm 1, full Newton or the
+// residual-based mode) on the batch stream, one launch per kernel for all
+// members: the timestep starts (and one synchronisation for their n_A),
+// assembly and scaling, one batched Krylov solve, the updates, the sets and
+// compaction, one synchronisation for the status words, then the supports
+// of the converged steps and the structure of the next local systems.
 fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t* modes,
                                  fim_iter_stats* stats, int32_t* codes) {
     if (!b || !dts || !modes || !codes) return FIM_E_ARG;
@@ -2549,65 +2557,71 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
         codes[q] = FIM_OK;
     }
     auto restore = [&]() {
-        (void)batch_join(b);
         (void)hipEventRecord(b->done_ev, b->s);
         for (int q = 0; q < K; q++) {
             b->ms[q]->s = saved[q];
             if (saved[q] != b->s) (void)hipStreamWaitEvent(saved[q], b->done_ev, 0);
         }
     };
-    if (batch_fork(b) != FIM_OK) {
-        b->err = "stream fork failed";
-        restore();
-        return FIM_E_HIP;
-    }
-    // members that start a timestep: their first active set on the aux
-    // streams, one synchronisation for all of them, then one structure pass
-    std::vector<fim_model*> starters;
+    // members that start a timestep: u^n, accumulation and the first
+    // active set in one launch per kernel, one synchronisation for the new
+    // n_A, then one structure pass
+    std::vector<fim_model*> starters, pending;
+    std::vector<BMember> bent;
     for (int q = 0; q < K; q++) {
         fim_model* m = b->ms[q];
-        m->s = b->aux[q % BATCH_AUX];
         if (m->in_step && (dts[q] != m->step_dt || modes[q] != m->step_mode)) {
             m->err = "dt or mode changed inside a timestep";
             codes[q] = FIM_E_STATE;
             continue;
         }
         if (!m->in_step) {
-            bool pending = false;
-            fim_status r = begin_launch(m, dts[q], modes[q], &pending);
-            if (r != FIM_OK) {
-                codes[q] = r;
-                continue;
-            }
-            if (pending) starters.push_back(m);
+            const int kind = begin_state(m, dts[q], modes[q]);
+            BMember x = bmember(m);
+            x.begin = kind;
+            x.compact = kind <= 3 ? 1 : 0;
+            x.layers = kind == 2 ? std::min(m->o.m_layers, MAX_LAYERS) : 0;
+            bent.push_back(x);
+            starters.push_back(m);
+            if (kind <= 3) pending.push_back(m);
         }
     }
-    if (batch_join(b) != FIM_OK) {
-        b->err = "stream join failed";
-        restore();
-        return FIM_E_HIP;
-    }
-    for (fim_model* m : b->ms) m->s = b->s;
     if (!starters.empty()) {
-        if (hipStreamSynchronize(b->s) != hipSuccess) {
-            b->err = "hipStreamSynchronize failed";
-            restore();
-            return FIM_E_HIP;
-        }
-        for (fim_model* m : starters) {
-            pflush(m);
-            m->nA = m->hint[1];
-        }
-        fim_status r = batch_structure(b, starters);
+        fim_model* lead = starters[0];
+        BPhase ph;
+        fim_status r = batch_upload(b, bent, ph);
         if (r != FIM_OK) {
             restore();
             return r;
         }
+        const int pi = pbeg(lead, PK_SETUP);
+        launch_begin_seg(b->B, ph.t, ph.cells, ph.ncells, ph.layers, b->s);
         for (fim_model* m : starters)
-            if (m->step_mode == FIM_FULL || m->step_mode == FIM_RESID) {
-                m->full_ready = true;
-                m->nA = m->n;
+            if (m->step_mode == FIM_LOCAL) frac_closure(m);
+        launch_compact_seg(ph.t, ph.tiles, ph.ntiles, b->s);
+        pend(lead, pi, ph.ncells * NT);
+        if (!pending.empty()) {
+            launch_status_seg(ph.t, ph.mem, ph.K, b->dstat, b->s);
+            if (hipStreamSynchronize(b->s) != hipSuccess) {
+                b->err = "hipStreamSynchronize failed";
+                restore();
+                return FIM_E_HIP;
             }
+            for (size_t t = 0; t < starters.size(); t++) {
+                pflush(starters[t]);
+                if (bent[t].compact) starters[t]->nA = b->hstat[t].dint[1];
+            }
+            r = batch_structure(b, pending);
+            if (r != FIM_OK) {
+                restore();
+                return r;
+            }
+            for (fim_model* m : pending)
+                if (m->step_mode == FIM_FULL || m->step_mode == FIM_RESID) {
+                    m->full_ready = true;
+                    m->nA = m->n;
+                }
+        }
     }
     // the live members: one launch per kernel for all of them
     std::vector<fim_model*> live;
@@ -2625,7 +2639,7 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
     if (!live.empty()) {
         fim_model* lead = live[0];
         BPhase ph;
-        fim_status r = batch_upload(b, live, ph);
+        fim_status r = batch_upload(b, bmembers(live), ph);
         if (r != FIM_OK) {
             restore();
             return r;
@@ -2664,17 +2678,19 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
             restore();
             return FIM_E_HIP;
         }
-        std::vector<fim_model*> next;
+        std::vector<fim_model*> next, done;
         for (size_t t = 0; t < live.size(); t++) {
             fim_model* m = live[t];
             pflush(m);
             *m->hns = b->hstat[t].ns;
             for (int k = 0; k < 4; k++) m->hint[k] = b->hstat[t].dint[k];
-            bool need = false;
-            codes[pos[t]] = newton_post_finish(m, stats ? &stats[pos[t]] : nullptr, &need);
-            if (need) next.push_back(m);
+            BatchDefer d;
+            codes[pos[t]] = newton_post_finish(m, stats ? &stats[pos[t]] : nullptr, &d);
+            if (d.structure) next.push_back(m);
+            if (d.commit) done.push_back(m);
         }
-        r = batch_structure(b, next);
+        r = batch_commit(b, done);
+        if (r == FIM_OK) r = batch_structure(b, next);
         if (r != FIM_OK) {
             restore();
             return r;

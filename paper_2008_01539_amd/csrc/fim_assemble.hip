@@ -32,6 +32,50 @@ __global__ __launch_bounds__(NT) void k_accumulation(int n, const double* __rest
     for (int c = 0; c < B; c++) M[(long)c * n + i] = P.M[c].v;
 }
 
+// batched timestep start (cell launch): copy of the state, accumulation at
+// it (the same arithmetic as k_accumulation) and the first active flags
+template <int FK>
+__global__ __launch_bounds__(NT) void k_begin_seg(const BMember* __restrict__ t,
+                                                  const BMap* __restrict__ map) {
+    constexpr int B = FluidTraits<FK>::B;
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    const int n = M.n, i = e.vb * NT + threadIdx.x;
+    if (!M.begin || i >= n) return;
+    double uu[B];
+#pragma unroll
+    for (int v = 0; v < B; v++) {
+        uu[v] = M.u[(long)v * n + i];
+        M.un[(long)v * n + i] = uu[v];
+    }
+    const int8_t s = M.st[i];
+    M.stn[i] = s;
+    Props<FK> P;
+    cell_props<FK>(uu, s, M.g.pv[i], M.f, P);
+#pragma unroll
+    for (int c = 0; c < B; c++) M.Mn[(long)c * n + i] = P.M[c].v;
+    if (M.begin == 1) {
+        M.act[i] = M.supp[i];
+    } else if (M.begin == 2) {
+        const bool seed = (M.g.flags[i] & CF_AA) != 0;
+        M.lvl[i] = seed ? 0 : 0xff;
+        M.act[i] = seed ? 1 : 0;
+    } else if (M.begin == 3) {
+        M.act[i] = 1;
+    }
+}
+
+void launch_begin_seg(int fk, const BMember* t, const BMap* cells, int ncells, int layers,
+                      hipStream_t s) {
+    if (ncells <= 0) return;
+    switch (fk) {
+    case 1: k_begin_seg<1><<<ncells, NT, 0, s>>>(t, cells); break;
+    case 2: k_begin_seg<2><<<ncells, NT, 0, s>>>(t, cells); break;
+    default: k_begin_seg<3><<<ncells, NT, 0, s>>>(t, cells); break;
+    }
+    launch_ball_steps_seg(t, cells, ncells, layers, s);
+}
+
 // (vb: the workgroup's index among the NT-row workgroups of this system)
 template <int FK>
 __device__ inline void assemble_rows(int nA, const LocalSys& ls, const Graph& g,

@@ -287,7 +287,10 @@ struct BMember {
     DevFluid f;
     double* u;
     int8_t* st;
-    const double* Mn;
+    double* Mn;
+    double* un;             // state and accumulation at the start of the step
+    int8_t* stn;
+    uint8_t* supp;          // support of the last converged step
     double inv_dt, dt, ds_max;
     double* dinv;
     void* At;
@@ -310,6 +313,11 @@ struct BMember {
     int* pcoff;
     int* pclist;
     int n, nA, mode, layers;
+    // per phase: begin = starts a timestep (0 no; 1 act = supp; 2 act = the
+    // always-active cells and their layers-layer neighbourhood; 3 act = all
+    // cells; 4 keep act), compact = compacts act, commit = the step
+    // converged (its support into supp)
+    int begin, compact, commit, pad;
 };
 // workgroup -> (member, the member's own workgroup index)
 struct BMap {
@@ -339,8 +347,19 @@ void launch_update_seg(int fk, const BMember* t, const BMap* rows, int nblk, con
 void launch_sets_seg(int fk, const BMember* t, const BMap* rows, int nrows, const BMap* cells,
                      int ncells, const BMap* mem, int nmem, int layers, bool any_resid,
                      hipStream_t s);
-// compaction of each member's act (FIM_LOCAL / FIM_RESID members)
+// compaction of act (the members with compact set)
 void launch_compact_seg(const BMember* t, const BMap* tiles, int ntiles, hipStream_t s);
+// timestep start of the members with begin set: u^n, status^n and the
+// accumulation at u^n, the first active flags (begin 1 - 3), then the
+// neighbour layers of begin-2 members (layers: their largest count)
+void launch_begin_seg(int fk, const BMember* t, const BMap* cells, int ncells, int layers,
+                      hipStream_t s);
+// (fim_sets.hip) layers passes of the neighbourhood marking over the
+// members' own layer counts
+void launch_ball_steps_seg(const BMember* t, const BMap* cells, int ncells, int layers,
+                           hipStream_t s);
+// the support of the converged steps (members with commit set)
+void launch_support_seg(const BMember* t, const BMap* cells, int ncells, hipStream_t s);
 // each member's NStat and dint[0..3] into out (pinned host, nmem records)
 struct BStatus {
     NStat ns;

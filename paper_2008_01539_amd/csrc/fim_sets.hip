@@ -128,7 +128,7 @@ __global__ __launch_bounds__(NT) void k_compact_count_seg(const BMember* __restr
                                                           const BMap* __restrict__ map) {
     const BMap e = map[blockIdx.x];
     const BMember& M = t[e.q];
-    if (M.mode == FIM_FULL) return;
+    if (!M.compact) return;
     compact_count(M.act, M.n, M.blk, e.vb);
 }
 
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_compact_scatter_seg(const BMember* __res
                                                             const BMap* __restrict__ map) {
     const BMap e = map[blockIdx.x];
     const BMember& M = t[e.q];
-    if (M.mode == FIM_FULL) return;
+    if (!M.compact) return;
     compact_scatter(M.act, M.n, M.blk, (int*)M.ls.l2g, (int*)M.ls.g2l, &M.dint[1], e.vb,
                     (M.n + TILE - 1) / TILE);
 }
@@ -381,6 +381,26 @@ __global__ __launch_bounds__(NT) void k_shrink_seg(const BMember* __restrict__ t
     shrink_rows(M.nA, M.ls.l2g, M.dp_abs, M.eps_loc, M.g, M.act, M.dint, e.vb);
 }
 
+void launch_ball_steps_seg(const BMember* t, const BMap* cells, int ncells, int layers,
+                           hipStream_t s) {
+    for (int k = 1; k <= (layers < MAX_LAYERS ? layers : MAX_LAYERS); k++)
+        k_ball_step_seg<<<ncells, NT, 0, s>>>(t, cells, k);
+}
+
+__global__ __launch_bounds__(NT) void k_support_seg(const BMember* __restrict__ t,
+                                                    const BMap* __restrict__ map) {
+    const BMap e = map[blockIdx.x];
+    const BMember& M = t[e.q];
+    if (!M.commit) return;
+    const int i = e.vb * NT + threadIdx.x;
+    if (i >= M.n) return;
+    M.supp[i] = (fabs(M.u[i] - M.un[i]) >= M.eps_loc || (M.g.flags[i] & CF_AA)) ? 1 : 0;
+}
+
+void launch_support_seg(const BMember* t, const BMap* cells, int ncells, hipStream_t s) {
+    if (ncells > 0) k_support_seg<<<ncells, NT, 0, s>>>(t, cells);
+}
+
 void launch_sets_seg(int fk, const BMember* t, const BMap* rows, int nrows, const BMap* cells,
                      int ncells, const BMap* mem, int nmem, int layers, bool any_resid,
                      hipStream_t s) {
@@ -390,8 +410,7 @@ void launch_sets_seg(int fk, const BMember* t, const BMap* rows, int nrows, cons
     if (any_resid) launch_resid_err_seg(fk, t, cells, ncells, s);
     k_sets_init_seg<<<ncells, NT, 0, s>>>(t, cells);
     if (nrows > 0) k_expand_seeds_seg<<<nrows, NT, 0, s>>>(t, rows);
-    for (int k = 1; k <= (layers < MAX_LAYERS ? layers : MAX_LAYERS); k++)
-        k_ball_step_seg<<<ncells, NT, 0, s>>>(t, cells, k);
+    launch_ball_steps_seg(t, cells, ncells, layers, s);
     if (nrows > 0) k_shrink_seg<<<nrows, NT, 0, s>>>(t, rows);
 }
 
