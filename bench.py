@@ -517,6 +517,11 @@ def run_single(workload, args):
             log(f"local, fracture cells localized: wall {legs['local_frac']['wall']:.3f}s")
         legs["local_fp64"] = run_gpu(model, P.Options(precision=P.FP64), P.LOCAL, K, W)
         log(f"local FP64: wall {legs['local_fp64']['wall']:.3f}s")
+        if args.profile:
+            # the product kernels over the whole system: full Newton's first
+            # three timed steps again with launch events
+            legs["full_events"] = run_gpu(model, opts, P.FULL, min(3, K), W, profile=True)
+            log(f"full (events, {min(3, K)} steps): wall {legs['full_events']['wall']:.3f}s")
         ref = run_gpu(model, P.Options.tight_mode(precision=P.FP64), P.FULL, K, W)["u"]
         log("tight FP64 full-Newton reference done")
     value = loc["active"] / loc["wall"]
@@ -582,6 +587,14 @@ def run_single(workload, args):
         out["roofline"].update(copy_gbps=copy, frac_of_copy=roof["achieved"] / copy,
                                profiled_wall_s=prof_run["wall"])
         out["kernel_profile_local"] = prof
+        if "full_events" in legs:
+            # the same kernel class over the whole system (every cell a row),
+            # the same byte definitions; context beside the headline's kernel
+            rf = roofline_of(legs["full_events"]["prof"], model.b, names=(roof["kernel"],))
+            out["roofline_full_system"] = {k: rf[k] for k in (
+                "kernel", "achieved", "peak", "unit", "frac", "avg_launch_us", "bytes_per_launch",
+                "rows_per_launch", "kernel_own_gbs", "fracture_block_gbs")}
+            out["roofline_full_system"]["frac_of_copy"] = rf["achieved"] / copy
     if args.calibrate_copy:
         # one plain device-to-device copy of known size (memory-counter scale)
         n_el = args.calibrate_copy * 2**20 // 4

@@ -362,6 +362,7 @@ static KrylovBufs kbufs(fim_model* m, bool fp32) {
     kb.sv = base + 7 * vb;
     kb.t = base + 8 * vb;
     kb.x64 = m->x64;
+    kb.xprev = m->xprev;
     kb.rir = m->rir;
     kb.sc = m->sc;
     kb.part_ir = m->part_ir;                 // 2 per block
@@ -634,7 +635,6 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
             nact++;
             it.passes++;
             fim_model* mq = it.m;
-            if (it.fp32) launch_copy_f64(mq->xprev, mq->x64, (long)mq->nA * mq->B, s);
             // inner target: the reduction this pass needs, not below what
             // the Krylov precision can deliver
             const double need = 0.5 * std::sqrt(it.target2 / it.rir2);

@@ -176,6 +176,7 @@ void launch_precond(int b, bool fp32, int nA, const LocalSys& ls,
 struct KrylovBufs {
     void* x; void* r; void* rh; void* p[2]; void* v[2]; void* sv; void* t;
     double* x64; double* rir; KScal* sc;
+    double* xprev;          // x64 before the last FP32 pass (its undo)
     // per-block partial dot products (part_ir 2 per block, the others 4)
     double* part_ir; double* part_a; double* part_b; double* part_c;
     const double* dinv; const void* At;

@@ -789,9 +789,15 @@ __global__ __launch_bounds__(KB_NT) void k_ir_accumulate(const KSeg* __restrict_
     const int nbk = S.nblk, lb = xcd_tile(S.blk0, nbk, blockIdx.x);
     double* __restrict__ x64 = S.kb.x64;
     const T* __restrict__ xT = (const T*)S.kb.x;
+    // (an FP32 pass keeps the previous x64 in xprev, to be undone if the
+    // pass stalls)
+    double* __restrict__ xprev = S.kb.xprev;
     for (long q = (long)lb * blockDim.x + threadIdx.x; q < (long)S.nA * B;
-         q += (long)nbk * blockDim.x)
-        x64[q] += (double)xT[q];
+         q += (long)nbk * blockDim.x) {
+        const double o = x64[q];
+        if (sizeof(T) == 4) xprev[q] = o;
+        x64[q] = o + (double)xT[q];
+    }
 }
 
 __global__ void k_copy_f64(double* __restrict__ d, const double* __restrict__ s, long n) {

@@ -124,3 +124,27 @@ def test_mixed_precision_error_per_result(which, c2s, c3s):
     ref = run_oracle(Solver(m, OOptions()), m, m.schedule)[-1].u
     rel = np.abs(u[0] - ref[0]).max() / ref[0].min()
     assert rel <= 1e-6, rel
+
+
+def test_stalled_fp32_passes_finish_in_fp64(c3s, oracle_c3s):
+    """Mixed precision whose FP32 passes cannot make progress (inner
+    tolerance 1: the FP32 BiCGStab stops at its initial guess): every
+    linear solve undoes its FP32 pass, continues with the FP64 Krylov and
+    reports it; tight-mode timesteps still reach the oracle."""
+    import paper_2008_01539_amd as P
+    o = P.Options.tight_mode(precision=P.MIXED, inner_rtol=1.0)
+    fm = _fm(c3s, o)
+    falls = []
+    for dt in c3s.schedule:
+        while True:
+            it = fm.newton_step(dt, P.FULL)
+            falls.append(it.fp64_fallback)
+            if it.converged:
+                break
+    u, st = fm.get_state()
+    fm.close()
+    assert len(falls) > len(c3s.schedule) and all(f == 1 for f in falls)
+    ref = oracle_c3s[-1]
+    assert np.array_equal(st, ref.status)
+    assert np.abs(u[0] - ref.u[0]).max() <= 1e-8 * ref.u[0].min()
+    assert np.abs(u[1] - ref.u[1]).max() <= 1e-8
