@@ -189,6 +189,63 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // the block in LDS, row stride MS (16-byte rows, offset banks per row)
 constexpr int PCI_MS = PC_DOF + 4;
 
+// Gauss-Jordan elimination of the block in M (rows 0 .. N-1 of the wave's
+// lanes, C >= N register columns; the identity padding of M's rows is
+// never a pivot): every step takes column 0 as the pivot column,
+// broadcasts the pivot row from the pivot lane's registers (lane reads,
+// no LDS round trip), eliminates with multiplier (entry / pivot), leaves
+// the pivot row unscaled (one FMA per entry and step) and shifts the
+// columns left by one, appending the new column of the inverse at the end,
+// so all register indices are compile-time constants; each row is divided
+// by its own pivot once at the end.  After N steps columns C - N .. C - 1
+// hold the inverse; the rows go back to M.  Returns whether a pivot was
+// below 1e-20 in magnitude or not finite.
+template <int C>
+__device__ inline bool gauss_jordan(float* M, int N) {
+    constexpr int MS = PCI_MS;
+    const int lane = threadIdx.x;
+    float a[C];
+    {
+        const f4v* row = (const f4v*)&M[lane * MS];
+#pragma unroll
+        for (int c = 0; c < C / 4; c++) {
+            const f4v v = row[c];
+            a[4 * c] = v[0];
+            a[4 * c + 1] = v[1];
+            a[4 * c + 2] = v[2];
+            a[4 * c + 3] = v[3];
+        }
+    }
+    wave_sync();
+    bool bad = false;
+    float myip = 1.0f;   // 1 / this row's pivot
+    for (int step = 0; step < N; step++) {
+        float pr[C];
+#pragma unroll
+        for (int c = 0; c < C; c++)
+            pr[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[c]), step));
+        const float p = pr[0];
+        bad = bad || !(fabsf(p) > 1e-20f) || !isfinite(p);
+        const float ip = 1.0f / p;
+        const bool me = lane == step;
+        if (me) myip = ip;
+        const float f = me ? 0.0f : a[0] * ip;
+#pragma unroll
+        for (int c = 1; c < C; c++) a[c - 1] = fmaf(-f, pr[c], a[c]);
+        a[C - 1] = me ? 1.0f : -f;
+    }
+#pragma unroll
+    for (int c = 0; c < C; c++) a[c] *= myip;
+    {
+        f4v* row = (f4v*)&M[lane * MS];
+#pragma unroll
+        for (int c = 0; c < C / 4; c++)
+            row[c] = f4v{a[4 * c], a[4 * c + 1], a[4 * c + 2], a[4 * c + 3]};
+    }
+    wave_sync();
+    return bad;
+}
+
 // Block q of one system's list, by one wave; M: PC_DOF x PCI_MS floats of
 // LDS.  Loops stay rolled where they run once per block: each wave runs
 // this code about once per launch, so its size (instruction fetch) costs
@@ -255,55 +312,20 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
             }
         }
         wave_sync();
-        float a[PC_DOF];
-        {
-            const f4v* row = (const f4v*)&M[lane * MS];
-#pragma unroll
-            for (int c = 0; c < PC_DOF / 4; c++) {
-                const f4v v = row[c];
-                a[4 * c] = v[0];
-                a[4 * c + 1] = v[1];
-                a[4 * c + 2] = v[2];
-                a[4 * c + 3] = v[3];
-            }
+        // the register width: the fewest of 32, 48 or 64 columns that hold
+        // the block (columns C - N .. C - 1 end up holding the inverse)
+        int C = PC_DOF;
+        bool bad;
+        if (N <= 32) {
+            bad = gauss_jordan<32>(M, N);
+            C = 32;
+        } else if (N <= 48) {
+            bad = gauss_jordan<48>(M, N);
+            C = 48;
+        } else {
+            bad = gauss_jordan<PC_DOF>(M, N);
         }
-        wave_sync();
-        bool bad = false;
-        float myip = 1.0f;   // 1 / this row's pivot
-        // N steps; afterwards columns 64 - N .. 63 of rows 0 .. N-1 hold the
-        // inverse, each row still times its pivot (the identity padding is
-        // never a pivot)
-        for (int step = 0; step < N; step++) {
-            // the pivot row, broadcast from the pivot lane's registers
-            float pr[PC_DOF];
-#pragma unroll
-            for (int c = 0; c < PC_DOF; c++)
-                pr[c] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[c]), step));
-            const float p = pr[0];
-            bad = bad || !(fabsf(p) > 1e-20f) || !isfinite(p);
-            const float ip = 1.0f / p;
-            const bool me = lane == step;
-            // the pivot row is not normalised here (one FMA per entry with
-            // the multiplier f / p); the pivot lane only shifts its row
-            if (me) myip = ip;
-            const float f = me ? 0.0f : a[0] * ip;
-#pragma unroll
-            for (int c = 1; c < PC_DOF; c++) a[c - 1] = fmaf(-f, pr[c], a[c]);
-            a[PC_DOF - 1] = me ? 1.0f : -f;
-        }
-#pragma unroll
-        for (int c = 0; c < PC_DOF; c++) a[c] *= myip;
-        // the inverse back to LDS (row lane), checked, then stored in the
-        // grouped layout (see fim_internal.hpp): lane = unknown rr b + ci,
-        // K consecutive columns per store, zero padding past column N
-        {
-            f4v* row = (f4v*)&M[lane * MS];
-#pragma unroll
-            for (int c = 0; c < PC_DOF / 4; c++)
-                row[c] = f4v{a[4 * c], a[4 * c + 1], a[4 * c + 2], a[4 * c + 3]};
-        }
-        wave_sync();
-        const int c0 = PC_DOF - N;
+        const int c0 = C - N;
         bool big = false;
         if (lane < N) {
 #pragma unroll 1
