@@ -262,10 +262,13 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o);
 /* ---------------- batches of models ------------------------------------ */
 
 /* A batch advances several independent models together: each call runs
- * one Newton iteration (Algorithm 1 or full Newton) of every member, with
- * the members' local linear systems solved by one set of Krylov launches
- * that covers all of them (per-member reductions and convergence).  A
- * member's result is the same alone and in any batch.  Members keep their
+ * one Newton iteration (Algorithm 1, full Newton or the residual-based
+ * mode) of every member with one launch per kernel for all members (the
+ * timestep starts, assembly, the local linear systems' Krylov solves, the
+ * updates, active sets and structure; per-member reductions and
+ * convergence) and one synchronisation for the members' status words, plus
+ * one when some member starts a timestep.  A member's result is the same
+ * alone and in any batch.  Members keep their
  * own state and may be in different phases of their own timesteps; a
  * member whose step converged starts its next step at its next call.
  * Members need the same block size and Krylov precision; the batch does
