@@ -38,8 +38,9 @@ __device__ inline void pc_blocks_tile(int nA, const int* __restrict__ l2g,
     constexpr int NW = KB_NT / WAVE;
     __shared__ int sf[KB_NT];              // fracture id of each row (-1 matrix, -2 past nA)
     __shared__ int su[KB_NT];              // funit of each fracture row, then its block
+    __shared__ int sfo[KB_NT];             // fracture-cell ordinal of each fracture row
     __shared__ int wfirst[NW], wlast[NW];  // first / last start in each wave
-    __shared__ int nlead[NW], sq[NW + 1], base_q;
+    __shared__ int nlead[NW], sq[NW + 1], base_q, wsq[NW];
     const int t = threadIdx.x, lane = t % WAVE, w = t / WAVE;
     const int base = vb * KB_NT, r = base + t;
     const bool valid = r < nA;
@@ -48,6 +49,7 @@ __device__ inline void pc_blocks_tile(int nA, const int* __restrict__ l2g,
     const int fu = f >= 0 ? funit[cell] : 0;
     sf[t] = f;
     su[t] = fu;
+    sfo[t] = f >= 0 ? ford[cell] : 0;
     const unsigned long long upto = (2ull << lane) - 1ull;   // lanes 0 .. lane
     // the segment around row t of the rows flagged by st: from the last
     // flagged row at or before t to before the first one after it
@@ -93,33 +95,37 @@ __device__ inline void pc_blocks_tile(int nA, const int* __restrict__ l2g,
     segment(t == 0 || f < 0 || sf[t - 1] != f || su[t - 1] != k, bs, be);
     const int size = be - bs;
     const bool lead = valid && size > 1 && bs == t;
-    // list slots: one atomic per workgroup
+    // list slots, and the sum of rows^2 over the blocks (profiling): one
+    // atomic each per workgroup
     const unsigned long long lm = __ballot(lead);
-    if (lane == 0) nlead[w] = __popcll(lm);
+    int s2 = lead ? size * size : 0;
+    for (int o = WAVE / 2; o > 0; o /= 2) s2 += __shfl_xor(s2, o);
+    if (lane == 0) {
+        nlead[w] = __popcll(lm);
+        wsq[w] = s2;
+    }
     __syncthreads();
     if (t == 0) {
-        int acc = 0;
+        int acc = 0, a2 = 0;
         for (int v = 0; v < NW; v++) {
             sq[v] = acc;
             acc += nlead[v];
+            a2 += wsq[v];
         }
         sq[NW] = acc;
         base_q = acc ? atomicAdd(&cnt[1], acc) : 0;
+        if (a2) atomicAdd(&cnt[0], a2);
     }
     __syncthreads();
     if (valid) {
         pcinfo[r] = (bs << 16) | size;
-        pcoff[r] = (size > 1) ? ford[l2g[base + bs]] * cell_stride : 0;
+        pcoff[r] = (size > 1) ? sfo[bs] * cell_stride : 0;
     }
     if (lead) {
         const int q = base_q + sq[w] + __popcll(lm & (upto >> 1));
         list[2 * q] = r;
         list[2 * q + 1] = size;
     }
-    // sum of rows^2 over the blocks (profiling): one atomic per wave
-    int s2 = lead ? size * size : 0;
-    for (int o = WAVE / 2; o > 0; o /= 2) s2 += __shfl_xor(s2, o);
-    if (lane == 0 && s2) atomicAdd(&cnt[0], s2);
 }
 
 __global__ __launch_bounds__(KB_NT) void k_pc_blocks(int nA, const int* __restrict__ l2g,
