@@ -115,12 +115,20 @@ typedef struct fim_model_desc {
     const int32_t* frac_id;       /* [n] or NULL                           */
 } fim_model_desc;
 
-/* Preconditioners of the local linear solve (the paper names none). */
+/* Preconditioners of the local linear solve (the paper names none).  A
+ * fracture block is a run of consecutive rows of one fracture inside a
+ * 256-row tile, cut at the fracture's units (fim_inspect_pc_blocks); on
+ * top of the b x b block-Jacobi scaling A~ = D^{-1} J, M^{-1} is applied
+ * on the left. */
 enum {
-    FIM_PC_JACOBI = 0,     /* block Jacobi over the b x b cell blocks          */
-    FIM_PC_FRACTURE = 1    /* plus exact inverses of fracture blocks: runs of
-                              up to 128/b consecutive rows of one fracture
-                              inside a 256-row tile, applied on the left      */
+    FIM_PC_JACOBI = 0,            /* block Jacobi over the b x b cell blocks   */
+    FIM_PC_FRACTURE = 1,          /* plus, per fracture block and unknown c,
+                                     the exact inverse of A~ restricted to
+                                     unknown c of the block's cells (the
+                                     unknowns decoupled inside the block;
+                                     b = 1: the block's exact inverse)        */
+    FIM_PC_FRACTURE_COUPLED = 2   /* plus the exact inverse of A~ restricted
+                                     to all unknowns of the block's cells     */
 };
 
 /* Solver options.  fim_default_options fills the paper's settings
@@ -145,8 +153,9 @@ typedef struct fim_options {
     int32_t krylov_maxit;    /* BiCGStab iterations per refinement pass        */
     int32_t max_refine;      /* refinement passes                              */
     int32_t check_every;     /* BiCGStab iterations between host checks        */
-    int32_t precond;         /* FIM_PC_JACOBI or FIM_PC_FRACTURE (default;
-                                Jacobi when the model has no frac_id)          */
+    int32_t precond;         /* FIM_PC_JACOBI, FIM_PC_FRACTURE (default) or
+                                FIM_PC_FRACTURE_COUPLED (both Jacobi when the
+                                model has no frac_id); others: FIM_E_ARG      */
     double  eps_res;         /* FIM_RESID: unconverged when e_i >= eps_res
                                 (default 1e-6)                                 */
     int32_t res_layers;      /* FIM_RESID: neighbour layers added (default 1,

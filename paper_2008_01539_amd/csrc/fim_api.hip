@@ -150,6 +150,7 @@ struct fim_model {
     // fracture-block preconditioner (use_pc false: block Jacobi only)
     bool use_pc = false;
     int pc_cap = 0;                 // rows per block
+    bool pc_dec = false;            // unknowns decoupled inside the blocks
     int* funit = nullptr;           // fracture cells: unit << 8 | units per block
     int pc_grid = KB_MAXB;          // Krylov workgroups with fracture blocks (2 per CU)
     int pc_grid_wide = KB_MAXB;     // the same in the three-per-CU FP32 variant
@@ -374,6 +375,7 @@ static KrylovBufs kbufs(fim_model* m, bool fp32) {
     kb.pcinfo = m->pcinfo;
     kb.pcoff = m->pcoff;
     kb.pcM = m->use_pc ? m->pcM : nullptr;
+    kb.pcdec = m->pc_dec ? 1 : 0;
     return kb;
 }
 
@@ -463,7 +465,8 @@ struct SolveItem {
 struct Group {
     std::vector<int> idx;   // items in this group
     int nblk = 0;
-    bool pc = false;        // some model uses fracture blocks
+    int pc = 0;             // fracture blocks of the models that have them:
+                            // 0 none, 1 coupled, 2 the unknowns decoupled
     bool wide = false;      // FP32 with fracture blocks, more tiles than 2 per CU
 };
 
@@ -475,11 +478,12 @@ static fim_status upload_group(fim_model* lead, SolveTable& t, int g, Group& G,
     // FP32 launches with fracture blocks and more 256-row tiles than two
     // resident workgroups per CU cover use the three-per-CU variant (its
     // grid cap is larger)
-    G.pc = false;
+    G.pc = 0;
     long tiles = 0;
     for (int q : G.idx) {
-        G.pc = G.pc || items[q].m->use_pc;
-        tiles += krylov_grid(items[q].m->nA, KB_MAXB);
+        const fim_model* m = items[q].m;
+        if (m->use_pc) G.pc = m->pc_dec ? 2 : 1;   // one mode per batch (batch_check)
+        tiles += krylov_grid(m->nA, KB_MAXB);
     }
     G.wide = G.pc && g == 0 && tiles > lead->pc_grid;
     for (int q : G.idx) {
@@ -572,7 +576,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
         if (mq->use_pc && K == 1) {
             const int pv = pbeg(lead, PK_PCINV);
             launch_pc_invert(mq->B, it.fp32, mq->pc_inv_grid, lsys(mq), mq->At, mq->pclist,
-                             &mq->dint[6], mq->pcoff, mq->pcM, s);
+                             &mq->dint[6], mq->pcoff, mq->pcM, mq->pc_dec, s);
             pend(lead, pv, mq->nA);
         }
         if (!prepped) launch_fill_f64(mq->x64, (long)mq->nA * mq->B, 0.0, s);
@@ -587,7 +591,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                 fim_model* mq = ms[q];
                 if (mq->use_pc)
                     pcs.push_back(PcSeg{lsys(mq), mq->At, mq->pclist, &mq->dint[6], mq->pcoff,
-                                        mq->pcM});
+                                        mq->pcM, mq->pc_dec ? 1 : 0});
             }
             if (pcs.empty()) continue;
             PcSeg* dpc = t.dpc + (size_t)g * t.cap;
@@ -613,7 +617,11 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
     TRY(read_status(lead, t, G, items, s));
     if (lead->prof.on) {
         lead->cur_nnzb = lead->hint[4];
-        lead->cur_pcn2 = lead->use_pc ? (double)lead->hint[5] * lead->B * lead->B : 0.0;
+        // FP32 entries one application reads: (rows b)^2 per block, or
+        // rows^2 b with the unknowns decoupled
+        lead->cur_pcn2 = lead->use_pc ? (double)lead->hint[5] * lead->B *
+                                            (lead->pc_dec ? 1 : lead->B)
+                                      : 0.0;
     }
     for (int g = 0; g < 2; g++)
         for (size_t pos = 0; pos < G[g].idx.size(); pos++) {
@@ -1122,6 +1130,7 @@ static fim_status make_clone(fim_model* m, fim_model** out) {
     c->max_deg = m->max_deg; c->slot_cap = m->slot_cap;
     c->u = m->u; c->un = m->un; c->Mn = m->Mn; c->st = m->st; c->stn = m->stn;
     c->use_pc = m->use_pc; c->pc_cap = m->pc_cap; c->pc_grid = m->pc_grid;
+    c->pc_dec = m->pc_dec;
     c->funit = m->funit;
     c->pc_grid_wide = m->pc_grid_wide; c->pc_inv_grid = m->pc_inv_grid; c->pc_nfc = m->pc_nfc;
     c->frac_id = m->frac_id; c->ford = m->ford; c->cus = m->cus; c->dev = m->dev;
@@ -1409,6 +1418,12 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
         delete m;
         return FIM_E_ARG;
     }
+    if (m->o.precond != FIM_PC_JACOBI && m->o.precond != FIM_PC_FRACTURE &&
+        m->o.precond != FIM_PC_FRACTURE_COUPLED) {
+        g_create_err = "unknown preconditioner";
+        delete m;
+        return FIM_E_ARG;
+    }
     const int n = d->n_cells;
     m->n = n;
     m->nconn = d->n_conn;
@@ -1592,7 +1607,9 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     }
     std::vector<int> ford;   // fracture-cell ordinal per cell, -1 elsewhere
     std::vector<int> funit;  // fracture cells: unit << 8 | units per block
-    if (d->frac_id && m->o.precond == FIM_PC_FRACTURE) {
+    if (d->frac_id && m->o.precond != FIM_PC_JACOBI) {
+        // (one unknown per cell: the decoupled and coupled blocks coincide)
+        m->pc_dec = m->o.precond == FIM_PC_FRACTURE && m->fk > 1;
         ford.assign(n, -1);
         int nfc = 0;
         for (int i = 0; i < n; i++)
@@ -2212,7 +2229,7 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o) {
         if (loc) b += nfc * 9;
     }
     const int pc = o ? o->precond : FIM_PC_FRACTURE;
-    if (d->frac_id && pc == FIM_PC_FRACTURE) {
+    if (d->frac_id && pc != FIM_PC_JACOBI) {
         size_t nfc = 0;
         for (size_t i = 0; i < n; i++) nfc += d->frac_id[i] >= 0 ? 1 : 0;
         if (nfc) b += n * 20 + nfc * (size_t)pc_cell_stride(B) * 4 + (nfc / 2 + 1) * 8;
@@ -2441,6 +2458,7 @@ static thread_local std::string g_batch_err;
 
 static fim_status batch_check(fim_batch* b, fim_model* const* models, int32_t k, std::string& e) {
     if (!models || k <= 0) { e = "empty batch"; return FIM_E_ARG; }
+    int pc_mode = 0;   // fracture-block mode of the members that have blocks
     for (int q = 0; q < k; q++) {
         if (!models[q]) { e = "null model in batch"; return FIM_E_ARG; }
         for (int r = 0; r < q; r++)
@@ -2448,6 +2466,14 @@ static fim_status batch_check(fim_batch* b, fim_model* const* models, int32_t k,
         if (models[q]->B != models[0]->B || models[q]->o.precision != models[0]->o.precision) {
             e = "batch members need the same block size and Krylov precision";
             return FIM_E_ARG;
+        }
+        if (models[q]->use_pc) {
+            const int mode = models[q]->pc_dec ? 2 : 1;
+            if (pc_mode && mode != pc_mode) {
+                e = "batch members with fracture blocks need the same fracture-block mode";
+                return FIM_E_ARG;
+            }
+            pc_mode = mode;
         }
     }
     (void)b;

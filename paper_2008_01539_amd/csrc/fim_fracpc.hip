@@ -259,7 +259,7 @@ __device__ inline bool gauss_jordan(float* M, int N) {
 template <int B, typename T>
 __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
                              const int* __restrict__ list, const int* __restrict__ pcoff,
-                             float* __restrict__ pcM, int q, float* M) {
+                             float* __restrict__ pcM, int q, float* M, bool dec) {
     constexpr int BB = B * B;
     constexpr int MS = PCI_MS;
     const int lane = threadIdx.x;
@@ -314,7 +314,10 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
                 for (int i = 0; i < B; i++)
 #pragma unroll
                     for (int j = 0; j < B; j++)
-                        M[(rl[u] * B + i) * MS + jl[u] * B + j] = (float)blk[u][i * B + j];
+                        if (!dec)
+                            M[(rl[u] * B + i) * MS + jl[u] * B + j] = (float)blk[u][i * B + j];
+                        else if (i == j)   // unknown i of both cells, component-major
+                            M[(i * size + rl[u]) * MS + i * size + jl[u]] = (float)blk[u][i * B + j];
             }
         }
         wave_sync();
@@ -341,16 +344,22 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
         constexpr int K = pc_group_cols(B), W = B * K;
         typedef float kv __attribute__((ext_vector_type(K)));
         float* out = pcM + pcoff[r0];
-        const int rr = lane / B, ci = lane - rr * B;
+        // lane: unknown rr b + ci of the block (coupled), or unknown ci of
+        // cell rr in component-major order (decoupled: the inverse is block
+        // diagonal, unknown ci's block at rows and columns ci size ..); the
+        // layout's columns: the block's unknowns, or its cells
+        const int rr = dec ? lane % size : lane / B, ci = dec ? lane / size : lane - rr * B;
         const int rowo = rr * W + ci * K, grp = size * W;
+        const int ncol = dec ? size : N, cb = c0 + (dec ? ci * size : 0);
+        const int diag = dec ? rr : lane;   // the row's own column (identity)
         if (lane < N) {
 #pragma unroll 1
-            for (int g = 0; g * K < N; g++) {
+            for (int g = 0; g * K < ncol; g++) {
                 kv v;
 #pragma unroll
                 for (int k = 0; k < K; k++) {
                     const int j = g * K + k;
-                    v[k] = j >= N ? 0.0f : bad ? (j == lane ? 1.0f : 0.0f) : M[lane * MS + c0 + j];
+                    v[k] = j >= ncol ? 0.0f : bad ? (j == diag ? 1.0f : 0.0f) : M[lane * MS + cb + j];
                 }
                 *(kv*)(out + g * grp + rowo) = v;
             }
@@ -365,11 +374,11 @@ __global__ __launch_bounds__(WAVE) void k_pc_invert(LocalSys ls, const T* __rest
                                                     const int* __restrict__ list,
                                                     const int* __restrict__ cnt,
                                                     const int* __restrict__ pcoff,
-                                                    float* __restrict__ pcM) {
+                                                    float* __restrict__ pcM, int dec) {
     __shared__ __align__(16) float M[PC_DOF * PCI_MS];
     const int nblk = *cnt;
     for (int q = blockIdx.x; q < nblk; q += gridDim.x)
-        invert_block<B, T>(ls, At, list, pcoff, pcM, q, M);
+        invert_block<B, T>(ls, At, list, pcoff, pcM, q, M, dec != 0);
 }
 
 // Many systems (a batch): the blocks of all lists in one sequence; pref
@@ -400,16 +409,17 @@ __global__ __launch_bounds__(WAVE) void k_pc_invert_batch(const PcSeg* __restric
             else hi = mid - 1;
         }
         const PcSeg& S = segs[lo];
-        invert_block<B, T>(S.ls, (const T*)S.At, S.list, S.pcoff, S.pcM, q - pref[lo], M);
+        invert_block<B, T>(S.ls, (const T*)S.At, S.list, S.pcoff, S.pcM, q - pref[lo], M,
+                           S.dec != 0);
     }
 }
 
 void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void* At,
                       const int* list, const int* cnt, const int* pcoff, float* pcM,
-                      hipStream_t s) {
+                      bool dec, hipStream_t s) {
     if (grid <= 0) return;
 #define PV(BV, TT) \
-    k_pc_invert<BV, TT><<<grid, WAVE, 0, s>>>(ls, (const TT*)At, list, cnt, pcoff, pcM)
+    k_pc_invert<BV, TT><<<grid, WAVE, 0, s>>>(ls, (const TT*)At, list, cnt, pcoff, pcM, dec ? 1 : 0)
     if (fp32) {
         if (b == 1) PV(1, float); else if (b == 2) PV(2, float); else PV(3, float);
     } else {

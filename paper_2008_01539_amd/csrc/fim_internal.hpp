@@ -182,6 +182,8 @@ struct KrylovBufs {
     const double* dinv; const void* At;
     // fracture-block preconditioner (pcM NULL: block Jacobi only)
     const int* pcinfo; const int* pcoff; const float* pcM;   // FP32 inverses
+    int pcdec;              // unknowns decoupled inside the blocks (FIM_PC_FRACTURE)
+    int pad_;
 };
 // workgroups of a Krylov launch over nA rows: one per 256-row tile, at most
 // cap (the kernels loop over further tiles)
@@ -223,7 +225,9 @@ void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int
 struct SegStatus;
 // wide (FP32 with fracture blocks only): the launch has more workgroups
 // than two per CU; a variant with three resident per CU runs it
-void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSeg* segs,
+// pc: the members' fracture blocks (0 none, 1 coupled, 2 the unknowns
+// decoupled; members without blocks use block Jacobi in any launch)
+void launch_bicg_part(int which, int b, bool fp32, bool solo, int pc, const KSeg* segs,
                       const int* blk_seg, int nblk_total, int it, hipStream_t s,
                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                       SegStatus* rec = nullptr, bool wide = false);
@@ -251,9 +255,11 @@ void launch_pc_blocks(int nA, const int* l2g, const int* frac_id, const int* for
                       int* cnt, hipStream_t s);
 // At: the scaled blocks in the Krylov precision (fp32: float, else double);
 // grid single-wave workgroups share the listed blocks
+// dec: one inverse per unknown over the block's cells (the unknowns
+// decoupled), stored as the block's rows x rows columns of the layout
 void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void* At,
                       const int* list, const int* cnt, const int* pcoff, float* pcM,
-                      hipStream_t s);
+                      bool dec, hipStream_t s);
 // one system of a batched inversion (device table entry)
 struct PcSeg {
     LocalSys ls;
@@ -262,6 +268,7 @@ struct PcSeg {
     const int* cnt;
     const int* pcoff;
     float* pcM;
+    int dec;
 };
 // the blocks of nseg systems (same b and Krylov precision) in one launch of
 // grid single-wave workgroups; pref: nseg + 1 ints of device scratch

@@ -119,11 +119,11 @@ constexpr int kbp_waves() { return (B == 3 && sizeof(T) == 8) ? 2 : 3; }
 // FP32 variant runs three (smaller neighbour chunks, chunk_budget) so that
 // systems of up to 3 x 64 x 4 x CUs rows take one pass of resident
 // workgroups instead of a second, mostly idle one.
-template <int B, typename T, bool PC, bool WIDE>
+template <int B, typename T, int PC, bool WIDE>
 constexpr int kb_waves() {
     return PC ? ((WIDE && sizeof(T) == 4) ? 3 : 2) : kbp_waves<B, T>();
 }
-template <typename T, bool PC, bool WIDE>
+template <typename T, int PC, bool WIDE>
 constexpr int chunk_budget() { return (PC && WIDE && sizeof(T) == 4) ? 48 : CHUNK_BUDGET; }
 
 // Slot geometry of row r: slot k at base + 64 k; width slots are in use
@@ -248,21 +248,23 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // columns per round with all loads of a round in flight together.  For
 // b <= 2 the first round does not wait for the product: pc_first issues it
 // before the row's product, pc_rows consumes it.
-template <int B, typename T>
+template <int B, typename T, bool DEC = false>
 struct PcShape {
     static constexpr int K = pc_group_cols(B), W = B * K, NV4 = W / 4;
-    static constexpr int QG = (B == 3 && sizeof(T) == 8) ? 2 : 16 / K;   // groups per round
+    // groups per round (decoupled blocks have b times fewer columns: two
+    // groups per round keep the registers of the fused kernels)
+    static constexpr int QG = DEC ? 2 : (B == 3 && sizeof(T) == 8) ? 2 : 16 / K;
     static constexpr bool PRE = B <= 2;                                   // first round early
 };
 
-template <int B, typename T>
-using PcRound = f4v[PcShape<B, T>::QG][PcShape<B, T>::NV4];
+template <int B, typename T, bool DEC = false>
+using PcRound = f4v[PcShape<B, T, DEC>::QG][PcShape<B, T, DEC>::NV4];
 
 // the inverse entries of round g0 of this thread's block row
-template <int B, typename T>
+template <int B, typename T, bool DEC>
 __device__ inline void pc_load(const float* pcM, unsigned row0, unsigned grpb, int G, int g0,
-                               PcRound<B, T>& mv) {
-    using Sh = PcShape<B, T>;
+                               PcRound<B, T, DEC>& mv) {
+    using Sh = PcShape<B, T, DEC>;
 #pragma unroll
     for (int q = 0; q < Sh::QG; q++) {
         const int gq = min(g0 + q, G - 1);
@@ -272,25 +274,28 @@ __device__ inline void pc_load(const float* pcM, unsigned row0, unsigned grpb, i
 }
 
 // first round of the row with layout words (info, off), if it is in a
-// multi-row block (called with the row's tile pass current)
-template <int B, typename T>
-__device__ inline void pc_first(const KrylovBufs& kb, int info, int off, PcRound<B, T>& pm) {
-    using Sh = PcShape<B, T>;
+// multi-row block (called with the row's tile pass current).  DEC: the
+// block's unknowns decoupled (FIM_PC_FRACTURE): the layout's columns are
+// the block's cells, and output c of a row takes unknown c of each cell.
+template <int B, typename T, bool DEC>
+__device__ inline void pc_first(const KrylovBufs& kb, int info, int off,
+                                PcRound<B, T, DEC>& pm) {
+    using Sh = PcShape<B, T, DEC>;
     if constexpr (Sh::PRE) {
         const int size = info & 0xffff;
         if (size > 1) {
-            const int bs = info >> 16, N = size * B;
+            const int bs = info >> 16, ncol = DEC ? size : size * B;
             const unsigned row0 = (unsigned)(off + ((int)threadIdx.x - bs) * Sh::W) * 4u;
-            pc_load<B, T>(kb.pcM, row0, (unsigned)(size * Sh::W) * 4u, (N + Sh::K - 1) / Sh::K, 0,
-                          pm);
+            pc_load<B, T, DEC>(kb.pcM, row0, (unsigned)(size * Sh::W) * 4u, (ncol + Sh::K - 1) / Sh::K,
+                          0, pm);
         }
     }
 }
 
-template <int B, typename T>
+template <int B, typename T, bool DEC>
 __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off,
-                               double (&y)[B], const PcRound<B, T>& pm) {
-    using Sh = PcShape<B, T>;
+                               double (&y)[B], const PcRound<B, T, DEC>& pm) {
+    using Sh = PcShape<B, T, DEC>;
     constexpr int K = Sh::K, W = Sh::W, QG = Sh::QG;
     __shared__ T yb[KB_NT * B];
     const int t = threadIdx.x;
@@ -302,7 +307,7 @@ __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off
     }
     __syncthreads();
     if (blk) {
-        const int size = info & 0xffff, bs = info >> 16, N = size * B;
+        const int size = info & 0xffff, bs = info >> 16, N = DEC ? size : size * B;
         const int G = (N + K - 1) / K;
         const unsigned row0 = (unsigned)(off + (t - bs) * W) * 4u;
         const unsigned grpb = (unsigned)(size * W) * 4u;
@@ -310,24 +315,48 @@ __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off
         double acc[B];
 #pragma unroll
         for (int c = 0; c < B; c++) acc[c] = 0.0;
-        auto round = [&](int g0, const PcRound<B, T>& mv) {
-            T ys[QG][K];
+        auto round = [&](int g0, const PcRound<B, T, DEC>& mv) {
+            if constexpr (!DEC) {
+                T ys[QG][K];
 #pragma unroll
-            for (int q = 0; q < QG; q++) {
-                const int gq = min(g0 + q, G - 1);
+                for (int q = 0; q < QG; q++) {
+                    const int gq = min(g0 + q, G - 1);
 #pragma unroll
-                for (int k = 0; k < K; k++) ys[q][k] = yv[min(gq * K + k, N - 1)];
-            }
+                    for (int k = 0; k < K; k++) ys[q][k] = yv[min(gq * K + k, N - 1)];
+                }
 #pragma unroll
-            for (int q = 0; q < QG; q++) {
+                for (int q = 0; q < QG; q++) {
 #pragma unroll
-                for (int k = 0; k < K; k++) {
-                    const int j = (g0 + q) * K + k;   // past N: padding or a clamped repeat
-                    const double w = j < N ? (double)ys[q][k] : 0.0;
+                    for (int k = 0; k < K; k++) {
+                        const int j = (g0 + q) * K + k;   // past N: padding or a clamped repeat
+                        const double w = j < N ? (double)ys[q][k] : 0.0;
 #pragma unroll
-                    for (int c = 0; c < B; c++) {
-                        const int e = c * K + k;
-                        acc[c] += (double)mv[q][e / 4][e % 4] * w;
+                        for (int c = 0; c < B; c++) {
+                            const int e = c * K + k;
+                            acc[c] += (double)mv[q][e / 4][e % 4] * w;
+                        }
+                    }
+                }
+            } else {
+                // column j = cell j of the block: output c takes its unknown c
+#pragma unroll
+                for (int q = 0; q < QG; q++) {
+                    const int gq = min(g0 + q, G - 1);
+                    T ys[K][B];
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        const int j = min(gq * K + k, N - 1);
+#pragma unroll
+                        for (int c = 0; c < B; c++) ys[k][c] = yv[j * B + c];
+                    }
+#pragma unroll
+                    for (int k = 0; k < K; k++) {
+                        const bool in = (g0 + q) * K + k < N;
+#pragma unroll
+                        for (int c = 0; c < B; c++) {
+                            const int e = c * K + k;
+                            acc[c] += (double)mv[q][e / 4][e % 4] * (in ? (double)ys[k][c] : 0.0);
+                        }
                     }
                 }
             }
@@ -339,8 +368,8 @@ __device__ inline void pc_rows(const KrylovBufs& kb, bool act, int info, int off
         }
 #pragma unroll 1
         for (; g0 < G; g0 += QG) {
-            PcRound<B, T> mv;
-            pc_load<B, T>(kb.pcM, row0, grpb, G, g0, mv);
+            PcRound<B, T, DEC> mv;
+            pc_load<B, T, DEC>(kb.pcM, row0, grpb, G, g0, mv);
             round(g0, mv);
         }
 #pragma unroll
@@ -439,9 +468,15 @@ __global__ __launch_bounds__(KB_NT) void k_ir_residual(const KSeg* __restrict__ 
                 poff = kb.pcoff[r];
             }
         }
-        PcRound<B, double> pm;
-        if (pc && act) pc_first<B, double>(kb, pinfo, poff, pm);
-        if (pc) pc_rows<B, double>(kb, act, pinfo, poff, bt, pm);
+        if (pc && kb.pcdec) {
+            PcRound<B, double, true> pm;
+            if (act) pc_first<B, double, true>(kb, pinfo, poff, pm);
+            pc_rows<B, double, true>(kb, act, pinfo, poff, bt, pm);
+        } else if (pc) {
+            PcRound<B, double, false> pm;
+            if (act) pc_first<B, double, false>(kb, pinfo, poff, pm);
+            pc_rows<B, double, false>(kb, act, pinfo, poff, bt, pm);
+        }
         if (act) {
 #pragma unroll
             for (int c = 0; c < B; c++) {
@@ -492,7 +527,8 @@ __device__ inline void put_status(SegStatus* o, double rr, int done, int iters, 
 // update) at the iteration cap or when omega = 0.  The own-row operands
 // and the first chunk of neighbour slots are fetched before the previous
 // kernel's partial sums are reduced, so those loads overlap the reduction.
-template <int B, typename T, bool FIRST, bool SOLO, bool PC, bool WIDE>
+// PC: fracture blocks (0 none, 1 coupled, 2 the unknowns decoupled)
+template <int B, typename T, bool FIRST, bool SOLO, int PC, bool WIDE>
 __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_p(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
                                                                       int it) {
@@ -590,7 +626,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_p(
         double vi[B];
 #pragma unroll
         for (int c = 0; c < B; c++) vi[c] = 0.0;
-        PcRound<B, T> pm;   // first round of the row's inverse entries
+        PcRound<B, T, PC == 2> pm;   // first round of the row's inverse entries
         if (act) {
             T ri[B];
             if constexpr (FIRST) {
@@ -609,7 +645,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_p(
                 stv<B, T>(V.r, ro, ri);
             }
             if (!stop) {
-                if (pc) pc_first<B, T>(S.kb, pinfo, poff, pm);
+                if (pc) pc_first<B, T, PC == 2>(S.kb, pinfo, poff, pm);
                 double pi[B];
                 fx(own, pi);
 #pragma unroll
@@ -628,7 +664,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_p(
             if (act && r + stride < nA) fetch(r + stride);
             continue;
         }
-        if (pc) pc_rows<B, T>(S.kb, act, pinfo, poff, vi, pm);   // v = M^{-1} A~ p
+        if (pc) pc_rows<B, T, PC == 2>(S.kb, act, pinfo, poff, vi, pm);   // v = M^{-1} A~ p
         if (act) {
             T vT[B];
 #pragma unroll
@@ -655,7 +691,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_p(
 // |r_i|^2 <= tol2 (x_i is the answer) or on a breakdown of sigma; else
 // alpha = rho_i / sigma, s = r_i - alpha v_i, t = A~ s (s rebuilt at the
 // neighbours).  Partial sums: (t,s), (t,t), (rh,s), (rh,t).
-template <int B, typename T, bool SOLO, bool PC, bool WIDE>
+template <int B, typename T, bool SOLO, int PC, bool WIDE>
 __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_s(const KSeg* __restrict__ segs,
                                                                       const int* __restrict__ blk_seg,
                                                                       int it,
@@ -744,9 +780,9 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_s(
             ti[c] = 0.0;
             sT[c] = (T)0;
         }
-        PcRound<B, T> pm;   // first round of the row's inverse entries
+        PcRound<B, T, PC == 2> pm;   // first round of the row's inverse entries
         if (act) {
-            if (pc) pc_first<B, T>(S.kb, pinfo, poff, pm);
+            if (pc) pc_first<B, T, PC == 2>(S.kb, pinfo, poff, pm);
             double si[B];
             fx(own, si);
 #pragma unroll
@@ -759,7 +795,7 @@ __global__ __launch_bounds__(KB_NT, (kb_waves<B, T, PC, WIDE>())) void k_bicg_s(
             }
             stv<B, T>(V.s, ro, sT);
         }
-        if (pc) pc_rows<B, T>(S.kb, act, pinfo, poff, ti, pm);   // t = M^{-1} A~ s
+        if (pc) pc_rows<B, T, PC == 2>(S.kb, act, pinfo, poff, ti, pm);   // t = M^{-1} A~ s
         if (act) {
             T tT[B];
 #pragma unroll
@@ -813,7 +849,7 @@ void launch_copy_f64(double* dst, const double* src, long n, hipStream_t s) {
 
 // ev0/ev1 (optional): events stamped by the dispatch itself
 // (hipExtLaunchKernelGGL), i.e. the kernel's own start and end
-template <int B, typename T, bool SOLO, bool PC, bool WIDE>
+template <int B, typename T, bool SOLO, int PC, bool WIDE>
 static void part_impl_w(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
                         hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, SegStatus* rec) {
     const dim3 nb(nblk_total), nt(KB_NT);
@@ -832,7 +868,7 @@ static void part_impl_w(int which, const KSeg* segs, const int* blk_seg, int nbl
 
 // wide: the launch has more tiles than two resident workgroups per CU
 // cover (FP32 with fracture blocks: the three-wave variant)
-template <int B, typename T, bool SOLO, bool PC>
+template <int B, typename T, bool SOLO, int PC>
 static void part_impl(int which, const KSeg* segs, const int* blk_seg, int nblk_total, int it,
                       hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, SegStatus* rec, bool wide) {
     if (PC && wide && sizeof(T) == 4)
@@ -897,29 +933,27 @@ void launch_ir_residual(int b, bool fp32, bool solo, const KSeg* segs, const int
 #undef IR
 }
 
-void launch_bicg_part(int which, int b, bool fp32, bool solo, bool pc, const KSeg* segs,
+void launch_bicg_part(int which, int b, bool fp32, bool solo, int pc, const KSeg* segs,
                       const int* blk_seg, int nblk_total, int it, hipStream_t s, hipEvent_t ev0,
                       hipEvent_t ev1, SegStatus* rec, bool wide) {
     if (nblk_total <= 0) return;
-#define PI(BV, TT)                                                                             \
-    do {                                                                                       \
-        if (solo) {                                                                            \
-            if (pc)                                                                            \
-                part_impl<BV, TT, true, true>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1, rec, wide); \
-            else                                                                               \
-                part_impl<BV, TT, true, false>(which, segs, blk_seg, nblk_total, it, s, ev0,   \
-                                               ev1, rec, wide);                                     \
-        } else {                                                                               \
-            if (pc)                                                                            \
-                part_impl<BV, TT, false, true>(which, segs, blk_seg, nblk_total, it, s, ev0,   \
-                                               ev1, rec, wide);                                     \
-            else                                                                               \
-                part_impl<BV, TT, false, false>(which, segs, blk_seg, nblk_total, it, s, ev0,  \
-                                                ev1, rec, wide);                                    \
-        }                                                                                      \
+#define PJ(BV, TT, SO, PM) \
+    part_impl<BV, TT, SO, PM>(which, segs, blk_seg, nblk_total, it, s, ev0, ev1, rec, wide)
+#define PI(BV, TT)                                                                        \
+    do {                                                                                  \
+        if (solo) {                                                                       \
+            if (pc == 2) PJ(BV, TT, true, 2);                                             \
+            else if (pc) PJ(BV, TT, true, 1);                                             \
+            else PJ(BV, TT, true, 0);                                                     \
+        } else {                                                                          \
+            if (pc == 2) PJ(BV, TT, false, 2);                                            \
+            else if (pc) PJ(BV, TT, false, 1);                                            \
+            else PJ(BV, TT, false, 0);                                                    \
+        }                                                                                 \
     } while (0)
     KDISPATCH(PI)
 #undef PI
+#undef PJ
 }
 
 void launch_ir_accumulate(int b, bool fp32, bool solo, const KSeg* segs, const int* blk_seg,

@@ -20,7 +20,7 @@ FIM_E_ARG, FIM_E_NOMEM, FIM_E_HIP, FIM_E_STATE, FIM_E_NONFINITE = -1, -2, -3, -4
 FULL, LOCAL, DD, RESID, DD_ADD = 0, 1, 2, 3, 4
 FP64, MIXED = 0, 1
 HOST, DEVICE = 0, 1
-PC_JACOBI, PC_FRACTURE = 0, 1
+PC_JACOBI, PC_FRACTURE, PC_FRACTURE_COUPLED = 0, 1, 2
 PSI = 6894.757293168
 
 
