@@ -263,13 +263,16 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
     constexpr int BB = B * B;
     constexpr int MS = PCI_MS;
     const int lane = threadIdx.x;
-    {
-        const int r0 = list[2 * q], size = list[2 * q + 1];
-        const int N = size * B;
-
-        // slot widths of the (at most two) slices the block's rows are in
-        const int sl0 = r0 / SLICE, sl1 = (r0 + size - 1) / SLICE;
-        const int w0 = ls.swidth[sl0], w1 = ls.swidth[sl1];
+    const int r0 = list[2 * q], size = list[2 * q + 1];
+    // slot widths of the (at most two) slices the block's rows are in
+    const int sl0 = r0 / SLICE, sl1 = (r0 + size - 1) / SLICE;
+    const int w0 = ls.swidth[sl0], w1 = ls.swidth[sl1];
+    // decoupled: one inversion per unknown comp, of A~ restricted to that
+    // unknown of the block's cells (rows x rows); coupled: one of all
+    // unknowns (rows b x rows b)
+#pragma unroll 1
+    for (int comp = 0; comp < (dec ? B : 1); comp++) {
+        const int N = dec ? size : size * B;
         // identity: the diagonal blocks of A~ and the padding to 64 x 64
         {
             f4v* row = (f4v*)&M[lane * MS];
@@ -305,7 +308,8 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
             for (int u = 0; u < FU; u++) {
                 const bool in = jl[u] >= 0 && jl[u] < size && jl[u] != rl[u];
 #pragma unroll
-                for (int e = 0; e < BB; e++) blk[u][e] = in ? At[ps[u] * BB + e] : (T)0;
+                for (int e = 0; e < BB; e++)   // decoupled: entry (comp, comp) only
+                    blk[u][e] = in && (!dec || e == comp * (B + 1)) ? At[ps[u] * BB + e] : (T)0;
             }
 #pragma unroll
             for (int u = 0; u < FU; u++) {
@@ -316,8 +320,8 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
                     for (int j = 0; j < B; j++)
                         if (!dec)
                             M[(rl[u] * B + i) * MS + jl[u] * B + j] = (float)blk[u][i * B + j];
-                        else if (i == j)   // unknown i of both cells, component-major
-                            M[(i * size + rl[u]) * MS + i * size + jl[u]] = (float)blk[u][i * B + j];
+                        else if (i == comp && j == comp)   // unknown comp of both cells
+                            M[rl[u] * MS + jl[u]] = (float)blk[u][i * B + j];
             }
         }
         wave_sync();
@@ -344,22 +348,19 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
         constexpr int K = pc_group_cols(B), W = B * K;
         typedef float kv __attribute__((ext_vector_type(K)));
         float* out = pcM + pcoff[r0];
-        // lane: unknown rr b + ci of the block (coupled), or unknown ci of
-        // cell rr in component-major order (decoupled: the inverse is block
-        // diagonal, unknown ci's block at rows and columns ci size ..); the
-        // layout's columns: the block's unknowns, or its cells
-        const int rr = dec ? lane % size : lane / B, ci = dec ? lane / size : lane - rr * B;
+        // lane: unknown rr b + ci of the block (coupled; the layout's
+        // columns are the block's unknowns), or cell rr, unknown comp
+        // (decoupled; the layout's columns are the block's cells)
+        const int rr = dec ? lane : lane / B, ci = dec ? comp : lane - rr * B;
         const int rowo = rr * W + ci * K, grp = size * W;
-        const int ncol = dec ? size : N, cb = c0 + (dec ? ci * size : 0);
-        const int diag = dec ? rr : lane;   // the row's own column (identity)
         if (lane < N) {
 #pragma unroll 1
-            for (int g = 0; g * K < ncol; g++) {
+            for (int g = 0; g * K < N; g++) {
                 kv v;
 #pragma unroll
                 for (int k = 0; k < K; k++) {
                     const int j = g * K + k;
-                    v[k] = j >= ncol ? 0.0f : bad ? (j == diag ? 1.0f : 0.0f) : M[lane * MS + cb + j];
+                    v[k] = j >= N ? 0.0f : bad ? (j == lane ? 1.0f : 0.0f) : M[lane * MS + c0 + j];
                 }
                 *(kv*)(out + g * grp + rowo) = v;
             }
