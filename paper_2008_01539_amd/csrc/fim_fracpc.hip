@@ -252,121 +252,188 @@ __device__ inline bool gauss_jordan(float* M, int N) {
     return bad;
 }
 
+// Gauss-Jordan elimination of G independent blocks of n rows at once (the
+// decoupled blocks: one per unknown), block g in lanes g n .. g n + n - 1
+// (n <= C, G n <= 64): the steps of gauss_jordan, with each lane taking
+// the pivot row from its own block's pivot lane (a lane permute instead of
+// a lane read, so one pass eliminates all G blocks).  Lanes from G n on
+// hold no block (they pivot on themselves; nothing reads them).  Returns,
+// per lane, whether a pivot of the lane's block was below 1e-20 in
+// magnitude or not finite.
+template <int C>
+__device__ inline bool gauss_jordan_groups(float* M, int n, int G) {
+    constexpr int MS = PCI_MS;
+    const int lane = threadIdx.x;
+    const int grp = lane / n, r = lane - grp * n;
+    const bool live = grp < G;
+    float a[C];
+    {
+        const f4v* row = (const f4v*)&M[lane * MS];
+#pragma unroll
+        for (int c = 0; c < C / 4; c++) {
+            const f4v v = row[c];
+            a[4 * c] = v[0];
+            a[4 * c + 1] = v[1];
+            a[4 * c + 2] = v[2];
+            a[4 * c + 3] = v[3];
+        }
+    }
+    wave_sync();
+    bool bad = false;
+    float myip = 1.0f;
+    const int base = (live ? grp * n : lane) * 4;   // byte address of lane grp n
+    for (int step = 0; step < n; step++) {
+        const int src = base + (live ? step * 4 : 0);
+        float pr[C];
+#pragma unroll
+        for (int c = 0; c < C; c++)
+            pr[c] = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(a[c])));
+        const float p = pr[0];
+        bad = bad || !(fabsf(p) > 1e-20f) || !isfinite(p);
+        const float ip = 1.0f / p;
+        const bool me = !live || r == step;
+        if (me) myip = ip;
+        const float f = me ? 0.0f : a[0] * ip;
+#pragma unroll
+        for (int c = 1; c < C; c++) a[c - 1] = fmaf(-f, pr[c], a[c]);
+        a[C - 1] = me ? 1.0f : -f;
+    }
+#pragma unroll
+    for (int c = 0; c < C; c++) a[c] *= myip;
+    {
+        f4v* row = (f4v*)&M[lane * MS];
+#pragma unroll
+        for (int c = 0; c < C / 4; c++)
+            row[c] = f4v{a[4 * c], a[4 * c + 1], a[4 * c + 2], a[4 * c + 3]};
+    }
+    wave_sync();
+    return live && bad;
+}
+
+// register columns of a decoupled block (at most pc_cells(b) cells)
+constexpr int PCI_DEC_C = 24;
+static_assert(pc_cells(2) <= PCI_DEC_C && pc_cells(3) <= PCI_DEC_C,
+              "decoupled blocks exceed their register columns");
+
 // Block q of one system's list, by one wave; M: PC_DOF x PCI_MS floats of
-// LDS.  Loops stay rolled where they run once per block: each wave runs
-// this code about once per launch, so its size (instruction fetch) costs
-// more than loop overhead.
+// LDS.  Coupled: one inversion of A~ over all the block's unknowns (rows
+// b x rows b, unknown-interleaved).  Decoupled (b > 1): A~ restricted to
+// each unknown over the block's cells, the b blocks side by side in the
+// lanes (unknown c's rows at lanes c rows ..) and eliminated together.
+// Loops stay rolled where they run once per block: each wave runs this
+// code about once per launch, so its size (instruction fetch) costs more
+// than loop overhead.
 template <int B, typename T>
 __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
                              const int* __restrict__ list, const int* __restrict__ pcoff,
-                             float* __restrict__ pcM, int q, float* M, bool dec) {
+                             float* __restrict__ pcM, int q, float* M, bool dec_) {
     constexpr int BB = B * B;
     constexpr int MS = PCI_MS;
+    const bool dec = B > 1 && dec_;
     const int lane = threadIdx.x;
     const int r0 = list[2 * q], size = list[2 * q + 1];
     // slot widths of the (at most two) slices the block's rows are in
     const int sl0 = r0 / SLICE, sl1 = (r0 + size - 1) / SLICE;
     const int w0 = ls.swidth[sl0], w1 = ls.swidth[sl1];
-    // decoupled: one inversion per unknown comp, of A~ restricted to that
-    // unknown of the block's cells (rows x rows); coupled: one of all
-    // unknowns (rows b x rows b)
+    const int N = dec ? size : size * B;   // rows of each inversion
+    // the register width: the fewest of 32, 48 or 64 columns that hold
+    // the block (columns C - N .. C - 1 end up holding the inverse)
+    const int C = dec ? PCI_DEC_C : N <= 32 ? 32 : N <= 48 ? 48 : PC_DOF;
+    // identity: the diagonal blocks of A~ and the padding
+    {
+        f4v* row = (f4v*)&M[lane * MS];
 #pragma unroll 1
-    for (int comp = 0; comp < (dec ? B : 1); comp++) {
-        const int N = dec ? size : size * B;
-        // identity: the diagonal blocks of A~ and the padding to 64 x 64
-        {
-            f4v* row = (f4v*)&M[lane * MS];
-#pragma unroll 1
-            for (int c = 0; c < PC_DOF / 4; c++) {
-                f4v z = {0.0f, 0.0f, 0.0f, 0.0f};
-                if (c == lane / 4) z[lane % 4] = 1.0f;
-                row[c] = z;
-            }
+        for (int c = 0; c < C / 4; c++) {
+            f4v z = {0.0f, 0.0f, 0.0f, 0.0f};
+            const int d = dec ? lane % size : lane;   // the row's own column
+            if (c == d / 4) z[d % 4] = 1.0f;
+            row[c] = z;
         }
-        wave_sync();
-        // off-diagonal blocks inside the block, from the scaled blocks
-        // k_precond wrote (At, Krylov precision): the (slot, row) pairs
-        // of the block are spread over the lanes, FU per lane at a time,
-        // the column loads first, then the blocks that couple two rows
-        constexpr int FU = 4;
-        const int items = size * (max(w0, w1) - 1);
-#pragma unroll 1
-        for (int i0 = 0; i0 < items; i0 += WAVE * FU) {
-            int jl[FU], rl[FU];
-            long ps[FU];
-#pragma unroll
-            for (int u = 0; u < FU; u++) {
-                const int i = i0 + u * WAVE + lane;
-                const int k = 1 + i / size, rr = i - (k - 1) * size, r = r0 + rr;
-                const bool ok = i < items && k < ((r / SLICE == sl0) ? w0 : w1);
-                rl[u] = rr;
-                ps[u] = ok ? slot_of(ls, r, k) : 0;
-                jl[u] = ok ? ls.col[ps[u]] - r0 : -1;
-            }
-            T blk[FU][BB];
-#pragma unroll
-            for (int u = 0; u < FU; u++) {
-                const bool in = jl[u] >= 0 && jl[u] < size && jl[u] != rl[u];
-#pragma unroll
-                for (int e = 0; e < BB; e++)   // decoupled: entry (comp, comp) only
-                    blk[u][e] = in && (!dec || e == comp * (B + 1)) ? At[ps[u] * BB + e] : (T)0;
-            }
-#pragma unroll
-            for (int u = 0; u < FU; u++) {
-                if (!(jl[u] >= 0 && jl[u] < size && jl[u] != rl[u])) continue;
-#pragma unroll
-                for (int i = 0; i < B; i++)
-#pragma unroll
-                    for (int j = 0; j < B; j++)
-                        if (!dec)
-                            M[(rl[u] * B + i) * MS + jl[u] * B + j] = (float)blk[u][i * B + j];
-                        else if (i == comp && j == comp)   // unknown comp of both cells
-                            M[rl[u] * MS + jl[u]] = (float)blk[u][i * B + j];
-            }
-        }
-        wave_sync();
-        // the register width: the fewest of 32, 48 or 64 columns that hold
-        // the block (columns C - N .. C - 1 end up holding the inverse)
-        int C = PC_DOF;
-        bool bad;
-        if (N <= 32) {
-            bad = gauss_jordan<32>(M, N);
-            C = 32;
-        } else if (N <= 48) {
-            bad = gauss_jordan<48>(M, N);
-            C = 48;
-        } else {
-            bad = gauss_jordan<PC_DOF>(M, N);
-        }
-        const int c0 = C - N;
-        bool big = false;
-        if (lane < N) {
-#pragma unroll 1
-            for (int j = 0; j < N; j++) big = big || !(fabsf(M[lane * MS + c0 + j]) <= 1e8f);
-        }
-        bad = bad || __any(big);
-        constexpr int K = pc_group_cols(B), W = B * K;
-        typedef float kv __attribute__((ext_vector_type(K)));
-        float* out = pcM + pcoff[r0];
-        // lane: unknown rr b + ci of the block (coupled; the layout's
-        // columns are the block's unknowns), or cell rr, unknown comp
-        // (decoupled; the layout's columns are the block's cells)
-        const int rr = dec ? lane : lane / B, ci = dec ? comp : lane - rr * B;
-        const int rowo = rr * W + ci * K, grp = size * W;
-        if (lane < N) {
-#pragma unroll 1
-            for (int g = 0; g * K < N; g++) {
-                kv v;
-#pragma unroll
-                for (int k = 0; k < K; k++) {
-                    const int j = g * K + k;
-                    v[k] = j >= N ? 0.0f : bad ? (j == lane ? 1.0f : 0.0f) : M[lane * MS + c0 + j];
-                }
-                *(kv*)(out + g * grp + rowo) = v;
-            }
-        }
-        wave_sync();
     }
+    wave_sync();
+    // off-diagonal blocks inside the block, from the scaled blocks
+    // k_precond wrote (At, Krylov precision): the (slot, row) pairs of the
+    // block are spread over the lanes, FU per lane at a time, the column
+    // loads first, then the blocks that couple two rows
+    constexpr int FU = 4;
+    const int items = size * (max(w0, w1) - 1);
+#pragma unroll 1
+    for (int i0 = 0; i0 < items; i0 += WAVE * FU) {
+        int jl[FU], rl[FU];
+        long ps[FU];
+#pragma unroll
+        for (int u = 0; u < FU; u++) {
+            const int i = i0 + u * WAVE + lane;
+            const int k = 1 + i / size, rr = i - (k - 1) * size, r = r0 + rr;
+            const bool ok = i < items && k < ((r / SLICE == sl0) ? w0 : w1);
+            rl[u] = rr;
+            ps[u] = ok ? slot_of(ls, r, k) : 0;
+            jl[u] = ok ? ls.col[ps[u]] - r0 : -1;
+        }
+        T blk[FU][BB];
+#pragma unroll
+        for (int u = 0; u < FU; u++) {
+            const bool in = jl[u] >= 0 && jl[u] < size && jl[u] != rl[u];
+#pragma unroll
+            for (int e = 0; e < BB; e++)   // decoupled: the diagonal entries only
+                blk[u][e] = in && (!dec || e % (B + 1) == 0) ? At[ps[u] * BB + e] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < FU; u++) {
+            if (!(jl[u] >= 0 && jl[u] < size && jl[u] != rl[u])) continue;
+#pragma unroll
+            for (int i = 0; i < B; i++)
+#pragma unroll
+                for (int j = 0; j < B; j++)
+                    if (!dec)
+                        M[(rl[u] * B + i) * MS + jl[u] * B + j] = (float)blk[u][i * B + j];
+                    else if (i == j)   // unknown i of both cells: block i
+                        M[(i * size + rl[u]) * MS + jl[u]] = (float)blk[u][i * B + j];
+        }
+    }
+    wave_sync();
+    bool bad;
+    if (dec)
+        bad = gauss_jordan_groups<PCI_DEC_C>(M, size, B);
+    else if (N <= 32)
+        bad = gauss_jordan<32>(M, N);
+    else if (N <= 48)
+        bad = gauss_jordan<48>(M, N);
+    else
+        bad = gauss_jordan<PC_DOF>(M, N);
+    const int c0 = C - N, nrow = dec ? B * size : N;
+    if (lane < nrow) {
+#pragma unroll 1
+        for (int j = 0; j < N; j++) bad = bad || !(fabsf(M[lane * MS + c0 + j]) <= 1e8f);
+    }
+    // a failed inversion leaves the identity: the whole block (coupled) or
+    // the unknown's block (decoupled)
+    const unsigned long long bm = __ballot(bad);
+    const int gi = dec ? lane / size : 0, gn = dec ? size : N;
+    const unsigned long long gm = gn >= 64 ? ~0ull : ((1ull << gn) - 1) << (gi * gn);
+    bad = (bm & gm) != 0;
+    constexpr int K = pc_group_cols(B), W = B * K;
+    typedef float kv __attribute__((ext_vector_type(K)));
+    float* out = pcM + pcoff[r0];
+    // lane: unknown rr b + ci of the block (coupled; the layout's columns
+    // are the block's unknowns), or cell rr, unknown ci (decoupled; the
+    // layout's columns are the block's cells)
+    const int rr = dec ? lane - gi * size : lane / B, ci = dec ? gi : lane - rr * B;
+    const int rowo = rr * W + ci * K, grp = size * W;
+    const int diag = dec ? rr : lane;   // the row's own column (identity)
+    if (lane < nrow) {
+#pragma unroll 1
+        for (int g = 0; g * K < N; g++) {
+            kv v;
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int j = g * K + k;
+                v[k] = j >= N ? 0.0f : bad ? (j == diag ? 1.0f : 0.0f) : M[lane * MS + c0 + j];
+            }
+            *(kv*)(out + g * grp + rowo) = v;
+        }
+    }
+    wave_sync();
 }
 
 // One system: workgroup w takes blocks w, w + grid, ... of its list.
