@@ -213,6 +213,28 @@ fim_status fim_set_state(fim_model* m, const double* u, const int8_t* status, in
 /* Copies the current state (mid-step: the current Newton iterate). */
 fim_status fim_get_state(fim_model* m, double* u_out, int8_t* status_out, int mem);
 
+/* Checkpoints between timesteps.  A timestep maps u^n to u^{n+1}
+ * (Section 4.1), but Algorithm 1 (Section 4.3) and Algorithm 2 (Section
+ * 4.4) seed a step's first active set from the previous step's support
+ * (the cells whose update reached the cutoff), so a run resumed from u and
+ * the phase status alone starts its next step from the first-step seed set
+ * instead.  A checkpoint carries both: a host byte blob of
+ * fim_checkpoint_bytes(m) bytes (a header with the model's n and b, the
+ * state as b planes of n doubles, the phase status, the support set).
+ * After fim_set_checkpoint the model's next timesteps run bit for bit as
+ * they ran after fim_get_checkpoint in the run that wrote it (same model
+ * description and options).
+ * fim_checkpoint_bytes: -1 for a NULL model.
+ * fim_get_checkpoint: buf is host memory the caller owns, of at least
+ * that size (FIM_E_ARG otherwise); FIM_E_STATE inside a timestep.
+ * fim_set_checkpoint: ends any timestep in progress; FIM_E_ARG on a blob
+ * that is shorter than the model's size, not a checkpoint of this library
+ * or of another n or b; FIM_E_NONFINITE on a non-finite state (the
+ * previous state is kept in both cases). */
+int64_t    fim_checkpoint_bytes(const fim_model* m);
+fim_status fim_get_checkpoint(fim_model* m, void* buf, int64_t cap);
+fim_status fim_set_checkpoint(fim_model* m, const void* buf, int64_t len);
+
 /* One Newton iteration (Algorithm 1 in FIM_LOCAL, the standard iteration
  * in FIM_FULL, one subdomain solve of Algorithm 2 in FIM_DD, one
  * residual-localized iteration in FIM_RESID).  The first
@@ -272,7 +294,8 @@ int64_t fim_estimate_bytes(const fim_model_desc* d, const fim_options* o);
 
 /* A batch advances several independent models together: each call runs
  * one Newton iteration (Algorithm 1, full Newton or the residual-based
- * mode) of every member with one launch per kernel for all members (the
+ * mode; Algorithm 2 members: see below) of every member with one launch
+ * per kernel for all members (the
  * timestep starts, assembly, the local linear systems' Krylov solves, the
  * updates, active sets and structure; per-member reductions and
  * convergence) and one synchronisation for the members' status words, plus
@@ -291,7 +314,10 @@ fim_status fim_batch_create(fim_model* const* models, int32_t k, void* hip_strea
                             fim_batch** out);
 fim_status fim_batch_set(fim_batch* b, fim_model* const* models, int32_t k);
 
-/* dts[k], modes[k] (FIM_FULL, FIM_LOCAL or FIM_RESID) per member; stats (nullable)
+/* dts[k], modes[k] (FIM_FULL, FIM_LOCAL, FIM_RESID, or FIM_DD /
+ * FIM_DD_ADD) per member; Algorithm 2 members run one inner iteration
+ * each with their own launches on the batch stream (their subdomain
+ * phases are host-driven), the others share the batched launches; stats (nullable)
  * and codes receive each member's statistics and status (FIM_OK,
  * FIM_NOT_CONVERGED after a rollback, or a negative error).  The call
  * itself returns FIM_OK unless the batch as a whole failed. */

@@ -1749,6 +1749,77 @@ fim_status fim_get_state(fim_model* m, double* u_out, int8_t* status_out, int me
     return FIM_OK;
 }
 
+// ------------------------------------------------------------ checkpoints
+// Blob: header, the state (b planes of n doubles), the phase status (n
+// bytes) and the previous step's support set (n bytes, zero without one).
+struct CkptHead {
+    char magic[8];
+    int32_t version, n, b, have_history;
+};
+static const char CKPT_MAGIC[8] = {'F', 'I', 'M', 'C', 'K', 'P', 'T', '1'};
+
+int64_t fim_checkpoint_bytes(const fim_model* m) {
+    if (!m) return -1;
+    return (int64_t)sizeof(CkptHead) + (int64_t)m->n * m->B * 8 + 2 * (int64_t)m->n;
+}
+
+fim_status fim_get_checkpoint(fim_model* m, void* buf, int64_t cap) {
+    if (!m || !buf) return FIM_E_ARG;
+    if (cap < fim_checkpoint_bytes(m)) {
+        m->err = "checkpoint buffer smaller than fim_checkpoint_bytes";
+        return FIM_E_ARG;
+    }
+    if (m->in_step) {
+        m->err = "checkpoints are taken between timesteps";
+        return FIM_E_STATE;
+    }
+    CkptHead h{};
+    std::memcpy(h.magic, CKPT_MAGIC, 8);
+    h.version = 1;
+    h.n = m->n;
+    h.b = m->B;
+    h.have_history = m->have_history ? 1 : 0;
+    char* p = (char*)buf;
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    const size_t nu = (size_t)m->n * m->B * sizeof(double);
+    HIPX(hipMemcpyAsync(p, m->u, nu, hipMemcpyDeviceToHost, m->s));
+    HIPX(hipMemcpyAsync(p + nu, m->st, m->n, hipMemcpyDeviceToHost, m->s));
+    if (m->have_history)
+        HIPX(hipMemcpyAsync(p + nu + m->n, m->supp, m->n, hipMemcpyDeviceToHost, m->s));
+    else
+        std::memset(p + nu + m->n, 0, m->n);
+    HIPX(hipStreamSynchronize(m->s));
+    return FIM_OK;
+}
+
+fim_status fim_set_checkpoint(fim_model* m, const void* buf, int64_t len) {
+    if (!m || !buf) return FIM_E_ARG;
+    CkptHead h{};
+    if (len < (int64_t)sizeof h) {
+        m->err = "checkpoint too short";
+        return FIM_E_ARG;
+    }
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, CKPT_MAGIC, 8) != 0 || h.version != 1) {
+        m->err = "not a checkpoint of this library";
+        return FIM_E_ARG;
+    }
+    if (h.n != m->n || h.b != m->B || len < fim_checkpoint_bytes(m)) {
+        m->err = "checkpoint of another model shape";
+        return FIM_E_ARG;
+    }
+    const char* p = (const char*)buf + sizeof h;
+    const size_t nu = (size_t)m->n * m->B * sizeof(double);
+    TRY(fim_set_state(m, (const double*)p, (const int8_t*)(p + nu), FIM_HOST));
+    if (h.have_history) {
+        HIPX(hipMemcpyAsync(m->supp, p + nu + m->n, m->n, hipMemcpyHostToDevice, m->s));
+        HIPX(hipStreamSynchronize(m->s));
+        m->have_history = true;
+    }
+    return FIM_OK;
+}
+
 // After the update of an Algorithm 1 / full iteration: the set update and
 // compaction for the next iteration and the status copies (launch only).
 static fim_status newton_post_launch(fim_model* m) {
@@ -2556,9 +2627,10 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
                                  fim_iter_stats* stats, int32_t* codes) {
     if (!b || !dts || !modes || !codes) return FIM_E_ARG;
     const int K = (int)b->ms.size();
+    auto is_dd = [&](int q) { return modes[q] == FIM_DD || modes[q] == FIM_DD_ADD; };
     for (int q = 0; q < K; q++) {
-        if (modes[q] != FIM_FULL && modes[q] != FIM_LOCAL && modes[q] != FIM_RESID) {
-            b->err = "batched steps run FIM_FULL, FIM_LOCAL or FIM_RESID";
+        if (modes[q] < FIM_FULL || modes[q] > FIM_DD_ADD) {
+            b->err = "batched steps run FIM_FULL, FIM_LOCAL, FIM_DD, FIM_RESID or FIM_DD_ADD";
             return FIM_E_ARG;
         }
         if (!(dts[q] > 0.0) || !std::isfinite(dts[q])) {
@@ -2589,6 +2661,12 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
             if (saved[q] != b->s) (void)hipStreamWaitEvent(saved[q], b->done_ev, 0);
         }
     };
+    // Algorithm 2 members: one inner iteration each with their own
+    // launches (a subdomain solve or an additive sweep has its own
+    // host-driven phase machine), on the batch stream
+    for (int q = 0; q < K; q++)
+        if (is_dd(q))
+            codes[q] = fim_newton_step(b->ms[q], dts[q], modes[q], stats ? &stats[q] : nullptr);
     // members that start a timestep: u^n, accumulation and the first
     // active set in one launch per kernel, one synchronisation for the new
     // n_A, then one structure pass
@@ -2596,6 +2674,7 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
     std::vector<BMember> bent;
     for (int q = 0; q < K; q++) {
         fim_model* m = b->ms[q];
+        if (is_dd(q)) continue;
         if (m->in_step && (dts[q] != m->step_dt || modes[q] != m->step_mode)) {
             m->err = "dt or mode changed inside a timestep";
             codes[q] = FIM_E_STATE;
@@ -2653,7 +2732,7 @@ fim_status fim_batch_newton_step(fim_batch* b, const double* dts, const int32_t*
     std::vector<fim_model*> live;
     std::vector<int> pos;
     for (int q = 0; q < K; q++) {
-        if (codes[q] != FIM_OK) continue;
+        if (codes[q] != FIM_OK || is_dd(q)) continue;
         fim_model* m = b->ms[q];
         if (m->nA == 0) {
             codes[q] = empty_iteration(m, stats ? &stats[q] : nullptr);

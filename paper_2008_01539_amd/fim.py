@@ -112,6 +112,9 @@ def _load():
         "fim_create_model": (i32, [vp, vp, vp, vp]),
         "fim_set_state": (i32, [vp, vp, vp, i32]),
         "fim_get_state": (i32, [vp, vp, vp, i32]),
+        "fim_checkpoint_bytes": (C.c_int64, [vp]),
+        "fim_get_checkpoint": (i32, [vp, vp, C.c_int64]),
+        "fim_set_checkpoint": (i32, [vp, vp, C.c_int64]),
         "fim_newton_step": (i32, [vp, f64, i32, vp]),
         "fim_newton_step_noalloc": (i32, [vp, f64, i32, vp]),
         "fim_solve_timestep": (i32, [vp, f64, i32, vp]),
@@ -300,6 +303,19 @@ class FimModel:
         st = np.empty(self.n, np.int8)
         _check(_lib.fim_get_state(self._h, _ptr(u), _ptr(st), HOST), self._h)
         return u, st
+
+    def get_checkpoint(self):
+        """The model's checkpoint between timesteps (state, phase status and
+        the previous step's support set) as bytes."""
+        nb = _lib.fim_checkpoint_bytes(self._h)
+        buf = C.create_string_buffer(nb)
+        _check(_lib.fim_get_checkpoint(self._h, buf, nb), self._h)
+        return buf.raw
+
+    def set_checkpoint(self, blob):
+        """Restore a checkpoint written by get_checkpoint (same model)."""
+        blob = bytes(blob)
+        _check(_lib.fim_set_checkpoint(self._h, blob, len(blob)), self._h)
 
     def get_state_device(self, u_out, st_out=None):
         _check(_lib.fim_get_state(self._h, u_out.data_ptr(),

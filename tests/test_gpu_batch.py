@@ -130,6 +130,24 @@ def test_batch_black_oil_mixed_modes_equals_solo():
     assert max(sizes) == 4
 
 
+def test_batch_algorithm2_members_equal_solo():
+    """Algorithm 2 members (multiplicative and additive) in a batch with
+    Algorithm 1 and full-Newton members: each runs its own inner
+    iterations inside the batched call and keeps its solo bits."""
+    import paper_2008_01539_amd as P
+    models = [make_small_c2(), make_small_c2(seed=23, nx=30, ny=14, nfrac=20),
+              make_small_c2(seed=24, nx=16, ny=10, nz=3, nfrac=6, nstage=2),
+              make_small_c2(seed=25, nx=20, ny=12, nfrac=10)]
+    modes = [P.DD, P.LOCAL, P.DD_ADD, P.FULL]
+    opts = P.Options(precision=P.MIXED)
+    n = 4
+    got, sizes = _batched(models, opts, modes, n)
+    for m, md, (u, st) in zip(models, modes, got):
+        ref, _ = _solo(m, opts, md, m.schedule[:n])
+        assert np.array_equal(u, ref)
+    assert max(sizes) == 4
+
+
 def test_batch_two_phase_fp64_equals_solo():
     """FP64 Krylov members with fracture blocks (the batched inversion reads
     FP64 scaled blocks): every member keeps its solo bits."""
