@@ -160,6 +160,17 @@ typedef struct fim_options {
                                 (default 1e-6)                                 */
     int32_t res_layers;      /* FIM_RESID: neighbour layers added (default 1,
                                 at most 8)                                     */
+    double  forcing_max;     /* > lin_rtol (default 0.1): inexact Newton
+                                forcing term of Eisenstat and Walker (1996,
+                                choice 2: eta = 0.9 (|F_k| / |F_k-1|)^2,
+                                safeguarded by 0.9 eta_k-1^2 when that
+                                exceeds 0.1) within [lin_rtol, forcing_max],
+                                forcing_max on a timestep's first iteration;
+                                |F| is the iteration's local residual
+                                (FIM_FULL, FIM_LOCAL).  FIM_RESID, Algorithm
+                                2, tight mode and forcing_max <= lin_rtol
+                                solve every iteration to lin_rtol.  Negative
+                                or non-finite: FIM_E_ARG                      */
 } fim_options;
 
 typedef struct fim_iter_stats {

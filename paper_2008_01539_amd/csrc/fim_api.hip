@@ -190,6 +190,7 @@ struct fim_model {
     bool is_clone = false;
     // step state machine
     bool in_step = false, have_history = false, full_ready = false;
+    double ew_fprev = 0.0, ew_eta = 0.0;   // forcing term: last |F| and eta of the step
     double step_dt = 0.0;
     int step_mode = 0, nu = 0, nA = 0, nB = 0;
     bool is_expand = true;
@@ -557,6 +558,33 @@ static void solve_prep(fim_model* m, hipStream_t s) {
     launch_fill_f64(m->x64, (long)m->nA * m->B, 0.0, s);
 }
 
+// Relative tolerance of this Newton iteration's linear solve: lin_rtol, or,
+// in full Newton and Algorithm 1, the inexact Newton forcing term of
+// Eisenstat and Walker (1996, choice 2, gamma 0.9, alpha 2, with their
+// safeguard) between lin_rtol and forcing_max, from the norms of the
+// iterations' local residuals (the first iteration of a timestep takes
+// forcing_max).  The residual-based mode and Algorithm 2 (whose
+// consecutive systems cover unrelated cell sets), tight mode and solves
+// outside a Newton iteration (fim_inspect_solve) take lin_rtol.
+static double forcing_eta(fim_model* m, double fnorm2) {
+    const double lo = m->o.lin_rtol, hi = m->o.forcing_max;
+    if (!(hi > lo) || m->o.tight || !m->in_step || m->is_clone ||
+        (m->step_mode != FIM_FULL && m->step_mode != FIM_LOCAL))
+        return lo;
+    const double fn = std::sqrt(fnorm2);
+    double eta = hi;
+    if (m->ew_fprev > 0.0 && std::isfinite(fn)) {
+        const double r = fn / m->ew_fprev;
+        eta = 0.9 * r * r;
+        const double safe = 0.9 * m->ew_eta * m->ew_eta;
+        if (safe > 0.1) eta = std::max(eta, safe);
+    }
+    eta = std::min(hi, std::max(lo, eta));
+    m->ew_fprev = fn;
+    m->ew_eta = eta;
+    return eta;
+}
+
 static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStream_t s,
                               bool prepped = false) {
     fim_model* lead = ms[0];
@@ -630,7 +658,8 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
             it.rir2 = st.rir2;
             it.bnorm2 = st.bnorm2;
             it.fnorm2 = st.rir2;
-            it.target2 = it.m->o.lin_rtol * it.m->o.lin_rtol * it.fnorm2;
+            const double eta = forcing_eta(it.m, it.fnorm2);
+            it.target2 = eta * eta * it.fnorm2;
         }
     const int max_refine = lead->o.max_refine;
     const int check = lead->o.check_every;
@@ -937,6 +966,8 @@ static void frac_closure(fim_model* m) {
 // and their neighbour layers, 3 = all cells, 4 = all cells, already
 // compacted (full Newton and the residual-based mode on a ready set).
 static int begin_state(fim_model* m, double dt, int mode) {
+    m->ew_fprev = 0.0;
+    m->ew_eta = 0.0;
     m->in_step = true;
     m->step_dt = dt;
     m->step_mode = mode;
@@ -1254,6 +1285,7 @@ void fim_default_options(fim_options* o) {
     o->precond = FIM_PC_FRACTURE;
     o->eps_res = 1e-6;
     o->res_layers = 1;
+    o->forcing_max = 0.1;
 }
 
 static thread_local std::string g_create_err;
@@ -1415,6 +1447,11 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     }
     if (!(m->o.eps_res >= 0.0) || !std::isfinite(m->o.eps_res)) {
         g_create_err = "eps_res must be finite and >= 0";
+        delete m;
+        return FIM_E_ARG;
+    }
+    if (!(m->o.forcing_max >= 0.0) || !std::isfinite(m->o.forcing_max)) {
+        g_create_err = "forcing_max must be finite and >= 0";
         delete m;
         return FIM_E_ARG;
     }

@@ -65,7 +65,7 @@ class _Opts(C.Structure):
                 ("inner_rtol", C.c_double), ("krylov_maxit", C.c_int32),
                 ("max_refine", C.c_int32), ("check_every", C.c_int32),
                 ("precond", C.c_int32), ("eps_res", C.c_double),
-                ("res_layers", C.c_int32)]
+                ("res_layers", C.c_int32), ("forcing_max", C.c_double)]
 
 
 class IterStats(C.Structure):
@@ -178,11 +178,12 @@ class Options:
     precond: int = PC_FRACTURE
     eps_res: float = 1e-6
     res_layers: int = 1
+    forcing_max: float = 0.1
 
     @staticmethod
     def tight_mode(**kw):
         o = Options(eps_conv=1e-7 * PSI, eps_loc=1e-7 * PSI, eps_s=1e-10, tight=1,
-                    max_newton=40, lin_rtol=1e-12)
+                    max_newton=40, lin_rtol=1e-12, forcing_max=0.0)
         for k, v in kw.items():
             setattr(o, k, v)
         return o

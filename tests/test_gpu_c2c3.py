@@ -117,10 +117,11 @@ def test_blackoil_timesteps_match_oracle(c3s, oracle_c3s, mode_name, prec):
 def test_mixed_precision_error_per_result(which, c2s, c3s):
     """Paper-mode settings (eps_p = 0.3 psi) with the FP32 Krylov inside
     FP64 refinement: full Newton against the FP64 oracle at the same
-    settings stays below the 1e-6 relative pressure target."""
+    settings stays below the 1e-6 relative pressure target (every linear
+    solve to the fixed 1e-4, so that only the precision differs)."""
     import paper_2008_01539_amd as P
     m = c2s if which == "c2s" else c3s
-    u, _, _ = _run(m, P.Options(precision=P.MIXED), P.FULL, m.schedule)
+    u, _, _ = _run(m, P.Options(precision=P.MIXED, forcing_max=0.0), P.FULL, m.schedule)
     ref = run_oracle(Solver(m, OOptions()), m, m.schedule)[-1].u
     rel = np.abs(u[0] - ref[0]).max() / ref[0].min()
     assert rel <= 1e-6, rel

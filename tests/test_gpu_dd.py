@@ -122,7 +122,7 @@ def test_dd_paper_mode_sequence_matches_oracle(which, nsteps, c1, c2s, c3s):
     import paper_2008_01539_amd as P
     model = {"c1": c1, "c2s": c2s, "c3s": c3s}[which]
     sched = model.schedule[:nsteps]
-    g = _gpu_dd_steps(model, P.Options(lin_rtol=1e-12), sched)
+    g = _gpu_dd_steps(model, P.Options(lin_rtol=1e-12, forcing_max=0.0), sched)
     o = _oracle_dd_steps(model, OOptions(), sched)
     saw_phase2 = False
     for k, (gs, os_) in enumerate(zip(g, o)):
@@ -149,7 +149,7 @@ def test_dd_sweep_cap_matches_oracle(c1):
     sweeps = log[-1]["sweeps"]
     assert sweeps >= 2
     for cap, ok in ((sweeps - 1, False), (sweeps, True)):
-        fm = P.FimModel(c1, P.Options(lin_rtol=1e-12, max_sweeps=cap))
+        fm = P.FimModel(c1, P.Options(lin_rtol=1e-12, forcing_max=0.0, max_sweeps=cap))
         fm.set_state(c1.u0, c1.status0)
         stats = fm.solve_timestep(dt, P.DD, raise_on_fail=False)
         u, _ = fm.get_state()
@@ -295,7 +295,7 @@ def test_dd_additive_paper_mode_sequence_matches_oracle(which, nsteps, c1, c2s, 
     import paper_2008_01539_amd as P
     model = {"c1": c1, "c2s": c2s, "c3s": c3s}[which]
     sched = model.schedule[:nsteps]
-    g = _gpu_dda_steps(model, P.Options(lin_rtol=1e-12), sched)
+    g = _gpu_dda_steps(model, P.Options(lin_rtol=1e-12, forcing_max=0.0), sched)
     o = _oracle_dda_steps(model, OOptions(), sched)
     multi = False
     for k, (gs, os_) in enumerate(zip(g, o)):

@@ -98,7 +98,7 @@ def test_localized_fractures_paper_mode_within_cutoff(c2s_loc):
     import paper_2008_01539_amd as P
     m = c2s_loc
     ref = run_oracle(Solver(m, OOptions()), m, m.schedule)[-1]
-    fm = P.FimModel(m, P.Options(lin_rtol=1e-10))
+    fm = P.FimModel(m, P.Options(lin_rtol=1e-10, forcing_max=0.0))
     fm.set_state(m.u0, m.status0)
     for dt in m.schedule:
         fm.solve_timestep(dt, P.LOCAL)

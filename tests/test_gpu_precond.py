@@ -41,7 +41,7 @@ def test_fracture_blocks_reach_the_direct_solution_in_fewer_iterations(fluid):
     ref = spla.spsolve(Jo.tocsc(), -Fo.reshape(-1))
     its = {}
     for pc in (PC_JACOBI, PC_FRACTURE):
-        fm = FimModel(model, Options(precision=FP64, lin_rtol=1e-12, precond=pc))
+        fm = FimModel(model, Options(precision=FP64, lin_rtol=1e-12, forcing_max=0.0, precond=pc))
         fm.set_state(model.u0, model.status0)
         fm.inspect_assemble(uo, ui, model.status0, dt)
         x, n_it, relres = fm.inspect_solve()
