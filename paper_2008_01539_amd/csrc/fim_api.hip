@@ -619,7 +619,7 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
                 fim_model* mq = ms[q];
                 if (mq->use_pc)
                     pcs.push_back(PcSeg{lsys(mq), mq->At, mq->pclist, &mq->dint[6], mq->pcoff,
-                                        mq->pcM, mq->pc_dec ? 1 : 0});
+                                        mq->pcM});
             }
             if (pcs.empty()) continue;
             PcSeg* dpc = t.dpc + (size_t)g * t.cap;
@@ -627,8 +627,11 @@ static fim_status solve_batch(std::vector<fim_model*>& ms, SolveTable& t, hipStr
             HIPX(hipMemcpyAsync(dpc, pcs.data(), pcs.size() * sizeof(PcSeg),
                                 hipMemcpyHostToDevice, s));
             const int pv = pbeg(lead, PK_PCINV);
-            launch_pc_invert_batch(lead->B, g == 0, 8 * lead->cus, dpc, (int)pcs.size(), dpref,
-                                   s);
+            // one fracture-block mode per batch (batch_check)
+            bool dec = false;
+            for (int q : G[g].idx) dec = dec || (ms[q]->use_pc && ms[q]->pc_dec);
+            launch_pc_invert_batch(lead->B, g == 0, (dec ? 20 : 8) * lead->cus, dpc,
+                                   (int)pcs.size(), dpref, dec, s);
             pend(lead, pv, lead->nA);
         }
     }
@@ -1675,7 +1678,9 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
             // blocks have >= 2 rows, all fracture cells
             CK(dal(m, &m->pclist, 2 * (nfc / 2 + 1)));
             // about as many single-wave workgroups as fit at once (LDS)
-            m->pc_inv_grid = std::min(nfc / 2 + 1, 8 * m->cus);
+            // resident single-wave workgroups per CU (LDS-bound: 8 with
+            // coupled blocks, about 20 with the decoupled blocks' rows)
+            m->pc_inv_grid = std::min(nfc / 2 + 1, (m->pc_dec ? 20 : 8) * m->cus);
             m->pc_nfc = nfc;
             m->use_pc = true;
         }

@@ -206,9 +206,8 @@ constexpr int PCI_MS = PC_DOF + 4;
 // by its own pivot once at the end.  After N steps columns C - N .. C - 1
 // hold the inverse; the rows go back to M.  Returns whether a pivot was
 // below 1e-20 in magnitude or not finite.
-template <int C>
+template <int C, int MS = PCI_MS>
 __device__ inline bool gauss_jordan(float* M, int N) {
-    constexpr int MS = PCI_MS;
     const int lane = threadIdx.x;
     float a[C];
     {
@@ -260,9 +259,8 @@ __device__ inline bool gauss_jordan(float* M, int N) {
 // hold no block (they pivot on themselves; nothing reads them).  Returns,
 // per lane, whether a pivot of the lane's block was below 1e-20 in
 // magnitude or not finite.
-template <int C>
+template <int C, int MS>
 __device__ inline bool gauss_jordan_groups(float* M, int n, int G) {
-    constexpr int MS = PCI_MS;
     const int lane = threadIdx.x;
     const int grp = lane / n, r = lane - grp * n;
     const bool live = grp < G;
@@ -310,8 +308,10 @@ __device__ inline bool gauss_jordan_groups(float* M, int n, int G) {
     return live && bad;
 }
 
-// register columns of a decoupled block (at most pc_cells(b) cells)
+// register columns of a decoupled block (at most pc_cells(b) cells) and
+// its LDS row stride
 constexpr int PCI_DEC_C = 24;
+constexpr int PCI_DEC_MS = PCI_DEC_C + 4;
 static_assert(pc_cells(2) <= PCI_DEC_C && pc_cells(3) <= PCI_DEC_C,
               "decoupled blocks exceed their register columns");
 
@@ -323,13 +323,13 @@ static_assert(pc_cells(2) <= PCI_DEC_C && pc_cells(3) <= PCI_DEC_C,
 // Loops stay rolled where they run once per block: each wave runs this
 // code about once per launch, so its size (instruction fetch) costs more
 // than loop overhead.
-template <int B, typename T>
+template <int B, typename T, bool DEC>
 __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
                              const int* __restrict__ list, const int* __restrict__ pcoff,
-                             float* __restrict__ pcM, int q, float* M, bool dec_) {
+                             float* __restrict__ pcM, int q, float* M) {
     constexpr int BB = B * B;
-    constexpr int MS = PCI_MS;
-    const bool dec = B > 1 && dec_;
+    constexpr bool dec = DEC && B > 1;
+    constexpr int MS = dec ? PCI_DEC_MS : PCI_MS;
     const int lane = threadIdx.x;
     const int r0 = list[2 * q], size = list[2 * q + 1];
     // slot widths of the (at most two) slices the block's rows are in
@@ -393,14 +393,16 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
     }
     wave_sync();
     bool bad;
-    if (dec)
-        bad = gauss_jordan_groups<PCI_DEC_C>(M, size, B);
-    else if (N <= 32)
-        bad = gauss_jordan<32>(M, N);
-    else if (N <= 48)
-        bad = gauss_jordan<48>(M, N);
-    else
-        bad = gauss_jordan<PC_DOF>(M, N);
+    if constexpr (dec) {
+        bad = gauss_jordan_groups<PCI_DEC_C, MS>(M, size, B);
+    } else {
+        if (N <= 32)
+            bad = gauss_jordan<32>(M, N);
+        else if (N <= 48)
+            bad = gauss_jordan<48>(M, N);
+        else
+            bad = gauss_jordan<PC_DOF>(M, N);
+    }
     const int c0 = C - N, nrow = dec ? B * size : N;
     if (lane < nrow) {
 #pragma unroll 1
@@ -437,16 +439,18 @@ __device__ void invert_block(const LocalSys& ls, const T* __restrict__ At,
 }
 
 // One system: workgroup w takes blocks w, w + grid, ... of its list.
-template <int B, typename T>
+// (DEC: decoupled blocks, whose 24-column rows need less LDS, so that more
+// workgroups fit on a CU)
+template <int B, typename T, bool DEC>
 __global__ __launch_bounds__(WAVE) void k_pc_invert(LocalSys ls, const T* __restrict__ At,
                                                     const int* __restrict__ list,
                                                     const int* __restrict__ cnt,
                                                     const int* __restrict__ pcoff,
-                                                    float* __restrict__ pcM, int dec) {
-    __shared__ __align__(16) float M[PC_DOF * PCI_MS];
+                                                    float* __restrict__ pcM) {
+    __shared__ __align__(16) float M[PC_DOF * (DEC && B > 1 ? PCI_DEC_MS : PCI_MS)];
     const int nblk = *cnt;
     for (int q = blockIdx.x; q < nblk; q += gridDim.x)
-        invert_block<B, T>(ls, At, list, pcoff, pcM, q, M, dec != 0);
+        invert_block<B, T, DEC>(ls, At, list, pcoff, pcM, q, M);
 }
 
 // Many systems (a batch): the blocks of all lists in one sequence; pref
@@ -463,11 +467,11 @@ __global__ __launch_bounds__(64) void k_pc_prefix(const PcSeg* __restrict__ segs
     }
 }
 
-template <int B, typename T>
+template <int B, typename T, bool DEC>
 __global__ __launch_bounds__(WAVE) void k_pc_invert_batch(const PcSeg* __restrict__ segs,
                                                           int nseg,
                                                           const int* __restrict__ pref) {
-    __shared__ __align__(16) float M[PC_DOF * PCI_MS];
+    __shared__ __align__(16) float M[PC_DOF * (DEC && B > 1 ? PCI_DEC_MS : PCI_MS)];
     const int total = pref[nseg];
     for (int q = blockIdx.x; q < total; q += gridDim.x) {
         int lo = 0, hi = nseg - 1;   // the system k with pref[k] <= q < pref[k + 1]
@@ -477,8 +481,7 @@ __global__ __launch_bounds__(WAVE) void k_pc_invert_batch(const PcSeg* __restric
             else hi = mid - 1;
         }
         const PcSeg& S = segs[lo];
-        invert_block<B, T>(S.ls, (const T*)S.At, S.list, S.pcoff, S.pcM, q - pref[lo], M,
-                           S.dec != 0);
+        invert_block<B, T, DEC>(S.ls, (const T*)S.At, S.list, S.pcoff, S.pcM, q - pref[lo], M);
     }
 }
 
@@ -486,8 +489,15 @@ void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void
                       const int* list, const int* cnt, const int* pcoff, float* pcM,
                       bool dec, hipStream_t s) {
     if (grid <= 0) return;
-#define PV(BV, TT) \
-    k_pc_invert<BV, TT><<<grid, WAVE, 0, s>>>(ls, (const TT*)At, list, cnt, pcoff, pcM, dec ? 1 : 0)
+#define PV(BV, TT)                                                                    \
+    do {                                                                              \
+        if (dec)                                                                      \
+            k_pc_invert<BV, TT, true><<<grid, WAVE, 0, s>>>(ls, (const TT*)At, list, cnt, \
+                                                            pcoff, pcM);              \
+        else                                                                          \
+            k_pc_invert<BV, TT, false><<<grid, WAVE, 0, s>>>(ls, (const TT*)At, list,   \
+                                                             cnt, pcoff, pcM);        \
+    } while (0)
     if (fp32) {
         if (b == 1) PV(1, float); else if (b == 2) PV(2, float); else PV(3, float);
     } else {
@@ -497,10 +507,14 @@ void launch_pc_invert(int b, bool fp32, int grid, const LocalSys& ls, const void
 }
 
 void launch_pc_invert_batch(int b, bool fp32, int grid, const PcSeg* segs, int nseg, int* pref,
-                            hipStream_t s) {
+                            bool dec, hipStream_t s) {
     if (grid <= 0 || nseg <= 0) return;
     k_pc_prefix<<<1, 64, 0, s>>>(segs, nseg, pref);
-#define PV(BV, TT) k_pc_invert_batch<BV, TT><<<grid, WAVE, 0, s>>>(segs, nseg, pref)
+#define PV(BV, TT)                                                              \
+    do {                                                                        \
+        if (dec) k_pc_invert_batch<BV, TT, true><<<grid, WAVE, 0, s>>>(segs, nseg, pref);  \
+        else k_pc_invert_batch<BV, TT, false><<<grid, WAVE, 0, s>>>(segs, nseg, pref);     \
+    } while (0)
     if (fp32) {
         if (b == 1) PV(1, float); else if (b == 2) PV(2, float); else PV(3, float);
     } else {

@@ -268,12 +268,12 @@ struct PcSeg {
     const int* cnt;
     const int* pcoff;
     float* pcM;
-    int dec;
 };
-// the blocks of nseg systems (same b and Krylov precision) in one launch of
-// grid single-wave workgroups; pref: nseg + 1 ints of device scratch
+// the blocks of nseg systems (same b, Krylov precision and fracture-block
+// mode dec) in one launch of grid single-wave workgroups; pref: nseg + 1
+// ints of device scratch
 void launch_pc_invert_batch(int b, bool fp32, int grid, const PcSeg* segs, int nseg, int* pref,
-                            hipStream_t s);
+                            bool dec, hipStream_t s);
 
 // update (fim_update.hip)
 void launch_update(int fk, int nA, const int* l2g, const double* x64,
