@@ -1,0 +1,68 @@
+"""The inexact Newton forcing term (Eisenstat and Walker 1996, choice 2;
+option forcing_max, on by default in full Newton and Algorithm 1): paper
+mode timesteps solved with it end within the Newton tolerance of the same
+steps with a fixed 1e-4 linear tolerance and of the oracle's full Newton
+with direct solves (Section 5: eps_p = 0.3 psi), with fewer BiCGStab
+iterations; tight mode ignores it; invalid values are refused."""
+import numpy as np
+import pytest
+
+from fimgen import PSI, make_small_c2, make_small_c3
+from oracle.newton import Options as OOptions
+from oracle.newton import Solver
+
+from gpu_util import run_oracle
+
+pytestmark = pytest.mark.gpu
+
+EPS = 0.3 * PSI
+
+
+def _run(model, opts, mode):
+    import paper_2008_01539_amd as P
+    fm = P.FimModel(model, opts)
+    fm.set_state(model.u0, model.status0)
+    kry = 0
+    for dt in model.schedule:
+        kry += fm.solve_timestep(dt, mode).as_dict()["krylov_iters"]
+    u, st = fm.get_state()
+    fm.close()
+    return u, kry
+
+
+@pytest.mark.parametrize("maker", [make_small_c2, make_small_c3], ids=["c2s", "c3s"])
+@pytest.mark.parametrize("mode_name", ["FULL", "LOCAL"])
+def test_forcing_term_ends_within_newton_tolerance(maker, mode_name):
+    import paper_2008_01539_amd as P
+    m = maker()
+    mode = getattr(P, mode_name)
+    u_ew, k_ew = _run(m, P.Options(precision=P.MIXED), mode)
+    u_fx, k_fx = _run(m, P.Options(precision=P.MIXED, forcing_max=0.0), mode)
+    assert k_ew < k_fx
+    ref = run_oracle(Solver(m, OOptions()), m, m.schedule)[-1].u
+    d_fx = np.abs(u_fx[0] - ref[0]).max()
+    d_ew = np.abs(u_ew[0] - ref[0]).max()
+    if mode_name == "FULL":
+        # full Newton: both within the Newton tolerance of the direct solves
+        assert d_ew <= EPS and d_fx <= EPS, (d_ew / PSI, d_fx / PSI)
+    else:
+        # Algorithm 1: the forcing term adds at most the Newton tolerance to
+        # the localization's own distance from full Newton
+        assert d_ew <= d_fx + EPS, (d_ew / PSI, d_fx / PSI)
+    assert np.abs(u_ew[0] - u_fx[0]).max() <= 2 * EPS
+
+
+def test_tight_mode_ignores_forcing_term():
+    import paper_2008_01539_amd as P
+    m = make_small_c2()
+    a, _ = _run(m, P.Options.tight_mode(precision=P.MIXED), P.LOCAL)
+    b, _ = _run(m, P.Options.tight_mode(precision=P.MIXED, forcing_max=0.1), P.LOCAL)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("bad", [-0.1, float("nan"), float("inf")])
+def test_invalid_forcing_max_is_refused(bad):
+    import paper_2008_01539_amd as P
+    from paper_2008_01539_amd.fim import FimError
+    with pytest.raises(FimError):
+        P.FimModel(make_small_c2(), P.Options(forcing_max=bad))
