@@ -200,13 +200,10 @@ __device__ inline void assemble_rows(int nA, const LocalSys& ls, const Graph& g,
 #pragma unroll
             for (int v = 0; v < B; v++) out[c * B + v] = Jd[c][v];
     }
-    for (; k < width; k++) {
-        const long pos = base + (long)k * SLICE;
-        ls.col[pos] = r;
-        double* out = ls.J + pos * BB;
-#pragma unroll
-        for (int q = 0; q < BB; q++) out[q] = 0.0;
-    }
+    // padding slots up to the slice width: column = the row itself, no
+    // block (readers of J recognise them by that column; k_precond writes
+    // the zero blocks the FP64 product kernels load)
+    for (; k < width; k++) ls.col[base + (long)k * SLICE] = r;
 #pragma unroll
     for (int c = 0; c < B; c++) ls.F[(long)r * B + c] = R[c];
 }
@@ -366,11 +363,19 @@ __device__ inline bool invert_block(const double* a, double* inv) {
             for (int r = c + 1; r < B; r++)
                 if (fabs(m[r][c]) > best) { best = fabs(m[r][c]); piv = r; }
             if (best == 0.0) ok = false;
+            // row swap c <-> piv with compile-time indices only (a
+            // runtime row index would put m in scratch memory)
 #pragma unroll
             for (int q = 0; q < 2 * B; q++) {
-                double t0 = m[c][q], t1 = m[piv][q];
-                m[c][q] = (piv == c) ? t0 : t1;
-                m[piv][q] = (piv == c) ? t1 : t0;
+                const double t0 = m[c][q];
+                double tp = t0;
+#pragma unroll
+                for (int r = c + 1; r < B; r++)
+                    if (piv == r) tp = m[r][q];
+#pragma unroll
+                for (int r = c + 1; r < B; r++)
+                    if (piv == r) m[r][q] = t0;
+                m[c][q] = tp;
             }
             const double ip = 1.0 / m[c][c];
 #pragma unroll
@@ -411,20 +416,38 @@ __device__ inline void precond_rows(int nA, const LocalSys& ls, double* __restri
     invert_block<B>(d, di);
 #pragma unroll
     for (int q = 0; q < BB; q++) dinv[(long)r * BB + q] = di[q];
-    for (int k = 1; k < width; k++) {
-        const long pos = base + (long)k * SLICE;
-        double a[BB];
+    // UR slots at a time, their column words and blocks in one round of
+    // loads.  Padding slots (column = the row itself past the diagonal)
+    // have no block in J (what their J slots hold is never used): the FP64
+    // product kernels load their A~ block, written here as zero; the FP32
+    // ones and every other reader skip them by their column.
+    constexpr int UR = 4;
+    for (int k0 = 1; k0 < width; k0 += UR) {
+        int cl[UR];
+        double a[UR][BB];
 #pragma unroll
-        for (int q = 0; q < BB; q++) a[q] = J[pos * BB + q];
+        for (int u = 0; u < UR; u++) {
+            const long pos = base + (long)min(k0 + u, width - 1) * SLICE;
+            cl[u] = k0 + u < width ? ls.col[pos] : r;
 #pragma unroll
-        for (int rr = 0; rr < B; rr++)
+            for (int q = 0; q < BB; q++) a[u][q] = J[pos * BB + q];
+        }
 #pragma unroll
-            for (int cc = 0; cc < B; cc++) {
-                double acc = 0.0;
+        for (int u = 0; u < UR; u++) {
+            if (k0 + u >= width) break;
+            const long pos = base + (long)(k0 + u) * SLICE;
+            const bool pad = cl[u] == r;
+            if (pad && sizeof(T) == 4) continue;
 #pragma unroll
-                for (int t = 0; t < B; t++) acc += di[rr * B + t] * a[t * B + cc];
-                At[pos * BB + rr * B + cc] = (T)acc;
-            }
+            for (int rr = 0; rr < B; rr++)
+#pragma unroll
+                for (int cc = 0; cc < B; cc++) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int t = 0; t < B; t++) acc += di[rr * B + t] * a[u][t * B + cc];
+                    At[pos * BB + rr * B + cc] = pad ? (T)0 : (T)acc;
+                }
+        }
     }
 }
 
