@@ -47,14 +47,16 @@ void launch_fill_f64(double* a, long n, double v, hipStream_t s) {
 constexpr int PER = TILE / NT;   // 16 cells per thread
 
 // (vb: the tile; the bodies below take the workgroup's index within its
-// own system, so that the batched launches share them)
+// own system, so that the batched launches share them).  Cell q NT + t of
+// a tile belongs to thread t (round q), so every load and store of a round
+// is one contiguous span per wave.
 __device__ inline void compact_count(const uint8_t* __restrict__ act, int n,
                                      int* __restrict__ blk_cnt, int vb) {
-    const int base = vb * TILE + threadIdx.x * PER;
+    const int base = vb * TILE + threadIdx.x;
     int c = 0;
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-        const int i = base + q;
+        const int i = base + q * NT;
         if (i < n && act[i]) c++;
     }
     c = block_sum_i(c);
@@ -66,53 +68,59 @@ __global__ __launch_bounds__(NT) void k_compact_count(const uint8_t* __restrict_
     compact_count(act, n, blk_cnt, blockIdx.x);
 }
 
-// (vb of ntile tiles; the last one writes n_out)
+// (vb of ntile tiles; the last one writes n_out).  The tile's cells in
+// index order are rounds q, then waves w, then lanes: each wave takes the
+// mask of its active cells per round (ballot), the PER x NW counts are
+// scanned in that order in LDS, and a cell's position is its tile's
+// offset + its (round, wave) offset + the active lanes below it.
 __device__ inline void compact_scatter(const uint8_t* __restrict__ act, int n,
                                        const int* __restrict__ blk_cnt, int* __restrict__ l2g,
                                        int* __restrict__ g2l, int* __restrict__ n_out, int vb,
                                        int ntile) {
-    __shared__ int wsum[NT / WAVE];
+    constexpr int NW = NT / WAVE;
+    static_assert(PER * NW <= WAVE, "one wave scans the round counts");
+    __shared__ int cnt[PER * NW];
     // offset of this tile: sum of the preceding tile counts
     int off = 0;
     for (int t = threadIdx.x; t < vb; t += NT) off += blk_cnt[t];
     off = block_sum_i(off);
-    const int base = vb * TILE + threadIdx.x * PER;
-    uint8_t f[PER];
-    int c = 0;
-#pragma unroll
-    for (int q = 0; q < PER; q++) {
-        const int i = base + q;
-        f[q] = (i < n && act[i]) ? 1 : 0;
-        c += f[q];
-    }
-    // exclusive scan of c across the block: wave inclusive scan + wave sums
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    int inc = c;
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        int y = __shfl_up(inc, o, WAVE);
-        if (lane >= o) inc += y;
-    }
-    __syncthreads();
-    if (lane == WAVE - 1) wsum[w] = inc;
-    __syncthreads();
-    int wo = 0;
-    for (int q = 0; q < w; q++) wo += wsum[q];
-    int pos = off + wo + inc - c;
+    const int base = vb * TILE + threadIdx.x;
+    unsigned long long mask[PER];
 #pragma unroll
     for (int q = 0; q < PER; q++) {
-        const int i = base + q;
-        if (i < n) {
-            if (f[q]) {
-                l2g[pos] = i;
-                g2l[i] = pos;
-                pos++;
-            } else {
-                g2l[i] = -1;
-            }
+        const int i = base + q * NT;
+        mask[q] = __ballot(i < n && act[i]);
+        if (lane == 0) cnt[q * NW + w] = __popcll(mask[q]);
+    }
+    __syncthreads();
+    if (threadIdx.x < WAVE) {   // exclusive scan of the PER x NW counts
+        const int v = threadIdx.x < PER * NW ? cnt[threadIdx.x] : 0;
+        int inc = v;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int y = __shfl_up(inc, o, WAVE);
+            if (lane >= o) inc += y;
+        }
+        if (threadIdx.x < PER * NW) cnt[threadIdx.x] = inc - v;
+        if (vb == ntile - 1 && threadIdx.x == WAVE - 1) *n_out = off + inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+        const int i = base + q * NT;
+        if (i >= n) break;
+        const unsigned long long m = mask[q];
+        if ((m >> lane) & 1ull) {
+            const int below = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+            const int pos = off + cnt[q * NW + w] + below;
+            l2g[pos] = i;
+            g2l[i] = pos;
+        } else {
+            g2l[i] = -1;
         }
     }
-    if (vb == ntile - 1 && threadIdx.x == NT - 1) *n_out = pos;
 }
 
 __global__ __launch_bounds__(NT) void k_compact_scatter(const uint8_t* __restrict__ act, int n,
