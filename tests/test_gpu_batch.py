@@ -111,6 +111,43 @@ def test_serving_results_same_alone_and_in_the_mix():
     ex.close()
 
 
+def test_serving_tight_sessions_match_oracle():
+    """Tight-mode sessions served by the continuously batching loop (Poisson
+    requests, members joining and leaving the batch) reach the oracle's
+    full-Newton solution of the steps each session received (1e-8 relative
+    p, 1e-8 S)."""
+    import paper_2008_01539_amd as P
+    from paper_2008_01539_amd.serve import GpuExecutor, Server, SessionSpec
+    from oracle.newton import Options as OOptions
+    from oracle.newton import Solver, State
+    models = [make_c1_variant(seed=13, nx=20, ny=16), make_small_c2(),
+              make_small_c2(seed=26, nx=18, ny=10, nfrac=8)]
+    specs = [SessionSpec(name=f"t{k}", model=m, options=P.Options.tight_mode(precision=P.MIXED),
+                         schedule=m.schedule) for k, m in enumerate(models)]
+    ex = GpuExecutor()
+    srv = Server(specs, ex, budget_bytes=8 << 30, max_inflight=8,
+                 footprint=lambda s: P.estimate_bytes(s.model, s.options))
+    summ = srv.run_poisson(rate=20.0, duration=1.0, mix=np.array([0.4, 0.3, 0.3]), seed=7)
+    assert summ["failed"] == 0
+    checked = 0
+    for s in srv.sessions:
+        if s.next_step == 0:
+            continue
+        u, _ = s.handle.get_state()
+        sched = s.spec.schedule
+        m = s.spec.model
+        st = State(m.u0.copy(), m.status0.copy())
+        sol = Solver(m, OOptions.tight_mode())
+        for k in range(s.next_step):
+            st, _ = sol.solve_timestep(st, sched[k % len(sched)])
+        assert np.abs(u[0] - st.u[0]).max() <= 1e-8 * st.u[0].min(), s.spec.name
+        if m.b > 1:
+            assert np.abs(u[1] - st.u[1]).max() <= 1e-8, s.spec.name
+        checked += 1
+    assert checked >= 2
+    ex.close()
+
+
 def test_batch_black_oil_mixed_modes_equals_solo():
     """Black-oil members (3x3 blocks, fracture blocks) in one batch, each in
     its own mode (Algorithm 1, full Newton, residual-based): every member
