@@ -173,6 +173,8 @@ struct fim_model {
     KScal* hsc = nullptr;
     NStat* hns = nullptr;
     int* hint = nullptr;
+    NStat* hns_dev = nullptr;   // device addresses of hns / hint (mapped)
+    int* hint_dev = nullptr;
     double* hsub = nullptr;
     // Algorithm 2 storage
     int *sd_cells = nullptr, *sd_outer = nullptr;
@@ -999,7 +1001,7 @@ static fim_status begin_launch(fim_model* m, double dt, int mode, bool* pending)
         if (!m->full_ready) {
             launch_fill_u8(m->act, m->n, 1, m->s);
             compact(m);
-            HIPX(hipMemcpyAsync(m->hint, m->dint, 4 * sizeof(int), hipMemcpyDeviceToHost, m->s));
+            launch_status_out(nullptr, m->dint, nullptr, m->hint_dev, m->s);
             *pending = true;
         }
         m->nA = m->n;
@@ -1031,7 +1033,7 @@ static fim_status begin_launch(fim_model* m, double dt, int mode, bool* pending)
         m->dd_k = 0;
     }
     compact(m);
-    HIPX(hipMemcpyAsync(m->hint, m->dint, 4 * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    launch_status_out(nullptr, m->dint, nullptr, m->hint_dev, m->s);
     *pending = true;
     return FIM_OK;
 }
@@ -1691,8 +1693,12 @@ fim_status fim_create_model(const fim_model_desc* d, const fim_options* o,
     CK(dal(m, &m->dint, 8));
     CK(dal(m, &m->dsub, 1024));
     if (hipHostMalloc((void**)&m->hsc, sizeof(KScal)) != hipSuccess ||
-        hipHostMalloc((void**)&m->hns, sizeof(NStat)) != hipSuccess ||
-        hipHostMalloc((void**)&m->hint, 8 * sizeof(int)) != hipSuccess ||
+        hipHostMalloc((void**)&m->hns, sizeof(NStat), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostMalloc((void**)&m->hint, 8 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void**)&m->hns_dev, m->hns, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&m->hint_dev, m->hint, 0) != hipSuccess ||
         hipHostMalloc((void**)&m->hsub, 1024 * sizeof(double)) != hipSuccess ||
         hipHostMalloc((void**)&m->hpart, 2 * KB_MAXB * sizeof(double)) != hipSuccess) {
         m->err = "hipHostMalloc failed";
@@ -1888,8 +1894,7 @@ static fim_status newton_post_launch(fim_model* m) {
         pend(m, pi, m->n);
         m->full_ready = false;   // l2g / g2l now hold the new set
     }
-    HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
-    HIPX(hipMemcpyAsync(m->hint, m->dint, 4 * sizeof(int), hipMemcpyDeviceToHost, m->s));
+    launch_status_out(m->ns, m->dint, m->hns_dev, m->hint_dev, m->s);
     return FIM_OK;
 }
 

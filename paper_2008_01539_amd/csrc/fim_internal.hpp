@@ -100,6 +100,9 @@ struct NStat {
 void launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s);
 void launch_fill_i32(int* a, int n, int v, hipStream_t s);
 void launch_fill_f64(double* a, long n, double v, hipStream_t s);
+// the iteration's status words (ns may be null: dint only) into mapped
+// pinned host memory, one launch instead of two copies
+void launch_status_out(const NStat* ns, const int* dint, NStat* ons, int* oint, hipStream_t s);
 void launch_compact(const uint8_t* act, int n, int* blk_cnt, int* l2g,
                     int* g2l, int* n_out, hipStream_t s);
 // also writes the number of blocks of the local matrix (diagonal included)

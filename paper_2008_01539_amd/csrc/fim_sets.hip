@@ -33,6 +33,21 @@ __global__ void k_fill_f64(double* a, long n, double v) {
     if (i < n) a[i] = v;
 }
 
+// lane w copies word w (vector stores into the mapped host buffers)
+__global__ __launch_bounds__(64) void k_status_out(const NStat* __restrict__ ns,
+                                                   const int* __restrict__ dint,
+                                                   NStat* __restrict__ ons, int* __restrict__ oint) {
+    constexpr int NW = (int)(sizeof(NStat) / sizeof(int));
+    static_assert(sizeof(NStat) % sizeof(int) == 0 && NW <= 60, "NStat words");
+    const int w = threadIdx.x;
+    if (ns && w < NW) ((int*)ons)[w] = ((const int*)ns)[w];
+    if (w >= 60) oint[w - 60] = dint[w - 60];
+}
+
+void launch_status_out(const NStat* ns, const int* dint, NStat* ons, int* oint, hipStream_t s) {
+    k_status_out<<<1, 64, 0, s>>>(ns, dint, ons, oint);
+}
+
 void launch_fill_u8(uint8_t* a, int n, uint8_t v, hipStream_t s) {
     if (n > 0) k_fill_u8<<<nblocks(n), NT, 0, s>>>(a, n, v);
 }
