@@ -193,6 +193,10 @@ struct fim_model {
     // step state machine
     bool in_step = false, have_history = false, full_ready = false;
     double ew_fprev = 0.0, ew_eta = 0.0;   // forcing term: last |F| and eta of the step
+    // Algorithm 2's phase 2: the forcing term per subdomain (its own last
+    // |F| and eta) and the subdomain being solved (-1: none)
+    std::vector<double> dd_ew_f, dd_ew_eta;
+    int dd_cur = -1;
     double step_dt = 0.0;
     int step_mode = 0, nu = 0, nA = 0, nB = 0;
     bool is_expand = true;
@@ -565,25 +569,34 @@ static void solve_prep(fim_model* m, hipStream_t s) {
 // Eisenstat and Walker (1996, choice 2, gamma 0.9, alpha 2, with their
 // safeguard) between lin_rtol and forcing_max, from the norms of the
 // iterations' local residuals (the first iteration of a timestep takes
-// forcing_max).  The residual-based mode and Algorithm 2 (whose
+// forcing_max).  Algorithm 2's sweeps (phase 2) keep one such sequence per
+// subdomain, over that subdomain's own solves.  The residual-based mode,
+// Algorithm 2's subdomain-building phase and its additive form (whose
 // consecutive systems cover unrelated cell sets), tight mode and solves
 // outside a Newton iteration (fim_inspect_solve) take lin_rtol.
 static double forcing_eta(fim_model* m, double fnorm2) {
     const double lo = m->o.lin_rtol, hi = m->o.forcing_max;
+    const bool dd2 = m->step_mode == FIM_DD && m->dd_phase == 2 && m->dd_cur >= 0;
     if (!(hi > lo) || m->o.tight || !m->in_step || m->is_clone ||
-        (m->step_mode != FIM_FULL && m->step_mode != FIM_LOCAL))
+        (m->step_mode != FIM_FULL && m->step_mode != FIM_LOCAL && !dd2))
         return lo;
+    if (dd2 && (int)m->dd_ew_f.size() <= m->dd_cur) {
+        m->dd_ew_f.resize(m->dd_cur + 1, 0.0);
+        m->dd_ew_eta.resize(m->dd_cur + 1, 0.0);
+    }
+    double& fprev = dd2 ? m->dd_ew_f[m->dd_cur] : m->ew_fprev;
+    double& eprev = dd2 ? m->dd_ew_eta[m->dd_cur] : m->ew_eta;
     const double fn = std::sqrt(fnorm2);
-    double eta = hi;
-    if (m->ew_fprev > 0.0 && std::isfinite(fn)) {
-        const double r = fn / m->ew_fprev;
+    double eta = hi;   // the first solve of the step (or of the subdomain)
+    if (fprev > 0.0 && std::isfinite(fn)) {
+        const double r = fn / fprev;
         eta = 0.9 * r * r;
-        const double safe = 0.9 * m->ew_eta * m->ew_eta;
+        const double safe = 0.9 * eprev * eprev;
         if (safe > 0.1) eta = std::max(eta, safe);
     }
     eta = std::min(hi, std::max(lo, eta));
-    m->ew_fprev = fn;
-    m->ew_eta = eta;
+    fprev = fn;
+    eprev = eta;
     return eta;
 }
 
@@ -1025,6 +1038,8 @@ static fim_status begin_launch(fim_model* m, double dt, int mode, bool* pending)
         launch_fill_f64(m->last_dp, m->n, 0.0, m->s);
         HIPX(hipMemcpyAsync(m->vt, m->act, m->n, hipMemcpyDeviceToDevice, m->s));
         m->subs.clear();
+        m->dd_ew_f.clear();
+        m->dd_ew_eta.clear();
         m->sd_used = m->ob_used = 0;
         m->dd_phase = 1;
         m->dd_valid = true;
@@ -2143,7 +2158,10 @@ static fim_status newton_dd(fim_model* m, fim_iter_stats* it) {
         }
         if (it) it->subdomain = pick;
         TRY(dd_activate(m, pick));
-        TRY(local_newton(m, it));
+        m->dd_cur = pick;
+        const fim_status ln = local_newton(m, it);
+        m->dd_cur = -1;
+        TRY(ln);
         launch_copy_masked(m->nA, m->l2g, m->dp_abs, m->last_dp, m->s);
         HIPX(hipMemcpyAsync(m->hns, m->ns, sizeof(NStat), hipMemcpyDeviceToHost, m->s));
         HIPX(spin_sync(m, m->s));
