@@ -197,6 +197,7 @@ struct fim_model {
     // |F| and eta) and the subdomain being solved (-1: none)
     std::vector<double> dd_ew_f, dd_ew_eta;
     int dd_cur = -1;
+    fim_model* ew_owner = nullptr;   // a subdomain workspace: the model whose sequences it uses
     double step_dt = 0.0;
     int step_mode = 0, nu = 0, nA = 0, nB = 0;
     bool is_expand = true;
@@ -569,23 +570,26 @@ static void solve_prep(fim_model* m, hipStream_t s) {
 // Eisenstat and Walker (1996, choice 2, gamma 0.9, alpha 2, with their
 // safeguard) between lin_rtol and forcing_max, from the norms of the
 // iterations' local residuals (the first iteration of a timestep takes
-// forcing_max).  Algorithm 2's sweeps (phase 2) keep one such sequence per
-// subdomain, over that subdomain's own solves.  The residual-based mode,
-// Algorithm 2's subdomain-building phase and its additive form (whose
+// forcing_max).  Algorithm 2's sweeps (phase 2, both forms) keep one such
+// sequence per subdomain, over that subdomain's own solves.  The
+// residual-based mode and Algorithm 2's subdomain-building phase (whose
 // consecutive systems cover unrelated cell sets), tight mode and solves
 // outside a Newton iteration (fim_inspect_solve) take lin_rtol.
 static double forcing_eta(fim_model* m, double fnorm2) {
     const double lo = m->o.lin_rtol, hi = m->o.forcing_max;
-    const bool dd2 = m->step_mode == FIM_DD && m->dd_phase == 2 && m->dd_cur >= 0;
-    if (!(hi > lo) || m->o.tight || !m->in_step || m->is_clone ||
+    // (a subdomain workspace of the additive form solves for its owner)
+    fim_model* o = m->is_clone ? m->ew_owner : m;
+    const bool dd2 = o && (m->step_mode == FIM_DD || m->step_mode == FIM_DD_ADD) &&
+                     o->dd_phase == 2 && m->dd_cur >= 0;
+    if (!(hi > lo) || m->o.tight || !o || !o->in_step || (m->is_clone && !dd2) ||
         (m->step_mode != FIM_FULL && m->step_mode != FIM_LOCAL && !dd2))
         return lo;
-    if (dd2 && (int)m->dd_ew_f.size() <= m->dd_cur) {
-        m->dd_ew_f.resize(m->dd_cur + 1, 0.0);
-        m->dd_ew_eta.resize(m->dd_cur + 1, 0.0);
+    if (dd2 && (int)o->dd_ew_f.size() <= m->dd_cur) {
+        o->dd_ew_f.resize(m->dd_cur + 1, 0.0);
+        o->dd_ew_eta.resize(m->dd_cur + 1, 0.0);
     }
-    double& fprev = dd2 ? m->dd_ew_f[m->dd_cur] : m->ew_fprev;
-    double& eprev = dd2 ? m->dd_ew_eta[m->dd_cur] : m->ew_eta;
+    double& fprev = dd2 ? o->dd_ew_f[m->dd_cur] : m->ew_fprev;
+    double& eprev = dd2 ? o->dd_ew_eta[m->dd_cur] : m->ew_eta;
     const double fn = std::sqrt(fnorm2);
     double eta = hi;   // the first solve of the step (or of the subdomain)
     if (fprev > 0.0 && std::isfinite(fn)) {
@@ -2048,6 +2052,8 @@ static fim_status dd_additive_sweep(fim_model* m, int N, fim_iter_stats* it) {
         c->s = m->s;
         c->step_dt = m->step_dt;
         c->step_mode = m->step_mode;
+        c->ew_owner = m;        // the subdomain's forcing sequence
+        c->dd_cur = todo[j];
         launch_fill_u8(c->act, c->n, 0, c->s);
         launch_scatter_flags(sd.cells_n, m->sd_cells + sd.cells_off, c->act, c->s);
         compact(c);
@@ -2057,7 +2063,9 @@ static fim_status dd_additive_sweep(fim_model* m, int N, fim_iter_stats* it) {
         solve_prep(c, c->s);
         sum_n += sd.cells_n;
     }
-    TRY(solve_batch(ws, m->dd_tab, m->s, true));
+    const fim_status sv = solve_batch(ws, m->dd_tab, m->s, true);
+    for (fim_model* c : ws) c->dd_cur = -1;
+    TRY(sv);
     int kry = 0;
     for (int j = 0; j < P; j++) {
         fim_model* c = ws[j];
