@@ -157,7 +157,9 @@ _lib = _load()
 
 @dataclass
 class Options:
-    """Mirror of fim_options; defaults are the paper's settings."""
+    """Mirror of fim_options with its defaults: the paper's cutoffs and
+    layers (Section 5); the linear-solve settings (tolerance, forcing term,
+    precision, preconditioner) are readings where the paper is silent."""
     eps_conv: float = 0.3 * PSI
     eps_loc: float = 0.3 * PSI
     eps_s: float = 1e-10
