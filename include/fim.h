@@ -167,13 +167,13 @@ typedef struct fim_options {
                                 exceeds 0.1) within [lin_rtol, forcing_max],
                                 forcing_max on a timestep's first iteration;
                                 |F| is the iteration's local residual
-                                (FIM_FULL, FIM_LOCAL; the sweeps of FIM_DD
-                                and FIM_DD_ADD with one sequence per
-                                subdomain).  FIM_RESID, Algorithm 2's
-                                subdomain-building phase, tight mode and
-                                forcing_max <= lin_rtol solve every
-                                iteration to lin_rtol.  Negative or
-                                non-finite: FIM_E_ARG                         */
+                                (FIM_FULL, FIM_LOCAL; FIM_RESID after a
+                                first iteration at lin_rtol; the sweeps of
+                                FIM_DD and FIM_DD_ADD with one sequence per
+                                subdomain).  Algorithm 2's subdomain-building
+                                phase, tight mode and forcing_max <=
+                                lin_rtol solve every iteration to lin_rtol.
+                                Negative or non-finite: FIM_E_ARG            */
 } fim_options;
 
 typedef struct fim_iter_stats {

@@ -571,10 +571,11 @@ static void solve_prep(fim_model* m, hipStream_t s) {
 // safeguard) between lin_rtol and forcing_max, from the norms of the
 // iterations' local residuals (the first iteration of a timestep takes
 // forcing_max).  Algorithm 2's sweeps (phase 2, both forms) keep one such
-// sequence per subdomain, over that subdomain's own solves.  The
-// residual-based mode and Algorithm 2's subdomain-building phase (whose
-// consecutive systems cover unrelated cell sets), tight mode and solves
-// outside a Newton iteration (fim_inspect_solve) take lin_rtol.
+// sequence per subdomain, over that subdomain's own solves; the
+// residual-based mode starts its sequence at lin_rtol.  Algorithm 2's
+// subdomain-building phase (the subdomains are built from the updates'
+// magnitudes), tight mode and solves outside a Newton iteration
+// (fim_inspect_solve) take lin_rtol.
 static double forcing_eta(fim_model* m, double fnorm2) {
     const double lo = m->o.lin_rtol, hi = m->o.forcing_max;
     // (a subdomain workspace of the additive form solves for its owner)
@@ -582,7 +583,8 @@ static double forcing_eta(fim_model* m, double fnorm2) {
     const bool dd2 = o && (m->step_mode == FIM_DD || m->step_mode == FIM_DD_ADD) &&
                      o->dd_phase == 2 && m->dd_cur >= 0;
     if (!(hi > lo) || m->o.tight || !o || !o->in_step || (m->is_clone && !dd2) ||
-        (m->step_mode != FIM_FULL && m->step_mode != FIM_LOCAL && !dd2))
+        (m->step_mode != FIM_FULL && m->step_mode != FIM_LOCAL && m->step_mode != FIM_RESID &&
+         !dd2))
         return lo;
     if (dd2 && (int)o->dd_ew_f.size() <= m->dd_cur) {
         o->dd_ew_f.resize(m->dd_cur + 1, 0.0);
@@ -591,7 +593,10 @@ static double forcing_eta(fim_model* m, double fnorm2) {
     double& fprev = dd2 ? o->dd_ew_f[m->dd_cur] : m->ew_fprev;
     double& eprev = dd2 ? o->dd_ew_eta[m->dd_cur] : m->ew_eta;
     const double fn = std::sqrt(fnorm2);
-    double eta = hi;   // the first solve of the step (or of the subdomain)
+    // the first solve of the step (or of the subdomain); the residual-based
+    // mode solves its first iteration, on every cell, to lin_rtol: its
+    // error measure, which picks the next iterations' cells, needs it
+    double eta = m->step_mode == FIM_RESID ? lo : hi;
     if (fprev > 0.0 && std::isfinite(fn)) {
         const double r = fn / fprev;
         eta = 0.9 * r * r;
