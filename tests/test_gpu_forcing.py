@@ -1,6 +1,7 @@
 """The inexact Newton forcing term (Eisenstat and Walker 1996, choice 2;
-option forcing_max, on by default in full Newton, Algorithm 1 and the
-sweeps of Algorithm 2): paper mode timesteps solved with it end within the
+option forcing_max, on by default in full Newton, Algorithm 1, the sweeps
+of Algorithm 2 and the residual-based mode after its first iteration):
+paper mode timesteps solved with it end within the
 Newton tolerance of the same steps with a fixed 1e-4 linear tolerance and
 of the oracle's full Newton with direct solves (Section 5: eps_p = 0.3
 psi), with no more BiCGStab iterations; tight mode ignores it; invalid
@@ -32,14 +33,14 @@ def _run(model, opts, mode):
 
 
 @pytest.mark.parametrize("maker", [make_small_c2, make_small_c3], ids=["c2s", "c3s"])
-@pytest.mark.parametrize("mode_name", ["FULL", "LOCAL", "DD"])
+@pytest.mark.parametrize("mode_name", ["FULL", "LOCAL", "DD", "RESID"])
 def test_forcing_term_ends_within_newton_tolerance(maker, mode_name):
     import paper_2008_01539_amd as P
     m = maker()
     mode = getattr(P, mode_name)
     u_ew, k_ew = _run(m, P.Options(precision=P.MIXED), mode)
     u_fx, k_fx = _run(m, P.Options(precision=P.MIXED, forcing_max=0.0), mode)
-    if mode_name == "DD":   # only the sweeps' re-solves use it
+    if mode_name in ("DD", "RESID"):   # the sweeps / the later iterations only
         assert k_ew <= k_fx
     else:
         assert k_ew < k_fx
@@ -50,7 +51,7 @@ def test_forcing_term_ends_within_newton_tolerance(maker, mode_name):
         # full Newton: both within the Newton tolerance of the direct solves
         assert d_ew <= EPS and d_fx <= EPS, (d_ew / PSI, d_fx / PSI)
     else:
-        # Algorithms 1 and 2: the forcing term adds at most the Newton
+        # the localized modes: the forcing term adds at most the Newton
         # tolerance to the localization's own distance from full Newton
         assert d_ew <= d_fx + EPS, (d_ew / PSI, d_fx / PSI)
     assert np.abs(u_ew[0] - u_fx[0]).max() <= 2 * EPS
