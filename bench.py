@@ -544,7 +544,8 @@ def run_single(workload, args):
                         + f"; timed steps {W}..{W + K - 1} after {W} untimed; localized "
                           "Newton (Algorithm 1, eps_p 0.3 psi, m 2), FP64 assembly/update/"
                           "switching, FP32 BiCGStab (block-Jacobi scaling + fracture-block "
-                          "inverses) inside FP64 refinement",
+                          "inverses) inside FP64 refinement to the Eisenstat-Walker forcing "
+                          "term in [1e-4, 0.1]",
             "n_cells": model.n,
             "fractures_always_active": not args.localize_fractures,
             "krylov_dtype": "f32",
