@@ -162,9 +162,10 @@ typedef struct fim_options {
                                 at most 8)                                     */
     double  forcing_max;     /* > lin_rtol (default 0.1): inexact Newton
                                 forcing term of Eisenstat and Walker (1996,
-                                choice 2: eta = 0.9 (|F_k| / |F_k-1|)^2,
-                                safeguarded by 0.9 eta_k-1^2 when that
-                                exceeds 0.1) within [lin_rtol, forcing_max],
+                                choice 2: eta = 0.9 (|F_k| / |F_k-1|)^a,
+                                a = (1 + sqrt 5) / 2, safeguarded by
+                                0.9 eta_k-1^a when that exceeds 0.1) within
+                                [lin_rtol, forcing_max],
                                 forcing_max on a timestep's first iteration;
                                 |F| is the iteration's local residual
                                 (FIM_FULL, FIM_LOCAL; FIM_RESID after a

@@ -567,8 +567,8 @@ static void solve_prep(fim_model* m, hipStream_t s) {
 
 // Relative tolerance of this Newton iteration's linear solve: lin_rtol, or,
 // in full Newton and Algorithm 1, the inexact Newton forcing term of
-// Eisenstat and Walker (1996, choice 2, gamma 0.9, alpha 2, with their
-// safeguard) between lin_rtol and forcing_max, from the norms of the
+// Eisenstat and Walker (1996, choice 2, gamma 0.9, alpha (1 + sqrt 5) / 2,
+// with their safeguard) between lin_rtol and forcing_max, from the norms of the
 // iterations' local residuals (the first iteration of a timestep takes
 // forcing_max).  Algorithm 2's sweeps (phase 2, both forms) keep one such
 // sequence per subdomain, over that subdomain's own solves; the
@@ -576,6 +576,9 @@ static void solve_prep(fim_model* m, hipStream_t s) {
 // subdomain-building phase (the subdomains are built from the updates'
 // magnitudes), tight mode and solves outside a Newton iteration
 // (fim_inspect_solve) take lin_rtol.
+// exponent of choice 2: the golden ratio, the order of the secant method
+constexpr double EW_ALPHA = 1.6180339887498949;
+
 static double forcing_eta(fim_model* m, double fnorm2) {
     const double lo = m->o.lin_rtol, hi = m->o.forcing_max;
     // (a subdomain workspace of the additive form solves for its owner)
@@ -599,8 +602,8 @@ static double forcing_eta(fim_model* m, double fnorm2) {
     double eta = m->step_mode == FIM_RESID ? lo : hi;
     if (fprev > 0.0 && std::isfinite(fn)) {
         const double r = fn / fprev;
-        eta = 0.9 * r * r;
-        const double safe = 0.9 * eprev * eprev;
+        eta = 0.9 * std::pow(r, EW_ALPHA);
+        const double safe = 0.9 * std::pow(eprev, EW_ALPHA);
         if (safe > 0.1) eta = std::max(eta, safe);
     }
     eta = std::min(hi, std::max(lo, eta));
