@@ -1313,7 +1313,7 @@ void fim_default_options(fim_options* o) {
     o->inner_rtol = 1e-5;
     o->krylov_maxit = 2000;
     o->max_refine = 20;
-    o->check_every = 8;
+    o->check_every = 4;
     o->precond = FIM_PC_FRACTURE;
     o->eps_res = 1e-6;
     o->res_layers = 1;

@@ -176,7 +176,7 @@ class Options:
     inner_rtol: float = 1e-5
     krylov_maxit: int = 2000
     max_refine: int = 20
-    check_every: int = 8
+    check_every: int = 4
     precond: int = PC_FRACTURE
     eps_res: float = 1e-6
     res_layers: int = 1
